@@ -1,0 +1,339 @@
+"""CPU oracle, part 2: the Krylov solvers around the projected Jacobian.
+
+TEST INFRASTRUCTURE ONLY (see oracle/disc.py).
+
+The paper (Sec. 1 and Sec. 3) computes steady states by Newton's method
+whose corrections come from BiCGstab(2) combined with GMRES, and leading
+eigenvalues by Chebyshev-preconditioned Arnoldi iteration applied directly
+to the divergence-free Krylov vectors (no shift-and-invert).  The operator
+everywhere is A = P J(X0) acting on divergence-free vectors, with the
+volume-weighted inner product <a, b>_W (P is W-orthogonal in it).
+
+Readings (the paper gives no parameters; its refs [21], [22] are absent):
+  * BiCGstab(l) with l = 2 in the form of Sleijpen & Fokkema (1993): two
+    BiCG sub-steps followed by a degree-2 minimal-residual polynomial;
+    shadow vector = initial residual; on breakdown or stagnation the solve
+    continues with restarted GMRES(m) from the current iterate.
+  * Arnoldi with classical Gram-Schmidt applied twice (CGS2).
+  * Chebyshev-Arnoldi in the style of Saad (1984): restarted Arnoldi whose
+    restart vector is filtered by a Chebyshev polynomial on the ellipse
+    enclosing the unwanted Ritz values.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import disc
+
+
+class Operator:
+    """A x = P J(X0) x with the grid's weighted inner product."""
+
+    def __init__(self, g: disc.Grid, X0):
+        self.g, self.X0 = g, np.asarray(X0, dtype=np.float64)
+        self.fd = disc.FastDiag(g)
+        self.w = g.weights()
+        self.matvecs = 0
+
+    def __call__(self, x):
+        self.matvecs += 1
+        return disc.project(self.g, disc.jacobian(self.g, self.X0, x), self.fd)
+
+    def dot(self, a, b):
+        return disc.wdot(self.w, a, b)
+
+    def norm(self, a):
+        return disc.wnorm(self.w, a)
+
+
+# ---- BiCGstab(2) ------------------------------------------------------------
+def bicgstab2(A: Operator, b, x0=None, tol=1e-8, max_matvec=10000,
+              stall_cycles=50):
+    """Solve A x = b.  Returns (x, info) with info keys relres, matvecs,
+    cycles, status in {"converged", "breakdown", "stagnation", "maxit"}."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    m0 = A.matvecs
+    r = [b - A(x) if x0 is not None else b.copy(), None, None]
+    bnorm = A.norm(b)
+    if bnorm == 0.0:
+        return x, dict(relres=0.0, matvecs=A.matvecs - m0, cycles=0, status="converged")
+    rt = r[0].copy()                                   # shadow residual
+    u = [np.zeros_like(b), None, None]
+    rho0, alpha, omega = 1.0, 0.0, 1.0
+    res = A.norm(r[0])
+    best, best_cycle, cycles = res, 0, 0
+    scale = bnorm * bnorm
+    while True:
+        if res <= tol * bnorm:
+            status = "converged"
+            break
+        if A.matvecs - m0 + 4 > max_matvec:
+            status = "maxit"
+            break
+        rho0 = -omega * rho0
+        # --- BiCG part: two steps, each extending u and r by one A-power
+        for j in range(2):
+            rho1 = A.dot(r[j], rt)
+            if abs(rho0) <= 1e-300 * scale or rho1 == 0.0:
+                return x, dict(relres=res / bnorm, matvecs=A.matvecs - m0,
+                               cycles=cycles, status="breakdown")
+            beta = alpha * rho1 / rho0
+            rho0 = rho1
+            for i in range(j + 1):
+                u[i] = r[i] - beta * u[i]
+            u[j + 1] = A(u[j])
+            gamma = A.dot(u[j + 1], rt)
+            if abs(gamma) <= 1e-300 * scale:
+                return x, dict(relres=res / bnorm, matvecs=A.matvecs - m0,
+                               cycles=cycles, status="breakdown")
+            alpha = rho0 / gamma
+            for i in range(j + 1):
+                r[i] = r[i] - alpha * u[i + 1]
+            r[j + 1] = A(r[j])
+            x = x + alpha * u[0]
+        # --- minimal-residual part over span{r1, r2} (modified Gram-Schmidt)
+        sigma1 = A.dot(r[1], r[1])
+        g1p = A.dot(r[0], r[1]) / sigma1
+        tau12 = A.dot(r[2], r[1]) / sigma1
+        r[2] = r[2] - tau12 * r[1]
+        sigma2 = A.dot(r[2], r[2])
+        g2p = A.dot(r[0], r[2]) / sigma2
+        g2 = g2p
+        omega = g2
+        g1 = g1p - tau12 * g2
+        g1pp = g2
+        x = x + g1 * r[0] + g1pp * r[1]
+        r[0] = r[0] - g2p * r[2] - g1p * r[1]
+        u[0] = u[0] - g2 * u[2] - g1 * u[1]
+        cycles += 1
+        res = A.norm(r[0])
+        if not np.isfinite(res):
+            return x, dict(relres=res, matvecs=A.matvecs - m0, cycles=cycles,
+                           status="breakdown")
+        if res < 0.9 * best:
+            best, best_cycle = res, cycles
+        elif cycles - best_cycle >= stall_cycles:
+            status = "stagnation"
+            break
+    return x, dict(relres=res / bnorm, matvecs=A.matvecs - m0, cycles=cycles,
+                   status=status)
+
+
+# ---- restarted GMRES ------------------------------------------------------------
+def gmres(A: Operator, b, x0=None, tol=1e-8, m=40, max_matvec=10000):
+    """Restarted GMRES(m) on A x = b with CGS2 Arnoldi and a least-squares
+    solve of the small Hessenberg system (library lstsq)."""
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    m0 = A.matvecs
+    bnorm = A.norm(b)
+    cycles = 0
+    while True:
+        r = b - A(x)
+        beta = A.norm(r)
+        if beta <= tol * bnorm or bnorm == 0.0:
+            return x, dict(relres=beta / bnorm if bnorm else 0.0, matvecs=A.matvecs - m0,
+                           cycles=cycles, status="converged")
+        if A.matvecs - m0 + 2 > max_matvec:
+            return x, dict(relres=beta / bnorm, matvecs=A.matvecs - m0,
+                           cycles=cycles, status="maxit")
+        mm = max(1, min(m, max_matvec - (A.matvecs - m0) - 1))
+        V, H, k = arnoldi(A, r, mm)
+        e = np.zeros(H.shape[0])
+        e[0] = beta
+        y = np.linalg.lstsq(H, e, rcond=None)[0]
+        x = x + y @ V[:k]
+        cycles += 1
+
+
+def newton_correction(A: Operator, F, tol=1e-8, max_matvec=10000, delta0=None,
+                      gmres_m=40):
+    """delta with P J delta = -F: BiCGstab(2), continued by GMRES(m) from the
+    current iterate after a breakdown or stagnation."""
+    F = A_project(A, F)
+    delta, info = bicgstab2(A, -F, x0=delta0, tol=tol, max_matvec=max_matvec)
+    info["used_gmres"] = 0
+    if info["status"] in ("breakdown", "stagnation"):
+        left = max_matvec - info["matvecs"]
+        delta, ginfo = gmres(A, -F, x0=delta, tol=tol, m=gmres_m, max_matvec=left)
+        info = dict(relres=ginfo["relres"], matvecs=info["matvecs"] + ginfo["matvecs"],
+                    cycles=info["cycles"] + ginfo["cycles"], status=ginfo["status"],
+                    used_gmres=1)
+    return delta, info
+
+
+# ---- Arnoldi with classical Gram-Schmidt twice ----------------------------------
+def arnoldi(A: Operator, v0, m, breakdown_tol=1e-14):
+    """m Arnoldi steps from v0.  Returns (V, H, k): V holds k+1 W-orthonormal
+    vectors as rows, H is (k+1) x k upper Hessenberg, k <= m (lucky
+    breakdown ends early)."""
+    n = len(v0)
+    V = np.zeros((m + 1, n))
+    H = np.zeros((m + 1, m))
+    V[0] = v0 / A.norm(v0)
+    Wt = A.w
+    for j in range(m):
+        w = A(V[j])
+        wn = A.norm(w)
+        for _ in range(2):
+            h = V[: j + 1] @ (Wt * w)                  # h = V^T W w
+            w = w - h @ V[: j + 1]
+            H[: j + 1, j] += h
+        H[j + 1, j] = A.norm(w)
+        if H[j + 1, j] <= breakdown_tol * wn:
+            return V[: j + 1], H[: j + 2, : j + 1], j + 1
+        V[j + 1] = w / H[j + 1, j]
+    return V, H, m
+
+
+def order_leading(vals):
+    """Indices ordering eigenvalues by decreasing real part, +Im first in a pair."""
+    vals = np.asarray(vals)
+    return sorted(range(len(vals)), key=lambda i: (-vals[i].real, -vals[i].imag))
+
+
+def wanted_set(vals, k):
+    """The k leading values, extended by one when that would split a pair."""
+    idx = order_leading(vals)
+    sel = idx[:k]
+    if k < len(idx):
+        last = vals[sel[-1]]
+        if last.imag > 0 and abs(vals[idx[k]] - np.conj(last)) <= 1e-12 * max(1.0, abs(last)):
+            sel = idx[: k + 1]
+    return sel
+
+
+def ritz(H, k):
+    """Ritz values, unit 2-norm Ritz coefficient vectors and residual estimates."""
+    Hm = H[:k, :k]
+    vals, vecs = np.linalg.eig(Hm)
+    vecs = vecs / np.linalg.norm(vecs, axis=0, keepdims=True)
+    hk = H[k, k - 1] if H.shape[0] > k else 0.0
+    res = np.abs(hk * vecs[k - 1, :])
+    return vals, vecs, res
+
+
+def arnoldi_ritz(A: Operator, v0, m, n_eigs):
+    """Leading Ritz values of one m-step Arnoldi cycle (no restart)."""
+    V, H, k = arnoldi(A, A_project(A, v0), m)
+    vals, vecs, res = ritz(H, k)
+    sel = wanted_set(vals, n_eigs)
+    return vals[sel], res[sel]
+
+
+def A_project(A: Operator, v):
+    return disc.project(A.g, np.asarray(v, dtype=np.float64), A.fd)
+
+
+# ---- Chebyshev-preconditioned Arnoldi -----------------------------------------
+def ellipse(unwanted):
+    """Centre d, semi-axes a (real) and b (imag), and c^2 = a^2 - b^2 of an
+    ellipse symmetric about the real axis enclosing the unwanted values."""
+    re, im = unwanted.real, np.abs(unwanted.imag)
+    rmin, rmax = float(re.min()), float(re.max())
+    d = 0.5 * (rmin + rmax)
+    a = max(0.5 * (rmax - rmin), 1e-300)
+    while True:
+        t = ((re - d) / a) ** 2
+        if np.all((t < 1.0) | (im == 0.0)):
+            break
+        a *= 1.1
+    ok = t < 1.0
+    b2 = float(np.max(im[ok] ** 2 / (1.0 - t[ok]), initial=0.0))
+    b = math.sqrt(b2)
+    return d, a, b, a * a - b2
+
+
+def cheb_degree(wr, a, b, c2, dmax, gain=1e6):
+    """Smallest degree whose Chebyshev growth at wr over the ellipse exceeds gain."""
+    s = np.sqrt(complex(wr * wr - c2))
+    ratio = max(abs(wr + s), abs(wr - s)) / (a + b)
+    if ratio <= 1.0 + 1e-12:
+        return 0
+    return int(min(dmax, max(1, math.ceil(math.log(gain) / math.log(ratio)))))
+
+
+def cheb_filter(A: Operator, z0, d, c2, wr, degree):
+    """z_deg = p_deg(A - dI) z0 / p_deg(wr) with p_0 = 1, p_1 = w,
+    p_{j+1} = 2 w p_j - c^2 p_{j-1} (real three-term recurrence)."""
+    if degree == 0:
+        return z0
+    rj = 1.0 / wr                                        # s_0 / s_1
+    zprev, z = z0, rj * (A(z0) - d * z0)
+    for _ in range(1, degree):
+        rnext = 1.0 / (2.0 * wr - c2 * rj)
+        znew = rnext * (2.0 * (A(z) - d * z) - c2 * rj * zprev)
+        zprev, z, rj = z, znew, rnext
+    return z
+
+
+def cheb_arnoldi(A: Operator, v0, m, n_eigs, tol=1e-8, max_matvec=100000,
+                 cheb_degree_max=200, max_restarts=1000):
+    """Leading eigenvalues of A.  Returns (vals, res, vecs, info)."""
+    m0 = A.matvecs
+    v = A_project(A, v0)
+    restarts = 0
+    while True:
+        V, H, k = arnoldi(A, v, m)
+        vals, S, res = ritz(H, k)
+        sel = wanted_set(vals, n_eigs)
+        scale = max(abs(vals[i]) for i in sel)
+        conv = all(res[i] <= tol * scale for i in sel) or k < m
+        if conv or A.matvecs - m0 >= max_matvec or restarts >= max_restarts:
+            Y = (V[:k].T @ S[:, sel]).T                 # Ritz vectors as rows
+            return (vals[sel], res[sel], Y,
+                    dict(matvecs=A.matvecs - m0, restarts=restarts, converged=conv))
+        # restart vector: sum of real and imaginary parts of wanted Ritz vectors
+        coef = np.zeros(k)
+        for i in sel:
+            coef += S[:, i].real + S[:, i].imag
+        z0 = V[:k].T @ coef
+        z0 = z0 / A.norm(z0)
+        unw = np.array([vals[i] for i in range(k) if i not in sel])
+        if len(unw) == 0:
+            v = z0
+        else:
+            d, a, b, c2 = ellipse(unw)
+            ref = min((vals[i] for i in sel), key=lambda t: t.real)
+            wr = ref.real - d
+            deg = cheb_degree(wr, a, b, c2, cheb_degree_max)
+            deg = min(deg, max(0, max_matvec - (A.matvecs - m0) - m))
+            v = cheb_filter(A, z0, d, c2, wr, deg)
+        # A = P J has the eigenvalue 0 on gradient fields, right of the wanted
+        # set; the filter's "- d z" term carries round-off there, so the start
+        # vector is put back into range(P) before the next Arnoldi cycle.
+        v = A_project(A, v)
+        v = v / A.norm(v)
+        restarts += 1
+
+
+# ---- Newton ------------------------------------------------------------------------
+def newton(g: disc.Grid, X, rtol=1e-10, atol=0.0, max_iter=30, lin_tol=None,
+           max_matvec=20000):
+    """Newton iteration X <- X + delta with P J(X) delta = -P N(X).
+
+    The initial state is projected first.  The right-hand side -F is
+    projected once more before the linear solve: F = P N(X) carries
+    round-off of size eps*||N|| outside range(P), which is not small next to
+    ||F|| near convergence and makes the singular system inconsistent.
+    Inner tolerance eta_k = max(1e-12, min(1e-2, ||F_k||_W)) unless lin_tol
+    is given.  Stops when ||F||_W <= max(atol, rtol*||F_0||_W).
+    Returns (X, history of ||F||_W, total matvecs)."""
+    fd = disc.FastDiag(g)
+    X = disc.project(g, np.asarray(X, dtype=np.float64), fd)
+    hist, mv = [], 0
+    for _ in range(max_iter + 1):
+        F = disc.residual(g, X, fd)
+        A = Operator(g, X)
+        A.fd = fd
+        fn = A.norm(F)
+        hist.append(fn)
+        if fn <= max(atol, rtol * hist[0]) or len(hist) > max_iter:
+            break
+        eta = lin_tol if lin_tol is not None else max(1e-12, min(1e-2, fn))
+        F = disc.project(g, F, fd)
+        delta, info = newton_correction(A, F, tol=eta, max_matvec=max_matvec)
+        mv += info["matvecs"]
+        X = X + delta
+    return X, hist, mv
