@@ -263,9 +263,11 @@ class FastDiag:
             s = 1.0 / np.sqrt(g.h[a])
             M = s[:, None] * laplacian_1d(g, a) * s[None, :]
             lam, Q = np.linalg.eigh(M)
+            null = int(np.argmax(lam))
+            lam[null] = 0.0          # K 1 = 0 exactly: the constant mode's eigenvalue is 0
             self.Q.append(Q)
             self.lam.append(lam)
-            self.null.append(int(np.argmax(lam)))
+            self.null.append(null)
         lx, ly, lz = (g.along(self.lam[a], a) for a in range(3))
         den = lx + ly + lz
         den[self.null[2], self.null[1], self.null[0]] = np.inf
