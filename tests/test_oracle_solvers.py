@@ -145,7 +145,7 @@ def test_linear_solvers_match_dense_saddle_solve(solver):
     z = np.linalg.lstsq(M, rhs, rcond=None)[0]
     delta_ref = z[:n]
     A = SV.Operator(g, X0)
-    F = O.residual(g, X0)
+    F = SV.A_project(A, O.residual(g, X0))      # as the Newton correction does
     if solver == "bicgstab2":
         delta, info = SV.bicgstab2(A, -F, tol=1e-12, max_matvec=4000)
     else:
