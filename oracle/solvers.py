@@ -317,8 +317,9 @@ def newton(g: disc.Grid, X, rtol=1e-10, atol=0.0, max_iter=30, lin_tol=None,
     projected once more before the linear solve: F = P N(X) carries
     round-off of size eps*||N|| outside range(P), which is not small next to
     ||F|| near convergence and makes the singular system inconsistent.
-    Inner tolerance eta_k = max(1e-12, min(1e-2, ||F_k||_W)) unless lin_tol
-    is given.  Stops when ||F||_W <= max(atol, rtol*||F_0||_W).
+    Inner tolerance eta_k = max(1e-10, min(1e-2, ||F_k||_W)) unless lin_tol
+    is given (the floor keeps the last solve above the round-off level of
+    the right-hand side).  Stops when ||F||_W <= max(atol, rtol*||F_0||_W).
     Returns (X, history of ||F||_W, total matvecs)."""
     fd = disc.FastDiag(g)
     X = disc.project(g, np.asarray(X, dtype=np.float64), fd)
@@ -331,7 +332,7 @@ def newton(g: disc.Grid, X, rtol=1e-10, atol=0.0, max_iter=30, lin_tol=None,
         hist.append(fn)
         if fn <= max(atol, rtol * hist[0]) or len(hist) > max_iter:
             break
-        eta = lin_tol if lin_tol is not None else max(1e-12, min(1e-2, fn))
+        eta = lin_tol if lin_tol is not None else max(1e-10, min(1e-2, fn))
         F = disc.project(g, F, fd)
         delta, info = newton_correction(A, F, tol=eta, max_matvec=max_matvec)
         mv += info["matvecs"]

@@ -160,8 +160,8 @@ def test_newton_quadratic_convergence_and_symmetry():
     cube to round-off (the paper reports ~1e-9 for symmetric solutions)."""
     f = S.faces_uniform(16)
     g = O.Grid(f, f, f, Gr=1e4, Pr=0.71)
-    X, hist, mv = SV.newton(g, S.conduction_state(f, f, f), rtol=1e-12, max_iter=12)
-    assert hist[-1] <= 1e-12 * hist[0]
+    X, hist, mv = SV.newton(g, S.conduction_state(f, f, f), rtol=1e-11, max_iter=12)
+    assert hist[-1] <= 1e-11 * hist[0]
     # once in the quadratic regime, ||F_{k+1}|| <= C ||F_k||^2
     k = next(i for i, r in enumerate(hist) if r < 1e-3)
     assert hist[k + 1] <= 10.0 * hist[k] ** 2
