@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Throughput of the projected Jacobian P J(X0) x (one Krylov vector of the
+Newton / Arnoldi method) on one MI355X, with the CPU oracle timed beside it.
+
+Workload (default): 256^3 wall-clustered staggered grid, Gr = 2e8, Pr = 0.71,
+base flow = discrete curl of a seeded sin-mode vector potential (K = 6,
+amplitude 0.1) with T0 = 1/2 - x, perturbations x ~ N(0,1) seeded 1000 + r.
+Inputs are resident in HBM before timing; each step is one
+kv_apply_jacobian(x_r, y_r, KV_PROJECT), cycling over a small batch.
+
+Prints one JSON line (see the "metric" field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_cell_fp64():
+    """HBM bytes per cell of one projected Krylov vector if every phase makes
+    one pass: stencil 104, 6 transform passes 96, correction 56."""
+    return {"stencil": 104.0, "fd": 96.0, "correction": 56.0, "divergence": 32.0}
+
+
+def cpu_baseline(g_args, X0, x0, y_gpu):
+    """Time the oracle on the host for one projected Krylov vector and report
+    the GPU output's error against it."""
+    from oracle import disc as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    g = O.Grid(*g_args["faces"], Gr=g_args["Gr"], Pr=g_args["Pr"])
+    t0 = time.perf_counter()
+    fd = O.FastDiag(g)
+    ref = O.apply_jacobian(g, X0, x0, projected=True, fd=fd)
+    dt = time.perf_counter() - t0
+    errs = []
+    for a, b in zip(g.unpack(y_gpu), g.unpack(ref)):
+        errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+    return {"value": 1.0 / dt, "unit": "Krylov vectors/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one P J x application (x seed 1000) on the full grid, {dt:.1f} s wall"}, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cube256_clustered_gr2e8")
+    ap.add_argument("--batch", type=int, default=4, help="resident perturbations cycled over")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(one solve per GPU is the sharding plan); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from synth import inputs as S
+    from paper_2210_08816_amd import kv
+
+    spec = S.WORKLOADS[args.workload]
+    xf, yf, zf = S.workload_grid(spec)
+    n_cells = spec["n"] ** 3
+    log(f"[bench] workload {args.workload}: building inputs")
+    X0 = S.base_flow(xf, yf, zf, K=spec["K"], amp=spec["amp"], seed=spec["base_seed"])
+    ctx = kv.Context(xf, yf, zf, Gr=spec["Gr"], Pr=spec["Pr"])
+    n = ctx.n
+    X0_d = torch.from_numpy(X0).to("cuda")
+    ctx.set_base_flow(X0_d)
+    B = max(1, args.batch)
+    xs_host0 = S.perturbation(n, 1000)
+    xs = [torch.from_numpy(xs_host0).to("cuda")]
+    for r in range(1, B):
+        xs.append(torch.from_numpy(S.perturbation(n, 1000 + r)).to("cuda"))
+    ys = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(B)]
+    torch.cuda.synchronize()
+    log(f"[bench] inputs resident: n = {n}, batch {B}")
+
+    for i in range(args.warmup):
+        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps / dt
+    log(f"[bench] timed {args.steps} steps in {dt:.3f} s: {value:.1f} vectors/s")
+
+    # per-phase device time with HIP events on the library's stream
+    ctx.timing(True)
+    nphase = min(args.steps, 200)
+    for i in range(nphase):
+        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
+    ms, calls = ctx.timing(False)
+    per_vec = [m / max(1, calls[1]) for m in ms]
+    fd_launch_ms = ms[2] / max(1, 6 * calls[1])
+    fd_flops = 2.0 * spec["n"] * n_cells                     # one axis pass: 2N flop per cell
+    achieved = fd_flops / (fd_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "fd_gemm_kernel (one axis transform of the FP64 fast-diagonalization solve)",
+                "launch_ms": round(fd_launch_ms, 5)}
+    bpc = algorithmic_bytes_per_cell_fp64()
+    phases = {"stencil_ms": per_vec[0], "divergence_ms": per_vec[1], "fd_ms": per_vec[2],
+              "correction_ms": per_vec[3],
+              "stencil_GBs": bpc["stencil"] * n_cells / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else None,
+              "correction_GBs": bpc["correction"] * n_cells / (per_vec[3] * 1e-3) / 1e9 if per_vec[3] else None}
+    # roofline time of the whole step: HBM for stencil/divergence/correction,
+    # FP64 peak for the transforms
+    t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
+              + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
+    step_roof_frac = t_roof / (dt / args.steps)
+
+    result = {
+        "metric": "Krylov vectors/s (J.v+projection) at 256^3, % HBM roofline; mixed vs FP64",
+        "value": round(value, 3), "unit": "Krylov vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "grid": f"{spec['n']}^3 {spec['grid']}", "Gr": spec["Gr"],
+                   "Pr": spec["Pr"], "form": "fp64", "resident_batch": B, "unknowns": n},
+        "roofline": roofline,
+        "step_roofline_frac": round(step_roof_frac, 4),
+        "phases_ms_per_vector": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in phases.items()},
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on one vector")
+        base, errs = cpu_baseline({"faces": (xf, yf, zf), "Gr": spec["Gr"], "Pr": spec["Pr"]}, X0, xs_host0,
+                                  ys[0].cpu().numpy() if args.steps % B != 0 or True else None)
+        result["cpu_baseline"] = base
+        result["parity_vs_oracle"] = {"x_seed": 1000, "field_rel_err_l2": errs}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+/*
+ * kv.h -- C ABI of the MI355X Krylov-vector library for Boussinesq convection
+ * in a laterally heated cube (Gelfgat, "Sequence of bifurcations of natural
+ * convection of air in a laterally heated cube with perfectly insulated
+ * horizontal and spanwise boundaries").
+ *
+ * The library computes, on one gfx950 GPU, the hot path of the paper's
+ * Newton / Arnoldi linear-stability method (Sec. 1 and Sec. 3): divergence-free
+ * Krylov vectors y = P J(X0) x that satisfy all boundary conditions, the
+ * steady residual F = P N(X), Newton corrections by BiCGstab(2) combined with
+ * GMRES, and leading eigenvalues by Chebyshev-preconditioned Arnoldi
+ * iteration without shift-and-invert.
+ *
+ * Equations (Sec. 2, Eqs. 1-3, the paper's scaling): nu = Gr^-1/2,
+ * kappa = 1/(Pr Gr^1/2), buoyancy +T e_z; no-slip walls, T = 1 / 0 on x = 0 / 1
+ * (Eq. 4), adiabatic y- and z-walls (Eqs. 5-6).  Gr == 0 selects the viscous
+ * scaling nu = 1, kappa = 1/Pr, no buoyancy.
+ *
+ * Discretization: second-order conservative staggered (MAC) finite volumes on
+ * a tensor-product grid of the unit cube, cell centres at face midpoints,
+ * distance-linear centre-to-face interpolation, wall values at half-cell
+ * distance.  The pressure is not a state variable: P = I - G (D G)^+ D is the
+ * discrete Leray projection, applied by fast diagonalization (exact in one
+ * pass in FP64).
+ *
+ * Packed state vector (all vector arguments): FP64, x fastest, then y, then z,
+ *   [ u: (nz, ny, nx-1) | v: (nz, ny-1, nx) | w: (nz-1, ny, nx) | T: (nz, ny, nx) ]
+ * u on interior x-faces, v on interior y-faces, w on interior z-faces, T at
+ * cell centres; wall-normal velocities are zero and not stored.  T is the
+ * centred temperature T - 1/2, so the x-walls hold +1/2 and -1/2.
+ *
+ * Inner product: volume weighted, <a,b> = sum V_q a_q b_q with V_q the
+ * control volume of unknown q; P is orthogonal in it.
+ *
+ * Conventions for every call:
+ *   - Vector arguments are DEVICE pointers owned by the caller (e.g. torch
+ *     tensors), never freed or retained by the library, 256-byte alignment
+ *     not required.  Host pointers are marked "host".
+ *   - All work is enqueued on the HIP stream given to kv_create.  Calls that
+ *     return host scalars synchronize that stream before returning.
+ *   - Return value: KV_OK or an error code; nothing throws across the ABI.
+ *     kv_last_error(ctx) gives a message for the last failed call.
+ *   - Calls that need a base flow return KV_ESTATE before kv_set_base_flow.
+ *   - The library allocates its own device scratch with hipMalloc inside
+ *     kv_create (cell fields, metrics) and lazily inside the solvers (Krylov
+ *     bases); kv_destroy frees it.
+ *   - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef KV_H
+#define KV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kv_ctx kv_ctx;
+
+enum kv_status {
+  KV_OK = 0,
+  KV_EINVAL = 1,      /* bad argument (sizes, grid, null pointer, flags) */
+  KV_ENOMEM = 2,      /* device or host allocation failed */
+  KV_EDEVICE = 3,     /* a HIP call failed (no gfx950 device, launch error) */
+  KV_ENOCONV = 4,     /* iteration limit reached; outputs hold the last iterate */
+  KV_ENONFINITE = 5,  /* NaN or Inf met in an input or an iterate */
+  KV_ESTATE = 6       /* call needs kv_set_base_flow first */
+};
+
+/* Per-call flags.  KV_PROJECT: follow J by the projection P.  KV_MIXED:
+ * reserved for the mixed-precision form; rejected with KV_EINVAL by calls
+ * that do not implement it. */
+enum kv_flags { KV_PROJECT = 1u, KV_MIXED = 2u };
+
+typedef struct {
+  int nx, ny, nz;           /* cells per axis, each >= 2 */
+  const double *xf, *yf, *zf; /* host: n+1 strictly increasing face
+                               * coordinates per axis, first 0, last 1 */
+  double Gr, Pr;            /* Gr >= 0, Pr > 0 */
+} kv_params;
+
+/* Create a context on the current HIP device: copies the grid, builds the
+ * metrics and the fast-diagonalization bases (one symmetric eigenproblem
+ * per axis, solved on the host).  hip_stream: a hipStream_t or NULL for the
+ * default stream.  Errors: KV_EINVAL (bad grid), KV_EDEVICE, KV_ENOMEM. */
+int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out);
+int kv_destroy(kv_ctx* ctx);
+
+/* Packed size n and block offsets off[0..4] (u, v, w, T, end). host out. */
+int kv_layout(const kv_ctx* ctx, int64_t* n, int64_t off[5]);
+
+/* Store the base flow X0 (device, packed, n values; copied).  Sec. 1: the
+ * Jacobian is taken about the steady flow.  KV_ENONFINITE if X0 holds a NaN
+ * or Inf. */
+int kv_set_base_flow(kv_ctx* ctx, const double* X0);
+
+/* F = P N(X0), the projected steady residual of Eqs. 1-6 at the base flow
+ * (device out, n values).  norm (host, may be NULL) receives ||F||_W.  Used
+ * by Newton's method (Sec. 1). */
+int kv_residual(kv_ctx* ctx, double* F, double* norm);
+
+/* y = J(X0) x, or y = P J(X0) x when flags has KV_PROJECT: one Krylov vector
+ * of the paper's Newton and Arnoldi iterations (Sec. 3: divergence free and
+ * satisfying all boundary conditions).  x, y: device, n values, must not
+ * overlap. */
+int kv_apply_jacobian(kv_ctx* ctx, const double* x, double* y, unsigned flags);
+
+/* In place y <- P y (velocity block; T unchanged).  div_max (host, may be
+ * NULL): normalized divergence max|net flux| / max|face flux| after the
+ * projection.  sweeps (host, may be NULL): projection sweeps used (1). */
+int kv_project(kv_ctx* ctx, double* y, unsigned flags, double* div_max, int* sweeps);
+
+/* <a, b>_W on the device, result to host *out. */
+int kv_dot(kv_ctx* ctx, const double* a, const double* b, double* out);
+
+/* Symmetry measures R_ref, R_2D, R_3D of Eqs. 7-9 (Sec. 2) of the packed
+ * state X (device), over cell-centred theta = T - (1 - x).  host out[3]. */
+int kv_symmetry_measures(kv_ctx* ctx, const double* X, double out[3]);
+
+typedef struct {
+  int matvecs;      /* applications of P J */
+  int cycles;       /* BiCGstab(2) cycles plus GMRES restarts */
+  int used_gmres;   /* 1 if the GMRES continuation ran */
+  double relres;    /* ||P J delta + F||_W / ||F||_W (recursive estimate) */
+} kv_solve_info;
+
+/* Newton correction (Sec. 1): delta with P J(X0) delta = -F, by BiCGstab(2)
+ * (Sleijpen-Fokkema form, shadow vector = initial residual), continued by
+ * restarted GMRES(40) from the current iterate after a breakdown or 50
+ * cycles without a 10% residual reduction.  F is projected once more before
+ * the solve.  Stops when relres <= tol or after max_matvec matvecs
+ * (KV_ENOCONV, delta holds the last iterate).  delta0: optional initial
+ * iterate (device, may be NULL).  F, delta: device, n values.  info: host,
+ * may be NULL.  flags: 0 (KV_MIXED is reserved). */
+int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matvec,
+                         unsigned flags, const double* delta0, double* delta,
+                         kv_solve_info* info);
+
+typedef struct {
+  int krylov_dim;       /* m, Arnoldi steps per cycle, 2..400 */
+  int n_eigs;           /* wanted leading eigenvalues, 1..m-1 */
+  int max_matvec;       /* budget over all cycles and filters */
+  int max_restarts;     /* 0: one Arnoldi cycle, Ritz values returned as is */
+  int cheb_degree_max;  /* cap on the Chebyshev filter degree per restart */
+  double tol;           /* converged when every wanted Ritz residual
+                           <= tol * max |wanted Ritz value| */
+  const double* v0;     /* device, n values: start vector (projected first) */
+  unsigned flags;       /* 0 (KV_MIXED is reserved) */
+} kv_arnoldi_params;
+
+typedef struct {
+  int n_out;      /* values written: n_eigs, or n_eigs+1 to keep a pair whole */
+  int matvecs;
+  int restarts;
+  int converged;  /* 1 if the tolerance was met */
+} kv_eig_info;
+
+/* Leading eigenvalues (largest real part first, +Im before -Im within a
+ * conjugate pair) of A = P J(X0) on divergence-free vectors, by restarted
+ * Arnoldi (classical Gram-Schmidt twice, FP64) whose restart vector, the sum
+ * of the real and imaginary parts of the wanted Ritz vectors, is filtered by
+ * a Chebyshev polynomial on the ellipse around the unwanted Ritz values
+ * (Sec. 1 and Sec. 3: Chebyshev-preconditioned Arnoldi, no shift-and-
+ * invert).  The Hessenberg eigenproblem is solved on the GPU by Francis
+ * double-shift QR.  lam_re, lam_im, resid: host arrays of n_eigs+1 values;
+ * resid gets the Ritz residual norms.  info: host, may be NULL.  Not
+ * converged within max_matvec: KV_ENOCONV with the last Ritz values. */
+int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
+                            double* lam_im, double* resid, kv_eig_info* info);
+
+/* Device time per phase of the projected Jacobian, measured with HIP events
+ * on the context's stream around each phase of every kv_apply_jacobian and
+ * kv_project call while enabled.  enable = 1 starts the accounting (clearing
+ * it), enable = 0 stops it; either way the sums since the last start are
+ * returned (after synchronizing the stream) in ms[0..4) (host, may be NULL):
+ * stencil, divergence, fast-diagonalization transforms (6 GEMM passes per
+ * projection), gradient correction; calls[0..2) (host, may be NULL): number of
+ * stencil applications and of projections measured. */
+int kv_timing(kv_ctx* ctx, int enable, double ms[4], int calls[2]);
+
+/* Message of the last failed call on ctx (static text if ctx is NULL). */
+const char* kv_last_error(const kv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KV_H */

@@ -1,0 +1,935 @@
+// C ABI of the Krylov-vector library: context, base flow, the projected
+// Jacobian, the residual, and the Newton (BiCGstab(2) + GMRES) and
+// Chebyshev-Arnoldi drivers.  The drivers run on the host and launch the
+// device kernels; only small scalars (dot products, the Hessenberg matrix,
+// Ritz data) cross to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kv_internal.h"
+
+namespace kv {
+hipError_t launch_hessenberg_values(hipStream_t s, double* Hwork, int m, double* wr, double* wi, int* info);
+hipError_t launch_hessenberg_vectors(hipStream_t s, const double* H, int m, const double* lr, const double* li,
+                                     int nsel, double* cwork, double* vr, double* vi);
+}  // namespace kv
+
+using namespace kv;
+
+namespace {
+
+const char* kNoCtx = "kv: null context";
+
+int fail(kv_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(c, call)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail((c), KV_EDEVICE, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #call); \
+  } while (0)
+
+// ---- host metrics -----------------------------------------------------------------
+struct HostAxis {
+  int n;
+  std::vector<double> h, ih, id, wlo, whi, sq, isq, dd, lam, c, Q, Qt;
+  int null_idx;
+};
+
+bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
+  a.n = n;
+  if (std::fabs(f[0]) > 1e-14 || std::fabs(f[n] - 1.0) > 1e-14) {
+    err = "faces must start at 0 and end at 1";
+    return false;
+  }
+  for (int i = 0; i < n; ++i)
+    if (!(f[i + 1] > f[i])) {
+      err = "faces must be strictly increasing";
+      return false;
+    }
+  a.h.resize(n);
+  a.ih.resize(n);
+  a.sq.resize(n);
+  a.isq.resize(n);
+  a.c.resize(n);
+  a.id.assign(n + 1, 0.0);
+  a.dd.assign(n + 1, 0.0);
+  a.wlo.assign(n + 1, 0.0);
+  a.whi.assign(n + 1, 0.0);
+  for (int i = 0; i < n; ++i) {
+    a.h[i] = f[i + 1] - f[i];
+    a.ih[i] = 1.0 / a.h[i];
+    a.c[i] = 0.5 * (f[i] + f[i + 1]);
+    a.sq[i] = std::sqrt(a.h[i]);
+    a.isq[i] = 1.0 / a.sq[i];
+  }
+  a.dd[0] = 0.5 * a.h[0];
+  a.dd[n] = 0.5 * a.h[n - 1];
+  for (int i = 1; i < n; ++i) {
+    a.dd[i] = a.c[i] - a.c[i - 1];
+    a.wlo[i] = (a.c[i] - f[i]) / a.dd[i];
+    a.whi[i] = (f[i] - a.c[i - 1]) / a.dd[i];
+  }
+  for (int i = 0; i <= n; ++i) a.id[i] = 1.0 / a.dd[i];
+  // M = H^-1/2 K H^-1/2, K the symmetric tridiagonal Neumann operator
+  std::vector<double> M((size_t)n * n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) {
+    const double t = a.id[i + 1];
+    M[(size_t)i * n + i + 1] += t * a.isq[i] * a.isq[i + 1];
+    M[(size_t)(i + 1) * n + i] += t * a.isq[i] * a.isq[i + 1];
+    M[(size_t)i * n + i] -= t * a.isq[i] * a.isq[i];
+    M[(size_t)(i + 1) * n + i + 1] -= t * a.isq[i + 1] * a.isq[i + 1];
+  }
+  jacobi_eigen(n, M, a.Q, a.lam);
+  a.null_idx = (int)(std::max_element(a.lam.begin(), a.lam.end()) - a.lam.begin());
+  a.lam[a.null_idx] = 0.0;  // K annihilates constants: the exact eigenvalue is 0
+  a.Qt.resize((size_t)n * n);
+  for (int r = 0; r < n; ++r)
+    for (int cc = 0; cc < n; ++cc) a.Qt[(size_t)cc * n + r] = a.Q[(size_t)r * n + cc];
+  return true;
+}
+
+// ---- small device helpers -----------------------------------------------------------
+int read_results(kv_ctx* c, int nq) {
+  HIPCHK(c, hipMemcpyAsync(c->hres, c->dres, sizeof(double) * nq, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return KV_OK;
+}
+
+// Host -> device copy that completes before returning (the host buffer may be
+// a temporary).
+int upload(kv_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return KV_OK;
+}
+
+int dots(kv_ctx* c, int np, const double* const* a, const double* const* b, double* out) {
+  HIPCHK(c, launch_wdots(c, np, a, b));
+  int rc = read_results(c, np);
+  if (rc) return rc;
+  for (int q = 0; q < np; ++q) out[q] = c->hres[q];
+  return KV_OK;
+}
+
+double dot1(kv_ctx* c, const double* a, const double* b, int* rc) {
+  double v = 0;
+  *rc = dots(c, 1, &a, &b, &v);
+  return v;
+}
+
+int lincomb(kv_ctx* c, int nt, std::initializer_list<double> cf, std::initializer_list<const double*> in,
+            double* out) {
+  std::vector<double> cc(cf);
+  std::vector<const double*> pp(in);
+  HIPCHK(c, launch_lincomb(c, c->g.n, nt, cc.data(), pp.data(), out));
+  return KV_OK;
+}
+
+// Phase timing: an event pair around a phase while kv_timing is enabled.
+hipEvent_t take_event(kv_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseMark {
+  kv_ctx* c;
+  int phase;
+  hipEvent_t e0 = nullptr;
+  PhaseMark(kv_ctx* cc, int ph) : c(cc), phase(ph) {
+    if (c->timing && (e0 = take_event(c))) hipEventRecord(e0, c->stream);
+  }
+  ~PhaseMark() {
+    if (!e0) return;
+    hipEvent_t e1 = take_event(c);
+    if (!e1) return;
+    hipEventRecord(e1, c->stream);
+    c->ev_marks.push_back({phase, {e0, e1}});
+  }
+};
+
+int project_inplace(kv_ctx* c, double* y) {
+  {
+    PhaseMark pm(c, 1);
+    HIPCHK(c, launch_scaled_divergence(c, y, c->cellA));
+  }
+  {
+    PhaseMark pm(c, 2);
+    HIPCHK(c, launch_fd_solve(c, c->cellA, c->cellA));
+  }
+  {
+    PhaseMark pm(c, 3);
+    HIPCHK(c, launch_gradient_correction(c, c->cellA, y));
+  }
+  return KV_OK;
+}
+
+int apply_operator(kv_ctx* c, const double* x, double* y) {
+  PhaseMark pm(c, 0);
+  HIPCHK(c, launch_operator(c, c->X0, x, y, 0));
+  return KV_OK;
+}
+
+int matvec(kv_ctx* c, const double* x, double* y) {
+  int rc = apply_operator(c, x, y);
+  if (rc) return rc;
+  return project_inplace(c, y);
+}
+
+int check_finite(kv_ctx* c, const double* a, int64_t n, const char* what) {
+  HIPCHK(c, launch_maxabs(c, a, n));
+  int rc = read_results(c, 1);
+  if (rc) return rc;
+  if (!std::isfinite(c->hres[0])) return fail(c, KV_ENONFINITE, std::string("non-finite value in ") + what);
+  return KV_OK;
+}
+
+int ensure_work(kv_ctx* c, size_t nvec) {
+  const size_t bytes = nvec * (size_t)c->g.n * sizeof(double);
+  if (bytes <= c->work_bytes) return KV_OK;
+  if (c->work) hipFree(c->work);
+  c->work = nullptr;
+  c->work_bytes = 0;
+  if (hipMalloc(&c->work, bytes) != hipSuccess) {
+    c->work = nullptr;
+    return fail(c, KV_ENOMEM, "cannot allocate solver workspace");
+  }
+  c->work_bytes = bytes;
+  return KV_OK;
+}
+
+int ensure_hess(kv_ctx* c, size_t bytes) {
+  if (bytes <= c->hess_bytes) return KV_OK;
+  if (c->hess) hipFree(c->hess);
+  c->hess = nullptr;
+  c->hess_bytes = 0;
+  if (hipMalloc(&c->hess, bytes) != hipSuccess) return fail(c, KV_ENOMEM, "cannot allocate Hessenberg workspace");
+  c->hess_bytes = bytes;
+  return KV_OK;
+}
+
+// ---- Arnoldi with classical Gram-Schmidt twice -----------------------------------------
+// V holds up to m+1 vectors (stride n).  On entry V[0] is W-normalized.  Fills
+// H ((m+1) x m, column-major by j: H[i + j*(m+1)]) and returns the number of
+// completed steps k (k < m on a lucky breakdown).
+int arnoldi(kv_ctx* c, double* V, int m, std::vector<double>& H, int* kout, int* matvecs) {
+  const int64_t n = c->g.n;
+  H.assign((size_t)(m + 1) * m, 0.0);
+  int rc;
+  for (int j = 0; j < m; ++j) {
+    double* w = V + (int64_t)(j + 1) * n;
+    if ((rc = matvec(c, V + (int64_t)j * n, w))) return rc;
+    ++*matvecs;
+    for (int pass = 0; pass < 2; ++pass) {
+      HIPCHK(c, launch_mdot(c, V, n, j + 1, w));
+      HIPCHK(c, launch_mupdate(c, V, n, j + 1, c->dres, w));
+      if ((rc = read_results(c, j + 1))) return rc;
+      for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] += c->hres[i];
+    }
+    const double hn = std::sqrt(std::max(0.0, dot1(c, w, w, &rc)));
+    if (rc) return rc;
+    if (!std::isfinite(hn)) return fail(c, KV_ENONFINITE, "non-finite Arnoldi vector");
+    double col = hn * hn;
+    for (int i = 0; i <= j; ++i) col += H[i + (size_t)j * (m + 1)] * H[i + (size_t)j * (m + 1)];
+    H[j + 1 + (size_t)j * (m + 1)] = hn;
+    if (hn <= 1e-14 * std::sqrt(col)) {
+      *kout = j + 1;
+      return KV_OK;
+    }
+    if ((rc = lincomb(c, 1, {1.0 / hn}, {w}, w))) return rc;
+  }
+  *kout = m;
+  return KV_OK;
+}
+
+// ---- Ritz data -----------------------------------------------------------------------
+struct Ritz {
+  std::vector<std::complex<double>> vals;
+  std::vector<int> sel;                                 // wanted, in output order
+  std::vector<std::vector<std::complex<double>>> vecs;  // coefficient vectors of sel
+  std::vector<double> res;                              // residual estimates of sel
+};
+
+std::vector<int> order_leading(const std::vector<std::complex<double>>& v) {
+  std::vector<int> idx(v.size());
+  for (size_t i = 0; i < v.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (v[a].real() != v[b].real()) return v[a].real() > v[b].real();
+    return v[a].imag() > v[b].imag();
+  });
+  return idx;
+}
+
+std::vector<int> wanted_set(const std::vector<std::complex<double>>& v, int k) {
+  std::vector<int> idx = order_leading(v);
+  std::vector<int> sel(idx.begin(), idx.begin() + std::min<size_t>(k, idx.size()));
+  if ((size_t)k < idx.size() && !sel.empty()) {
+    const auto last = v[sel.back()];
+    if (last.imag() > 0 && std::abs(v[idx[k]] - std::conj(last)) <= 1e-12 * std::max(1.0, std::abs(last)))
+      sel.push_back(idx[k]);
+  }
+  return sel;
+}
+
+// Eigen-decomposition of H_k on the device; Ritz residuals h_{k+1,k} |e_k^T s|.
+int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out) {
+  // device layout: Hk (k*k) | Hcopy (k*k) | wr k | wi k | lr, li (k each) | vr, vi (k*k) | info | cwork
+  const size_t kk = (size_t)k * k;
+  const size_t nd = 2 * kk + 4 * (size_t)k + 2 * kk + 2;
+  const size_t cw = 2 * ((size_t)k * kk + (size_t)k * k);  // complex work for up to k vectors
+  int rc;
+  if ((rc = ensure_hess(c, (nd + cw) * sizeof(double)))) return rc;
+  double* d = c->hess;
+  double *dH = d, *dHc = d + kk, *dwr = d + 2 * kk, *dwi = dwr + k, *dlr = dwi + k, *dli = dlr + k;
+  double *dvr = dli + k, *dvi = dvr + kk;
+  int* dinfo = reinterpret_cast<int*>(dvi + kk);
+  double* dcw = dvi + kk + 2;
+  std::vector<double> Hk(kk);
+  for (int r = 0; r < k; ++r)
+    for (int cc = 0; cc < k; ++cc) Hk[(size_t)r * k + cc] = H[r + (size_t)cc * (m + 1)];
+  if ((rc = upload(c, dH, Hk.data(), kk * sizeof(double)))) return rc;
+  HIPCHK(c, hipMemcpyAsync(dHc, dH, kk * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, launch_hessenberg_values(c->stream, dHc, k, dwr, dwi, dinfo));
+  std::vector<double> wr(k), wi(k);
+  int info = 0;
+  HIPCHK(c, hipMemcpyAsync(wr.data(), dwr, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(wi.data(), dwi, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
+  out.vals.resize(k);
+  for (int i = 0; i < k; ++i) out.vals[i] = {wr[i], wi[i]};
+  out.sel = wanted_set(out.vals, n_eigs);
+  const int ns = (int)out.sel.size();
+  std::vector<double> lr(ns), li(ns);
+  for (int q = 0; q < ns; ++q) {
+    lr[q] = out.vals[out.sel[q]].real();
+    li[q] = out.vals[out.sel[q]].imag();
+  }
+  if ((rc = upload(c, dlr, lr.data(), ns * sizeof(double)))) return rc;
+  if ((rc = upload(c, dli, li.data(), ns * sizeof(double)))) return rc;
+  HIPCHK(c, launch_hessenberg_vectors(c->stream, dH, k, dlr, dli, ns, dcw, dvr, dvi));
+  std::vector<double> vr((size_t)ns * k), vi((size_t)ns * k);
+  HIPCHK(c, hipMemcpyAsync(vr.data(), dvr, vr.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(vi.data(), dvi, vi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double hk = (k < m || H.size() > 0) ? H[k + (size_t)(k - 1) * (m + 1)] : 0.0;
+  out.vecs.assign(ns, std::vector<std::complex<double>>(k));
+  out.res.assign(ns, 0.0);
+  for (int q = 0; q < ns; ++q) {
+    // phase convention: unit 2-norm, largest-modulus component real positive
+    int imax = 0;
+    double amax = -1;
+    for (int r = 0; r < k; ++r) {
+      const double a = std::hypot(vr[(size_t)q * k + r], vi[(size_t)q * k + r]);
+      if (a > amax + 1e-14 * amax) {
+        amax = a;
+        imax = r;
+      }
+    }
+    const std::complex<double> ph =
+        std::conj(std::complex<double>(vr[(size_t)q * k + imax], vi[(size_t)q * k + imax])) / amax;
+    for (int r = 0; r < k; ++r) out.vecs[q][r] = std::complex<double>(vr[(size_t)q * k + r], vi[(size_t)q * k + r]) * ph;
+    out.res[q] = std::fabs(hk) * std::abs(out.vecs[q][k - 1]);
+  }
+  return KV_OK;
+}
+
+// ---- Chebyshev helpers (ellipse and degree), same definitions as the oracle's -------------
+void ellipse(const std::vector<std::complex<double>>& unw, double* d, double* a, double* b, double* c2) {
+  double rmin = 1e300, rmax = -1e300;
+  for (auto& z : unw) {
+    rmin = std::min(rmin, z.real());
+    rmax = std::max(rmax, z.real());
+  }
+  *d = 0.5 * (rmin + rmax);
+  double aa = std::max(0.5 * (rmax - rmin), 1e-300);
+  for (;;) {
+    bool ok = true;
+    for (auto& z : unw) {
+      const double t = std::pow((z.real() - *d) / aa, 2);
+      if (!(t < 1.0) && z.imag() != 0.0) ok = false;
+    }
+    if (ok) break;
+    aa *= 1.1;
+  }
+  double b2 = 0.0;
+  for (auto& z : unw) {
+    const double t = std::pow((z.real() - *d) / aa, 2);
+    if (t < 1.0) b2 = std::max(b2, z.imag() * z.imag() / (1.0 - t));
+  }
+  *a = aa;
+  *b = std::sqrt(b2);
+  *c2 = aa * aa - b2;
+}
+
+int cheb_degree(double wr, double a, double b, double c2, int dmax) {
+  const std::complex<double> s = std::sqrt(std::complex<double>(wr * wr - c2, 0.0));
+  const double ratio = std::max(std::abs(wr + s), std::abs(wr - s)) / (a + b);
+  if (ratio <= 1.0 + 1e-12) return 0;
+  const int d = (int)std::ceil(std::log(1e6) / std::log(ratio));
+  return std::min(dmax, std::max(1, d));
+}
+
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
+  if (!p || !out) return KV_EINVAL;
+  *out = nullptr;
+  if (p->nx < 2 || p->ny < 2 || p->nz < 2 || !p->xf || !p->yf || !p->zf || !(p->Gr >= 0) || !(p->Pr > 0))
+    return KV_EINVAL;
+  if (p->nx > 4096 || p->ny > 4096 || p->nz > 4096) return KV_EINVAL;
+  kv_ctx* c = new (std::nothrow) kv_ctx();
+  if (!c) return KV_ENOMEM;
+  HostAxis ax[3];
+  const double* faces[3] = {p->xf, p->yf, p->zf};
+  const int ns[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (!build_axis(faces[a], ns[a], ax[a], c->err)) {
+      delete c;
+      return KV_EINVAL;
+    }
+    c->hf[a].assign(faces[a], faces[a] + ns[a] + 1);
+  }
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return KV_EDEVICE;
+  }
+  Grid& g = c->g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
+  g.ou = 0;
+  g.ov = nz * ny * (nx - 1);
+  g.ow = g.ov + nz * (ny - 1) * nx;
+  g.oT = g.ow + (nz - 1) * ny * nx;
+  g.n = g.oT + nz * ny * nx;
+  c->ncell = nx * ny * nz;
+  c->Gr = p->Gr;
+  c->Pr = p->Pr;
+  if (p->Gr > 0) {
+    g.nu = 1.0 / std::sqrt(p->Gr);
+    g.kappa = 1.0 / (p->Pr * std::sqrt(p->Gr));
+    g.beta = 1.0;
+  } else {
+    g.nu = 1.0;
+    g.kappa = 1.0 / p->Pr;
+    g.beta = 0.0;
+  }
+  g.null3 = (int)(((int64_t)ax[2].null_idx * ny + ax[1].null_idx) * nx + ax[0].null_idx);
+  // metrics: per axis 10 arrays of n+1 doubles
+  size_t per_axis[3], total = 0;
+  for (int a = 0; a < 3; ++a) {
+    per_axis[a] = 10 * (size_t)(ns[a] + 1);
+    total += per_axis[a];
+  }
+  std::vector<double> hm(total, 0.0);
+  size_t o = 0;
+  size_t offs[3][10];
+  for (int a = 0; a < 3; ++a) {
+    const std::vector<double>* arrs[10] = {&ax[a].h,  &ax[a].ih,  &ax[a].id, &ax[a].wlo, &ax[a].whi,
+                                           &ax[a].sq, &ax[a].isq, &ax[a].dd, &ax[a].lam, &ax[a].c};
+    for (int q = 0; q < 10; ++q) {
+      offs[a][q] = o;
+      std::copy(arrs[q]->begin(), arrs[q]->end(), hm.begin() + o);
+      o += ns[a] + 1;
+    }
+  }
+  auto cleanup = [&](int code, const char* msg) {
+    kv_destroy(c);
+    (void)msg;
+    return code;
+  };
+  if (hipMalloc(&c->metric, total * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "metric");
+  if (hipMemcpy(c->metric, hm.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(KV_EDEVICE, "metric copy");
+  for (int a = 0; a < 3; ++a) {
+    Axis& A = g.ax[a];
+    A.n = ns[a];
+    const double* base = c->metric;
+    A.h = base + offs[a][0];
+    A.ih = base + offs[a][1];
+    A.id = base + offs[a][2];
+    A.wlo = base + offs[a][3];
+    A.whi = base + offs[a][4];
+    A.sq = base + offs[a][5];
+    A.isq = base + offs[a][6];
+    A.dd = base + offs[a][7];
+    A.lam = base + offs[a][8];
+    A.c = base + offs[a][9];
+    const size_t nn = (size_t)ns[a] * ns[a];
+    if (hipMalloc(&c->Qf[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Q");
+    if (hipMalloc(&c->Qt[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Qt");
+    if (hipMemcpy(c->Qf[a], ax[a].Q.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->Qt[a], ax[a].Qt.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(KV_EDEVICE, "Q copy");
+  }
+  const int64_t rows = 2 * nz * ny + nz * (ny - 1) + (nz - 1) * ny;
+  c->npart_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 3) / 4));
+  if (hipMalloc(&c->X0, g.n * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "X0");
+  if (hipMalloc(&c->cellA, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellA");
+  if (hipMalloc(&c->cellB, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellB");
+  if (hipMalloc(&c->part, (size_t)512 * c->npart_blocks * sizeof(double)) != hipSuccess)
+    return cleanup(KV_ENOMEM, "part");
+  if (hipMalloc(&c->dres, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dres");
+  if (hipHostMalloc(&c->hres, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return cleanup(KV_ENOMEM, "hres");
+  *out = c;
+  return KV_OK;
+}
+
+int kv_destroy(kv_ctx* c) {
+  if (!c) return KV_OK;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  hipFree(c->metric);
+  for (int a = 0; a < 3; ++a) {
+    hipFree(c->Qf[a]);
+    hipFree(c->Qt[a]);
+  }
+  hipFree(c->X0);
+  hipFree(c->cellA);
+  hipFree(c->cellB);
+  hipFree(c->part);
+  hipFree(c->dres);
+  if (c->hres) hipHostFree(c->hres);
+  for (auto& m : c->ev_marks) {
+    hipEventDestroy(m.second.first);
+    hipEventDestroy(m.second.second);
+  }
+  for (auto e : c->ev_pool) hipEventDestroy(e);
+  hipFree(c->work);
+  hipFree(c->hess);
+  delete c;
+  return KV_OK;
+}
+
+int kv_layout(const kv_ctx* c, int64_t* n, int64_t off[5]) {
+  if (!c) return KV_EINVAL;
+  if (n) *n = c->g.n;
+  if (off) {
+    off[0] = c->g.ou;
+    off[1] = c->g.ov;
+    off[2] = c->g.ow;
+    off[3] = c->g.oT;
+    off[4] = c->g.n;
+  }
+  return KV_OK;
+}
+
+int kv_set_base_flow(kv_ctx* c, const double* X0) {
+  if (!c) return KV_EINVAL;
+  if (!X0) return fail(c, KV_EINVAL, "null base flow");
+  int rc = check_finite(c, X0, c->g.n, "base flow");
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->X0, X0, c->g.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  c->has_base = true;
+  return KV_OK;
+}
+
+int kv_apply_jacobian(kv_ctx* c, const double* x, double* y, unsigned flags) {
+  if (!c) return KV_EINVAL;
+  if (!x || !y || x == y) return fail(c, KV_EINVAL, "x and y must be distinct device vectors");
+  if (flags & ~(unsigned)KV_PROJECT) return fail(c, KV_EINVAL, "unsupported flags");
+  if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  int rc = apply_operator(c, x, y);
+  if (rc) return rc;
+  if (flags & KV_PROJECT) return project_inplace(c, y);
+  return KV_OK;
+}
+
+int kv_project(kv_ctx* c, double* y, unsigned flags, double* div_max, int* sweeps) {
+  if (!c) return KV_EINVAL;
+  if (!y) return fail(c, KV_EINVAL, "null vector");
+  if (flags & ~(unsigned)KV_PROJECT) return fail(c, KV_EINVAL, "unsupported flags");
+  int rc = project_inplace(c, y);
+  if (rc) return rc;
+  if (sweeps) *sweeps = 1;
+  if (div_max) {
+    HIPCHK(c, launch_div_measure(c, y));
+    if ((rc = read_results(c, 2))) return rc;
+    *div_max = c->hres[1] > 0 ? c->hres[0] / c->hres[1] : 0.0;
+  }
+  return KV_OK;
+}
+
+int kv_residual(kv_ctx* c, double* F, double* norm) {
+  if (!c) return KV_EINVAL;
+  if (!F) return fail(c, KV_EINVAL, "null output");
+  if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  HIPCHK(c, launch_operator(c, c->X0, c->X0, F, 1));
+  int rc = project_inplace(c, F);
+  if (rc) return rc;
+  if (norm) {
+    double v = dot1(c, F, F, &rc);
+    if (rc) return rc;
+    *norm = std::sqrt(std::max(0.0, v));
+  }
+  return KV_OK;
+}
+
+int kv_dot(kv_ctx* c, const double* a, const double* b, double* out) {
+  if (!c) return KV_EINVAL;
+  if (!a || !b || !out) return fail(c, KV_EINVAL, "null argument");
+  int rc;
+  *out = dot1(c, a, b, &rc);
+  return rc;
+}
+
+int kv_symmetry_measures(kv_ctx* c, const double* X, double out[3]) {
+  if (!c) return KV_EINVAL;
+  if (!X || !out) return fail(c, KV_EINVAL, "null argument");
+  HIPCHK(c, launch_symmetry(c, X));
+  int rc = read_results(c, 3);
+  if (rc) return rc;
+  for (int q = 0; q < 3; ++q) out[q] = c->hres[q];
+  return KV_OK;
+}
+
+// ---- Newton correction: BiCGstab(2), continued by GMRES(m) -------------------------------
+static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, double tol, int m, int budget,
+                       int* used, int* cycles, double* relres) {
+  const int64_t n = c->g.n;
+  int rc;
+  double* V = c->work + 8 * n;  // caller reserved 8 + m + 1 vectors
+  std::vector<double> H;
+  for (;;) {
+    // r = b - A x into V[0]
+    if ((rc = matvec(c, x, V))) return rc;
+    ++*used;
+    if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
+    double beta = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
+    if (rc) return rc;
+    *relres = bnorm > 0 ? beta / bnorm : 0.0;
+    if (!std::isfinite(beta)) return fail(c, KV_ENONFINITE, "non-finite GMRES residual");
+    if (beta <= tol * bnorm) return KV_OK;
+    if (*used + 2 > budget) return KV_ENOCONV;
+    if ((rc = lincomb(c, 1, {1.0 / beta}, {V}, V))) return rc;
+    const int mm = std::max(1, std::min(m, budget - *used - 1));
+    int k = 0, mv = 0;
+    if ((rc = arnoldi(c, V, mm, H, &k, &mv))) return rc;
+    *used += mv;
+    // least squares min || beta e1 - H y || by Givens rotations on the host
+    const int ld = mm + 1;
+    std::vector<double> R(H), g(k + 1, 0.0), cs(k), sn(k);
+    g[0] = beta;
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * R[i + j * ld] + sn[i] * R[i + 1 + j * ld];
+        R[i + 1 + j * ld] = -sn[i] * R[i + j * ld] + cs[i] * R[i + 1 + j * ld];
+        R[i + j * ld] = t;
+      }
+      const double a = R[j + j * ld], bb = R[j + 1 + j * ld];
+      const double r = std::hypot(a, bb);
+      cs[j] = r > 0 ? a / r : 1.0;
+      sn[j] = r > 0 ? bb / r : 0.0;
+      R[j + j * ld] = r;
+      R[j + 1 + j * ld] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+    }
+    std::vector<double> y(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int q = i + 1; q < k; ++q) s -= R[i + q * ld] * y[q];
+      y[i] = (R[i + i * ld] != 0.0) ? s / R[i + i * ld] : 0.0;
+    }
+    // x += V y  (mupdate subtracts, so pass -y)
+    std::vector<double> ny(k);
+    for (int i = 0; i < k; ++i) ny[i] = -y[i];
+    if ((rc = upload(c, c->dres, ny.data(), k * sizeof(double)))) return rc;
+    HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, x));
+    ++*cycles;
+  }
+}
+
+int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, unsigned flags,
+                         const double* delta0, double* delta, kv_solve_info* info) {
+  if (!c) return KV_EINVAL;
+  if (!F || !delta || F == delta) return fail(c, KV_EINVAL, "F and delta must be distinct device vectors");
+  if (flags != 0) return fail(c, KV_EINVAL, "unsupported flags");
+  if (!(tol > 0) || max_matvec < 4) return fail(c, KV_EINVAL, "bad tolerance or budget");
+  if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  const int64_t n = c->g.n;
+  int rc;
+  if ((rc = check_finite(c, F, n, "F"))) return rc;
+  // BiCGstab(2) vectors and the GMRES(40) basis, reserved together so that the
+  // fallback never reallocates live vectors
+  if ((rc = ensure_work(c, 8 + 41))) return rc;
+  double* W = c->work;
+  double *b = W, *rt = W + n, *r0 = W + 2 * n, *r1 = W + 3 * n, *r2 = W + 4 * n;
+  double *u0 = W + 5 * n, *u1 = W + 6 * n, *u2 = W + 7 * n;
+  double* r[3] = {r0, r1, r2};
+  double* u[3] = {u0, u1, u2};
+  double* x = delta;
+  kv_solve_info inf{0, 0, 0, 0.0};
+  // b = -P F
+  if ((rc = lincomb(c, 1, {-1.0}, {F}, b))) return rc;
+  if ((rc = project_inplace(c, b))) return rc;
+  const double bnorm = std::sqrt(std::max(0.0, dot1(c, b, b, &rc)));
+  if (rc) return rc;
+  if (delta0) {
+    HIPCHK(c, hipMemcpyAsync(x, delta0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = matvec(c, x, r0))) return rc;
+    ++inf.matvecs;
+    if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, r0}, r0))) return rc;
+  } else {
+    HIPCHK(c, launch_fill(c, n, 0.0, x));
+    HIPCHK(c, hipMemcpyAsync(r0, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (bnorm == 0.0) {
+    if (info) *info = inf;
+    return KV_OK;
+  }
+  HIPCHK(c, hipMemcpyAsync(rt, r0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, launch_fill(c, n, 0.0, u0));
+  double rho0 = 1.0, alpha = 0.0, omega = 1.0;
+  double res = std::sqrt(std::max(0.0, dot1(c, r0, r0, &rc)));
+  if (rc) return rc;
+  double best = res;
+  int best_cycle = 0;
+  const double scale = bnorm * bnorm;
+  enum { CONV, BREAK, STAG, MAXIT } status = CONV;
+  for (;;) {
+    if (res <= tol * bnorm) {
+      status = CONV;
+      break;
+    }
+    if (inf.matvecs + 4 > max_matvec) {
+      status = MAXIT;
+      break;
+    }
+    rho0 = -omega * rho0;
+    bool broke = false;
+    for (int j = 0; j < 2 && !broke; ++j) {
+      const double rho1 = dot1(c, r[j], rt, &rc);
+      if (rc) return rc;
+      if (std::fabs(rho0) <= 1e-300 * scale || rho1 == 0.0) {
+        broke = true;
+        break;
+      }
+      const double beta = alpha * rho1 / rho0;
+      rho0 = rho1;
+      for (int i = 0; i <= j; ++i)
+        if ((rc = lincomb(c, 2, {1.0, -beta}, {r[i], u[i]}, u[i]))) return rc;
+      if ((rc = matvec(c, u[j], u[j + 1]))) return rc;
+      ++inf.matvecs;
+      const double gamma = dot1(c, u[j + 1], rt, &rc);
+      if (rc) return rc;
+      if (std::fabs(gamma) <= 1e-300 * scale) {
+        broke = true;
+        break;
+      }
+      alpha = rho0 / gamma;
+      for (int i = 0; i <= j; ++i)
+        if ((rc = lincomb(c, 2, {1.0, -alpha}, {r[i], u[i + 1]}, r[i]))) return rc;
+      if ((rc = matvec(c, r[j], r[j + 1]))) return rc;
+      ++inf.matvecs;
+      if ((rc = lincomb(c, 2, {1.0, alpha}, {x, u[0]}, x))) return rc;
+    }
+    if (broke) {
+      status = BREAK;
+      break;
+    }
+    // minimal-residual part over span{r1, r2}
+    double d3[3];
+    {
+      const double* a[3] = {r1, r0, r2};
+      const double* bb[3] = {r1, r1, r1};
+      if ((rc = dots(c, 3, a, bb, d3))) return rc;
+    }
+    const double sigma1 = d3[0], g1p = d3[1] / sigma1, tau12 = d3[2] / sigma1;
+    if ((rc = lincomb(c, 2, {1.0, -tau12}, {r2, r1}, r2))) return rc;
+    double d2[2];
+    {
+      const double* a[2] = {r2, r0};
+      const double* bb[2] = {r2, r2};
+      if ((rc = dots(c, 2, a, bb, d2))) return rc;
+    }
+    const double sigma2 = d2[0], g2p = d2[1] / sigma2;
+    const double g2 = g2p, g1 = g1p - tau12 * g2, g1pp = g2;
+    omega = g2;
+    if ((rc = lincomb(c, 3, {1.0, g1, g1pp}, {x, r0, r1}, x))) return rc;
+    if ((rc = lincomb(c, 3, {1.0, -g2p, -g1p}, {r0, r2, r1}, r0))) return rc;
+    if ((rc = lincomb(c, 3, {1.0, -g2, -g1}, {u0, u2, u1}, u0))) return rc;
+    ++inf.cycles;
+    res = std::sqrt(std::max(0.0, dot1(c, r0, r0, &rc)));
+    if (rc) return rc;
+    if (!std::isfinite(res)) {
+      status = BREAK;
+      break;
+    }
+    if (res < 0.9 * best) {
+      best = res;
+      best_cycle = inf.cycles;
+    } else if (inf.cycles - best_cycle >= 50) {
+      status = STAG;
+      break;
+    }
+  }
+  inf.relres = res / bnorm;
+  if (status == BREAK || status == STAG) {
+    inf.used_gmres = 1;
+    int used = inf.matvecs, cyc = inf.cycles;
+    double rr = inf.relres;
+    rc = gmres_solve(c, b, bnorm, x, tol, 40, max_matvec, &used, &cyc, &rr);
+    inf.matvecs = used;
+    inf.cycles = cyc;
+    inf.relres = rr;
+    if (info) *info = inf;
+    if (rc == KV_ENOCONV) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
+    return rc;
+  }
+  if (info) *info = inf;
+  if (status == MAXIT) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
+  return KV_OK;
+}
+
+// ---- Chebyshev-preconditioned Arnoldi -------------------------------------------------------
+int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_re, double* lam_im,
+                            double* resid, kv_eig_info* info) {
+  if (!c) return KV_EINVAL;
+  if (!p || !lam_re || !lam_im || !p->v0) return fail(c, KV_EINVAL, "null argument");
+  if (p->flags != 0) return fail(c, KV_EINVAL, "unsupported flags");
+  const int m = p->krylov_dim;
+  if (m < 2 || m > 400 || p->n_eigs < 1 || p->n_eigs >= m || p->max_matvec < m || p->max_restarts < 0)
+    return fail(c, KV_EINVAL, "bad Arnoldi parameters");
+  if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  const int64_t n = c->g.n;
+  int rc;
+  if ((rc = check_finite(c, p->v0, n, "v0"))) return rc;
+  // workspace: V (m+1 vectors) + z_prev, z, tmp
+  if ((rc = ensure_work(c, (size_t)m + 4))) return rc;
+  double* V = c->work;
+  double* zp = c->work + (int64_t)(m + 1) * n;
+  double* zc = zp + n;
+  double* tmp = zc + n;
+  HIPCHK(c, hipMemcpyAsync(V, p->v0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = project_inplace(c, V))) return rc;
+  int matvecs = 0, restarts = 0;
+  std::vector<double> H;
+  Ritz rz;
+  bool conv = false;
+  for (;;) {
+    double vn = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
+    if (rc) return rc;
+    if (!(vn > 0) || !std::isfinite(vn)) return fail(c, KV_ENONFINITE, "zero or non-finite start vector");
+    if ((rc = lincomb(c, 1, {1.0 / vn}, {V}, V))) return rc;
+    int k = 0;
+    if ((rc = arnoldi(c, V, m, H, &k, &matvecs))) return rc;
+    if ((rc = ritz(c, H, m, k, p->n_eigs, rz))) return rc;
+    double scale = 0.0;
+    for (int i : rz.sel) scale = std::max(scale, std::abs(rz.vals[i]));
+    conv = true;
+    for (double r : rz.res)
+      if (!(r <= p->tol * scale)) conv = false;
+    if (k < m) conv = true;  // invariant subspace found
+    if (conv || matvecs >= p->max_matvec || restarts >= p->max_restarts) break;
+    // restart vector: sum of the real and imaginary parts of the wanted Ritz vectors
+    std::vector<double> coef(k, 0.0);
+    for (size_t q = 0; q < rz.sel.size(); ++q)
+      for (int r = 0; r < k; ++r) coef[r] += rz.vecs[q][r].real() + rz.vecs[q][r].imag();
+    for (int r = 0; r < k; ++r) coef[r] = -coef[r];
+    HIPCHK(c, launch_fill(c, n, 0.0, zc));
+    if ((rc = upload(c, c->dres, coef.data(), k * sizeof(double)))) return rc;
+    HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, zc));
+    double zn = std::sqrt(std::max(0.0, dot1(c, zc, zc, &rc)));
+    if (rc) return rc;
+    if ((rc = lincomb(c, 1, {1.0 / zn}, {zc}, zc))) return rc;
+    std::vector<std::complex<double>> unw;
+    for (int i = 0; i < k; ++i)
+      if (std::find(rz.sel.begin(), rz.sel.end(), i) == rz.sel.end()) unw.push_back(rz.vals[i]);
+    int deg = 0;
+    double d = 0, a = 0, bb = 0, c2 = 0, wr = 0;
+    if (!unw.empty()) {
+      ellipse(unw, &d, &a, &bb, &c2);
+      double ref = 1e300;
+      for (int i : rz.sel) ref = std::min(ref, rz.vals[i].real());
+      wr = ref - d;
+      deg = cheb_degree(wr, a, bb, c2, p->cheb_degree_max);
+      deg = std::min(deg, std::max(0, p->max_matvec - matvecs - m));
+    }
+    if (deg > 0) {
+      // z1 = r1 (A - d) z0, z_{j+1} = r_{j+1} (2 (A - d) z_j - c^2 r_j z_{j-1})
+      double rj = 1.0 / wr;
+      HIPCHK(c, hipMemcpyAsync(zp, zc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      if ((rc = matvec(c, zp, tmp))) return rc;
+      ++matvecs;
+      if ((rc = lincomb(c, 2, {rj, -d * rj}, {tmp, zp}, zc))) return rc;
+      for (int it = 1; it < deg; ++it) {
+        const double rn = 1.0 / (2.0 * wr - c2 * rj);
+        if ((rc = matvec(c, zc, tmp))) return rc;
+        ++matvecs;
+        // new = rn * (2 tmp - 2 d zc - c2 rj zp), stored in zp, then swap
+        if ((rc = lincomb(c, 3, {2.0 * rn, -2.0 * d * rn, -c2 * rj * rn}, {tmp, zc, zp}, zp))) return rc;
+        std::swap(zp, zc);
+        rj = rn;
+      }
+    }
+    // back into range(P): the filter's -d z term carries round-off onto gradient
+    // fields, where A has the eigenvalue 0 (right of the wanted set)
+    HIPCHK(c, hipMemcpyAsync(V, zc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = project_inplace(c, V))) return rc;
+    ++restarts;
+  }
+  const int nout = (int)rz.sel.size();
+  for (int q = 0; q < nout; ++q) {
+    lam_re[q] = rz.vals[rz.sel[q]].real();
+    lam_im[q] = rz.vals[rz.sel[q]].imag();
+    if (resid) resid[q] = rz.res[q];
+  }
+  if (info) *info = kv_eig_info{nout, matvecs, restarts, conv ? 1 : 0};
+  if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");
+  return KV_OK;
+}
+
+int kv_timing(kv_ctx* c, int enable, double ms[4], int calls[2]) {
+  if (!c) return KV_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double acc[4] = {0, 0, 0, 0};
+  int cnt[4] = {0, 0, 0, 0};
+  for (auto& m : c->ev_marks) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
+      acc[m.first] += t;
+      cnt[m.first] += 1;
+    }
+    c->ev_pool.push_back(m.second.first);
+    c->ev_pool.push_back(m.second.second);
+  }
+  c->ev_marks.clear();
+  if (ms)
+    for (int q = 0; q < 4; ++q) ms[q] = acc[q];
+  if (calls) {
+    calls[0] = cnt[0];
+    calls[1] = cnt[2];
+  }
+  c->timing = enable != 0;
+  return KV_OK;
+}
+
+const char* kv_last_error(const kv_ctx* c) { return c ? c->err.c_str() : kNoCtx; }
+
+}  // extern "C"

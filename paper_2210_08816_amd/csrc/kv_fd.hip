@@ -1,0 +1,169 @@
+// Pressure Poisson solve L p = r, L = D G, by fast diagonalization.
+//
+// L = sum_a H_a^-1 K_a with K_a symmetric tridiagonal (Neumann), so with
+// S = (H_x H_y H_z)^1/2 and M_a = H_a^-1/2 K_a H_a^-1/2 = Q_a Lam_a Q_a^T,
+//   p = S^-1 (Q_x Q_y Q_z) (Lam_x + Lam_y + Lam_z)^+ (Q_x Q_y Q_z)^T S r.
+// Each 1-D transform is a dense GEMM along one axis of the (z, y, x) cell
+// field, done on the FP64 matrix cores (v_mfma_f64_16x16x4):
+//   x: C (ny nz x nx) = F (ny nz x nx) * Q_x            (rows contiguous)
+//   y: C_k (ny x nx)  = Q_y^T * F_k (ny x nx), k < nz    (batched)
+//   z: C (nz x nx ny) = Q_z^T * F (nz x nx ny)
+// None needs a transpose in memory.  The spectral divide is fused into the
+// epilogue of the last forward pass, the S^-1 scaling into the last inverse
+// pass; the S r scaling is fused into the divergence kernel that produces r.
+#include "kv_internal.h"
+
+namespace kv {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+enum { EPI_NONE = 0, EPI_DIVIDE = 1, EPI_ISQ = 2 };
+
+struct Epi {
+  const double *lx, *ly, *lz;     // per-axis eigenvalues
+  const double *isx, *isy, *isz;  // 1/sqrt(h) per axis
+  int nx, ny;
+  int64_t null3;                  // flat (c, b, a) index of the constant mode
+};
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// C[b] = A[b] * B[b], row-major, 256 threads = 4 waves, 64x64 tile per block,
+// each wave a 32x32 quarter as 2x2 MFMA 16x16 accumulators.  Work items are
+// laid out so that the blocks sharing the large operand's tile are
+// consecutive on one XCD (blocks are dealt round-robin over the 8 XCDs).
+template <int EPI>
+__global__ void __launch_bounds__(256) fd_gemm_kernel(const double* __restrict__ A, int64_t lda, int64_t sA,
+                                                      const double* __restrict__ B, int64_t ldb, int64_t sB,
+                                                      double* __restrict__ C, int64_t ldc, int64_t sC,
+                                                      int M, int N, int K, int mtiles, int ntiles, int batch,
+                                                      int a_is_big, Epi ep) {
+  __shared__ double As[BK][BM + 2];  // [k][m]
+  __shared__ double Bs[BK][BN + 2];  // [k][n]
+  const int64_t total = (int64_t)mtiles * ntiles * batch;
+  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t f = blockIdx.x;
+  const int64_t w = (f % 8) * per_xcd + f / 8;
+  if (w >= total) return;
+  int mt, nt;
+  int64_t b;
+  if (a_is_big) {  // A tile shared by the ntiles blocks of one row of tiles
+    nt = (int)(w % ntiles);
+    mt = (int)((w / ntiles) % mtiles);
+    b = w / ((int64_t)ntiles * mtiles);
+  } else {         // B tile shared by the mtiles blocks of one column of tiles
+    mt = (int)(w % mtiles);
+    nt = (int)((w / mtiles) % ntiles);
+    b = w / ((int64_t)ntiles * mtiles);
+  }
+  A += b * sA;
+  B += b * sB;
+  C += b * sC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = mt * BM, n0 = nt * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+
+  const int ar = tid >> 2, ak = (tid & 3) * 4;     // A tile: row, first k
+  const int bk = tid >> 4, bn = (tid & 15) * 4;    // B tile: k, first n
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    {
+      const int gm = m0 + ar;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gk = k0 + ak + q;
+        As[ak + q][ar] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
+      }
+    }
+    {
+      const int gk = k0 + bk;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gn = n0 + bn + q;
+        Bs[bk][bn + q] = (gk < K && gn < N) ? B[(int64_t)gk * ldb + gn] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a0 = As[kr][wm + (lane & 15)];
+      const double a1 = As[kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[kr][wn + (lane & 15)];
+      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // D[i][j] of a 16x16 block: lane = j + 16 * (i % 4), element i / 4.
+  const v4d* accs[4] = {&acc00, &acc01, &acc10, &acc11};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = t >> 1, cblk = t & 1;
+    const int gn = n0 + wn + cblk * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int gm = m0 + wm + r * 16 + (lane >> 4) + 4 * q;
+      if (gm < M && gn < N) {
+        double v = (*accs[t])[q];
+        if (EPI == EPI_DIVIDE) {
+          // C is (nz x nx*ny): m = z-mode c, n = b * nx + a
+          const int a = gn % ep.nx, bb = gn / ep.nx;
+          const int64_t flat = (int64_t)gm * ((int64_t)ep.nx * ep.ny) + gn;
+          const double den = ep.lz[gm] + ep.ly[bb] + ep.lx[a];
+          v = (flat == ep.null3) ? 0.0 : v / den;
+        } else if (EPI == EPI_ISQ) {
+          // C is (ny*nz x nx): m = k * ny + j, n = i
+          const int j = gm % ep.ny, k = gm / ep.ny;
+          v *= ep.isx[gn] * ep.isy[j] * ep.isz[k];
+        }
+        C[(int64_t)gm * ldc + gn] = v;
+      }
+    }
+  }
+}
+
+template <int EPI>
+hipError_t gemm(const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
+                double* C, int64_t ldc, int64_t sC, int M, int N, int K, int batch, int a_is_big,
+                const Epi& ep, hipStream_t s) {
+  const int mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
+  const int64_t total = (int64_t)mt * nt * batch;
+  const int64_t blocks = ((total + 7) / 8) * 8;
+  fd_gemm_kernel<EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(A, lda, sA, B, ldb, sB, C, ldc, sC, M, N,
+                                                                   K, mt, nt, batch, a_is_big, ep);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out) {
+  const Grid& g = c->g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t plane = (int64_t)nx * ny;
+  Epi ep{g.ax[0].lam, g.ax[1].lam, g.ax[2].lam, g.ax[0].isq, g.ax[1].isq, g.ax[2].isq, nx, ny, g.null3};
+  double* A = in;
+  double* Bf = c->cellB;
+  hipStream_t s = c->stream;
+  hipError_t e;
+  // forward: x, y, z (+ divide)
+  if ((e = gemm<EPI_NONE>(A, nx, 0, c->Qf[0], nx, 0, Bf, nx, 0, ny * nz, nx, nx, 1, 1, ep, s))) return e;
+  if ((e = gemm<EPI_NONE>(c->Qt[1], ny, 0, Bf, nx, plane, A, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
+  if ((e = gemm<EPI_DIVIDE>(c->Qt[2], nz, 0, A, plane, 0, Bf, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
+  // inverse: z, y, x (+ S^-1)
+  if ((e = gemm<EPI_NONE>(c->Qf[2], nz, 0, Bf, plane, 0, A, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
+  if ((e = gemm<EPI_NONE>(c->Qf[1], ny, 0, A, nx, plane, Bf, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
+  return gemm<EPI_ISQ>(Bf, nx, 0, c->Qt[0], nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
+}
+
+hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K, hipStream_t s) {
+  Epi ep{};
+  return gemm<EPI_NONE>(A, K, 0, B, N, 0, C, N, 0, M, N, K, 1, M >= N, ep, s);
+}
+
+}  // namespace kv

@@ -1,0 +1,115 @@
+// Internal declarations of the gfx950 Krylov-vector library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kv.h"
+
+namespace kv {
+
+// Per-axis metrics on the device.  n cells, faces 0..n.
+//   h[i]    cell width, i < n           ih[i] = 1/h[i]
+//   id[f]   1/(centre gap) at face f, f = 0..n; the wall gaps are h/2
+//   wlo[f], whi[f]  interpolation weights of cells f-1 and f at interior face f
+//   sq[i]   sqrt(h[i])                  isq[i] = 1/sqrt(h[i])
+//   dd[f]   centre gap at face f (control-volume width of a face unknown)
+//   lam[i]  eigenvalues of the symmetric 1-D Neumann operator (FD basis)
+//   c[i]    cell-centre coordinate
+struct Axis {
+  int n;
+  const double *h, *ih, *id, *wlo, *whi, *sq, *isq, *dd, *lam, *c;
+};
+
+// Everything a stencil or vector kernel needs about the grid and the layout.
+struct Grid {
+  int nx, ny, nz;
+  int64_t ou, ov, ow, oT, n;  // packed offsets and size
+  Axis ax[3];
+  double nu, kappa, beta;
+  int null3;                  // flat index (c*ny + b)*nx + a of the FD null mode
+};
+
+}  // namespace kv
+
+struct kv_ctx {
+  kv::Grid g;
+  int64_t ncell = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double Gr = 0, Pr = 0;
+  // host copies of the metrics (used by host-side solver bookkeeping)
+  std::vector<double> hf[3];
+  // device allocations
+  double* metric = nullptr;   // all Axis arrays
+  double* Qf[3] = {nullptr, nullptr, nullptr};   // Q (n x n row-major): forward uses Q
+  double* Qt[3] = {nullptr, nullptr, nullptr};   // Q^T
+  double* X0 = nullptr;       // base flow copy
+  bool has_base = false;
+  double* cellA = nullptr;    // two cell-sized scratch fields for the Poisson solve
+  double* cellB = nullptr;
+  double* part = nullptr;     // reduction partials
+  double* dres = nullptr;     // reduction results on the device (64 doubles)
+  double* hres = nullptr;     // pinned host mirror of dres
+  int npart_blocks = 0;
+  // solver workspace (lazily allocated)
+  double* work = nullptr;
+  size_t work_bytes = 0;
+  double* hess = nullptr;     // device Hessenberg / Schur workspace
+  size_t hess_bytes = 0;
+  // phase timing (kv_timing): events recorded around each phase while enabled
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;       // reusable events
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;  // (phase, start, stop)
+  std::string err;
+};
+
+namespace kv {
+
+// ---- launchers (all enqueue on ctx->stream) -----------------------------------
+// y = J(X0) x (mode 0) or y = N(x) (mode 1, X0 unused), unprojected.
+hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode);
+// cellA = V^1/2 D y  (net face flux over sqrt of the cell volume)
+hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* out);
+// p = L^+ (V^-1/2 in) by fast diagonalization; in and out are cell fields.
+// in is overwritten (used as scratch); result in out.
+hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out);
+// y_vel -= G p
+hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* y);
+
+// Weighted dot products over the packed layout.  npair <= 4 pairs (a_i, b_i);
+// results land in c->dres[0..npair).
+hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b);
+// res[i] = <V_i, w>_W for i < nvec (V row stride ldv), results in c->dres (nvec <= 64)
+hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w);
+// w -= sum_i h[i] V_i, h on the device (nvec values)
+hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w);
+// out = sum_k coef[k] * in[k], k < nterm <= 4 (out may alias in[k])
+hipError_t launch_lincomb(const kv_ctx* c, int64_t n, int nterm, const double* coef,
+                          const double* const* in, double* out);
+// out[0..n) = v
+hipError_t launch_fill(const kv_ctx* c, int64_t n, double v, double* out);
+// maxima: dres[0] = max|a| (or a NaN flag), used for non-finite checks and norms
+hipError_t launch_maxabs(kv_ctx* c, const double* a, int64_t n);
+// dres[0] = max |net flux|, dres[1] = max |face flux| of the velocity block of y
+hipError_t launch_div_measure(kv_ctx* c, const double* y);
+// dres[0..3) = R_ref, R_2D, R_3D of X
+hipError_t launch_symmetry(kv_ctx* c, const double* X);
+
+// FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
+hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K,
+                            hipStream_t s);
+
+// Hessenberg eigen-solve on the device: H (m x m, row-major, leading dim ld)
+// -> eigenvalues (wr, wi) and, for the requested columns, eigenvector
+// coefficients.  See kv_hess.hip.
+hipError_t launch_hessenberg_eig(const kv_ctx* c, double* H, int m, int ld, double* Z, double* wr,
+                                 double* wi, int* info, double* vr, double* vi, int want_vectors);
+
+// Host symmetric eigen-solver (cyclic Jacobi) for the FD bases.
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& Q, std::vector<double>& lam);
+
+}  // namespace kv

@@ -1,0 +1,433 @@
+// Finite-volume stencils of the Boussinesq operator on the staggered grid.
+//
+// One thread per cell (i, j, k) produces every unknown that the cell owns:
+// u on its west x-face (i >= 1), v on its south y-face (j >= 1), w on its
+// bottom z-face (k >= 1) and T at its centre.  Threads of a block run along
+// x, so all loads and stores are coalesced rows of the packed layout; the
+// +-1 neighbours along y and z are re-read from the L1/L2 caches.
+//
+// The same kernel gives the Jacobian J(X0) x (paper Sec. 1: Newton and
+// Arnoldi both act on it) and the steady right-hand side N(X) of Eqs. 1-2:
+// every convective flux is a product (carrier velocity) x (carried
+// quantity); J uses the product rule, N the product itself, which is the
+// product-rule form with base = perturbation = X and a factor 1/2.
+// Wall values: no-slip (velocities 0) at half-cell distance, T = +-1/2 on
+// the x-walls for N (Eq. 4 in the centred variable), 0 for J, and no flux
+// through the y- and z-walls (Eqs. 5-6).
+#include "kv_internal.h"
+
+namespace kv {
+namespace {
+
+__device__ __forceinline__ double Uat(const double* __restrict__ X, const Grid& g, int i, int j, int k) {
+  return (i <= 0 || i >= g.nx) ? 0.0 : X[g.ou + ((int64_t)k * g.ny + j) * (g.nx - 1) + (i - 1)];
+}
+__device__ __forceinline__ double Vat(const double* __restrict__ X, const Grid& g, int i, int j, int k) {
+  return (j <= 0 || j >= g.ny) ? 0.0 : X[g.ov + ((int64_t)k * (g.ny - 1) + (j - 1)) * g.nx + i];
+}
+__device__ __forceinline__ double Wat(const double* __restrict__ X, const Grid& g, int i, int j, int k) {
+  return (k <= 0 || k >= g.nz) ? 0.0 : X[g.ow + ((int64_t)(k - 1) * g.ny + j) * g.nx + i];
+}
+__device__ __forceinline__ double Tat(const double* __restrict__ X, const Grid& g, int i, int j, int k) {
+  return X[g.oT + ((int64_t)k * g.ny + j) * g.nx + i];
+}
+
+// MODE 0: y = J(B) x.  MODE 1: y = N(x) (B must equal x).
+template <int MODE>
+__global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __restrict__ B,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const Axis& AX = g.ax[0];
+  const Axis& AY = g.ax[1];
+  const Axis& AZ = g.ax[2];
+  const double s = MODE ? 0.5 : 1.0;
+  const double TW = MODE ? 0.5 : 0.0, TE = MODE ? -0.5 : 0.0;
+
+  // ---------------- u on x-face i ----------------
+  if (i >= 1) {
+    const double Uc = Uat(B, g, i, j, k), uc = Uat(x, g, i, j, k);
+    const double Um = Uat(B, g, i - 1, j, k), um = Uat(x, g, i - 1, j, k);
+    const double Up = Uat(B, g, i + 1, j, k), up = Uat(x, g, i + 1, j, k);
+    // x: centre fluxes (u_bar)^2 at cells i (east) and i-1 (west)
+    double adv = (0.5 * (Uc + Up) * (uc + up) - 0.5 * (Um + Uc) * (um + uc)) * AX.id[i];
+    const double xl = AX.wlo[i], xh = AX.whi[i];
+    // y: fluxes v_hat * u_hat at y-faces j and j+1 of the u control volume
+    double fS = 0.0, fN = 0.0, uS = 0.0, uN = 0.0;
+    if (j > 0) {
+      const double yl = AY.wlo[j], yh = AY.whi[j];
+      const double UB = Uat(B, g, i, j - 1, k);
+      uS = Uat(x, g, i, j - 1, k);
+      const double Vh = xl * Vat(B, g, i - 1, j, k) + xh * Vat(B, g, i, j, k);
+      const double vh = xl * Vat(x, g, i - 1, j, k) + xh * Vat(x, g, i, j, k);
+      fS = Vh * (yl * uS + yh * uc) + vh * (yl * UB + yh * Uc);
+    }
+    if (j < ny - 1) {
+      const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+      const double UB = Uat(B, g, i, j + 1, k);
+      uN = Uat(x, g, i, j + 1, k);
+      const double Vh = xl * Vat(B, g, i - 1, j + 1, k) + xh * Vat(B, g, i, j + 1, k);
+      const double vh = xl * Vat(x, g, i - 1, j + 1, k) + xh * Vat(x, g, i, j + 1, k);
+      fN = Vh * (yl * uc + yh * uN) + vh * (yl * Uc + yh * UB);
+    }
+    adv += (fN - fS) * AY.ih[j];
+    // z: fluxes w_hat * u_hat at z-faces k and k+1
+    double fB = 0.0, fT = 0.0, uB = 0.0, uT = 0.0;
+    if (k > 0) {
+      const double zl = AZ.wlo[k], zh = AZ.whi[k];
+      const double UB = Uat(B, g, i, j, k - 1);
+      uB = Uat(x, g, i, j, k - 1);
+      const double Wh = xl * Wat(B, g, i - 1, j, k) + xh * Wat(B, g, i, j, k);
+      const double wh = xl * Wat(x, g, i - 1, j, k) + xh * Wat(x, g, i, j, k);
+      fB = Wh * (zl * uB + zh * uc) + wh * (zl * UB + zh * Uc);
+    }
+    if (k < nz - 1) {
+      const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+      const double UB = Uat(B, g, i, j, k + 1);
+      uT = Uat(x, g, i, j, k + 1);
+      const double Wh = xl * Wat(B, g, i - 1, j, k + 1) + xh * Wat(B, g, i, j, k + 1);
+      const double wh = xl * Wat(x, g, i - 1, j, k + 1) + xh * Wat(x, g, i, j, k + 1);
+      fT = Wh * (zl * uc + zh * uT) + wh * (zl * Uc + zh * UB);
+    }
+    adv += (fT - fB) * AZ.ih[k];
+    double lap = ((up - uc) * AX.ih[i] - (uc - um) * AX.ih[i - 1]) * AX.id[i];
+    lap += ((uN - uc) * AY.id[j + 1] - (uc - uS) * AY.id[j]) * AY.ih[j];
+    lap += ((uT - uc) * AZ.id[k + 1] - (uc - uB) * AZ.id[k]) * AZ.ih[k];
+    y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] = -s * adv + g.nu * lap;
+  }
+
+  // ---------------- v on y-face j ----------------
+  if (j >= 1) {
+    const double Vc = Vat(B, g, i, j, k), vc = Vat(x, g, i, j, k);
+    const double Vm = Vat(B, g, i, j - 1, k), vm = Vat(x, g, i, j - 1, k);
+    const double Vp = Vat(B, g, i, j + 1, k), vp = Vat(x, g, i, j + 1, k);
+    double adv = (0.5 * (Vc + Vp) * (vc + vp) - 0.5 * (Vm + Vc) * (vm + vc)) * AY.id[j];
+    const double yl = AY.wlo[j], yh = AY.whi[j];
+    double fW = 0.0, fE = 0.0, vW = 0.0, vE = 0.0;
+    if (i > 0) {
+      const double xl = AX.wlo[i], xh = AX.whi[i];
+      const double VB = Vat(B, g, i - 1, j, k);
+      vW = Vat(x, g, i - 1, j, k);
+      const double Uh = yl * Uat(B, g, i, j - 1, k) + yh * Uat(B, g, i, j, k);
+      const double uh = yl * Uat(x, g, i, j - 1, k) + yh * Uat(x, g, i, j, k);
+      fW = Uh * (xl * vW + xh * vc) + uh * (xl * VB + xh * Vc);
+    }
+    if (i < nx - 1) {
+      const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+      const double VB = Vat(B, g, i + 1, j, k);
+      vE = Vat(x, g, i + 1, j, k);
+      const double Uh = yl * Uat(B, g, i + 1, j - 1, k) + yh * Uat(B, g, i + 1, j, k);
+      const double uh = yl * Uat(x, g, i + 1, j - 1, k) + yh * Uat(x, g, i + 1, j, k);
+      fE = Uh * (xl * vc + xh * vE) + uh * (xl * Vc + xh * VB);
+    }
+    adv += (fE - fW) * AX.ih[i];
+    double fB = 0.0, fT = 0.0, vB = 0.0, vT = 0.0;
+    if (k > 0) {
+      const double zl = AZ.wlo[k], zh = AZ.whi[k];
+      const double VB = Vat(B, g, i, j, k - 1);
+      vB = Vat(x, g, i, j, k - 1);
+      const double Wh = yl * Wat(B, g, i, j - 1, k) + yh * Wat(B, g, i, j, k);
+      const double wh = yl * Wat(x, g, i, j - 1, k) + yh * Wat(x, g, i, j, k);
+      fB = Wh * (zl * vB + zh * vc) + wh * (zl * VB + zh * Vc);
+    }
+    if (k < nz - 1) {
+      const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+      const double VB = Vat(B, g, i, j, k + 1);
+      vT = Vat(x, g, i, j, k + 1);
+      const double Wh = yl * Wat(B, g, i, j - 1, k + 1) + yh * Wat(B, g, i, j, k + 1);
+      const double wh = yl * Wat(x, g, i, j - 1, k + 1) + yh * Wat(x, g, i, j, k + 1);
+      fT = Wh * (zl * vc + zh * vT) + wh * (zl * Vc + zh * VB);
+    }
+    adv += (fT - fB) * AZ.ih[k];
+    double lap = ((vp - vc) * AY.ih[j] - (vc - vm) * AY.ih[j - 1]) * AY.id[j];
+    lap += ((vE - vc) * AX.id[i + 1] - (vc - vW) * AX.id[i]) * AX.ih[i];
+    lap += ((vT - vc) * AZ.id[k + 1] - (vc - vB) * AZ.id[k]) * AZ.ih[k];
+    y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] = -s * adv + g.nu * lap;
+  }
+
+  // ---------------- w on z-face k ----------------
+  if (k >= 1) {
+    const double Wc = Wat(B, g, i, j, k), wc = Wat(x, g, i, j, k);
+    const double Wm = Wat(B, g, i, j, k - 1), wm = Wat(x, g, i, j, k - 1);
+    const double Wp = Wat(B, g, i, j, k + 1), wp = Wat(x, g, i, j, k + 1);
+    double adv = (0.5 * (Wc + Wp) * (wc + wp) - 0.5 * (Wm + Wc) * (wm + wc)) * AZ.id[k];
+    const double zl = AZ.wlo[k], zh = AZ.whi[k];
+    double fW = 0.0, fE = 0.0, wW = 0.0, wE = 0.0;
+    if (i > 0) {
+      const double xl = AX.wlo[i], xh = AX.whi[i];
+      const double WB = Wat(B, g, i - 1, j, k);
+      wW = Wat(x, g, i - 1, j, k);
+      const double Uh = zl * Uat(B, g, i, j, k - 1) + zh * Uat(B, g, i, j, k);
+      const double uh = zl * Uat(x, g, i, j, k - 1) + zh * Uat(x, g, i, j, k);
+      fW = Uh * (xl * wW + xh * wc) + uh * (xl * WB + xh * Wc);
+    }
+    if (i < nx - 1) {
+      const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+      const double WB = Wat(B, g, i + 1, j, k);
+      wE = Wat(x, g, i + 1, j, k);
+      const double Uh = zl * Uat(B, g, i + 1, j, k - 1) + zh * Uat(B, g, i + 1, j, k);
+      const double uh = zl * Uat(x, g, i + 1, j, k - 1) + zh * Uat(x, g, i + 1, j, k);
+      fE = Uh * (xl * wc + xh * wE) + uh * (xl * Wc + xh * WB);
+    }
+    adv += (fE - fW) * AX.ih[i];
+    double fS = 0.0, fN = 0.0, wS = 0.0, wN = 0.0;
+    if (j > 0) {
+      const double yl = AY.wlo[j], yh = AY.whi[j];
+      const double WB = Wat(B, g, i, j - 1, k);
+      wS = Wat(x, g, i, j - 1, k);
+      const double Vh = zl * Vat(B, g, i, j, k - 1) + zh * Vat(B, g, i, j, k);
+      const double vh = zl * Vat(x, g, i, j, k - 1) + zh * Vat(x, g, i, j, k);
+      fS = Vh * (yl * wS + yh * wc) + vh * (yl * WB + yh * Wc);
+    }
+    if (j < ny - 1) {
+      const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+      const double WB = Wat(B, g, i, j + 1, k);
+      wN = Wat(x, g, i, j + 1, k);
+      const double Vh = zl * Vat(B, g, i, j + 1, k - 1) + zh * Vat(B, g, i, j + 1, k);
+      const double vh = zl * Vat(x, g, i, j + 1, k - 1) + zh * Vat(x, g, i, j + 1, k);
+      fN = Vh * (yl * wc + yh * wN) + vh * (yl * Wc + yh * WB);
+    }
+    adv += (fN - fS) * AY.ih[j];
+    double lap = ((wp - wc) * AZ.ih[k] - (wc - wm) * AZ.ih[k - 1]) * AZ.id[k];
+    lap += ((wE - wc) * AX.id[i + 1] - (wc - wW) * AX.id[i]) * AX.ih[i];
+    lap += ((wN - wc) * AY.id[j + 1] - (wc - wS) * AY.id[j]) * AY.ih[j];
+    const double buoy = zl * Tat(x, g, i, j, k - 1) + zh * Tat(x, g, i, j, k);
+    y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = -s * adv + g.nu * lap + g.beta * buoy;
+  }
+
+  // ---------------- T at the cell centre ----------------
+  {
+    const double Tb = Tat(B, g, i, j, k), tc = Tat(x, g, i, j, k);
+    double adv = 0.0, lap = 0.0;
+    // x
+    {
+      double fW = 0.0, fE = 0.0;
+      const double tW = (i > 0) ? Tat(x, g, i - 1, j, k) : TW;
+      const double tE = (i < nx - 1) ? Tat(x, g, i + 1, j, k) : TE;
+      if (i > 0) {
+        const double xl = AX.wlo[i], xh = AX.whi[i];
+        const double Th = xl * Tat(B, g, i - 1, j, k) + xh * Tb;
+        fW = Uat(B, g, i, j, k) * (xl * tW + xh * tc) + Uat(x, g, i, j, k) * Th;
+      }
+      if (i < nx - 1) {
+        const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+        const double Th = xl * Tb + xh * Tat(B, g, i + 1, j, k);
+        fE = Uat(B, g, i + 1, j, k) * (xl * tc + xh * tE) + Uat(x, g, i + 1, j, k) * Th;
+      }
+      adv += (fE - fW) * AX.ih[i];
+      lap += ((tE - tc) * AX.id[i + 1] - (tc - tW) * AX.id[i]) * AX.ih[i];
+    }
+    // y
+    {
+      double fS = 0.0, fN = 0.0, gS = 0.0, gN = 0.0;
+      if (j > 0) {
+        const double yl = AY.wlo[j], yh = AY.whi[j];
+        const double tS = Tat(x, g, i, j - 1, k);
+        const double Th = yl * Tat(B, g, i, j - 1, k) + yh * Tb;
+        fS = Vat(B, g, i, j, k) * (yl * tS + yh * tc) + Vat(x, g, i, j, k) * Th;
+        gS = (tc - tS) * AY.id[j];
+      }
+      if (j < ny - 1) {
+        const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+        const double tN = Tat(x, g, i, j + 1, k);
+        const double Th = yl * Tb + yh * Tat(B, g, i, j + 1, k);
+        fN = Vat(B, g, i, j + 1, k) * (yl * tc + yh * tN) + Vat(x, g, i, j + 1, k) * Th;
+        gN = (tN - tc) * AY.id[j + 1];
+      }
+      adv += (fN - fS) * AY.ih[j];
+      lap += (gN - gS) * AY.ih[j];
+    }
+    // z
+    {
+      double fB = 0.0, fT = 0.0, gB = 0.0, gT = 0.0;
+      if (k > 0) {
+        const double zl = AZ.wlo[k], zh = AZ.whi[k];
+        const double tB = Tat(x, g, i, j, k - 1);
+        const double Th = zl * Tat(B, g, i, j, k - 1) + zh * Tb;
+        fB = Wat(B, g, i, j, k) * (zl * tB + zh * tc) + Wat(x, g, i, j, k) * Th;
+        gB = (tc - tB) * AZ.id[k];
+      }
+      if (k < nz - 1) {
+        const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+        const double tT = Tat(x, g, i, j, k + 1);
+        const double Th = zl * Tb + zh * Tat(B, g, i, j, k + 1);
+        fT = Wat(B, g, i, j, k + 1) * (zl * tc + zh * tT) + Wat(x, g, i, j, k + 1) * Th;
+        gT = (tT - tc) * AZ.id[k + 1];
+      }
+      adv += (fT - fB) * AZ.ih[k];
+      lap += (gT - gB) * AZ.ih[k];
+    }
+    y[g.oT + ((int64_t)k * ny + j) * nx + i] = -s * adv + g.kappa * lap;
+  }
+}
+
+// out = V^{1/2} (D y) = (net outward face flux of the velocity) / sqrt(V_c)
+__global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const double* __restrict__ y,
+                                                                double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const Axis& AX = g.ax[0];
+  const Axis& AY = g.ax[1];
+  const Axis& AZ = g.ax[2];
+  const double fx = Uat(y, g, i + 1, j, k) - Uat(y, g, i, j, k);
+  const double fy = Vat(y, g, i, j + 1, k) - Vat(y, g, i, j, k);
+  const double fz = Wat(y, g, i, j, k + 1) - Wat(y, g, i, j, k);
+  const double hx = AX.h[i], hy = AY.h[j], hz = AZ.h[k];
+  const double net = hy * hz * fx + hx * hz * fy + hx * hy * fz;
+  out[((int64_t)k * g.ny + j) * g.nx + i] = net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]);
+}
+
+// y_vel -= G p at the interior faces owned by cell (i, j, k)
+__global__ void __launch_bounds__(256) gradient_correction_kernel(Grid g, const double* __restrict__ p,
+                                                                  double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int nx = g.nx, ny = g.ny;
+  const int64_t c = ((int64_t)k * ny + j) * nx + i;
+  const double pc = p[c];
+  if (i >= 1) y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] -= (pc - p[c - 1]) * g.ax[0].id[i];
+  if (j >= 1) y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] -= (pc - p[c - nx]) * g.ax[1].id[j];
+  if (k >= 1) y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] -= (pc - p[c - (int64_t)nx * ny]) * g.ax[2].id[k];
+}
+
+// Block maxima of |net flux| and |face flux|; non-finite values count as +inf.
+__device__ __forceinline__ double fin_abs(double v) {
+  const double a = fabs(v);
+  return (a <= 1.7976931348623157e308) ? a : __builtin_inf();
+}
+
+__global__ void __launch_bounds__(256) div_measure_kernel(Grid g, const double* __restrict__ y,
+                                                          double* __restrict__ part) {
+  __shared__ double s0[256], s1[256];
+  const int t = threadIdx.x;
+  double mb = 0.0, mf = 0.0;
+  const int64_t C = (int64_t)g.nx * g.ny * g.nz;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + t; c < C; c += (int64_t)gridDim.x * 256) {
+    const int i = (int)(c % g.nx);
+    const int j = (int)((c / g.nx) % g.ny);
+    const int k = (int)(c / ((int64_t)g.nx * g.ny));
+    const double hx = g.ax[0].h[i], hy = g.ax[1].h[j], hz = g.ax[2].h[k];
+    const double u0 = Uat(y, g, i, j, k), u1 = Uat(y, g, i + 1, j, k);
+    const double v0 = Vat(y, g, i, j, k), v1 = Vat(y, g, i, j + 1, k);
+    const double w0 = Wat(y, g, i, j, k), w1 = Wat(y, g, i, j, k + 1);
+    const double net = hy * hz * (u1 - u0) + hx * hz * (v1 - v0) + hx * hy * (w1 - w0);
+    mb = fmax(mb, fin_abs(net));
+    mf = fmax(mf, fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy))));
+  }
+  s0[t] = mb;
+  s1[t] = mf;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s0[t] = fmax(s0[t], s0[t + o]);
+      s1[t] = fmax(s1[t], s1[t + o]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+// Block maxima of the three symmetry measures over theta = T - (1/2 - x_c)
+// (T is the centred temperature), Eqs. 7-9.
+__global__ void __launch_bounds__(256) symmetry_kernel(Grid g, const double* __restrict__ X, const double* __restrict__ cx,
+                                                       double* __restrict__ part) {
+  __shared__ double s[3][256];
+  const int t = threadIdx.x;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t C = (int64_t)nx * ny * nz;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + t; c < C; c += (int64_t)gridDim.x * 256) {
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / ((int64_t)nx * ny));
+    const int im = nx - 1 - i, jm = ny - 1 - j, km = nz - 1 - k;
+    const double th = Tat(X, g, i, j, k) - (0.5 - cx[i]);
+    const double th_ref = Tat(X, g, i, jm, k) - (0.5 - cx[i]);
+    const double th_2d = Tat(X, g, im, j, km) - (0.5 - cx[im]);
+    const double th_3d = Tat(X, g, im, jm, km) - (0.5 - cx[im]);
+    r0 = fmax(r0, fin_abs(th - th_ref));
+    r1 = fmax(r1, fin_abs(th + th_2d));
+    r2 = fmax(r2, fin_abs(th + th_3d));
+  }
+  s[0][t] = r0;
+  s[1][t] = r1;
+  s[2][t] = r2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o)
+      for (int q = 0; q < 3; ++q) s[q][t] = fmax(s[q][t], s[q][t + o]);
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = s[q][0];
+}
+
+__global__ void max_finish_kernel(const double* __restrict__ part, int nblk, int nq, double* __restrict__ out) {
+  __shared__ double s[256];
+  const int t = threadIdx.x;
+  for (int q = 0; q < nq; ++q) {
+    double m = 0.0;
+    for (int b = t; b < nblk; b += 256) m = fmax(m, part[nq * b + q]);
+    s[t] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) s[t] = fmax(s[t], s[t + o]);
+      __syncthreads();
+    }
+    if (t == 0) out[q] = s[0];
+    __syncthreads();
+  }
+}
+
+inline dim3 cell_block(const Grid& g) { return dim3(64, 4, 1); }
+inline dim3 cell_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
+
+}  // namespace
+
+hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode) {
+  const Grid& g = c->g;
+  if (mode == 0)
+    operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
+  else
+    operator_kernel<1><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, x, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* out) {
+  const Grid& g = c->g;
+  scaled_divergence_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* y) {
+  const Grid& g = c->g;
+  gradient_correction_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, p, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_div_measure(kv_ctx* c, const double* y) {
+  const int nblk = c->npart_blocks;
+  div_measure_kernel<<<nblk, 256, 0, c->stream>>>(c->g, y, c->part);
+  max_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, 2, c->dres);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetry(kv_ctx* c, const double* X) {
+  const int nblk = c->npart_blocks;
+  symmetry_kernel<<<nblk, 256, 0, c->stream>>>(c->g, X, c->g.ax[0].c, c->part);
+  max_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, 3, c->dres);
+  return hipGetLastError();
+}
+
+}  // namespace kv

@@ -1,0 +1,267 @@
+// Vector kernels of the Krylov solvers: volume-weighted inner products
+// (single, fused pairs, and block Gram-Schmidt multi-dots), block updates,
+// linear combinations and max-reductions.  All reductions are two-pass
+// (per-block partials, then one finishing block) so results do not depend
+// on scheduling.
+//
+// The weighted inner product walks the packed layout row by row: one wave
+// per x-row, lanes along x, so every load is a coalesced row segment and the
+// control volume of each unknown is the product of three per-axis metrics
+// (never stored as a vector).
+#include "kv_internal.h"
+
+namespace kv {
+namespace {
+
+struct RowInfo {
+  int64_t off;
+  int len;
+  const double* wx;
+  double wyz;
+};
+
+// Row r of the packed vector: block u (nz*ny rows of nx-1), v (nz*(ny-1) rows
+// of nx), w ((nz-1)*ny rows of nx), T (nz*ny rows of nx).
+__device__ __forceinline__ RowInfo row_info(const Grid& g, int64_t r) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t R0 = (int64_t)nz * ny, R1 = (int64_t)nz * (ny - 1), R2 = (int64_t)(nz - 1) * ny;
+  if (r < R0) {
+    const int k = (int)(r / ny), j = (int)(r % ny);
+    return {g.ou + r * (nx - 1), nx - 1, g.ax[0].dd + 1, g.ax[1].h[j] * g.ax[2].h[k]};
+  }
+  r -= R0;
+  if (r < R1) {
+    const int k = (int)(r / (ny - 1)), jj = (int)(r % (ny - 1));
+    return {g.ov + r * nx, nx, g.ax[0].h, g.ax[1].dd[jj + 1] * g.ax[2].h[k]};
+  }
+  r -= R1;
+  if (r < R2) {
+    const int kk = (int)(r / ny), j = (int)(r % ny);
+    return {g.ow + r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].dd[kk + 1]};
+  }
+  r -= R2;
+  const int k = (int)(r / ny), j = (int)(r % ny);
+  return {g.oT + r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].h[k]};
+}
+
+__device__ __forceinline__ int64_t total_rows(const Grid& g) {
+  return (int64_t)g.nz * g.ny * 2 + (int64_t)g.nz * (g.ny - 1) + (int64_t)(g.nz - 1) * g.ny;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of v over the 256-thread block (4 waves); valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  return (threadIdx.x == 0) ? (sh[0] + sh[1]) + (sh[2] + sh[3]) : 0.0;
+}
+
+struct Ptr4 {
+  const double* p[4];
+};
+
+template <int NP>
+__global__ void __launch_bounds__(256) wdots_kernel(Grid g, Ptr4 a, Ptr4 b, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  const int64_t nrows = total_rows(g);
+  for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
+    const RowInfo ri = row_info(g, r);
+    for (int e = lane; e < ri.len; e += 64) {
+      const double w = ri.wx[e] * ri.wyz;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[q] += w * a.p[q][ri.off + e] * b.p[q][ri.off + e];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const double s = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) part[(int64_t)q * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Block multi-dot for classical Gram-Schmidt: part[q][blk] for q < nv <= 8
+// against the vectors V + q * ldv; w * weight is formed once per element.
+__global__ void __launch_bounds__(256) mdot8_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
+                                                    const double* __restrict__ w, double* __restrict__ part,
+                                                    int qbase) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  const int64_t nrows = total_rows(g);
+  for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
+    const RowInfo ri = row_info(g, r);
+    for (int e = lane; e < ri.len; e += 64) {
+      const int64_t idx = ri.off + e;
+      const double ww = ri.wx[e] * ri.wyz * w[idx];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < nv) acc[q] += ww * V[q * ldv + idx];
+    }
+  }
+  for (int q = 0; q < nv; ++q) {
+    const double s = block_sum(acc[q], sh);
+    if (threadIdx.x == 0) part[(int64_t)(qbase + q) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ void sum_finish_kernel(const double* __restrict__ part, int nblk, int nq, double* __restrict__ out) {
+  __shared__ double sh[4];
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) v += part[(int64_t)q * nblk + b];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) out[q] = s;
+  }
+}
+
+// w -= sum_i h[i] V_i over the flat vector
+__global__ void __launch_bounds__(256) mupdate_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int nv,
+                                                      const double* __restrict__ h, double* __restrict__ w) {
+  __shared__ double hs[512];
+  for (int q = threadIdx.x; q < nv; q += 256) hs[q] = h[q];
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double acc = w[e];
+    for (int q = 0; q < nv; ++q) acc -= hs[q] * V[q * ldv + e];
+    w[e] = acc;
+  }
+}
+
+struct Coef4 {
+  double c[4];
+};
+
+template <int NT>
+__global__ void __launch_bounds__(256) lincomb_kernel(int64_t n, Coef4 c, Ptr4 in, double* out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double v = c.c[0] * in.p[0][e];
+#pragma unroll
+    for (int q = 1; q < NT; ++q) v += c.c[q] * in.p[q][e];
+    out[e] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) fill_kernel(int64_t n, double v, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) out[e] = v;
+}
+
+__device__ __forceinline__ double fin_abs(double v) {
+  const double a = fabs(v);
+  return (a <= 1.7976931348623157e308) ? a : __builtin_inf();
+}
+
+__global__ void __launch_bounds__(256) maxabs_kernel(int64_t n, const double* __restrict__ a, double* __restrict__ part) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    m = fmax(m, fin_abs(a[e]));
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void max1_finish_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, part[b]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+inline int flat_blocks(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b) {
+  Ptr4 pa{}, pb{};
+  for (int q = 0; q < npair; ++q) {
+    pa.p[q] = a[q];
+    pb.p[q] = b[q];
+  }
+  const int nblk = c->npart_blocks;
+  switch (npair) {
+    case 1: wdots_kernel<1><<<nblk, 256, 0, c->stream>>>(c->g, pa, pb, c->part); break;
+    case 2: wdots_kernel<2><<<nblk, 256, 0, c->stream>>>(c->g, pa, pb, c->part); break;
+    case 3: wdots_kernel<3><<<nblk, 256, 0, c->stream>>>(c->g, pa, pb, c->part); break;
+    case 4: wdots_kernel<4><<<nblk, 256, 0, c->stream>>>(c->g, pa, pb, c->part); break;
+    default: return hipErrorInvalidValue;
+  }
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, npair, c->dres);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w) {
+  if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
+  const int nblk = c->npart_blocks;
+  for (int q0 = 0; q0 < nvec; q0 += 8) {
+    const int nv = (nvec - q0 < 8) ? nvec - q0 : 8;
+    mdot8_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
+  }
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, c->dres);
+  return hipGetLastError();
+}
+
+hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w) {
+  if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
+  mupdate_kernel<<<flat_blocks(c->g.n), 256, 0, c->stream>>>(c->g.n, V, ldv, nvec, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const kv_ctx* c, int64_t n, int nterm, const double* coef, const double* const* in,
+                          double* out) {
+  Coef4 cf{};
+  Ptr4 p{};
+  for (int q = 0; q < nterm; ++q) {
+    cf.c[q] = coef[q];
+    p.p[q] = in[q];
+  }
+  const int nb = flat_blocks(n);
+  switch (nterm) {
+    case 1: lincomb_kernel<1><<<nb, 256, 0, c->stream>>>(n, cf, p, out); break;
+    case 2: lincomb_kernel<2><<<nb, 256, 0, c->stream>>>(n, cf, p, out); break;
+    case 3: lincomb_kernel<3><<<nb, 256, 0, c->stream>>>(n, cf, p, out); break;
+    case 4: lincomb_kernel<4><<<nb, 256, 0, c->stream>>>(n, cf, p, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(const kv_ctx* c, int64_t n, double v, double* out) {
+  fill_kernel<<<flat_blocks(n), 256, 0, c->stream>>>(n, v, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxabs(kv_ctx* c, const double* a, int64_t n) {
+  const int nblk = c->npart_blocks;
+  maxabs_kernel<<<nblk, 256, 0, c->stream>>>(n, a, c->part);
+  max1_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, c->dres);
+  return hipGetLastError();
+}
+
+}  // namespace kv

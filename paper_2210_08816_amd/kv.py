@@ -1,0 +1,210 @@
+"""Python binding of libkv_hip.so (the C ABI in include/kv.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels on the GPU.  Vectors are torch float64 CUDA (ROCm) tensors in the
+packed [u | v | w | T] layout; the library enqueues its work on the torch
+stream that is current when the Context is created.  There is no CPU
+fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkv_hip.so")
+
+KV_OK, KV_EINVAL, KV_ENOMEM, KV_EDEVICE, KV_ENOCONV, KV_ENONFINITE, KV_ESTATE = range(7)
+KV_PROJECT, KV_MIXED = 1, 2
+STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: "KV_ENOCONV",
+                5: "KV_ENONFINITE", 6: "KV_ESTATE"}
+
+# every extern "C" symbol declared in include/kv.h
+ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
+               "kv_apply_jacobian", "kv_project", "kv_dot", "kv_symmetry_measures",
+               "kv_newton_correction", "kv_arnoldi_leading_eigs", "kv_timing", "kv_last_error")
+
+
+class KVError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("xf", ctypes.POINTER(ctypes.c_double)), ("yf", ctypes.POINTER(ctypes.c_double)),
+                ("zf", ctypes.POINTER(ctypes.c_double)), ("Gr", ctypes.c_double), ("Pr", ctypes.c_double)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("matvecs", ctypes.c_int), ("cycles", ctypes.c_int), ("used_gmres", ctypes.c_int),
+                ("relres", ctypes.c_double)]
+
+
+class _ArnoldiParams(ctypes.Structure):
+    _fields_ = [("krylov_dim", ctypes.c_int), ("n_eigs", ctypes.c_int), ("max_matvec", ctypes.c_int),
+                ("max_restarts", ctypes.c_int), ("cheb_degree_max", ctypes.c_int),
+                ("tol", ctypes.c_double), ("v0", ctypes.c_void_p), ("flags", ctypes.c_uint)]
+
+
+class _EigInfo(ctypes.Structure):
+    _fields_ = [("n_out", ctypes.c_int), ("matvecs", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("converged", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2210_08816_amd.build")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    PD = ctypes.POINTER(ctypes.c_double)
+    lib.kv_create.argtypes = [ctypes.POINTER(_Params), P, ctypes.POINTER(P)]
+    lib.kv_destroy.argtypes = [P]
+    lib.kv_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.kv_set_base_flow.argtypes = [P, P]
+    lib.kv_residual.argtypes = [P, P, PD]
+    lib.kv_apply_jacobian.argtypes = [P, P, P, ctypes.c_uint]
+    lib.kv_project.argtypes = [P, P, ctypes.c_uint, PD, ctypes.POINTER(ctypes.c_int)]
+    lib.kv_dot.argtypes = [P, P, P, PD]
+    lib.kv_symmetry_measures.argtypes = [P, P, PD]
+    lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
+    lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD,
+                                            ctypes.POINTER(_EigInfo)]
+    lib.kv_timing.argtypes = [P, ctypes.c_int, PD, ctypes.POINTER(ctypes.c_int)]
+    lib.kv_last_error.argtypes = [P]
+    lib.kv_last_error.restype = ctypes.c_char_p
+    for name in ABI_SYMBOLS:
+        if name != "kv_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dptr(t, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (ROCm) torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One grid, one base flow, one HIP stream (the current torch stream)."""
+
+    def __init__(self, xf, yf, zf, Gr: float, Pr: float, stream=None):
+        import torch
+        self._lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the Krylov-vector library runs on gfx950 only")
+        self._faces = [np.ascontiguousarray(np.asarray(f, dtype=np.float64)) for f in (xf, yf, zf)]
+        self.nx, self.ny, self.nz = (len(f) - 1 for f in self._faces)
+        p = _Params(self.nx, self.ny, self.nz,
+                    *(f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for f in self._faces),
+                    float(Gr), float(Pr))
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        rc = self._lib.kv_create(ctypes.byref(p), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+        if rc != KV_OK:
+            raise KVError(rc, "kv_create failed")
+        self._h = h
+        n = ctypes.c_int64()
+        off = (ctypes.c_int64 * 5)()
+        self._check(self._lib.kv_layout(self._h, ctypes.byref(n), off))
+        self.n = int(n.value)
+        self.offsets = [int(o) for o in off]
+
+    def _check(self, rc):
+        if rc != KV_OK:
+            raise KVError(rc, self._lib.kv_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.kv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- the C-ABI calls -----------------------------------------------------------
+    def set_base_flow(self, X):
+        self._check(self._lib.kv_set_base_flow(self._h, _dptr(X, self.n)))
+
+    def residual(self, F):
+        norm = ctypes.c_double()
+        self._check(self._lib.kv_residual(self._h, _dptr(F, self.n), ctypes.byref(norm)))
+        return norm.value
+
+    def apply_jacobian(self, x, y, project=True):
+        flags = KV_PROJECT if project else 0
+        self._check(self._lib.kv_apply_jacobian(self._h, _dptr(x, self.n), _dptr(y, self.n), flags))
+
+    def project(self, y):
+        dm = ctypes.c_double()
+        sw = ctypes.c_int()
+        self._check(self._lib.kv_project(self._h, _dptr(y, self.n), KV_PROJECT, ctypes.byref(dm),
+                                         ctypes.byref(sw)))
+        return dm.value, sw.value
+
+    def dot(self, a, b):
+        out = ctypes.c_double()
+        self._check(self._lib.kv_dot(self._h, _dptr(a, self.n), _dptr(b, self.n), ctypes.byref(out)))
+        return out.value
+
+    def timing(self, enable: bool):
+        """Start (True) or stop (False) phase timing; returns the sums since the
+        last start: ms per phase (stencil, divergence, FD transforms,
+        correction) and (stencil calls, projections)."""
+        ms = (ctypes.c_double * 4)()
+        calls = (ctypes.c_int * 2)()
+        self._check(self._lib.kv_timing(self._h, 1 if enable else 0, ms, calls))
+        return list(ms), (calls[0], calls[1])
+
+    def symmetry_measures(self, X):
+        out = (ctypes.c_double * 3)()
+        self._check(self._lib.kv_symmetry_measures(self._h, _dptr(X, self.n), out))
+        return tuple(out)
+
+    def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True):
+        info = _SolveInfo()
+        d0 = _dptr(delta0, self.n) if delta0 is not None else None
+        rc = self._lib.kv_newton_correction(self._h, _dptr(F, self.n), float(tol), int(max_matvec), 0, d0,
+                                            _dptr(delta, self.n), ctypes.byref(info))
+        if check and rc != KV_ENOCONV:
+            self._check(rc)
+        return dict(status=rc, matvecs=info.matvecs, cycles=info.cycles, used_gmres=info.used_gmres,
+                    relres=info.relres)
+
+    def arnoldi_leading_eigs(self, v0, krylov_dim, n_eigs, tol=1e-8, max_matvec=100000,
+                             max_restarts=1000, cheb_degree_max=200, check=True):
+        p = _ArnoldiParams(int(krylov_dim), int(n_eigs), int(max_matvec), int(max_restarts),
+                           int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, 0)
+        re = (ctypes.c_double * (n_eigs + 1))()
+        im = (ctypes.c_double * (n_eigs + 1))()
+        res = (ctypes.c_double * (n_eigs + 1))()
+        info = _EigInfo()
+        rc = self._lib.kv_arnoldi_leading_eigs(self._h, ctypes.byref(p), re, im, res, ctypes.byref(info))
+        if check and rc != KV_ENOCONV:
+            self._check(rc)
+        k = info.n_out
+        vals = np.array([complex(re[i], im[i]) for i in range(k)])
+        return vals, np.array(res[:k]), dict(status=rc, n_out=k, matvecs=info.matvecs,
+                                              restarts=info.restarts, converged=bool(info.converged))

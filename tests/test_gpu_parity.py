@@ -1,0 +1,115 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerance: FP64 results agree with the FP64 oracle to 1e-12 relative per
+field (||delta y_f||_2 / ||y_f||_2).  Grids span several 64-wide tiles with
+ragged tails, odd and unequal sizes, both grid kinds.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import disc as O  # noqa: E402
+from synth import inputs as S  # noqa: E402
+from tests.gpu_util import faces, field_rel_errors, to_dev, to_host  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+GRIDS = [
+    ("uniform", (32, 32, 32), 1e5, 3, 0.05),      # the 32^3 uniform workload's shape
+    ("clustered", (7, 6, 5), 2e5, 2, 0.1),        # odd, unequal, smaller than one tile
+    ("clustered", (70, 9, 66), 4e7, 4, 0.1),      # one full tile plus ragged tails
+    ("uniform", (2, 3, 2), 1e3, 1, 0.1),          # minimal sizes
+]
+
+
+def make(kind, shape, Gr, K, amp, seed=0):
+    from paper_2210_08816_amd import kv
+    fx = [faces(kind, n) for n in shape]
+    g = O.Grid(*fx, Gr=Gr, Pr=0.71)
+    X0 = S.base_flow(*fx, K=K, amp=amp, seed=seed)
+    ctx = kv.Context(*fx, Gr=Gr, Pr=0.71)
+    assert ctx.n == g.size
+    ctx.set_base_flow(to_dev(X0))
+    return g, X0, ctx
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS)
+def test_jacobian_unprojected(kind, shape, Gr, K, amp):
+    print(f"case J {kind} {shape}", flush=True)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    x = S.perturbation(g.size, 1000)
+    y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    ctx.apply_jacobian(to_dev(x), y, project=False)
+    err = field_rel_errors(g, to_host(y), O.jacobian(g, X0, x))
+    assert max(err) <= TOL64, err
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS)
+def test_projected_jacobian(kind, shape, Gr, K, amp):
+    print(f"case PJ {kind} {shape}", flush=True)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    for r in range(2):
+        x = S.perturbation(g.size, 1000 + r)
+        y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.apply_jacobian(to_dev(x), y, project=True)
+        got = to_host(y)
+        ref = O.apply_jacobian(g, X0, x)
+        err = field_rel_errors(g, got, ref)
+        assert max(err) <= TOL64, err
+        assert O.div_measure(g, got) < 1e-11
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS[:3])
+def test_project_and_divergence(kind, shape, Gr, K, amp):
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    y0 = S.perturbation(g.size, 7)
+    y = to_dev(y0)
+    dm, sweeps = ctx.project(y)
+    got = to_host(y)
+    assert sweeps == 1
+    assert max(field_rel_errors(g, got, O.project(g, y0))) <= TOL64
+    assert dm < 1e-11 and abs(dm - O.div_measure(g, got)) <= 1e-3 * max(dm, 1e-300) + 1e-16
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS[:3])
+def test_residual(kind, shape, Gr, K, amp):
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    norm = ctx.residual(F)
+    ref = O.residual(g, X0)
+    assert max(field_rel_errors(g, to_host(F), ref)) <= TOL64
+    assert abs(norm - O.wnorm(g.weights(), ref)) <= 1e-12 * norm
+
+
+def test_weighted_dot_and_symmetry():
+    g, X0, ctx = make("clustered", (33, 20, 17), 1e6, 3, 0.1)
+    a = S.perturbation(g.size, 1)
+    b = S.perturbation(g.size, 2)
+    w = g.weights()
+    assert abs(ctx.dot(to_dev(a), to_dev(b)) - O.wdot(w, a, b)) <= 1e-12 * O.wnorm(w, a) * O.wnorm(w, b)
+    X = X0 + 0.01 * a
+    got = ctx.symmetry_measures(to_dev(X))
+    ref = O.symmetry_measures(g, X)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-15)
+
+
+def test_error_codes():
+    from paper_2210_08816_amd import kv
+    f = S.faces_uniform(8)
+    ctx = kv.Context(f, f, f, Gr=1e5, Pr=0.71)
+    x = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    with pytest.raises(kv.KVError) as e:
+        ctx.apply_jacobian(x, y)
+    assert e.value.code == kv.KV_ESTATE
+    bad = x.clone()
+    bad[5] = float("nan")
+    with pytest.raises(kv.KVError) as e:
+        ctx.set_base_flow(bad)
+    assert e.value.code == kv.KV_ENONFINITE
+    with pytest.raises(kv.KVError) as e:
+        kv.Context(f[::-1].copy(), f, f, Gr=1e5, Pr=0.71)
+    assert e.value.code == kv.KV_EINVAL
