@@ -47,13 +47,16 @@ class Grid:
             c = 0.5 * (f[:-1] + f[1:])
             d = np.empty(len(f))
             d[0], d[-1] = 0.5 * h[0], 0.5 * h[-1]
-            d[1:-1] = np.diff(c)
+            # centres are midpoints, so c_i - c_{i-1} = (h_{i-1} + h_i) / 2
+            # (formed from the widths: no cancellation near x = 1)
+            d[1:-1] = 0.5 * (h[:-1] + h[1:])
             self.h.append(h)
             self.c.append(c)
             self.d.append(d)
-            # value at interior face i from cells i-1 (lo) and i (hi)
-            self.wlo.append((c[1:] - f[1:-1]) / d[1:-1])
-            self.whi.append((f[1:-1] - c[:-1]) / d[1:-1])
+            # value at interior face i from cells i-1 (lo) and i (hi):
+            # weights (c_i - x_i)/d_i = (h_i/2)/d_i and (x_i - c_{i-1})/d_i = (h_{i-1}/2)/d_i
+            self.wlo.append((0.5 * h[1:]) / d[1:-1])
+            self.whi.append((0.5 * h[:-1]) / d[1:-1])
         self.Gr, self.Pr = float(Gr), float(Pr)
         if Gr > 0:
             self.nu = Gr ** -0.5

@@ -45,6 +45,7 @@ struct HostAxis {
   int n;
   std::vector<double> h, ih, id, wlo, whi, sq, isq, dd, lam, c, Q, Qt;
   int null_idx;
+  bool split = false;  // Q / Qt hold the even/odd half bases [2][H][H]
 };
 
 bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
@@ -76,10 +77,12 @@ bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
   }
   a.dd[0] = 0.5 * a.h[0];
   a.dd[n] = 0.5 * a.h[n - 1];
+  // midpoint centres: the centre gap is (h_{i-1} + h_i)/2 and the weights of
+  // cells i-1 and i at face i are (h_i/2)/d_i and (h_{i-1}/2)/d_i
   for (int i = 1; i < n; ++i) {
-    a.dd[i] = a.c[i] - a.c[i - 1];
-    a.wlo[i] = (a.c[i] - f[i]) / a.dd[i];
-    a.whi[i] = (f[i] - a.c[i - 1]) / a.dd[i];
+    a.dd[i] = 0.5 * (a.h[i - 1] + a.h[i]);
+    a.wlo[i] = (0.5 * a.h[i]) / a.dd[i];
+    a.whi[i] = (0.5 * a.h[i - 1]) / a.dd[i];
   }
   for (int i = 0; i <= n; ++i) a.id[i] = 1.0 / a.dd[i];
   // M = H^-1/2 K H^-1/2, K the symmetric tridiagonal Neumann operator
@@ -90,6 +93,46 @@ bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
     M[(size_t)(i + 1) * n + i] += t * a.isq[i] * a.isq[i + 1];
     M[(size_t)i * n + i] -= t * a.isq[i] * a.isq[i];
     M[(size_t)(i + 1) * n + i + 1] -= t * a.isq[i + 1] * a.isq[i + 1];
+  }
+  // Mirror-symmetric axis (h_i = h_{n-1-i} to round-off, n even): M is
+  // persymmetric and its eigenvectors are [w; +-J w]/sqrt(2) with w the
+  // eigenvectors of the half blocks M_11 +- M_{H-1,H} e_{H-1} e_{H-1}^T.
+  bool sym = (n % 2 == 0) && n >= 4;
+  for (int i = 0; sym && i < n; ++i)
+    if (a.h[i] != a.h[n - 1 - i]) sym = false;
+  if (sym) {
+    const int H = n / 2;
+    std::vector<double> Ms((size_t)n * n);
+    for (int r = 0; r < n; ++r)
+      for (int cc = 0; cc < n; ++cc)
+        Ms[(size_t)r * n + cc] = 0.5 * (M[(size_t)r * n + cc] + M[(size_t)(n - 1 - r) * n + (n - 1 - cc)]);
+    const double t = Ms[(size_t)(H - 1) * n + H];
+    std::vector<double> Wp[2], lp[2];
+    for (int par = 0; par < 2; ++par) {
+      std::vector<double> Mh((size_t)H * H);
+      for (int r = 0; r < H; ++r)
+        for (int cc = 0; cc < H; ++cc) Mh[(size_t)r * H + cc] = Ms[(size_t)r * n + cc];
+      Mh[(size_t)(H - 1) * H + (H - 1)] += par ? -t : t;
+      jacobi_eigen(H, Mh, Wp[par], lp[par]);
+    }
+    a.split = true;
+    a.lam.resize(n);
+    a.Q.assign((size_t)2 * H * H, 0.0);
+    a.Qt.assign((size_t)2 * H * H, 0.0);
+    const double rs2 = 1.0 / std::sqrt(2.0);
+    for (int par = 0; par < 2; ++par)
+      for (int e = 0; e < H; ++e) {
+        a.lam[par * H + e] = lp[par][e];
+        for (int k = 0; k < H; ++k) {
+          const double q = Wp[par][(size_t)k * H + e] * rs2;
+          a.Q[(size_t)par * H * H + (size_t)k * H + e] = q;
+          a.Qt[(size_t)par * H * H + (size_t)e * H + k] = q;
+        }
+      }
+    // the constant mode is symmetric: the largest even eigenvalue
+    a.null_idx = (int)(std::max_element(a.lam.begin(), a.lam.begin() + H) - a.lam.begin());
+    a.lam[a.null_idx] = 0.0;  // K annihilates constants: the exact eigenvalue is 0
+    return true;
   }
   jacobi_eigen(n, M, a.Q, a.lam);
   a.null_idx = (int)(std::max_element(a.lam.begin(), a.lam.end()) - a.lam.begin());
@@ -479,7 +522,8 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
     A.dd = base + offs[a][7];
     A.lam = base + offs[a][8];
     A.c = base + offs[a][9];
-    const size_t nn = (size_t)ns[a] * ns[a];
+    const size_t nn = ax[a].Q.size();
+    c->split[a] = ax[a].split ? 1 : 0;
     if (hipMalloc(&c->Qf[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Q");
     if (hipMalloc(&c->Qt[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Qt");
     if (hipMemcpy(c->Qf[a], ax[a].Q.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||

@@ -151,13 +151,24 @@ hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out) {
   double* Bf = c->cellB;
   hipStream_t s = c->stream;
   hipError_t e;
-  // forward: x, y, z (+ divide)
-  if ((e = gemm<EPI_NONE>(A, nx, 0, c->Qf[0], nx, 0, Bf, nx, 0, ny * nz, nx, nx, 1, 1, ep, s))) return e;
-  if ((e = gemm<EPI_NONE>(c->Qt[1], ny, 0, Bf, nx, plane, A, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
-  if ((e = gemm<EPI_DIVIDE>(c->Qt[2], nz, 0, A, plane, 0, Bf, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
+  // forward: x, y, z (+ divide); mirror-symmetric axes use the half-size split
+  if (c->split[0]) e = launch_fd_split_pass(c, 0, false, 0, A, Bf);
+  else e = gemm<EPI_NONE>(A, nx, 0, c->Qf[0], nx, 0, Bf, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
+  if (e) return e;
+  if (c->split[1]) e = launch_fd_split_pass(c, 1, false, 0, Bf, A);
+  else e = gemm<EPI_NONE>(c->Qt[1], ny, 0, Bf, nx, plane, A, nx, plane, ny, nx, ny, nz, 0, ep, s);
+  if (e) return e;
+  if (c->split[2]) e = launch_fd_split_pass(c, 2, false, 1, A, Bf);
+  else e = gemm<EPI_DIVIDE>(c->Qt[2], nz, 0, A, plane, 0, Bf, plane, 0, nz, (int)plane, nz, 1, 0, ep, s);
+  if (e) return e;
   // inverse: z, y, x (+ S^-1)
-  if ((e = gemm<EPI_NONE>(c->Qf[2], nz, 0, Bf, plane, 0, A, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
-  if ((e = gemm<EPI_NONE>(c->Qf[1], ny, 0, A, nx, plane, Bf, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
+  if (c->split[2]) e = launch_fd_split_pass(c, 2, true, 0, Bf, A);
+  else e = gemm<EPI_NONE>(c->Qf[2], nz, 0, Bf, plane, 0, A, plane, 0, nz, (int)plane, nz, 1, 0, ep, s);
+  if (e) return e;
+  if (c->split[1]) e = launch_fd_split_pass(c, 1, true, 0, A, Bf);
+  else e = gemm<EPI_NONE>(c->Qf[1], ny, 0, A, nx, plane, Bf, nx, plane, ny, nx, ny, nz, 0, ep, s);
+  if (e) return e;
+  if (c->split[0]) return launch_fd_split_pass(c, 0, true, 2, Bf, out);
   return gemm<EPI_ISQ>(Bf, nx, 0, c->Qt[0], nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
 }
 

@@ -1,0 +1,296 @@
+// Even/odd split of the fast-diagonalization transforms for mirror-symmetric
+// axes (h_i = h_{N-1-i}, N even; both grids of the workloads are).
+//
+// A persymmetric M has eigenvectors that are either symmetric or
+// antisymmetric about the midpoint, q = [w; +-J w] / sqrt(2), with w the
+// eigenvectors of the half-size matrices M_11 +- M_{H-1,H} e e^T (H = N/2).
+// The transform of f along the axis then needs only half-size products:
+//   forward:  c_even = Qe^T (f_lo + J f_hi),  c_odd = Qo^T (f_lo - J f_hi)
+//   inverse:  t = Qe c_even, u = Qo c_odd,   f_lo = t + u, J f_hi = t - u
+// (Qe, Qo hold the first halves of the full unit eigenvectors), i.e. 6N
+// instead of 12N flop per cell for the three axes of one Poisson solve.  The
+// butterflies are fused into the operand loads (forward) and the epilogue
+// (inverse); every product runs on v_mfma_f64_16x16x4.
+//
+// Coefficient order along a split axis: [H even modes | H odd modes].
+#include "kv_internal.h"
+
+namespace kv {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+enum { RIGHT_FWD = 0, RIGHT_INV = 1, LEFT_FWD = 2, LEFT_INV = 3 };
+enum { EPI_NONE = 0, EPI_DIVIDE = 1, EPI_ISQ = 2 };
+
+struct SplitEpi {
+  const double *lx, *ly, *lz;
+  const double *isx, *isy, *isz;
+  int nx, ny;
+  int64_t null3;
+};
+
+struct SplitArgs {
+  const double* in;
+  double* out;
+  const double* Qs;   // [2][H][H]: Qs[par][k][e]
+  const double* QsT;  // [2][H][H]: QsT[par][e][k]
+  int N, H;
+  int64_t P;          // LEFT: contiguous length of a line (plane or row); RIGHT: unused
+  int64_t R;          // RIGHT: number of rows; LEFT: unused
+  int64_t bstride;    // LEFT: batch stride (y pass); 0 otherwise
+  int batch;
+  int mtiles, ntiles;
+};
+
+constexpr int BM = 64, BN = 64, BK = 16, LDP = 64 + 2;
+
+// One 64x64 output tile.  RIGHT kinds: m = row, n = mode (fwd) or position
+// (inv).  LEFT kinds: m = mode (fwd) or position (inv), n = line position p.
+// The inverse kinds keep two accumulator sets (even -> t, odd -> u).
+template <int KIND, int EPI>
+__global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep) {
+  constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
+  constexpr bool RIGHT = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  constexpr int NS = INV ? 2 : 1;  // operand sets
+  __shared__ double As[NS][BK][LDP];
+  __shared__ double Bs[NS][BK][LDP];
+
+  const int pars = INV ? 1 : 2;
+  const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * pars;
+  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (w >= total) return;
+  // tile order: the tiles that share a big-operand tile are adjacent
+  int mt, nt, par;
+  int64_t b;
+  {
+    int64_t t = w;
+    if (RIGHT) {  // big operand = rows (m); modes (n) and parity fastest
+      par = (int)(t % pars);
+      t /= pars;
+      nt = (int)(t % a.ntiles);
+      t /= a.ntiles;
+      mt = (int)(t % a.mtiles);
+      t /= a.mtiles;
+    } else {      // big operand = line positions (n); modes (m) and parity fastest
+      par = (int)(t % pars);
+      t /= pars;
+      mt = (int)(t % a.mtiles);
+      t /= a.mtiles;
+      nt = (int)(t % a.ntiles);
+      t /= a.ntiles;
+    }
+    b = t;
+  }
+  if (INV) par = 0;
+  const int N = a.N, H = a.H;
+  const double sgn = par ? -1.0 : 1.0;
+  const double* in = a.in + (RIGHT ? 0 : b * a.bstride);
+  double* out = a.out + (RIGHT ? 0 : b * a.bstride);
+  const int M = RIGHT ? (int)a.R : H;                 // rows of the output tile space
+  const int64_t NN = RIGHT ? H : a.P;                 // columns of the output tile space
+  const int K = H;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = mt * BM;
+  const int64_t n0 = (int64_t)nt * BN;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int ar = tid >> 2, ak = (tid & 3) * 4;   // A tile element (row, first k)
+  const int bk = tid >> 4, bn = (tid & 15) * 4;  // B tile element (k, first n)
+
+  double ra[NS][4], rb[NS][4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ps = INV ? s : par;  // parity of this operand set
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        // ---- A(m, k)
+        {
+          const int gm = m0 + ar, gk = k0 + ak + q;
+          double v = 0.0;
+          if (gm < M && gk < K) {
+            if (KIND == RIGHT_FWD) {
+              const double* row = in + (int64_t)gm * N;
+              v = row[gk] + sgn * row[N - 1 - gk];
+            } else if (KIND == RIGHT_INV) {
+              v = in[(int64_t)gm * N + ps * H + gk];
+            } else if (KIND == LEFT_FWD) {
+              v = a.QsT[(int64_t)ps * H * H + (int64_t)gm * H + gk];
+            } else {
+              v = a.Qs[(int64_t)ps * H * H + (int64_t)gm * H + gk];
+            }
+          }
+          ra[s][q] = v;
+        }
+        // ---- B(k, n)
+        {
+          const int gk = k0 + bk;
+          const int64_t gn = n0 + bn + q;
+          double v = 0.0;
+          if (gk < K && gn < NN) {
+            if (KIND == RIGHT_FWD) {
+              v = a.Qs[(int64_t)ps * H * H + (int64_t)gk * H + gn];
+            } else if (KIND == RIGHT_INV) {
+              v = a.QsT[(int64_t)ps * H * H + (int64_t)gk * H + gn];
+            } else if (KIND == LEFT_FWD) {
+              v = in[(int64_t)gk * a.P + gn] + sgn * in[(int64_t)(N - 1 - gk) * a.P + gn];
+            } else {
+              v = in[(int64_t)(ps * H + gk) * a.P + gn];
+            }
+          }
+          rb[s][q] = v;
+        }
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        As[s][ak + q][ar] = ra[s][q];
+        Bs[s][bk][bn + q] = rb[s][q];
+      }
+  };
+
+  v4d acc[NS][2][2];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[s][r][c] = v4d{0, 0, 0, 0};
+
+  fetch(0);
+  stash();
+  __syncthreads();
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) fetch(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const double a0 = As[s][kr][wm + (lane & 15)];
+        const double a1 = As[s][kr][wm + 16 + (lane & 15)];
+        const double b0 = Bs[s][kr][wn + (lane & 15)];
+        const double b1 = Bs[s][kr][wn + 16 + (lane & 15)];
+        acc[s][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[s][0][0], 0, 0, 0);
+        acc[s][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[s][0][1], 0, 0, 0);
+        acc[s][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[s][1][0], 0, 0, 0);
+        acc[s][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[s][1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      stash();
+      __syncthreads();
+    }
+  }
+
+  // D[i][j] of a 16x16 block: lane = j + 16 * (i % 4), element i / 4.
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int64_t gn = n0 + wn + c * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gm = m0 + wm + r * 16 + (lane >> 4) + 4 * q;
+        if (gm >= M || gn >= NN) continue;
+        if (!INV) {
+          double v = acc[0][r][c][q];
+          if (RIGHT) {
+            out[(int64_t)gm * N + par * H + gn] = v;
+          } else {
+            const int mode = par * H + gm;
+            if (EPI == EPI_DIVIDE) {
+              const int aa = (int)(gn % ep.nx), bb = (int)(gn / ep.nx);
+              const int64_t flat = (int64_t)mode * ((int64_t)ep.nx * ep.ny) + gn;
+              v = (flat == ep.null3) ? 0.0 : v / (ep.lz[mode] + ep.ly[bb] + ep.lx[aa]);
+            }
+            out[(int64_t)mode * a.P + gn] = v;
+          }
+        } else {
+          const double t = acc[0][r][c][q], u = acc[1][r][c][q];
+          double lo = t + u, hi = t - u;
+          if (RIGHT) {
+            const int i = (int)gn;
+            if (EPI == EPI_ISQ) {
+              const int j = gm % ep.ny, k = gm / ep.ny;
+              const double syz = ep.isy[j] * ep.isz[k];
+              lo *= ep.isx[i] * syz;
+              hi *= ep.isx[N - 1 - i] * syz;
+            }
+            out[(int64_t)gm * N + i] = lo;
+            out[(int64_t)gm * N + (N - 1 - i)] = hi;
+          } else {
+            const int i = gm;
+            out[(int64_t)i * a.P + gn] = lo;
+            out[(int64_t)(N - 1 - i) * a.P + gn] = hi;
+          }
+        }
+      }
+    }
+}
+
+template <int KIND, int EPI>
+hipError_t launch(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) {
+  SplitArgs a = a0;
+  const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
+  const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  const int64_t M = right ? a.R : a.H;
+  const int64_t NN = right ? a.H : a.P;
+  a.mtiles = (int)((M + BM - 1) / BM);
+  a.ntiles = (int)((NN + BN - 1) / BN);
+  const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
+  const int64_t blocks = ((total + 7) / 8) * 8;
+  fd_split_kernel<KIND, EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// One axis pass of the split transform.  axis 0 (x): RIGHT kinds on rows of
+// length nx; axis 1 (y): LEFT kinds on lines of nx, batched over z; axis 2
+// (z): LEFT kinds on lines of nx*ny.  epi: 0 none, 1 spectral divide (z
+// forward), 2 S^-1 scaling (x inverse).
+hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const double* in, double* out) {
+  const Grid& g = c->g;
+  SplitArgs a{};
+  a.in = in;
+  a.out = out;
+  a.Qs = c->Qf[axis];
+  a.QsT = c->Qt[axis];
+  a.N = g.ax[axis].n;
+  a.H = a.N / 2;
+  a.batch = 1;
+  const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
+  if (axis == 0) {
+    a.R = ny * nz;
+  } else if (axis == 1) {
+    a.P = nx;
+    a.bstride = nx * ny;
+    a.batch = (int)nz;
+  } else {
+    a.P = nx * ny;
+  }
+  SplitEpi ep{g.ax[0].lam, g.ax[1].lam, g.ax[2].lam, g.ax[0].isq, g.ax[1].isq, g.ax[2].isq,
+              g.nx, g.ny, g.null3};
+  hipStream_t s = c->stream;
+  if (axis == 0) {
+    if (!inverse) return launch<RIGHT_FWD, EPI_NONE>(a, ep, s);
+    if (epi == 2) return launch<RIGHT_INV, EPI_ISQ>(a, ep, s);
+    return launch<RIGHT_INV, EPI_NONE>(a, ep, s);
+  }
+  if (!inverse) {
+    if (epi == 1) return launch<LEFT_FWD, EPI_DIVIDE>(a, ep, s);
+    return launch<LEFT_FWD, EPI_NONE>(a, ep, s);
+  }
+  return launch<LEFT_INV, EPI_NONE>(a, ep, s);
+}
+
+}  // namespace kv

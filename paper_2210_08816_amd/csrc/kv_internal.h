@@ -47,6 +47,7 @@ struct kv_ctx {
   double* metric = nullptr;   // all Axis arrays
   double* Qf[3] = {nullptr, nullptr, nullptr};   // Q (n x n row-major): forward uses Q
   double* Qt[3] = {nullptr, nullptr, nullptr};   // Q^T
+  int split[3] = {0, 0, 0};   // 1: mirror-symmetric axis, Qf/Qt hold the even/odd half bases
   double* X0 = nullptr;       // base flow copy
   bool has_base = false;
   double* cellA = nullptr;    // two cell-sized scratch fields for the Poisson solve
@@ -77,6 +78,8 @@ hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* ou
 // p = L^+ (V^-1/2 in) by fast diagonalization; in and out are cell fields.
 // in is overwritten (used as scratch); result in out.
 hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out);
+// One axis pass of the even/odd split transform (mirror-symmetric axes).
+hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const double* in, double* out);
 // y_vel -= G p
 hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* y);
 

@@ -32,15 +32,23 @@ __device__ __forceinline__ double Tat(const double* __restrict__ X, const Grid& 
   return X[g.oT + ((int64_t)k * g.ny + j) * g.nx + i];
 }
 
-// MODE 0: y = J(B) x.  MODE 1: y = N(x) (B must equal x).
-template <int MODE>
-__global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __restrict__ B,
-                                                       const double* __restrict__ x,
-                                                       double* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+// Fields straight from global memory (walls read as zero).
+struct GlobalAcc {
+  const Grid* g;
+  const double* base;
+  const double* pert;
+  __device__ __forceinline__ const double* p(int s) const { return s ? pert : base; }
+  __device__ __forceinline__ double U(int s, int i, int j, int k) const { return Uat(p(s), *g, i, j, k); }
+  __device__ __forceinline__ double V(int s, int i, int j, int k) const { return Vat(p(s), *g, i, j, k); }
+  __device__ __forceinline__ double W(int s, int i, int j, int k) const { return Wat(p(s), *g, i, j, k); }
+  __device__ __forceinline__ double T(int s, int i, int j, int k) const { return Tat(p(s), *g, i, j, k); }
+};
+
+// Every unknown owned by cell (i, j, k).  MODE 0: y = J(base) pert.  MODE 1:
+// y = N(pert) (base = pert).  A supplies the fields: A.U(s, i, j, k) etc. with
+// s = 0 for the base flow and 1 for the perturbation, zero on walls.
+template <int MODE, class Acc>
+__device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j, int k, double* __restrict__ y) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const Axis& AX = g.ax[0];
   const Axis& AY = g.ax[1];
@@ -50,9 +58,9 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 
   // ---------------- u on x-face i ----------------
   if (i >= 1) {
-    const double Uc = Uat(B, g, i, j, k), uc = Uat(x, g, i, j, k);
-    const double Um = Uat(B, g, i - 1, j, k), um = Uat(x, g, i - 1, j, k);
-    const double Up = Uat(B, g, i + 1, j, k), up = Uat(x, g, i + 1, j, k);
+    const double Uc = A.U(0, i, j, k), uc = A.U(1, i, j, k);
+    const double Um = A.U(0, i - 1, j, k), um = A.U(1, i - 1, j, k);
+    const double Up = A.U(0, i + 1, j, k), up = A.U(1, i + 1, j, k);
     // x: centre fluxes (u_bar)^2 at cells i (east) and i-1 (west)
     double adv = (0.5 * (Uc + Up) * (uc + up) - 0.5 * (Um + Uc) * (um + uc)) * AX.id[i];
     const double xl = AX.wlo[i], xh = AX.whi[i];
@@ -60,18 +68,18 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
     double fS = 0.0, fN = 0.0, uS = 0.0, uN = 0.0;
     if (j > 0) {
       const double yl = AY.wlo[j], yh = AY.whi[j];
-      const double UB = Uat(B, g, i, j - 1, k);
-      uS = Uat(x, g, i, j - 1, k);
-      const double Vh = xl * Vat(B, g, i - 1, j, k) + xh * Vat(B, g, i, j, k);
-      const double vh = xl * Vat(x, g, i - 1, j, k) + xh * Vat(x, g, i, j, k);
+      const double UB = A.U(0, i, j - 1, k);
+      uS = A.U(1, i, j - 1, k);
+      const double Vh = xl * A.V(0, i - 1, j, k) + xh * A.V(0, i, j, k);
+      const double vh = xl * A.V(1, i - 1, j, k) + xh * A.V(1, i, j, k);
       fS = Vh * (yl * uS + yh * uc) + vh * (yl * UB + yh * Uc);
     }
     if (j < ny - 1) {
       const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
-      const double UB = Uat(B, g, i, j + 1, k);
-      uN = Uat(x, g, i, j + 1, k);
-      const double Vh = xl * Vat(B, g, i - 1, j + 1, k) + xh * Vat(B, g, i, j + 1, k);
-      const double vh = xl * Vat(x, g, i - 1, j + 1, k) + xh * Vat(x, g, i, j + 1, k);
+      const double UB = A.U(0, i, j + 1, k);
+      uN = A.U(1, i, j + 1, k);
+      const double Vh = xl * A.V(0, i - 1, j + 1, k) + xh * A.V(0, i, j + 1, k);
+      const double vh = xl * A.V(1, i - 1, j + 1, k) + xh * A.V(1, i, j + 1, k);
       fN = Vh * (yl * uc + yh * uN) + vh * (yl * Uc + yh * UB);
     }
     adv += (fN - fS) * AY.ih[j];
@@ -79,18 +87,18 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
     double fB = 0.0, fT = 0.0, uB = 0.0, uT = 0.0;
     if (k > 0) {
       const double zl = AZ.wlo[k], zh = AZ.whi[k];
-      const double UB = Uat(B, g, i, j, k - 1);
-      uB = Uat(x, g, i, j, k - 1);
-      const double Wh = xl * Wat(B, g, i - 1, j, k) + xh * Wat(B, g, i, j, k);
-      const double wh = xl * Wat(x, g, i - 1, j, k) + xh * Wat(x, g, i, j, k);
+      const double UB = A.U(0, i, j, k - 1);
+      uB = A.U(1, i, j, k - 1);
+      const double Wh = xl * A.W(0, i - 1, j, k) + xh * A.W(0, i, j, k);
+      const double wh = xl * A.W(1, i - 1, j, k) + xh * A.W(1, i, j, k);
       fB = Wh * (zl * uB + zh * uc) + wh * (zl * UB + zh * Uc);
     }
     if (k < nz - 1) {
       const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
-      const double UB = Uat(B, g, i, j, k + 1);
-      uT = Uat(x, g, i, j, k + 1);
-      const double Wh = xl * Wat(B, g, i - 1, j, k + 1) + xh * Wat(B, g, i, j, k + 1);
-      const double wh = xl * Wat(x, g, i - 1, j, k + 1) + xh * Wat(x, g, i, j, k + 1);
+      const double UB = A.U(0, i, j, k + 1);
+      uT = A.U(1, i, j, k + 1);
+      const double Wh = xl * A.W(0, i - 1, j, k + 1) + xh * A.W(0, i, j, k + 1);
+      const double wh = xl * A.W(1, i - 1, j, k + 1) + xh * A.W(1, i, j, k + 1);
       fT = Wh * (zl * uc + zh * uT) + wh * (zl * Uc + zh * UB);
     }
     adv += (fT - fB) * AZ.ih[k];
@@ -102,44 +110,44 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 
   // ---------------- v on y-face j ----------------
   if (j >= 1) {
-    const double Vc = Vat(B, g, i, j, k), vc = Vat(x, g, i, j, k);
-    const double Vm = Vat(B, g, i, j - 1, k), vm = Vat(x, g, i, j - 1, k);
-    const double Vp = Vat(B, g, i, j + 1, k), vp = Vat(x, g, i, j + 1, k);
+    const double Vc = A.V(0, i, j, k), vc = A.V(1, i, j, k);
+    const double Vm = A.V(0, i, j - 1, k), vm = A.V(1, i, j - 1, k);
+    const double Vp = A.V(0, i, j + 1, k), vp = A.V(1, i, j + 1, k);
     double adv = (0.5 * (Vc + Vp) * (vc + vp) - 0.5 * (Vm + Vc) * (vm + vc)) * AY.id[j];
     const double yl = AY.wlo[j], yh = AY.whi[j];
     double fW = 0.0, fE = 0.0, vW = 0.0, vE = 0.0;
     if (i > 0) {
       const double xl = AX.wlo[i], xh = AX.whi[i];
-      const double VB = Vat(B, g, i - 1, j, k);
-      vW = Vat(x, g, i - 1, j, k);
-      const double Uh = yl * Uat(B, g, i, j - 1, k) + yh * Uat(B, g, i, j, k);
-      const double uh = yl * Uat(x, g, i, j - 1, k) + yh * Uat(x, g, i, j, k);
+      const double VB = A.V(0, i - 1, j, k);
+      vW = A.V(1, i - 1, j, k);
+      const double Uh = yl * A.U(0, i, j - 1, k) + yh * A.U(0, i, j, k);
+      const double uh = yl * A.U(1, i, j - 1, k) + yh * A.U(1, i, j, k);
       fW = Uh * (xl * vW + xh * vc) + uh * (xl * VB + xh * Vc);
     }
     if (i < nx - 1) {
       const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
-      const double VB = Vat(B, g, i + 1, j, k);
-      vE = Vat(x, g, i + 1, j, k);
-      const double Uh = yl * Uat(B, g, i + 1, j - 1, k) + yh * Uat(B, g, i + 1, j, k);
-      const double uh = yl * Uat(x, g, i + 1, j - 1, k) + yh * Uat(x, g, i + 1, j, k);
+      const double VB = A.V(0, i + 1, j, k);
+      vE = A.V(1, i + 1, j, k);
+      const double Uh = yl * A.U(0, i + 1, j - 1, k) + yh * A.U(0, i + 1, j, k);
+      const double uh = yl * A.U(1, i + 1, j - 1, k) + yh * A.U(1, i + 1, j, k);
       fE = Uh * (xl * vc + xh * vE) + uh * (xl * Vc + xh * VB);
     }
     adv += (fE - fW) * AX.ih[i];
     double fB = 0.0, fT = 0.0, vB = 0.0, vT = 0.0;
     if (k > 0) {
       const double zl = AZ.wlo[k], zh = AZ.whi[k];
-      const double VB = Vat(B, g, i, j, k - 1);
-      vB = Vat(x, g, i, j, k - 1);
-      const double Wh = yl * Wat(B, g, i, j - 1, k) + yh * Wat(B, g, i, j, k);
-      const double wh = yl * Wat(x, g, i, j - 1, k) + yh * Wat(x, g, i, j, k);
+      const double VB = A.V(0, i, j, k - 1);
+      vB = A.V(1, i, j, k - 1);
+      const double Wh = yl * A.W(0, i, j - 1, k) + yh * A.W(0, i, j, k);
+      const double wh = yl * A.W(1, i, j - 1, k) + yh * A.W(1, i, j, k);
       fB = Wh * (zl * vB + zh * vc) + wh * (zl * VB + zh * Vc);
     }
     if (k < nz - 1) {
       const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
-      const double VB = Vat(B, g, i, j, k + 1);
-      vT = Vat(x, g, i, j, k + 1);
-      const double Wh = yl * Wat(B, g, i, j - 1, k + 1) + yh * Wat(B, g, i, j, k + 1);
-      const double wh = yl * Wat(x, g, i, j - 1, k + 1) + yh * Wat(x, g, i, j, k + 1);
+      const double VB = A.V(0, i, j, k + 1);
+      vT = A.V(1, i, j, k + 1);
+      const double Wh = yl * A.W(0, i, j - 1, k + 1) + yh * A.W(0, i, j, k + 1);
+      const double wh = yl * A.W(1, i, j - 1, k + 1) + yh * A.W(1, i, j, k + 1);
       fT = Wh * (zl * vc + zh * vT) + wh * (zl * Vc + zh * VB);
     }
     adv += (fT - fB) * AZ.ih[k];
@@ -151,72 +159,72 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 
   // ---------------- w on z-face k ----------------
   if (k >= 1) {
-    const double Wc = Wat(B, g, i, j, k), wc = Wat(x, g, i, j, k);
-    const double Wm = Wat(B, g, i, j, k - 1), wm = Wat(x, g, i, j, k - 1);
-    const double Wp = Wat(B, g, i, j, k + 1), wp = Wat(x, g, i, j, k + 1);
+    const double Wc = A.W(0, i, j, k), wc = A.W(1, i, j, k);
+    const double Wm = A.W(0, i, j, k - 1), wm = A.W(1, i, j, k - 1);
+    const double Wp = A.W(0, i, j, k + 1), wp = A.W(1, i, j, k + 1);
     double adv = (0.5 * (Wc + Wp) * (wc + wp) - 0.5 * (Wm + Wc) * (wm + wc)) * AZ.id[k];
     const double zl = AZ.wlo[k], zh = AZ.whi[k];
     double fW = 0.0, fE = 0.0, wW = 0.0, wE = 0.0;
     if (i > 0) {
       const double xl = AX.wlo[i], xh = AX.whi[i];
-      const double WB = Wat(B, g, i - 1, j, k);
-      wW = Wat(x, g, i - 1, j, k);
-      const double Uh = zl * Uat(B, g, i, j, k - 1) + zh * Uat(B, g, i, j, k);
-      const double uh = zl * Uat(x, g, i, j, k - 1) + zh * Uat(x, g, i, j, k);
+      const double WB = A.W(0, i - 1, j, k);
+      wW = A.W(1, i - 1, j, k);
+      const double Uh = zl * A.U(0, i, j, k - 1) + zh * A.U(0, i, j, k);
+      const double uh = zl * A.U(1, i, j, k - 1) + zh * A.U(1, i, j, k);
       fW = Uh * (xl * wW + xh * wc) + uh * (xl * WB + xh * Wc);
     }
     if (i < nx - 1) {
       const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
-      const double WB = Wat(B, g, i + 1, j, k);
-      wE = Wat(x, g, i + 1, j, k);
-      const double Uh = zl * Uat(B, g, i + 1, j, k - 1) + zh * Uat(B, g, i + 1, j, k);
-      const double uh = zl * Uat(x, g, i + 1, j, k - 1) + zh * Uat(x, g, i + 1, j, k);
+      const double WB = A.W(0, i + 1, j, k);
+      wE = A.W(1, i + 1, j, k);
+      const double Uh = zl * A.U(0, i + 1, j, k - 1) + zh * A.U(0, i + 1, j, k);
+      const double uh = zl * A.U(1, i + 1, j, k - 1) + zh * A.U(1, i + 1, j, k);
       fE = Uh * (xl * wc + xh * wE) + uh * (xl * Wc + xh * WB);
     }
     adv += (fE - fW) * AX.ih[i];
     double fS = 0.0, fN = 0.0, wS = 0.0, wN = 0.0;
     if (j > 0) {
       const double yl = AY.wlo[j], yh = AY.whi[j];
-      const double WB = Wat(B, g, i, j - 1, k);
-      wS = Wat(x, g, i, j - 1, k);
-      const double Vh = zl * Vat(B, g, i, j, k - 1) + zh * Vat(B, g, i, j, k);
-      const double vh = zl * Vat(x, g, i, j, k - 1) + zh * Vat(x, g, i, j, k);
+      const double WB = A.W(0, i, j - 1, k);
+      wS = A.W(1, i, j - 1, k);
+      const double Vh = zl * A.V(0, i, j, k - 1) + zh * A.V(0, i, j, k);
+      const double vh = zl * A.V(1, i, j, k - 1) + zh * A.V(1, i, j, k);
       fS = Vh * (yl * wS + yh * wc) + vh * (yl * WB + yh * Wc);
     }
     if (j < ny - 1) {
       const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
-      const double WB = Wat(B, g, i, j + 1, k);
-      wN = Wat(x, g, i, j + 1, k);
-      const double Vh = zl * Vat(B, g, i, j + 1, k - 1) + zh * Vat(B, g, i, j + 1, k);
-      const double vh = zl * Vat(x, g, i, j + 1, k - 1) + zh * Vat(x, g, i, j + 1, k);
+      const double WB = A.W(0, i, j + 1, k);
+      wN = A.W(1, i, j + 1, k);
+      const double Vh = zl * A.V(0, i, j + 1, k - 1) + zh * A.V(0, i, j + 1, k);
+      const double vh = zl * A.V(1, i, j + 1, k - 1) + zh * A.V(1, i, j + 1, k);
       fN = Vh * (yl * wc + yh * wN) + vh * (yl * Wc + yh * WB);
     }
     adv += (fN - fS) * AY.ih[j];
     double lap = ((wp - wc) * AZ.ih[k] - (wc - wm) * AZ.ih[k - 1]) * AZ.id[k];
     lap += ((wE - wc) * AX.id[i + 1] - (wc - wW) * AX.id[i]) * AX.ih[i];
     lap += ((wN - wc) * AY.id[j + 1] - (wc - wS) * AY.id[j]) * AY.ih[j];
-    const double buoy = zl * Tat(x, g, i, j, k - 1) + zh * Tat(x, g, i, j, k);
+    const double buoy = zl * A.T(1, i, j, k - 1) + zh * A.T(1, i, j, k);
     y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = -s * adv + g.nu * lap + g.beta * buoy;
   }
 
   // ---------------- T at the cell centre ----------------
   {
-    const double Tb = Tat(B, g, i, j, k), tc = Tat(x, g, i, j, k);
+    const double Tb = A.T(0, i, j, k), tc = A.T(1, i, j, k);
     double adv = 0.0, lap = 0.0;
     // x
     {
       double fW = 0.0, fE = 0.0;
-      const double tW = (i > 0) ? Tat(x, g, i - 1, j, k) : TW;
-      const double tE = (i < nx - 1) ? Tat(x, g, i + 1, j, k) : TE;
+      const double tW = (i > 0) ? A.T(1, i - 1, j, k) : TW;
+      const double tE = (i < nx - 1) ? A.T(1, i + 1, j, k) : TE;
       if (i > 0) {
         const double xl = AX.wlo[i], xh = AX.whi[i];
-        const double Th = xl * Tat(B, g, i - 1, j, k) + xh * Tb;
-        fW = Uat(B, g, i, j, k) * (xl * tW + xh * tc) + Uat(x, g, i, j, k) * Th;
+        const double Th = xl * A.T(0, i - 1, j, k) + xh * Tb;
+        fW = A.U(0, i, j, k) * (xl * tW + xh * tc) + A.U(1, i, j, k) * Th;
       }
       if (i < nx - 1) {
         const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
-        const double Th = xl * Tb + xh * Tat(B, g, i + 1, j, k);
-        fE = Uat(B, g, i + 1, j, k) * (xl * tc + xh * tE) + Uat(x, g, i + 1, j, k) * Th;
+        const double Th = xl * Tb + xh * A.T(0, i + 1, j, k);
+        fE = A.U(0, i + 1, j, k) * (xl * tc + xh * tE) + A.U(1, i + 1, j, k) * Th;
       }
       adv += (fE - fW) * AX.ih[i];
       lap += ((tE - tc) * AX.id[i + 1] - (tc - tW) * AX.id[i]) * AX.ih[i];
@@ -226,16 +234,16 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
       double fS = 0.0, fN = 0.0, gS = 0.0, gN = 0.0;
       if (j > 0) {
         const double yl = AY.wlo[j], yh = AY.whi[j];
-        const double tS = Tat(x, g, i, j - 1, k);
-        const double Th = yl * Tat(B, g, i, j - 1, k) + yh * Tb;
-        fS = Vat(B, g, i, j, k) * (yl * tS + yh * tc) + Vat(x, g, i, j, k) * Th;
+        const double tS = A.T(1, i, j - 1, k);
+        const double Th = yl * A.T(0, i, j - 1, k) + yh * Tb;
+        fS = A.V(0, i, j, k) * (yl * tS + yh * tc) + A.V(1, i, j, k) * Th;
         gS = (tc - tS) * AY.id[j];
       }
       if (j < ny - 1) {
         const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
-        const double tN = Tat(x, g, i, j + 1, k);
-        const double Th = yl * Tb + yh * Tat(B, g, i, j + 1, k);
-        fN = Vat(B, g, i, j + 1, k) * (yl * tc + yh * tN) + Vat(x, g, i, j + 1, k) * Th;
+        const double tN = A.T(1, i, j + 1, k);
+        const double Th = yl * Tb + yh * A.T(0, i, j + 1, k);
+        fN = A.V(0, i, j + 1, k) * (yl * tc + yh * tN) + A.V(1, i, j + 1, k) * Th;
         gN = (tN - tc) * AY.id[j + 1];
       }
       adv += (fN - fS) * AY.ih[j];
@@ -246,22 +254,152 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
       double fB = 0.0, fT = 0.0, gB = 0.0, gT = 0.0;
       if (k > 0) {
         const double zl = AZ.wlo[k], zh = AZ.whi[k];
-        const double tB = Tat(x, g, i, j, k - 1);
-        const double Th = zl * Tat(B, g, i, j, k - 1) + zh * Tb;
-        fB = Wat(B, g, i, j, k) * (zl * tB + zh * tc) + Wat(x, g, i, j, k) * Th;
+        const double tB = A.T(1, i, j, k - 1);
+        const double Th = zl * A.T(0, i, j, k - 1) + zh * Tb;
+        fB = A.W(0, i, j, k) * (zl * tB + zh * tc) + A.W(1, i, j, k) * Th;
         gB = (tc - tB) * AZ.id[k];
       }
       if (k < nz - 1) {
         const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
-        const double tT = Tat(x, g, i, j, k + 1);
-        const double Th = zl * Tb + zh * Tat(B, g, i, j, k + 1);
-        fT = Wat(B, g, i, j, k + 1) * (zl * tc + zh * tT) + Wat(x, g, i, j, k + 1) * Th;
+        const double tT = A.T(1, i, j, k + 1);
+        const double Th = zl * Tb + zh * A.T(0, i, j, k + 1);
+        fT = A.W(0, i, j, k + 1) * (zl * tc + zh * tT) + A.W(1, i, j, k + 1) * Th;
         gT = (tT - tc) * AZ.id[k + 1];
       }
       adv += (fT - fB) * AZ.ih[k];
       lap += (gT - gB) * AZ.ih[k];
     }
     y[g.oT + ((int64_t)k * ny + j) * nx + i] = -s * adv + g.kappa * lap;
+  }
+}
+
+
+// One thread per cell, fields from global memory (kept for very small grids).
+template <int MODE>
+__global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __restrict__ B,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  GlobalAcc A{&g, B, x};
+  point<MODE>(g, A, i, j, k, y);
+}
+
+// ---- 2.5-D tiled version ---------------------------------------------------------
+// A block owns a TX x TY tile of (x, y) columns and a chunk of KC z-planes.  It
+// marches up in z keeping three planes (k-1, k, k+1) of every field, with a
+// one-cell halo in x and y, in an LDS ring; each plane is loaded once, as
+// coalesced x-rows, and every output row is written once.
+constexpr int TX = 64, TY = 4, KC = 32;
+constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
+
+template <int NF>
+struct TileAcc {
+  const double* lds;  // [3 slots][NF fields][PY][PX]
+  int i0, j0;
+  __device__ __forceinline__ double at(int f, int i, int j, int k) const {
+    const int slot = (k + 3) % 3;
+    return lds[(slot * NF + f) * PLANE + (j - j0 + 1) * PX + (i - i0 + 1)];
+  }
+  // field index: (component, s) -> 2*comp + s for NF = 8, comp for NF = 4
+  __device__ __forceinline__ int fi(int comp, int s) const { return NF == 8 ? 2 * comp + s : comp; }
+  __device__ __forceinline__ double U(int s, int i, int j, int k) const { return at(fi(0, s), i, j, k); }
+  __device__ __forceinline__ double V(int s, int i, int j, int k) const { return at(fi(1, s), i, j, k); }
+  __device__ __forceinline__ double W(int s, int i, int j, int k) const { return at(fi(2, s), i, j, k); }
+  __device__ __forceinline__ double T(int s, int i, int j, int k) const { return at(fi(3, s), i, j, k); }
+};
+
+// Plane kp of every field, fetched into registers (each thread owns the tile
+// entries tid and tid + 256 of every field; all loads are issued before any
+// is used), then stored into the plane's ring slot.  Outside the domain and
+// on walls the value is zero.
+constexpr int PER = (PLANE + 255) / 256;
+
+template <int NF>
+struct PlaneRegs {
+  double v[NF][PER];
+};
+
+template <int NF>
+__device__ __forceinline__ void fetch_plane(const Grid& g, const double* __restrict__ B, const double* __restrict__ x,
+                                            int i0, int j0, int kp, PlaneRegs<NF>& R) {
+  const bool kin = (kp >= 0 && kp < g.nz);
+  const bool win = (kp >= 0 && kp <= g.nz);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int r = threadIdx.x + 256 * q;
+    const int i = i0 - 1 + r % PX, j = j0 - 1 + r / PX;
+    const bool rin = r < PLANE;
+    const bool iin = i >= 0 && i < g.nx, jin = j >= 0 && j < g.ny;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int comp = NF == 8 ? f >> 1 : f;
+      const double* src = (NF == 8 && (f & 1) == 0) ? B : x;
+      double v = 0.0;
+      if (comp == 0) {
+        if (rin && kin && jin) v = Uat(src, g, i, j, kp);
+      } else if (comp == 1) {
+        if (rin && kin && iin) v = Vat(src, g, i, j, kp);
+      } else if (comp == 2) {
+        if (rin && win && iin && jin) v = Wat(src, g, i, j, kp);
+      } else {
+        if (rin && kin && iin && jin) v = Tat(src, g, i, j, kp);
+      }
+      R.v[f][q] = v;
+    }
+  }
+}
+
+template <int NF>
+__device__ __forceinline__ void store_plane(double* lds, int kp, const PlaneRegs<NF>& R) {
+  const int slot = (kp + 3) % 3;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int r = threadIdx.x + 256 * q;
+    if (r < PLANE) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) lds[(slot * NF + f) * PLANE + r] = R.v[f][q];
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const double* __restrict__ B,
+                                                             const double* __restrict__ x, double* __restrict__ y,
+                                                             int tiles_x, int tiles_y, int chunks) {
+  constexpr int NF = MODE ? 4 : 8;
+  extern __shared__ double lds[];
+  // XCD-aware order: blocks are dealt round-robin over 8 XCDs; give each XCD a
+  // contiguous range of tiles so y-neighbouring tiles share an L2.
+  const int64_t total = (int64_t)tiles_x * tiles_y * chunks;
+  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (w >= total) return;
+  const int bx = (int)(w % tiles_x);
+  const int by = (int)((w / tiles_x) % tiles_y);
+  const int bz = (int)(w / ((int64_t)tiles_x * tiles_y));
+  const int i0 = bx * TX, j0 = by * TY, k0 = bz * KC;
+  const int k1 = min(g.nz, k0 + KC);
+  const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
+  TileAcc<NF> A{lds, i0, j0};
+  PlaneRegs<NF> R;
+  fetch_plane<NF>(g, B, x, i0, j0, k0 - 1, R);
+  store_plane<NF>(lds, k0 - 1, R);
+  fetch_plane<NF>(g, B, x, i0, j0, k0, R);
+  store_plane<NF>(lds, k0, R);
+  fetch_plane<NF>(g, B, x, i0, j0, k0 + 1, R);
+  store_plane<NF>(lds, k0 + 1, R);
+  __syncthreads();
+  for (int k = k0; k < k1; ++k) {
+    // software pipeline: plane k+2 is in flight while plane k is computed
+    const bool more = k + 1 < k1;
+    if (more) fetch_plane<NF>(g, B, x, i0, j0, k + 2, R);
+    if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, y);
+    __syncthreads();
+    if (more) store_plane<NF>(lds, k + 2, R);   // slot of plane k-1, no longer read
+    __syncthreads();
   }
 }
 
@@ -397,10 +535,23 @@ inline dim3 cell_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) 
 
 hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode) {
   const Grid& g = c->g;
-  if (mode == 0)
-    operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
-  else
-    operator_kernel<1><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, x, x, y);
+  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, ch = (g.nz + KC - 1) / KC;
+  const int64_t total = (int64_t)tx * ty * ch;
+  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
+  const size_t lds0 = 3 * 8 * PLANE * sizeof(double), lds1 = 3 * 4 * PLANE * sizeof(double);
+  // the 8-field ring needs more than the default 64 KB of dynamic LDS
+  static int lds_ok = -1;
+  if (lds_ok < 0)
+    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&operator_tiled_kernel<0>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds0) == hipSuccess;
+  if (mode == 0) {
+    if (lds_ok)
+      operator_tiled_kernel<0><<<blocks, 256, lds0, c->stream>>>(g, X0, x, y, tx, ty, ch);
+    else
+      operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
+  } else {
+    operator_tiled_kernel<1><<<blocks, 256, lds1, c->stream>>>(g, x, x, y, tx, ty, ch);
+  }
   return hipGetLastError();
 }
 

@@ -45,8 +45,14 @@ def faces_clustered(n: int) -> np.ndarray:
 
 
 def _mirror(x: np.ndarray) -> np.ndarray:
+    """Make the faces exactly mirror-symmetric in floating point.
+
+    The lower half is rounded to multiples of 2^-53, so 1 - x_i is exact and
+    every width h_i = x_{i+1} - x_i equals its mirror image h_{N-1-i}
+    bit for bit (both differences are exact).  The change is below 1.2e-16.
+    """
     n = len(x) - 1
-    x = x.copy()
+    x = np.round(x * 2.0 ** 53) / 2.0 ** 53
     x[0], x[n] = 0.0, 1.0
     for i in range(n // 2 + 1, n + 1):
         x[i] = 1.0 - x[n - i]
