@@ -34,7 +34,25 @@ def log(*a):
 def algorithmic_bytes_per_cell_fp64():
     """HBM bytes per cell of one projected Krylov vector if every phase makes
     one pass: stencil 104, 6 transform passes 96, correction 56."""
-    return {"stencil": 104.0, "fd": 96.0, "correction": 56.0, "divergence": 32.0}
+    return {"stencil": 104.0, "stencil_io": 96.0, "fd": 96.0, "correction": 56.0, "divergence": 32.0}
+
+
+def profiled_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "projected_jacobian_cube256_fp64_traffic.md")
+    try:
+        text = open(path).read()
+        src = open(os.path.join(ROOT, "paper_2210_08816_amd", "csrc", source), "rb").read()
+    except OSError:
+        return None
+    t = re.search(r"traffic_bytes_per_launch\[%s\]: (\d+)" % re.escape(kernel), text)
+    h = re.search(r"source_sha256\[%s\]: ([0-9a-f]+)" % re.escape(kernel), text)
+    if not t or not h or h.group(1) != hashlib.sha256(src).hexdigest():
+        return None
+    return int(t.group(1))
 
 
 def cpu_baseline(g_args, X0, x0, y_gpu):
@@ -121,11 +139,24 @@ def main():
     # per line of N cells, i.e. N flop per cell (the grid is mirror-symmetric)
     fd_flops = 1.0 * spec["n"] * n_cells
     achieved = fd_flops / (fd_launch_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "fd_gemm_kernel (one axis transform of the FP64 fast-diagonalization solve)",
-                "launch_ms": round(fd_launch_ms, 5)}
+    roof_fd = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+               "traffic": profiled_traffic("fd_split_kernel", "kv_fd_split.hip"),
+               "kernel": "fd_split_kernel (one axis pass of the FP64 fast-diagonalization transforms)",
+               "launch_ms": round(fd_launch_ms, 5), "launches_per_step": 6}
     bpc = algorithmic_bytes_per_cell_fp64()
+    st_bytes = bpc["stencil_io"] * n_cells
+    st_ach = st_bytes / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else 0.0
+    roof_st = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(st_ach / HBM_PEAK_GBS, 4),
+               "traffic": profiled_traffic("operator_tiled_kernel", "kv_stencil.hip"),
+               "kernel": "operator_tiled_kernel (J x stencil)", "launch_ms": round(per_vec[0], 5),
+               "launches_per_step": 1}
+    # the dominant kernel family by device time per step
+    if per_vec[2] >= per_vec[0]:
+        roofline, secondary = roof_fd, roof_st
+    else:
+        roofline, secondary = roof_st, roof_fd
     phases = {"stencil_ms": per_vec[0], "divergence_ms": per_vec[1], "fd_ms": per_vec[2],
               "correction_ms": per_vec[3],
               "stencil_GBs": bpc["stencil"] * n_cells / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else None,
@@ -148,6 +179,7 @@ def main():
         "config": {"workload": args.workload, "grid": f"{spec['n']}^3 {spec['grid']}", "Gr": spec["Gr"],
                    "Pr": spec["Pr"], "form": "fp64", "resident_batch": B, "unknowns": n},
         "roofline": roofline,
+        "roofline_secondary": secondary,
         "step_roofline_frac": round(step_roof_frac, 4),
         "phases_ms_per_vector": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in phases.items()},
         "device": torch.cuda.get_device_name(0),
