@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(const double* __restrict__
         double v = (*accs[t])[q];
         if (EPI == EPI_DIVIDE) {
           // C is (nz x nx*ny): m = z-mode c, n = b * nx + a
-          const int a = gn % ep.nx, bb = gn / ep.nx;
+          const int bb = gn / ep.nx, a = gn - bb * ep.nx;
           const int64_t flat = (int64_t)gm * ((int64_t)ep.nx * ep.ny) + gn;
           const double den = ep.lz[gm] + ep.ly[bb] + ep.lx[a];
           v = (flat == ep.null3) ? 0.0 : v / den;

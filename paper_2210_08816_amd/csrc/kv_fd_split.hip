@@ -13,6 +13,8 @@
 // (inverse); every product runs on v_mfma_f64_16x16x4.
 //
 // Coefficient order along a split axis: [H even modes | H odd modes].
+#include <cstdlib>
+
 #include "kv_internal.h"
 
 namespace kv {
@@ -43,18 +45,21 @@ struct SplitArgs {
   int mtiles, ntiles;
 };
 
-constexpr int BM = 64, BN = 64, BK = 16, LDP = 64 + 2;
+constexpr int BK = 16;
 
-// One 64x64 output tile.  RIGHT kinds: m = row, n = mode (fwd) or position
+// One BM x BN output tile (4 waves in a 2 x 2 layout, each wave a
+// (BM/2) x (BN/2) block of 16x16 MFMA accumulators).  RIGHT kinds: m = row, n = mode (fwd) or position
 // (inv).  LEFT kinds: m = mode (fwd) or position (inv), n = line position p.
 // The inverse kinds keep two accumulator sets (even -> t, odd -> u).
-template <int KIND, int EPI>
+template <int KIND, int EPI, int BM, int BN>
 __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep) {
   constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
   constexpr bool RIGHT = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
   constexpr int NS = INV ? 2 : 1;  // operand sets
-  __shared__ double As[NS][BK][LDP];
-  __shared__ double Bs[NS][BK][LDP];
+  constexpr int RM = BM / 32, RN = BN / 32;   // 16x16 blocks per wave
+  constexpr int AE = BM * BK / 256, BE = BK * BN / 256;  // tile elements per thread
+  __shared__ double As[NS][BK][BM + 2];
+  __shared__ double Bs[NS][BK][BN + 2];
 
   const int pars = INV ? 1 : 2;
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * pars;
@@ -95,17 +100,20 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = mt * BM;
   const int64_t n0 = (int64_t)nt * BN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int ar = tid >> 2, ak = (tid & 3) * 4;   // A tile element (row, first k)
-  const int bk = tid >> 4, bn = (tid & 15) * 4;  // B tile element (k, first n)
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  // A tile (BM x BK): thread -> row tid / (BK/AE'), AE consecutive k
+  constexpr int AKT = BK / AE;                      // threads per A row
+  const int ar = tid / AKT, ak = (tid % AKT) * AE;
+  constexpr int BNT = BN / BE;                      // threads per B row
+  const int bk = tid / BNT, bn = (tid % BNT) * BE;
 
-  double ra[NS][4], rb[NS][4];
+  double ra[NS][AE], rb[NS][BE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int ps = INV ? s : par;  // parity of this operand set
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < AE; ++q) {
         // ---- A(m, k)
         {
           const int gm = m0 + ar, gk = k0 + ak + q;
@@ -124,6 +132,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
           }
           ra[s][q] = v;
         }
+      }
+#pragma unroll
+      for (int q = 0; q < BE; ++q) {
         // ---- B(k, n)
         {
           const int gk = k0 + bk;
@@ -147,21 +158,21 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int s = 0; s < NS; ++s)
+    for (int s = 0; s < NS; ++s) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        As[s][ak + q][ar] = ra[s][q];
-        Bs[s][bk][bn + q] = rb[s][q];
-      }
+      for (int q = 0; q < AE; ++q) As[s][ak + q][ar] = ra[s][q];
+#pragma unroll
+      for (int q = 0; q < BE; ++q) Bs[s][bk][bn + q] = rb[s][q];
+    }
   };
 
-  v4d acc[NS][2][2];
+  v4d acc[NS][RM][RN];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < RM; ++r)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) acc[s][r][c] = v4d{0, 0, 0, 0};
+      for (int c = 0; c < RN; ++c) acc[s][r][c] = v4d{0, 0, 0, 0};
 
   fetch(0);
   stash();
@@ -174,14 +185,16 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
       const int kr = kk + (lane >> 4);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const double a0 = As[s][kr][wm + (lane & 15)];
-        const double a1 = As[s][kr][wm + 16 + (lane & 15)];
-        const double b0 = Bs[s][kr][wn + (lane & 15)];
-        const double b1 = Bs[s][kr][wn + 16 + (lane & 15)];
-        acc[s][0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[s][0][0], 0, 0, 0);
-        acc[s][0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[s][0][1], 0, 0, 0);
-        acc[s][1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[s][1][0], 0, 0, 0);
-        acc[s][1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[s][1][1], 0, 0, 0);
+        double af[RM], bf[RN];
+#pragma unroll
+        for (int r = 0; r < RM; ++r) af[r] = As[s][kr][wm + 16 * r + (lane & 15)];
+#pragma unroll
+        for (int c = 0; c < RN; ++c) bf[c] = Bs[s][kr][wn + 16 * c + (lane & 15)];
+#pragma unroll
+        for (int r = 0; r < RM; ++r)
+#pragma unroll
+          for (int c = 0; c < RN; ++c)
+            acc[s][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[s][r][c], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -193,9 +206,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
 
   // D[i][j] of a 16x16 block: lane = j + 16 * (i % 4), element i / 4.
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < RM; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < RN; ++c) {
       const int64_t gn = n0 + wn + c * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -208,7 +221,8 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
           } else {
             const int mode = par * H + gm;
             if (EPI == EPI_DIVIDE) {
-              const int aa = (int)(gn % ep.nx), bb = (int)(gn / ep.nx);
+              const int g32 = (int)gn;  // position in an (nx * ny) plane: fits 32 bits
+              const int bb = g32 / ep.nx, aa = g32 - bb * ep.nx;
               const int64_t flat = (int64_t)mode * ((int64_t)ep.nx * ep.ny) + gn;
               v = (flat == ep.null3) ? 0.0 : v / (ep.lz[mode] + ep.ly[bb] + ep.lx[aa]);
             }
@@ -237,8 +251,8 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
     }
 }
 
-template <int KIND, int EPI>
-hipError_t launch(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) {
+template <int KIND, int EPI, int BM, int BN>
+hipError_t launch_tiles(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) {
   SplitArgs a = a0;
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
   const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
@@ -248,8 +262,33 @@ hipError_t launch(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) {
   a.ntiles = (int)((NN + BN - 1) / BN);
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
   const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_split_kernel<KIND, EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  fd_split_kernel<KIND, EPI, BM, BN><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
   return hipGetLastError();
+}
+
+// Tile size: 64 x 64 by default (it measured faster: four waves per SIMD
+// stay resident); KV_FD_TILE=128 selects large tiles when the half size fills
+// them (more MFMA work per operand
+// byte and per prologue); 64 x 64 otherwise.  The inverse kinds carry two
+// accumulator sets, so their tiles are half as wide.
+int tile_choice() {
+  static int t = -1;
+  if (t < 0) {
+    const char* e = getenv("KV_FD_TILE");
+    t = (e && atoi(e) == 128) ? 128 : 64;
+  }
+  return t;
+}
+
+template <int KIND, int EPI>
+hipError_t launch(const SplitArgs& a, const SplitEpi& ep, hipStream_t s) {
+  const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
+  const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  if (a.H >= 96 && tile_choice() == 128) {
+    if (inv) return right ? launch_tiles<KIND, EPI, 128, 64>(a, ep, s) : launch_tiles<KIND, EPI, 64, 128>(a, ep, s);
+    return launch_tiles<KIND, EPI, 128, 128>(a, ep, s);
+  }
+  return launch_tiles<KIND, EPI, 64, 64>(a, ep, s);
 }
 
 }  // namespace

@@ -47,12 +47,47 @@ struct GlobalAcc {
 // Every unknown owned by cell (i, j, k).  MODE 0: y = J(base) pert.  MODE 1:
 // y = N(pert) (base = pert).  A supplies the fields: A.U(s, i, j, k) etc. with
 // s = 0 for the base flow and 1 for the perturbation, zero on walls.
-template <int MODE, class Acc>
-__device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j, int k, double* __restrict__ y) {
+// Outputs: plain stores (one-cell kernel) or raw buffer stores with 32-bit
+// offsets (tiled kernel).
+struct PtrOut {
+  double* y;
+  __device__ __forceinline__ void put(int64_t idx, double v) const { y[idx] = v; }
+};
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+struct BufOut {
+  __amdgpu_buffer_rsrc_t r;
+  const Grid* g;
+  __device__ __forceinline__ void put(int64_t idx, double v) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)idx * 8, 0, 0);
+  }
+};
+
+// The metrics one cell needs along one axis, held in registers: at the
+// cell's low face f and high face f+1 (id = 1/centre gap, wl/wh =
+// interpolation weights) and the widths of the cell and its low neighbour.
+struct Met {
+  double id0, id1, ih0, ihm, wl0, wh0, wl1, wh1;
+};
+
+__device__ __forceinline__ Met load_met(const Axis& A, int c) {
+  Met m;
+  const int n = A.n;
+  const int cc = c < n ? c : n - 1;  // threads past the domain edge still load in range
+  m.id0 = A.id[cc];
+  m.id1 = A.id[cc + 1];
+  m.ih0 = A.ih[cc];
+  m.ihm = cc > 0 ? A.ih[cc - 1] : 0.0;
+  m.wl0 = A.wlo[cc];
+  m.wh0 = A.whi[cc];
+  m.wl1 = A.wlo[cc + 1];
+  m.wh1 = A.whi[cc + 1];
+  return m;
+}
+
+template <int MODE, class Acc, class Out>
+__device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j, int k, const Met& MX, const Met& MY,
+                                      const Met& MZ, const Out& y) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const Axis& AX = g.ax[0];
-  const Axis& AY = g.ax[1];
-  const Axis& AZ = g.ax[2];
   const double s = MODE ? 0.5 : 1.0;
   const double TW = MODE ? 0.5 : 0.0, TE = MODE ? -0.5 : 0.0;
 
@@ -62,12 +97,12 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     const double Um = A.U(0, i - 1, j, k), um = A.U(1, i - 1, j, k);
     const double Up = A.U(0, i + 1, j, k), up = A.U(1, i + 1, j, k);
     // x: centre fluxes (u_bar)^2 at cells i (east) and i-1 (west)
-    double adv = (0.5 * (Uc + Up) * (uc + up) - 0.5 * (Um + Uc) * (um + uc)) * AX.id[i];
-    const double xl = AX.wlo[i], xh = AX.whi[i];
+    double adv = (0.5 * (Uc + Up) * (uc + up) - 0.5 * (Um + Uc) * (um + uc)) * MX.id0;
+    const double xl = MX.wl0, xh = MX.wh0;
     // y: fluxes v_hat * u_hat at y-faces j and j+1 of the u control volume
     double fS = 0.0, fN = 0.0, uS = 0.0, uN = 0.0;
     if (j > 0) {
-      const double yl = AY.wlo[j], yh = AY.whi[j];
+      const double yl = MY.wl0, yh = MY.wh0;
       const double UB = A.U(0, i, j - 1, k);
       uS = A.U(1, i, j - 1, k);
       const double Vh = xl * A.V(0, i - 1, j, k) + xh * A.V(0, i, j, k);
@@ -75,18 +110,18 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fS = Vh * (yl * uS + yh * uc) + vh * (yl * UB + yh * Uc);
     }
     if (j < ny - 1) {
-      const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+      const double yl = MY.wl1, yh = MY.wh1;
       const double UB = A.U(0, i, j + 1, k);
       uN = A.U(1, i, j + 1, k);
       const double Vh = xl * A.V(0, i - 1, j + 1, k) + xh * A.V(0, i, j + 1, k);
       const double vh = xl * A.V(1, i - 1, j + 1, k) + xh * A.V(1, i, j + 1, k);
       fN = Vh * (yl * uc + yh * uN) + vh * (yl * Uc + yh * UB);
     }
-    adv += (fN - fS) * AY.ih[j];
+    adv += (fN - fS) * MY.ih0;
     // z: fluxes w_hat * u_hat at z-faces k and k+1
     double fB = 0.0, fT = 0.0, uB = 0.0, uT = 0.0;
     if (k > 0) {
-      const double zl = AZ.wlo[k], zh = AZ.whi[k];
+      const double zl = MZ.wl0, zh = MZ.wh0;
       const double UB = A.U(0, i, j, k - 1);
       uB = A.U(1, i, j, k - 1);
       const double Wh = xl * A.W(0, i - 1, j, k) + xh * A.W(0, i, j, k);
@@ -94,18 +129,18 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fB = Wh * (zl * uB + zh * uc) + wh * (zl * UB + zh * Uc);
     }
     if (k < nz - 1) {
-      const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+      const double zl = MZ.wl1, zh = MZ.wh1;
       const double UB = A.U(0, i, j, k + 1);
       uT = A.U(1, i, j, k + 1);
       const double Wh = xl * A.W(0, i - 1, j, k + 1) + xh * A.W(0, i, j, k + 1);
       const double wh = xl * A.W(1, i - 1, j, k + 1) + xh * A.W(1, i, j, k + 1);
       fT = Wh * (zl * uc + zh * uT) + wh * (zl * Uc + zh * UB);
     }
-    adv += (fT - fB) * AZ.ih[k];
-    double lap = ((up - uc) * AX.ih[i] - (uc - um) * AX.ih[i - 1]) * AX.id[i];
-    lap += ((uN - uc) * AY.id[j + 1] - (uc - uS) * AY.id[j]) * AY.ih[j];
-    lap += ((uT - uc) * AZ.id[k + 1] - (uc - uB) * AZ.id[k]) * AZ.ih[k];
-    y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] = -s * adv + g.nu * lap;
+    adv += (fT - fB) * MZ.ih0;
+    double lap = ((up - uc) * MX.ih0 - (uc - um) * MX.ihm) * MX.id0;
+    lap += ((uN - uc) * MY.id1 - (uc - uS) * MY.id0) * MY.ih0;
+    lap += ((uT - uc) * MZ.id1 - (uc - uB) * MZ.id0) * MZ.ih0;
+    y.put(g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1), -s * adv + g.nu * lap);
   }
 
   // ---------------- v on y-face j ----------------
@@ -113,11 +148,11 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     const double Vc = A.V(0, i, j, k), vc = A.V(1, i, j, k);
     const double Vm = A.V(0, i, j - 1, k), vm = A.V(1, i, j - 1, k);
     const double Vp = A.V(0, i, j + 1, k), vp = A.V(1, i, j + 1, k);
-    double adv = (0.5 * (Vc + Vp) * (vc + vp) - 0.5 * (Vm + Vc) * (vm + vc)) * AY.id[j];
-    const double yl = AY.wlo[j], yh = AY.whi[j];
+    double adv = (0.5 * (Vc + Vp) * (vc + vp) - 0.5 * (Vm + Vc) * (vm + vc)) * MY.id0;
+    const double yl = MY.wl0, yh = MY.wh0;
     double fW = 0.0, fE = 0.0, vW = 0.0, vE = 0.0;
     if (i > 0) {
-      const double xl = AX.wlo[i], xh = AX.whi[i];
+      const double xl = MX.wl0, xh = MX.wh0;
       const double VB = A.V(0, i - 1, j, k);
       vW = A.V(1, i - 1, j, k);
       const double Uh = yl * A.U(0, i, j - 1, k) + yh * A.U(0, i, j, k);
@@ -125,17 +160,17 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fW = Uh * (xl * vW + xh * vc) + uh * (xl * VB + xh * Vc);
     }
     if (i < nx - 1) {
-      const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+      const double xl = MX.wl1, xh = MX.wh1;
       const double VB = A.V(0, i + 1, j, k);
       vE = A.V(1, i + 1, j, k);
       const double Uh = yl * A.U(0, i + 1, j - 1, k) + yh * A.U(0, i + 1, j, k);
       const double uh = yl * A.U(1, i + 1, j - 1, k) + yh * A.U(1, i + 1, j, k);
       fE = Uh * (xl * vc + xh * vE) + uh * (xl * Vc + xh * VB);
     }
-    adv += (fE - fW) * AX.ih[i];
+    adv += (fE - fW) * MX.ih0;
     double fB = 0.0, fT = 0.0, vB = 0.0, vT = 0.0;
     if (k > 0) {
-      const double zl = AZ.wlo[k], zh = AZ.whi[k];
+      const double zl = MZ.wl0, zh = MZ.wh0;
       const double VB = A.V(0, i, j, k - 1);
       vB = A.V(1, i, j, k - 1);
       const double Wh = yl * A.W(0, i, j - 1, k) + yh * A.W(0, i, j, k);
@@ -143,18 +178,18 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fB = Wh * (zl * vB + zh * vc) + wh * (zl * VB + zh * Vc);
     }
     if (k < nz - 1) {
-      const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+      const double zl = MZ.wl1, zh = MZ.wh1;
       const double VB = A.V(0, i, j, k + 1);
       vT = A.V(1, i, j, k + 1);
       const double Wh = yl * A.W(0, i, j - 1, k + 1) + yh * A.W(0, i, j, k + 1);
       const double wh = yl * A.W(1, i, j - 1, k + 1) + yh * A.W(1, i, j, k + 1);
       fT = Wh * (zl * vc + zh * vT) + wh * (zl * Vc + zh * VB);
     }
-    adv += (fT - fB) * AZ.ih[k];
-    double lap = ((vp - vc) * AY.ih[j] - (vc - vm) * AY.ih[j - 1]) * AY.id[j];
-    lap += ((vE - vc) * AX.id[i + 1] - (vc - vW) * AX.id[i]) * AX.ih[i];
-    lap += ((vT - vc) * AZ.id[k + 1] - (vc - vB) * AZ.id[k]) * AZ.ih[k];
-    y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] = -s * adv + g.nu * lap;
+    adv += (fT - fB) * MZ.ih0;
+    double lap = ((vp - vc) * MY.ih0 - (vc - vm) * MY.ihm) * MY.id0;
+    lap += ((vE - vc) * MX.id1 - (vc - vW) * MX.id0) * MX.ih0;
+    lap += ((vT - vc) * MZ.id1 - (vc - vB) * MZ.id0) * MZ.ih0;
+    y.put(g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i, -s * adv + g.nu * lap);
   }
 
   // ---------------- w on z-face k ----------------
@@ -162,11 +197,11 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     const double Wc = A.W(0, i, j, k), wc = A.W(1, i, j, k);
     const double Wm = A.W(0, i, j, k - 1), wm = A.W(1, i, j, k - 1);
     const double Wp = A.W(0, i, j, k + 1), wp = A.W(1, i, j, k + 1);
-    double adv = (0.5 * (Wc + Wp) * (wc + wp) - 0.5 * (Wm + Wc) * (wm + wc)) * AZ.id[k];
-    const double zl = AZ.wlo[k], zh = AZ.whi[k];
+    double adv = (0.5 * (Wc + Wp) * (wc + wp) - 0.5 * (Wm + Wc) * (wm + wc)) * MZ.id0;
+    const double zl = MZ.wl0, zh = MZ.wh0;
     double fW = 0.0, fE = 0.0, wW = 0.0, wE = 0.0;
     if (i > 0) {
-      const double xl = AX.wlo[i], xh = AX.whi[i];
+      const double xl = MX.wl0, xh = MX.wh0;
       const double WB = A.W(0, i - 1, j, k);
       wW = A.W(1, i - 1, j, k);
       const double Uh = zl * A.U(0, i, j, k - 1) + zh * A.U(0, i, j, k);
@@ -174,17 +209,17 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fW = Uh * (xl * wW + xh * wc) + uh * (xl * WB + xh * Wc);
     }
     if (i < nx - 1) {
-      const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+      const double xl = MX.wl1, xh = MX.wh1;
       const double WB = A.W(0, i + 1, j, k);
       wE = A.W(1, i + 1, j, k);
       const double Uh = zl * A.U(0, i + 1, j, k - 1) + zh * A.U(0, i + 1, j, k);
       const double uh = zl * A.U(1, i + 1, j, k - 1) + zh * A.U(1, i + 1, j, k);
       fE = Uh * (xl * wc + xh * wE) + uh * (xl * Wc + xh * WB);
     }
-    adv += (fE - fW) * AX.ih[i];
+    adv += (fE - fW) * MX.ih0;
     double fS = 0.0, fN = 0.0, wS = 0.0, wN = 0.0;
     if (j > 0) {
-      const double yl = AY.wlo[j], yh = AY.whi[j];
+      const double yl = MY.wl0, yh = MY.wh0;
       const double WB = A.W(0, i, j - 1, k);
       wS = A.W(1, i, j - 1, k);
       const double Vh = zl * A.V(0, i, j, k - 1) + zh * A.V(0, i, j, k);
@@ -192,19 +227,19 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fS = Vh * (yl * wS + yh * wc) + vh * (yl * WB + yh * Wc);
     }
     if (j < ny - 1) {
-      const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+      const double yl = MY.wl1, yh = MY.wh1;
       const double WB = A.W(0, i, j + 1, k);
       wN = A.W(1, i, j + 1, k);
       const double Vh = zl * A.V(0, i, j + 1, k - 1) + zh * A.V(0, i, j + 1, k);
       const double vh = zl * A.V(1, i, j + 1, k - 1) + zh * A.V(1, i, j + 1, k);
       fN = Vh * (yl * wc + yh * wN) + vh * (yl * Wc + yh * WB);
     }
-    adv += (fN - fS) * AY.ih[j];
-    double lap = ((wp - wc) * AZ.ih[k] - (wc - wm) * AZ.ih[k - 1]) * AZ.id[k];
-    lap += ((wE - wc) * AX.id[i + 1] - (wc - wW) * AX.id[i]) * AX.ih[i];
-    lap += ((wN - wc) * AY.id[j + 1] - (wc - wS) * AY.id[j]) * AY.ih[j];
+    adv += (fN - fS) * MY.ih0;
+    double lap = ((wp - wc) * MZ.ih0 - (wc - wm) * MZ.ihm) * MZ.id0;
+    lap += ((wE - wc) * MX.id1 - (wc - wW) * MX.id0) * MX.ih0;
+    lap += ((wN - wc) * MY.id1 - (wc - wS) * MY.id0) * MY.ih0;
     const double buoy = zl * A.T(1, i, j, k - 1) + zh * A.T(1, i, j, k);
-    y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = -s * adv + g.nu * lap + g.beta * buoy;
+    y.put(g.ow + ((int64_t)(k - 1) * ny + j) * nx + i, -s * adv + g.nu * lap + g.beta * buoy);
   }
 
   // ---------------- T at the cell centre ----------------
@@ -217,59 +252,59 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       const double tW = (i > 0) ? A.T(1, i - 1, j, k) : TW;
       const double tE = (i < nx - 1) ? A.T(1, i + 1, j, k) : TE;
       if (i > 0) {
-        const double xl = AX.wlo[i], xh = AX.whi[i];
+        const double xl = MX.wl0, xh = MX.wh0;
         const double Th = xl * A.T(0, i - 1, j, k) + xh * Tb;
         fW = A.U(0, i, j, k) * (xl * tW + xh * tc) + A.U(1, i, j, k) * Th;
       }
       if (i < nx - 1) {
-        const double xl = AX.wlo[i + 1], xh = AX.whi[i + 1];
+        const double xl = MX.wl1, xh = MX.wh1;
         const double Th = xl * Tb + xh * A.T(0, i + 1, j, k);
         fE = A.U(0, i + 1, j, k) * (xl * tc + xh * tE) + A.U(1, i + 1, j, k) * Th;
       }
-      adv += (fE - fW) * AX.ih[i];
-      lap += ((tE - tc) * AX.id[i + 1] - (tc - tW) * AX.id[i]) * AX.ih[i];
+      adv += (fE - fW) * MX.ih0;
+      lap += ((tE - tc) * MX.id1 - (tc - tW) * MX.id0) * MX.ih0;
     }
     // y
     {
       double fS = 0.0, fN = 0.0, gS = 0.0, gN = 0.0;
       if (j > 0) {
-        const double yl = AY.wlo[j], yh = AY.whi[j];
+        const double yl = MY.wl0, yh = MY.wh0;
         const double tS = A.T(1, i, j - 1, k);
         const double Th = yl * A.T(0, i, j - 1, k) + yh * Tb;
         fS = A.V(0, i, j, k) * (yl * tS + yh * tc) + A.V(1, i, j, k) * Th;
-        gS = (tc - tS) * AY.id[j];
+        gS = (tc - tS) * MY.id0;
       }
       if (j < ny - 1) {
-        const double yl = AY.wlo[j + 1], yh = AY.whi[j + 1];
+        const double yl = MY.wl1, yh = MY.wh1;
         const double tN = A.T(1, i, j + 1, k);
         const double Th = yl * Tb + yh * A.T(0, i, j + 1, k);
         fN = A.V(0, i, j + 1, k) * (yl * tc + yh * tN) + A.V(1, i, j + 1, k) * Th;
-        gN = (tN - tc) * AY.id[j + 1];
+        gN = (tN - tc) * MY.id1;
       }
-      adv += (fN - fS) * AY.ih[j];
-      lap += (gN - gS) * AY.ih[j];
+      adv += (fN - fS) * MY.ih0;
+      lap += (gN - gS) * MY.ih0;
     }
     // z
     {
       double fB = 0.0, fT = 0.0, gB = 0.0, gT = 0.0;
       if (k > 0) {
-        const double zl = AZ.wlo[k], zh = AZ.whi[k];
+        const double zl = MZ.wl0, zh = MZ.wh0;
         const double tB = A.T(1, i, j, k - 1);
         const double Th = zl * A.T(0, i, j, k - 1) + zh * Tb;
         fB = A.W(0, i, j, k) * (zl * tB + zh * tc) + A.W(1, i, j, k) * Th;
-        gB = (tc - tB) * AZ.id[k];
+        gB = (tc - tB) * MZ.id0;
       }
       if (k < nz - 1) {
-        const double zl = AZ.wlo[k + 1], zh = AZ.whi[k + 1];
+        const double zl = MZ.wl1, zh = MZ.wh1;
         const double tT = A.T(1, i, j, k + 1);
         const double Th = zl * Tb + zh * A.T(0, i, j, k + 1);
         fT = A.W(0, i, j, k + 1) * (zl * tc + zh * tT) + A.W(1, i, j, k + 1) * Th;
-        gT = (tT - tc) * AZ.id[k + 1];
+        gT = (tT - tc) * MZ.id1;
       }
-      adv += (fT - fB) * AZ.ih[k];
-      lap += (gT - gB) * AZ.ih[k];
+      adv += (fT - fB) * MZ.ih0;
+      lap += (gT - gB) * MZ.ih0;
     }
-    y[g.oT + ((int64_t)k * ny + j) * nx + i] = -s * adv + g.kappa * lap;
+    y.put(g.oT + ((int64_t)k * ny + j) * nx + i, -s * adv + g.kappa * lap);
   }
 }
 
@@ -284,7 +319,7 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   GlobalAcc A{&g, B, x};
-  point<MODE>(g, A, i, j, k, y);
+  point<MODE>(g, A, i, j, k, load_met(g.ax[0], i), load_met(g.ax[1], j), load_met(g.ax[2], k), PtrOut{y});
 }
 
 // ---- 2.5-D tiled version ---------------------------------------------------------
@@ -297,11 +332,10 @@ constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
 
 template <int NF>
 struct TileAcc {
-  const double* lds;  // [3 slots][NF fields][PY][PX]
-  int i0, j0;
+  const double* pl[3];  // planes k-1, k, k+1: [NF fields][PY][PX] each
+  int ic, jc, kc, off;  // this thread's cell and its offset inside a plane
   __device__ __forceinline__ double at(int f, int i, int j, int k) const {
-    const int slot = (k + 3) % 3;
-    return lds[(slot * NF + f) * PLANE + (j - j0 + 1) * PX + (i - i0 + 1)];
+    return pl[k - kc + 1][f * PLANE + off + (j - jc) * PX + (i - ic)];
   }
   // field index: (component, s) -> 2*comp + s for NF = 8, comp for NF = 4
   __device__ __forceinline__ int fi(int comp, int s) const { return NF == 8 ? 2 * comp + s : comp; }
@@ -322,32 +356,67 @@ struct PlaneRegs {
   double v[NF][PER];
 };
 
-template <int NF>
-__device__ __forceinline__ void fetch_plane(const Grid& g, const double* __restrict__ B, const double* __restrict__ x,
-                                            int i0, int j0, int kp, PlaneRegs<NF>& R) {
-  const bool kin = (kp >= 0 && kp < g.nz);
-  const bool win = (kp >= 0 && kp <= g.nz);
+// Where this thread's two tile entries live in each packed block, once per
+// block: a plane kp of block c is at  base[c][q] + kp * stride[c]  (32-bit
+// offsets: n < 2^31), valid where the in-plane position lies in the block.
+struct FetchMap {
+  int32_t base[4][PER];
+  int32_t stride[4];
+  uint32_t ok[PER];  // bit c: in-plane position valid for block c
+};
+
+__device__ __forceinline__ FetchMap fetch_map(const Grid& g, int i0, int j0) {
+  FetchMap m;
+  const int nx = g.nx, ny = g.ny;
+  m.stride[0] = ny * (nx - 1);
+  m.stride[1] = (ny - 1) * nx;
+  m.stride[2] = ny * nx;
+  m.stride[3] = ny * nx;
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int r = threadIdx.x + 256 * q;
     const int i = i0 - 1 + r % PX, j = j0 - 1 + r / PX;
     const bool rin = r < PLANE;
-    const bool iin = i >= 0 && i < g.nx, jin = j >= 0 && j < g.ny;
+    const bool iin = i >= 0 && i < nx, jin = j >= 0 && j < ny;
+    uint32_t ok = 0;
+    if (rin && jin && i >= 1 && i <= nx - 1) ok |= 1u;
+    if (rin && iin && j >= 1 && j <= ny - 1) ok |= 2u;
+    if (rin && iin && jin) ok |= 4u | 8u;
+    m.ok[q] = ok;
+    m.base[0][q] = (int32_t)g.ou + j * (nx - 1) + (i - 1);
+    m.base[1][q] = (int32_t)g.ov + (j - 1) * nx + i;
+    m.base[2][q] = (int32_t)g.ow + (j - ny) * nx + i;  // w plane kp is stored as kp - 1
+    m.base[3][q] = (int32_t)g.oT + j * nx + i;
+  }
+  return m;
+}
+
+// A raw buffer over one packed vector: loads past num_records return 0, so
+// wall and out-of-domain tile entries need no branch.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const double* p, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, (int)(n * 8), 0x00020000);
+}
+constexpr int OOB = 0x7ffffff8;  // a byte offset past every buffer
+
+template <int NF>
+__device__ __forceinline__ void fetch_plane(const Grid& g, __amdgpu_buffer_rsrc_t rB, __amdgpu_buffer_rsrc_t rx,
+                                            const FetchMap& m, int kp, PlaneRegs<NF>& R) {
+  // plane validity per block: u, v, T need 0 <= kp < nz; w (faces) 1 <= kp <= nz-1
+  const bool kin = (kp >= 0 && kp < g.nz);
+  const bool win = (kp >= 1 && kp < g.nz);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int off[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool valid = ((m.ok[q] >> c) & 1u) && (c == 2 ? win : kin);
+      off[c] = valid ? (m.base[c][q] + kp * m.stride[c]) * 8 : OOB;
+    }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const int comp = NF == 8 ? f >> 1 : f;
-      const double* src = (NF == 8 && (f & 1) == 0) ? B : x;
-      double v = 0.0;
-      if (comp == 0) {
-        if (rin && kin && jin) v = Uat(src, g, i, j, kp);
-      } else if (comp == 1) {
-        if (rin && kin && iin) v = Vat(src, g, i, j, kp);
-      } else if (comp == 2) {
-        if (rin && win && iin && jin) v = Wat(src, g, i, j, kp);
-      } else {
-        if (rin && kin && iin && jin) v = Tat(src, g, i, j, kp);
-      }
-      R.v[f][q] = v;
+      const __amdgpu_buffer_rsrc_t r = (NF == 8 && (f & 1) == 0) ? rB : rx;
+      R.v[f][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off[comp], 0, 0));
     }
   }
 }
@@ -383,20 +452,33 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   const int i0 = bx * TX, j0 = by * TY, k0 = bz * KC;
   const int k1 = min(g.nz, k0 + KC);
   const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
-  TileAcc<NF> A{lds, i0, j0};
+  const Met MX = load_met(g.ax[0], i), MY = load_met(g.ax[1], j);
+  const FetchMap fm = fetch_map(g, i0, j0);
+  const __amdgpu_buffer_rsrc_t rB = vec_rsrc(B, g.n), rx = vec_rsrc(x, g.n);
+  BufOut out{vec_rsrc(y, g.n), &g};
   PlaneRegs<NF> R;
-  fetch_plane<NF>(g, B, x, i0, j0, k0 - 1, R);
+  fetch_plane<NF>(g, rB, rx, fm, k0 - 1, R);
   store_plane<NF>(lds, k0 - 1, R);
-  fetch_plane<NF>(g, B, x, i0, j0, k0, R);
+  fetch_plane<NF>(g, rB, rx, fm, k0, R);
   store_plane<NF>(lds, k0, R);
-  fetch_plane<NF>(g, B, x, i0, j0, k0 + 1, R);
+  fetch_plane<NF>(g, rB, rx, fm, k0 + 1, R);
   store_plane<NF>(lds, k0 + 1, R);
   __syncthreads();
   for (int k = k0; k < k1; ++k) {
     // software pipeline: plane k+2 is in flight while plane k is computed
     const bool more = k + 1 < k1;
-    if (more) fetch_plane<NF>(g, B, x, i0, j0, k + 2, R);
-    if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, y);
+    if (more) fetch_plane<NF>(g, rB, rx, fm, k + 2, R);
+    if (i < g.nx && j < g.ny) {
+      TileAcc<NF> A;
+      A.pl[0] = lds + ((k + 2) % 3) * NF * PLANE;
+      A.pl[1] = lds + (k % 3) * NF * PLANE;
+      A.pl[2] = lds + ((k + 1) % 3) * NF * PLANE;
+      A.ic = i;
+      A.jc = j;
+      A.kc = k;
+      A.off = (j - j0 + 1) * PX + (i - i0 + 1);
+      point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out);
+    }
     __syncthreads();
     if (more) store_plane<NF>(lds, k + 2, R);   // slot of plane k-1, no longer read
     __syncthreads();
@@ -535,6 +617,13 @@ inline dim3 cell_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) 
 
 hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode) {
   const Grid& g = c->g;
+  if (g.n * 8 >= ((int64_t)1 << 31)) {  // 32-bit byte offsets: fall back to the one-cell-per-thread kernel
+    if (mode == 0)
+      operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
+    else
+      operator_kernel<1><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, x, x, y);
+    return hipGetLastError();
+  }
   const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, ch = (g.nz + KC - 1) / KC;
   const int64_t total = (int64_t)tx * ty * ch;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
