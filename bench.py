@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32
 
 
 def log(*a):
@@ -69,9 +70,9 @@ def cpu_baseline(g_args, X0, x0, y_gpu):
     fd = O.FastDiag(g)
     ref = O.apply_jacobian(g, X0, x0, projected=True, fd=fd)
     dt = time.perf_counter() - t0
-    errs = []
-    for a, b in zip(g.unpack(y_gpu), g.unpack(ref)):
-        errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+    errs = {}
+    for form, y in y_gpu.items():
+        errs[form] = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(g.unpack(y), g.unpack(ref))]
     return {"value": 1.0 / dt, "unit": "Krylov vectors/s", "cores": int(threads), "kind": "oracle",
             "sample": f"one P J x application (x seed 1000) on the full grid, {dt:.1f} s wall"}, errs
 
@@ -84,6 +85,8 @@ def main():
     ap.add_argument("--workload", default="cube256_clustered_gr2e8")
     ap.add_argument("--batch", type=int, default=4, help="resident perturbations cycled over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--form", choices=("fp64", "mixed", "both"), default="both",
+                    help="projection form(s) to time; the headline value is the mixed form's")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="also run this many plain device copies of one vector (a known-size "
                          "reference for hardware byte counters)")
@@ -115,80 +118,100 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] inputs resident: n = {n}, batch {B}")
 
-    for i in range(args.warmup):
-        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
-    torch.cuda.synchronize()
+    def run_form(mixed):
+        """Time args.steps projected Jacobians, then the per-phase device time
+        (HIP events on the library's stream) over a further pass."""
+        for i in range(args.warmup):
+            ctx.apply_jacobian(xs[i % B], ys[i % B], project=True, mixed=mixed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            ctx.apply_jacobian(xs[i % B], ys[i % B], project=True, mixed=mixed)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"[bench] {'mixed' if mixed else 'fp64'}: {args.steps} steps in {dt:.3f} s: "
+            f"{args.steps / dt:.1f} vectors/s")
+        ctx.timing(True)
+        nphase = min(args.steps, 200)
+        for i in range(nphase):
+            ctx.apply_jacobian(xs[i % B], ys[i % B], project=True, mixed=mixed)
+        ms, calls = ctx.timing(False)
+        per_vec = [m / nphase for m in ms]
+        sweeps = calls[1] / nphase                      # Poisson solves per vector
+        fd_launches = 6 * calls[1]
+        fd_launch_ms = ms[2] / max(1, fd_launches)
+        # one axis pass of the even/odd split transform: two (N/2 x N/2)
+        # products per line of N cells, i.e. N flop per cell
+        fd_flops = 1.0 * spec["n"] * n_cells
+        achieved = fd_flops / (fd_launch_ms * 1e-3) / 1e12
+        peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+        roof_fd = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                   "frac": round(achieved / peak, 4),
+                   "traffic": None if mixed else profiled_traffic("fd_split_kernel", "kv_fd_split.hip"),
+                   "kernel": "fd_split_kernel<%s> (one axis pass of the fast-diagonalization transforms)"
+                             % ("float" if mixed else "double"),
+                   "launch_ms": round(fd_launch_ms, 5), "launches_per_step": round(6 * sweeps, 2)}
+        bpc = algorithmic_bytes_per_cell_fp64()
+        st_bytes = bpc["stencil_io"] * n_cells
+        st_ach = st_bytes / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else 0.0
+        roof_st = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(st_ach / HBM_PEAK_GBS, 4),
+                   "traffic": profiled_traffic("operator_tiled_kernel", "kv_stencil.hip"),
+                   "kernel": "operator_tiled_kernel (J x stencil)", "launch_ms": round(per_vec[0], 5),
+                   "launches_per_step": 1}
+        if per_vec[2] >= per_vec[0]:
+            roofline, secondary = roof_fd, roof_st
+        else:
+            roofline, secondary = roof_st, roof_fd
+        if mixed:
+            # HBM bytes per cell: stencil 96, FP32 divergence 28 (read y 24,
+            # write 4), per sweep six FP32 transform passes (8 B each) and the
+            # fused correction + divergence (read y 24, p 4; write y 24, T copy
+            # 16, b 4)
+            t_roof = (96.0 + 28.0 + sweeps * (48.0 + 72.0)) * n_cells / (HBM_PEAK_GBS * 1e9)
+        else:
+            t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
+                      + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
+        return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "roofline": roofline,
+                "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / (dt / args.steps), 4),
+                "sweeps_per_vector": round(sweeps, 3),
+                "phases_ms_per_vector": {"stencil": round(per_vec[0], 5), "divergence": round(per_vec[1], 5),
+                                         "fd_transforms": round(per_vec[2], 5),
+                                         "correction": round(per_vec[3], 5)}}
 
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = args.steps / dt
-    log(f"[bench] timed {args.steps} steps in {dt:.3f} s: {value:.1f} vectors/s")
-
-    # per-phase device time with HIP events on the library's stream
-    ctx.timing(True)
-    nphase = min(args.steps, 200)
-    for i in range(nphase):
-        ctx.apply_jacobian(xs[i % B], ys[i % B], project=True)
-    ms, calls = ctx.timing(False)
-    per_vec = [m / max(1, calls[1]) for m in ms]
-    fd_launch_ms = ms[2] / max(1, 6 * calls[1])
-    # one axis pass of the even/odd split transform: two (N/2 x N/2) products
-    # per line of N cells, i.e. N flop per cell (the grid is mirror-symmetric)
-    fd_flops = 1.0 * spec["n"] * n_cells
-    achieved = fd_flops / (fd_launch_ms * 1e-3) / 1e12
-    roof_fd = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-               "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-               "traffic": profiled_traffic("fd_split_kernel", "kv_fd_split.hip"),
-               "kernel": "fd_split_kernel (one axis pass of the FP64 fast-diagonalization transforms)",
-               "launch_ms": round(fd_launch_ms, 5), "launches_per_step": 6}
-    bpc = algorithmic_bytes_per_cell_fp64()
-    st_bytes = bpc["stencil_io"] * n_cells
-    st_ach = st_bytes / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else 0.0
-    roof_st = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "frac": round(st_ach / HBM_PEAK_GBS, 4),
-               "traffic": profiled_traffic("operator_tiled_kernel", "kv_stencil.hip"),
-               "kernel": "operator_tiled_kernel (J x stencil)", "launch_ms": round(per_vec[0], 5),
-               "launches_per_step": 1}
-    # the dominant kernel family by device time per step
-    if per_vec[2] >= per_vec[0]:
-        roofline, secondary = roof_fd, roof_st
-    else:
-        roofline, secondary = roof_st, roof_fd
-    phases = {"stencil_ms": per_vec[0], "divergence_ms": per_vec[1], "fd_ms": per_vec[2],
-              "correction_ms": per_vec[3],
-              "stencil_GBs": bpc["stencil"] * n_cells / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else None,
-              "correction_GBs": bpc["correction"] * n_cells / (per_vec[3] * 1e-3) / 1e9 if per_vec[3] else None}
-    # roofline time of the whole step: HBM for stencil/divergence/correction,
-    # FP64 peak for the transforms
-    t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
-              + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
-    step_roof_frac = t_roof / (dt / args.steps)
-
+    forms = {}
+    if args.form in ("fp64", "both"):
+        forms["fp64"] = run_form(False)
+    if args.form in ("mixed", "both"):
+        forms["mixed"] = run_form(True)
     for _ in range(args.copy_ref):
         ys[0].copy_(xs[0])
     torch.cuda.synchronize()
-
+    head = forms["mixed"] if "mixed" in forms else forms["fp64"]
     result = {
         "metric": "Krylov vectors/s (J.v+projection) at 256^3, % HBM roofline; mixed vs FP64",
-        "value": round(value, 3), "unit": "Krylov vectors/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "value": round(head["value"], 3), "unit": "Krylov vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 stencil + f32 transforms + f64 refinement" if "mixed" in forms else "f64",
+        "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{spec['n']}^3 {spec['grid']}", "Gr": spec["Gr"],
-                   "Pr": spec["Pr"], "form": "fp64", "resident_batch": B, "unknowns": n},
-        "roofline": roofline,
-        "roofline_secondary": secondary,
-        "step_roofline_frac": round(step_roof_frac, 4),
-        "phases_ms_per_vector": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in phases.items()},
+                   "Pr": spec["Pr"], "form": "mixed" if "mixed" in forms else "fp64", "resident_batch": B,
+                   "unknowns": n},
+        "roofline": head["roofline"],
+        "roofline_secondary": head["roofline_secondary"],
+        "step_roofline_frac": head["step_roofline_frac"],
+        "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one vector")
-        ctx.apply_jacobian(xs[0], ys[0], project=True)
+        outs = {}
+        for form in forms:
+            ctx.apply_jacobian(xs[0], ys[0], project=True, mixed=(form == "mixed"))
+            outs[form] = ys[0].cpu().numpy()
         base, errs = cpu_baseline({"faces": (xf, yf, zf), "Gr": spec["Gr"], "Pr": spec["Pr"]}, X0, xs_host0,
-                                  ys[0].cpu().numpy())
+                                  outs)
         result["cpu_baseline"] = base
         result["parity_vs_oracle"] = {"x_seed": 1000, "field_rel_err_l2": errs}
     print(json.dumps(result), flush=True)

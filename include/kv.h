@@ -68,9 +68,13 @@ enum kv_status {
   KV_ESTATE = 6       /* call needs kv_set_base_flow first */
 };
 
-/* Per-call flags.  KV_PROJECT: follow J by the projection P.  KV_MIXED:
- * reserved for the mixed-precision form; rejected with KV_EINVAL by calls
- * that do not implement it. */
+/* Per-call flags.  KV_PROJECT: follow J by the projection P.  KV_MIXED
+ * (kv_apply_jacobian, kv_project): the mixed-precision projection -- the
+ * fast-diagonalization solve in FP32 storage on the FP32 matrix cores,
+ * refined on the FP64 residual (in pairs of sweeps) until the normalized
+ * divergence max|net flux| / max|face flux| is <= 1e-10 (KV_ENOCONV after 8
+ * sweeps).  It needs every axis mirror-symmetric with an even cell count; on
+ * other grids the FP64 projection is used.  The solvers reject KV_MIXED. */
 enum kv_flags { KV_PROJECT = 1u, KV_MIXED = 2u };
 
 typedef struct {
@@ -108,7 +112,8 @@ int kv_apply_jacobian(kv_ctx* ctx, const double* x, double* y, unsigned flags);
 
 /* In place y <- P y (velocity block; T unchanged).  div_max (host, may be
  * NULL): normalized divergence max|net flux| / max|face flux| after the
- * projection.  sweeps (host, may be NULL): projection sweeps used (1). */
+ * projection.  sweeps (host, may be NULL): projection sweeps used (1 for
+ * the FP64 projection, the refinement sweeps with KV_MIXED). */
 int kv_project(kv_ctx* ctx, double* y, unsigned flags, double* div_max, int* sweeps);
 
 /* <a, b>_W on the device, result to host *out. */

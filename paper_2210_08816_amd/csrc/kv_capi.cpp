@@ -224,6 +224,61 @@ int project_inplace(kv_ctx* c, double* y) {
   return KV_OK;
 }
 
+// Mixed form of the projection: FP32-storage fast diagonalization on the
+// FP32 matrix cores, refined on the FP64 residual.  Each sweep solves for
+// the divergence left by the previous one; corrections and the next
+// divergence are fused and ping-pong between y and a scratch vector, so the
+// sweeps come in pairs and the result lands in y.  Stops when the normalized
+// divergence max|net flux| / max|face flux| <= tol (at most 8 sweeps).
+constexpr double kMixedDivTol = 1e-10;
+
+int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
+  const int64_t C = c->ncell;
+  if (!c->ymix) {
+    if (hipMalloc(&c->ymix, c->g.n * sizeof(double)) != hipSuccess) {
+      c->ymix = nullptr;
+      return fail(c, KV_ENOMEM, "cannot allocate the mixed-form scratch vector");
+    }
+  }
+  // FP32 fields inside the two FP64 cell buffers
+  float* F0 = reinterpret_cast<float*>(c->cellA);
+  float* F1 = F0 + C;
+  int rc;
+  {
+    PhaseMark pm(c, 1);
+    HIPCHK(c, launch_scaled_divergence_f32(c, y, F0));
+  }
+  double div = 1.0;
+  int sweeps = 0;
+  while (sweeps < 8) {
+    for (int half = 0; half < 2; ++half) {
+      const double* src = half == 0 ? y : c->ymix;
+      double* dst = half == 0 ? c->ymix : y;
+      float* b = half == 0 ? F0 : F1;
+      float* bn = half == 0 ? F1 : F0;
+      {
+        PhaseMark pm(c, 2);
+        HIPCHK(c, launch_fd_solve_f32(c, b, b));
+      }
+      {
+        PhaseMark pm(c, 3);
+        HIPCHK(c, launch_correct_divergence(c, src, b, dst, bn));
+      }
+      ++sweeps;
+    }
+    if ((rc = read_results(c, 2))) return rc;
+    div = c->hres[1] > 0 ? c->hres[0] / c->hres[1] : 0.0;
+    if (!std::isfinite(div)) return fail(c, KV_ENONFINITE, "non-finite value in the mixed projection");
+    if (div <= kMixedDivTol) break;
+  }
+  if (div_out) *div_out = div;
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (div > kMixedDivTol) return fail(c, KV_ENOCONV, "mixed projection: divergence not reduced to 1e-10");
+  return KV_OK;
+}
+
+bool mixed_ok(const kv_ctx* c) { return c->split[0] && c->split[1] && c->split[2]; }
+
 int apply_operator(kv_ctx* c, const double* x, double* y) {
   PhaseMark pm(c, 0);
   HIPCHK(c, launch_operator(c, c->X0, x, y, 0));
@@ -529,6 +584,15 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
     if (hipMemcpy(c->Qf[a], ax[a].Q.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c->Qt[a], ax[a].Qt.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(KV_EDEVICE, "Q copy");
+    if (c->split[a]) {
+      std::vector<float> q32(ax[a].Q.begin(), ax[a].Q.end()), qt32(ax[a].Qt.begin(), ax[a].Qt.end());
+      if (hipMalloc(&c->Qf32[a], nn * sizeof(float)) != hipSuccess ||
+          hipMalloc(&c->Qt32[a], nn * sizeof(float)) != hipSuccess)
+        return cleanup(KV_ENOMEM, "Q32");
+      if (hipMemcpy(c->Qf32[a], q32.data(), nn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->Qt32[a], qt32.data(), nn * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(KV_EDEVICE, "Q32 copy");
+    }
   }
   const int64_t rows = 2 * nz * ny + nz * (ny - 1) + (nz - 1) * ny;
   c->npart_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 3) / 4));
@@ -552,7 +616,10 @@ int kv_destroy(kv_ctx* c) {
   for (int a = 0; a < 3; ++a) {
     hipFree(c->Qf[a]);
     hipFree(c->Qt[a]);
+    hipFree(c->Qf32[a]);
+    hipFree(c->Qt32[a]);
   }
+  hipFree(c->ymix);
   hipFree(c->X0);
   hipFree(c->cellA);
   hipFree(c->cellB);
@@ -596,18 +663,22 @@ int kv_set_base_flow(kv_ctx* c, const double* X0) {
 int kv_apply_jacobian(kv_ctx* c, const double* x, double* y, unsigned flags) {
   if (!c) return KV_EINVAL;
   if (!x || !y || x == y) return fail(c, KV_EINVAL, "x and y must be distinct device vectors");
-  if (flags & ~(unsigned)KV_PROJECT) return fail(c, KV_EINVAL, "unsupported flags");
+  if (flags & ~(unsigned)(KV_PROJECT | KV_MIXED)) return fail(c, KV_EINVAL, "unsupported flags");
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   int rc = apply_operator(c, x, y);
   if (rc) return rc;
-  if (flags & KV_PROJECT) return project_inplace(c, y);
+  if (flags & KV_PROJECT) {
+    if ((flags & KV_MIXED) && mixed_ok(c)) return project_mixed(c, y, nullptr, nullptr);
+    return project_inplace(c, y);
+  }
   return KV_OK;
 }
 
 int kv_project(kv_ctx* c, double* y, unsigned flags, double* div_max, int* sweeps) {
   if (!c) return KV_EINVAL;
   if (!y) return fail(c, KV_EINVAL, "null vector");
-  if (flags & ~(unsigned)KV_PROJECT) return fail(c, KV_EINVAL, "unsupported flags");
+  if (flags & ~(unsigned)(KV_PROJECT | KV_MIXED)) return fail(c, KV_EINVAL, "unsupported flags");
+  if ((flags & KV_MIXED) && mixed_ok(c)) return project_mixed(c, y, div_max, sweeps);
   int rc = project_inplace(c, y);
   if (rc) return rc;
   if (sweeps) *sweeps = 1;

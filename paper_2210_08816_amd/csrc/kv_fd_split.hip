@@ -21,6 +21,30 @@ namespace kv {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Storage / matrix-core precision of one transform pass.  FP64:
+// v_mfma_f64_16x16x4 (D[i][j] in lane j + 16 (i % 4), element i / 4).  FP32:
+// v_mfma_f32_16x16x4 (D[i][j] in lane j + 16 (i / 4), element i % 4), the
+// mixed form's transforms.
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+template <>
+struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
 
 enum { RIGHT_FWD = 0, RIGHT_INV = 1, LEFT_FWD = 2, LEFT_INV = 3 };
 enum { EPI_NONE = 0, EPI_DIVIDE = 1, EPI_ISQ = 2 };
@@ -32,11 +56,12 @@ struct SplitEpi {
   int64_t null3;
 };
 
+template <typename T>
 struct SplitArgs {
-  const double* in;
-  double* out;
-  const double* Qs;   // [2][H][H]: Qs[par][k][e]
-  const double* QsT;  // [2][H][H]: QsT[par][e][k]
+  const T* in;
+  T* out;
+  const T* Qs;   // [2][H][H]: Qs[par][k][e]
+  const T* QsT;  // [2][H][H]: QsT[par][e][k]
   int N, H;
   int64_t P;          // LEFT: contiguous length of a line (plane or row); RIGHT: unused
   int64_t R;          // RIGHT: number of rows; LEFT: unused
@@ -51,15 +76,16 @@ constexpr int BK = 16;
 // (BM/2) x (BN/2) block of 16x16 MFMA accumulators).  RIGHT kinds: m = row, n = mode (fwd) or position
 // (inv).  LEFT kinds: m = mode (fwd) or position (inv), n = line position p.
 // The inverse kinds keep two accumulator sets (even -> t, odd -> u).
-template <int KIND, int EPI, int BM, int BN>
-__global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep) {
+template <typename T, int KIND, int EPI, int BM, int BN>
+__global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
+  typedef typename Mfma<T>::acc_t acc_t;
   constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
   constexpr bool RIGHT = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
   constexpr int NS = INV ? 2 : 1;  // operand sets
   constexpr int RM = BM / 32, RN = BN / 32;   // 16x16 blocks per wave
   constexpr int AE = BM * BK / 256, BE = BK * BN / 256;  // tile elements per thread
-  __shared__ double As[NS][BK][BM + 2];
-  __shared__ double Bs[NS][BK][BN + 2];
+  __shared__ T As[NS][BK][BM + 2];
+  __shared__ T Bs[NS][BK][BN + 2];
 
   const int pars = INV ? 1 : 2;
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * pars;
@@ -90,9 +116,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
   }
   if (INV) par = 0;
   const int N = a.N, H = a.H;
-  const double sgn = par ? -1.0 : 1.0;
-  const double* in = a.in + (RIGHT ? 0 : b * a.bstride);
-  double* out = a.out + (RIGHT ? 0 : b * a.bstride);
+  const T sgn = par ? T(-1) : T(1);
+  const T* in = a.in + (RIGHT ? 0 : b * a.bstride);
+  T* out = a.out + (RIGHT ? 0 : b * a.bstride);
   const int M = RIGHT ? (int)a.R : H;                 // rows of the output tile space
   const int64_t NN = RIGHT ? H : a.P;                 // columns of the output tile space
   const int K = H;
@@ -107,7 +133,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
   constexpr int BNT = BN / BE;                      // threads per B row
   const int bk = tid / BNT, bn = (tid % BNT) * BE;
 
-  double ra[NS][AE], rb[NS][BE];
+  T ra[NS][AE], rb[NS][BE];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -117,10 +143,10 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
         // ---- A(m, k)
         {
           const int gm = m0 + ar, gk = k0 + ak + q;
-          double v = 0.0;
+          T v = T(0);
           if (gm < M && gk < K) {
             if (KIND == RIGHT_FWD) {
-              const double* row = in + (int64_t)gm * N;
+              const T* row = in + (int64_t)gm * N;
               v = row[gk] + sgn * row[N - 1 - gk];
             } else if (KIND == RIGHT_INV) {
               v = in[(int64_t)gm * N + ps * H + gk];
@@ -139,7 +165,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
         {
           const int gk = k0 + bk;
           const int64_t gn = n0 + bn + q;
-          double v = 0.0;
+          T v = T(0);
           if (gk < K && gn < NN) {
             if (KIND == RIGHT_FWD) {
               v = a.Qs[(int64_t)ps * H * H + (int64_t)gk * H + gn];
@@ -166,13 +192,13 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
     }
   };
 
-  v4d acc[NS][RM][RN];
+  acc_t acc[NS][RM][RN];
 #pragma unroll
   for (int s = 0; s < NS; ++s)
 #pragma unroll
     for (int r = 0; r < RM; ++r)
 #pragma unroll
-      for (int c = 0; c < RN; ++c) acc[s][r][c] = v4d{0, 0, 0, 0};
+      for (int c = 0; c < RN; ++c) acc[s][r][c] = acc_t{0, 0, 0, 0};
 
   fetch(0);
   stash();
@@ -185,7 +211,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
       const int kr = kk + (lane >> 4);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        double af[RM], bf[RN];
+        T af[RM], bf[RN];
 #pragma unroll
         for (int r = 0; r < RM; ++r) af[r] = As[s][kr][wm + 16 * r + (lane & 15)];
 #pragma unroll
@@ -194,7 +220,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
         for (int r = 0; r < RM; ++r)
 #pragma unroll
           for (int c = 0; c < RN; ++c)
-            acc[s][r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[s][r][c], 0, 0, 0);
+            acc[s][r][c] = Mfma<T>::op(af[r], bf[c], acc[s][r][c]);
       }
     }
     __syncthreads();
@@ -204,7 +230,6 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
     }
   }
 
-  // D[i][j] of a 16x16 block: lane = j + 16 * (i % 4), element i / 4.
 #pragma unroll
   for (int r = 0; r < RM; ++r)
 #pragma unroll
@@ -212,12 +237,12 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
       const int64_t gn = n0 + wn + c * 16 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int gm = m0 + wm + r * 16 + (lane >> 4) + 4 * q;
+        const int gm = m0 + wm + r * 16 + Mfma<T>::row(lane, q);
         if (gm >= M || gn >= NN) continue;
         if (!INV) {
           double v = acc[0][r][c][q];
           if (RIGHT) {
-            out[(int64_t)gm * N + par * H + gn] = v;
+            out[(int64_t)gm * N + par * H + gn] = (T)v;
           } else {
             const int mode = par * H + gm;
             if (EPI == EPI_DIVIDE) {
@@ -226,7 +251,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
               const int64_t flat = (int64_t)mode * ((int64_t)ep.nx * ep.ny) + gn;
               v = (flat == ep.null3) ? 0.0 : v / (ep.lz[mode] + ep.ly[bb] + ep.lx[aa]);
             }
-            out[(int64_t)mode * a.P + gn] = v;
+            out[(int64_t)mode * a.P + gn] = (T)v;
           }
         } else {
           const double t = acc[0][r][c][q], u = acc[1][r][c][q];
@@ -239,21 +264,21 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs a, SplitEpi ep)
               lo *= ep.isx[i] * syz;
               hi *= ep.isx[N - 1 - i] * syz;
             }
-            out[(int64_t)gm * N + i] = lo;
-            out[(int64_t)gm * N + (N - 1 - i)] = hi;
+            out[(int64_t)gm * N + i] = (T)lo;
+            out[(int64_t)gm * N + (N - 1 - i)] = (T)hi;
           } else {
             const int i = gm;
-            out[(int64_t)i * a.P + gn] = lo;
-            out[(int64_t)(N - 1 - i) * a.P + gn] = hi;
+            out[(int64_t)i * a.P + gn] = (T)lo;
+            out[(int64_t)(N - 1 - i) * a.P + gn] = (T)hi;
           }
         }
       }
     }
 }
 
-template <int KIND, int EPI, int BM, int BN>
-hipError_t launch_tiles(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) {
-  SplitArgs a = a0;
+template <typename T, int KIND, int EPI, int BM, int BN>
+hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t s) {
+  SplitArgs<T> a = a0;
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
   const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
   const int64_t M = right ? a.R : a.H;
@@ -262,7 +287,7 @@ hipError_t launch_tiles(const SplitArgs& a0, const SplitEpi& ep, hipStream_t s) 
   a.ntiles = (int)((NN + BN - 1) / BN);
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
   const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_split_kernel<KIND, EPI, BM, BN><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  fd_split_kernel<T, KIND, EPI, BM, BN><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
   return hipGetLastError();
 }
 
@@ -280,30 +305,27 @@ int tile_choice() {
   return t;
 }
 
-template <int KIND, int EPI>
-hipError_t launch(const SplitArgs& a, const SplitEpi& ep, hipStream_t s) {
+template <typename T, int KIND, int EPI>
+hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
   const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
-  if (a.H >= 96 && tile_choice() == 128) {
-    if (inv) return right ? launch_tiles<KIND, EPI, 128, 64>(a, ep, s) : launch_tiles<KIND, EPI, 64, 128>(a, ep, s);
-    return launch_tiles<KIND, EPI, 128, 128>(a, ep, s);
+  if (sizeof(T) == 8 && a.H >= 96 && tile_choice() == 128) {
+    if (inv)
+      return right ? launch_tiles<T, KIND, EPI, 128, 64>(a, ep, s) : launch_tiles<T, KIND, EPI, 64, 128>(a, ep, s);
+    return launch_tiles<T, KIND, EPI, 128, 128>(a, ep, s);
   }
-  return launch_tiles<KIND, EPI, 64, 64>(a, ep, s);
+  return launch_tiles<T, KIND, EPI, 64, 64>(a, ep, s);
 }
 
-}  // namespace
-
-// One axis pass of the split transform.  axis 0 (x): RIGHT kinds on rows of
-// length nx; axis 1 (y): LEFT kinds on lines of nx, batched over z; axis 2
-// (z): LEFT kinds on lines of nx*ny.  epi: 0 none, 1 spectral divide (z
-// forward), 2 S^-1 scaling (x inverse).
-hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const double* in, double* out) {
+template <typename T>
+hipError_t split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const T* in, T* out, const T* Qs,
+                      const T* QsT) {
   const Grid& g = c->g;
-  SplitArgs a{};
+  SplitArgs<T> a{};
   a.in = in;
   a.out = out;
-  a.Qs = c->Qf[axis];
-  a.QsT = c->Qt[axis];
+  a.Qs = Qs;
+  a.QsT = QsT;
   a.N = g.ax[axis].n;
   a.H = a.N / 2;
   a.batch = 1;
@@ -321,15 +343,44 @@ hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi
               g.nx, g.ny, g.null3};
   hipStream_t s = c->stream;
   if (axis == 0) {
-    if (!inverse) return launch<RIGHT_FWD, EPI_NONE>(a, ep, s);
-    if (epi == 2) return launch<RIGHT_INV, EPI_ISQ>(a, ep, s);
-    return launch<RIGHT_INV, EPI_NONE>(a, ep, s);
+    if (!inverse) return launch<T, RIGHT_FWD, EPI_NONE>(a, ep, s);
+    if (epi == 2) return launch<T, RIGHT_INV, EPI_ISQ>(a, ep, s);
+    return launch<T, RIGHT_INV, EPI_NONE>(a, ep, s);
   }
   if (!inverse) {
-    if (epi == 1) return launch<LEFT_FWD, EPI_DIVIDE>(a, ep, s);
-    return launch<LEFT_FWD, EPI_NONE>(a, ep, s);
+    if (epi == 1) return launch<T, LEFT_FWD, EPI_DIVIDE>(a, ep, s);
+    return launch<T, LEFT_FWD, EPI_NONE>(a, ep, s);
   }
-  return launch<LEFT_INV, EPI_NONE>(a, ep, s);
+  return launch<T, LEFT_INV, EPI_NONE>(a, ep, s);
+}
+
+}  // namespace
+
+// One axis pass of the split transform.  axis 0 (x): RIGHT kinds on rows of
+// length nx; axis 1 (y): LEFT kinds on lines of nx, batched over z; axis 2
+// (z): LEFT kinds on lines of nx*ny.  epi: 0 none, 1 spectral divide (z
+// forward), 2 S^-1 scaling (x inverse).
+hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const double* in, double* out) {
+  return split_pass<double>(c, axis, inverse, epi, in, out, c->Qf[axis], c->Qt[axis]);
+}
+
+// The same in FP32 storage on the FP32 matrix cores (mixed form).
+hipError_t launch_fd_split_pass_f32(const kv_ctx* c, int axis, bool inverse, int epi, const float* in, float* out) {
+  return split_pass<float>(c, axis, inverse, epi, in, out, c->Qf32[axis], c->Qt32[axis]);
+}
+
+// Poisson solve in FP32 storage: in (scaled divergence) -> out (pressure);
+// every axis must be split.  in is overwritten.
+hipError_t launch_fd_solve_f32(const kv_ctx* c, float* in, float* out) {
+  float* A = in;
+  float* Bf = reinterpret_cast<float*>(c->cellB);
+  hipError_t e;
+  if ((e = launch_fd_split_pass_f32(c, 0, false, 0, A, Bf))) return e;
+  if ((e = launch_fd_split_pass_f32(c, 1, false, 0, Bf, A))) return e;
+  if ((e = launch_fd_split_pass_f32(c, 2, false, 1, A, Bf))) return e;
+  if ((e = launch_fd_split_pass_f32(c, 2, true, 0, Bf, A))) return e;
+  if ((e = launch_fd_split_pass_f32(c, 1, true, 0, A, Bf))) return e;
+  return launch_fd_split_pass_f32(c, 0, true, 2, Bf, out);
 }
 
 }  // namespace kv

@@ -48,6 +48,9 @@ struct kv_ctx {
   double* Qf[3] = {nullptr, nullptr, nullptr};   // Q (n x n row-major): forward uses Q
   double* Qt[3] = {nullptr, nullptr, nullptr};   // Q^T
   int split[3] = {0, 0, 0};   // 1: mirror-symmetric axis, Qf/Qt hold the even/odd half bases
+  float* Qf32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the split bases (mixed form)
+  float* Qt32[3] = {nullptr, nullptr, nullptr};
+  double* ymix = nullptr;     // FP64 scratch vector for the mixed refinement sweeps
   double* X0 = nullptr;       // base flow copy
   bool has_base = false;
   double* cellA = nullptr;    // two cell-sized scratch fields for the Poisson solve
@@ -80,6 +83,15 @@ hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* ou
 hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out);
 // One axis pass of the even/odd split transform (mirror-symmetric axes).
 hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const double* in, double* out);
+hipError_t launch_fd_split_pass_f32(const kv_ctx* c, int axis, bool inverse, int epi, const float* in, float* out);
+// FP32-storage Poisson solve (all axes split): in = scaled divergence, out = p
+hipError_t launch_fd_solve_f32(const kv_ctx* c, float* in, float* out);
+// mixed form: FP32 b = V^1/2 D y from FP64 y
+hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float* out);
+// mixed form: yout = yin - G p (FP32 p), and from the corrected field the
+// next scaled divergence bnext (FP32, may be null) and block maxima of
+// |net flux| and |face flux| (c->part) finished into c->dres[0..2)
+hipError_t launch_correct_divergence(kv_ctx* c, const double* yin, const float* p, double* yout, float* bnext);
 // y_vel -= G p
 hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* y);
 

@@ -503,6 +503,86 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
   out[((int64_t)k * g.ny + j) * g.nx + i] = net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]);
 }
 
+__device__ __forceinline__ double fin_abs(double v);
+
+// Mixed form: the same scaled divergence of an FP64 field, stored in FP32.
+__global__ void __launch_bounds__(256) scaled_divergence_f32_kernel(Grid g, const double* __restrict__ y,
+                                                                    float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const double fx = Uat(y, g, i + 1, j, k) - Uat(y, g, i, j, k);
+  const double fy = Vat(y, g, i, j + 1, k) - Vat(y, g, i, j, k);
+  const double fz = Wat(y, g, i, j, k + 1) - Wat(y, g, i, j, k);
+  const double hx = g.ax[0].h[i], hy = g.ax[1].h[j], hz = g.ax[2].h[k];
+  const double net = hy * hz * fx + hx * hz * fy + hx * hy * fz;
+  out[((int64_t)k * g.ny + j) * g.nx + i] = (float)(net * (g.ax[0].isq[i] * g.ax[1].isq[j] * g.ax[2].isq[k]));
+}
+
+// Mixed-form refinement sweep, fused: yout = yin - G p on the velocity (T
+// copied), and from the corrected field (every face of the cell corrected
+// locally from p, so no thread reads another's output) the net flux of the
+// cell: its scaled value feeds the next sweep (bnext, FP32, optional) and
+// block maxima of |net flux| and |face flux| give the normalized divergence.
+__global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const double* __restrict__ yin,
+                                                                 const float* __restrict__ p,
+                                                                 double* __restrict__ yout,
+                                                                 float* __restrict__ bnext,
+                                                                 double* __restrict__ part) {
+  __shared__ double s0[256], s1[256];
+  const int t = threadIdx.x;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t C = (int64_t)nx * ny * nz;
+  const int64_t plane = (int64_t)nx * ny;
+  double mb = 0.0, mf = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + t; c < C; c += (int64_t)gridDim.x * 256) {
+    const int i = (int)(c % nx);
+    const int j = (int)((c / nx) % ny);
+    const int k = (int)(c / plane);
+    const double pc = p[c];
+    const Axis& AX = g.ax[0];
+    const Axis& AY = g.ax[1];
+    const Axis& AZ = g.ax[2];
+    double u0 = 0.0, u1 = 0.0, v0 = 0.0, v1 = 0.0, w0 = 0.0, w1 = 0.0;
+    if (i >= 1) {
+      u0 = Uat(yin, g, i, j, k) - (pc - p[c - 1]) * AX.id[i];
+      yout[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] = u0;
+    }
+    if (i + 1 <= nx - 1) u1 = Uat(yin, g, i + 1, j, k) - (p[c + 1] - pc) * AX.id[i + 1];
+    if (j >= 1) {
+      v0 = Vat(yin, g, i, j, k) - (pc - p[c - nx]) * AY.id[j];
+      yout[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] = v0;
+    }
+    if (j + 1 <= ny - 1) v1 = Vat(yin, g, i, j + 1, k) - (p[c + nx] - pc) * AY.id[j + 1];
+    if (k >= 1) {
+      w0 = Wat(yin, g, i, j, k) - (pc - p[c - plane]) * AZ.id[k];
+      yout[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = w0;
+    }
+    if (k + 1 <= nz - 1) w1 = Wat(yin, g, i, j, k + 1) - (p[c + plane] - pc) * AZ.id[k + 1];
+    yout[g.oT + c] = yin[g.oT + c];
+    const double hx = AX.h[i], hy = AY.h[j], hz = AZ.h[k];
+    const double net = hy * hz * (u1 - u0) + hx * hz * (v1 - v0) + hx * hy * (w1 - w0);
+    if (bnext) bnext[c] = (float)(net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]));
+    mb = fmax(mb, fin_abs(net));
+    mf = fmax(mf, fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy))));
+  }
+  s0[t] = mb;
+  s1[t] = mf;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s0[t] = fmax(s0[t], s0[t + o]);
+      s1[t] = fmax(s1[t], s1[t + o]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = s0[0];
+    part[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
 // y_vel -= G p at the interior faces owned by cell (i, j, k)
 __global__ void __launch_bounds__(256) gradient_correction_kernel(Grid g, const double* __restrict__ p,
                                                                   double* __restrict__ y) {
@@ -647,6 +727,19 @@ hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, d
 hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* out) {
   const Grid& g = c->g;
   scaled_divergence_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float* out) {
+  const Grid& g = c->g;
+  scaled_divergence_f32_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct_divergence(kv_ctx* c, const double* yin, const float* p, double* yout, float* bnext) {
+  const int nblk = c->npart_blocks;
+  correct_divergence_kernel<<<nblk, 256, 0, c->stream>>>(c->g, yin, p, yout, bnext, c->part);
+  max_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, 2, c->dres);
   return hipGetLastError();
 }
 

@@ -153,14 +153,15 @@ class Context:
         self._check(self._lib.kv_residual(self._h, _dptr(F, self.n), ctypes.byref(norm)))
         return norm.value
 
-    def apply_jacobian(self, x, y, project=True):
-        flags = KV_PROJECT if project else 0
+    def apply_jacobian(self, x, y, project=True, mixed=False):
+        flags = (KV_PROJECT if project else 0) | (KV_MIXED if mixed else 0)
         self._check(self._lib.kv_apply_jacobian(self._h, _dptr(x, self.n), _dptr(y, self.n), flags))
 
-    def project(self, y):
+    def project(self, y, mixed=False):
         dm = ctypes.c_double()
         sw = ctypes.c_int()
-        self._check(self._lib.kv_project(self._h, _dptr(y, self.n), KV_PROJECT, ctypes.byref(dm),
+        flags = KV_PROJECT | (KV_MIXED if mixed else 0)
+        self._check(self._lib.kv_project(self._h, _dptr(y, self.n), flags, ctypes.byref(dm),
                                          ctypes.byref(sw)))
         return dm.value, sw.value
 

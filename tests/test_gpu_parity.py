@@ -113,3 +113,48 @@ def test_error_codes():
     with pytest.raises(kv.KVError) as e:
         kv.Context(f[::-1].copy(), f, f, Gr=1e5, Pr=0.71)
     assert e.value.code == kv.KV_EINVAL
+
+
+# ---- mixed form: FP32 fast diagonalization refined on the FP64 residual ---------
+MIXED_GRIDS = [
+    ("uniform", (32, 32, 32), 1e5, 3, 0.05),
+    ("clustered", (24, 18, 20), 4e7, 4, 0.1),
+    ("clustered", (64, 64, 64), 2e8, 6, 0.1),
+]
+TOL_MIXED = 1e-5
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", MIXED_GRIDS)
+def test_mixed_projected_jacobian(kind, shape, Gr, K, amp):
+    print(f"case mixed PJ {kind} {shape}", flush=True)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    x = S.perturbation(g.size, 1000)
+    y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    ctx.apply_jacobian(to_dev(x), y, project=True, mixed=True)
+    got = to_host(y)
+    ref = O.apply_jacobian(g, X0, x)
+    err = field_rel_errors(g, got, ref)
+    print("mixed field errors", err, flush=True)
+    assert max(err) <= TOL_MIXED, err
+    assert O.div_measure(g, got) <= 1e-10
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", MIXED_GRIDS[:2])
+def test_mixed_project_reports_sweeps(kind, shape, Gr, K, amp):
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    y0 = S.perturbation(g.size, 8)
+    y = to_dev(y0)
+    dm, sweeps = ctx.project(y, mixed=True)
+    assert sweeps >= 2 and sweeps % 2 == 0
+    assert dm <= 1e-10
+    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL_MIXED
+
+
+def test_mixed_falls_back_on_unsplit_grid():
+    """Odd cell counts have no even/odd split: the FP64 projection runs."""
+    g, X0, ctx = make("clustered", (7, 6, 5), 2e5, 2, 0.1)
+    y0 = S.perturbation(g.size, 9)
+    y = to_dev(y0)
+    dm, sweeps = ctx.project(y, mixed=True)
+    assert sweeps == 1
+    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL64
