@@ -86,7 +86,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4, help="resident perturbations cycled over")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=("fp64", "mixed", "both"), default="both",
-                    help="projection form(s) to time; the headline value is the mixed form's")
+                    help="projection form(s) to time; the headline value is the faster form's")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="also run this many plain device copies of one vector (a known-size "
                          "reference for hardware byte counters)")
@@ -187,16 +187,18 @@ def main():
     for _ in range(args.copy_ref):
         ys[0].copy_(xs[0])
     torch.cuda.synchronize()
-    head = forms["mixed"] if "mixed" in forms else forms["fp64"]
+    # headline: the faster form (both are reported under "forms")
+    head_name = max(forms, key=lambda k: forms[k]["value"])
+    head = forms[head_name]
     result = {
         "metric": "Krylov vectors/s (J.v+projection) at 256^3, % HBM roofline; mixed vs FP64",
         "value": round(head["value"], 3), "unit": "Krylov vectors/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 stencil + f32 transforms + f64 refinement" if "mixed" in forms else "f64",
+        "dtype": "f64 stencil + f32 transforms + f64 refinement" if head_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{spec['n']}^3 {spec['grid']}", "Gr": spec["Gr"],
-                   "Pr": spec["Pr"], "form": "mixed" if "mixed" in forms else "fp64", "resident_batch": B,
+                   "Pr": spec["Pr"], "form": head_name, "resident_batch": B,
                    "unknowns": n},
         "roofline": head["roofline"],
         "roofline_secondary": head["roofline_secondary"],

@@ -48,7 +48,9 @@ struct HostAxis {
   bool split = false;  // Q / Qt hold the even/odd half bases [2][H][H]
 };
 
-bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
+void general_basis(HostAxis& a, std::vector<double>& M);
+
+bool build_axis(const double* f, int n, HostAxis& a, std::string& err, bool allow_split = true) {
   a.n = n;
   if (std::fabs(f[0]) > 1e-14 || std::fabs(f[n] - 1.0) > 1e-14) {
     err = "faces must start at 0 and end at 1";
@@ -97,7 +99,7 @@ bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
   // Mirror-symmetric axis (h_i = h_{n-1-i} to round-off, n even): M is
   // persymmetric and its eigenvectors are [w; +-J w]/sqrt(2) with w the
   // eigenvectors of the half blocks M_11 +- M_{H-1,H} e_{H-1} e_{H-1}^T.
-  bool sym = (n % 2 == 0) && n >= 4;
+  bool sym = allow_split && (n % 2 == 0) && n >= 4;
   for (int i = 0; sym && i < n; ++i)
     if (a.h[i] != a.h[n - 1 - i]) sym = false;
   if (sym) {
@@ -134,13 +136,25 @@ bool build_axis(const double* f, int n, HostAxis& a, std::string& err) {
     a.lam[a.null_idx] = 0.0;  // K annihilates constants: the exact eigenvalue is 0
     return true;
   }
+  general_basis(a, M);
+  return true;
+}
+
+// Full n x n eigenbasis of M (no even/odd split).
+void general_basis(HostAxis& a, std::vector<double>& M) {
+  const int n = a.n;
+  a.split = false;
   jacobi_eigen(n, M, a.Q, a.lam);
   a.null_idx = (int)(std::max_element(a.lam.begin(), a.lam.end()) - a.lam.begin());
   a.lam[a.null_idx] = 0.0;  // K annihilates constants: the exact eigenvalue is 0
   a.Qt.resize((size_t)n * n);
   for (int r = 0; r < n; ++r)
     for (int cc = 0; cc < n; ++cc) a.Qt[(size_t)cc * n + r] = a.Q[(size_t)r * n + cc];
-  return true;
+}
+
+void build_axis_general(const double* f, int n, HostAxis& a) {
+  std::string err;
+  build_axis(f, n, a, err, false);
 }
 
 // ---- small device helpers -----------------------------------------------------------
@@ -578,7 +592,15 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
     A.lam = base + offs[a][8];
     A.c = base + offs[a][9];
     const size_t nn = ax[a].Q.size();
-    c->split[a] = ax[a].split ? 1 : 0;
+    // the split kernels address a cell field with 32-bit byte offsets
+    c->split[a] = (ax[a].split && c->ncell * 8 < ((int64_t)1 << 31)) ? 1 : 0;
+    if (ax[a].split && !c->split[a]) {
+      // rebuild this axis as a general (unsplit) basis
+      HostAxis full;
+      std::string e2;
+      build_axis_general(faces[a], ns[a], full);
+      ax[a] = full;
+    }
     if (hipMalloc(&c->Qf[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Q");
     if (hipMalloc(&c->Qt[a], nn * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "Qt");
     if (hipMemcpy(c->Qf[a], ax[a].Q.data(), nn * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -602,6 +624,13 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   if (hipMalloc(&c->part, (size_t)512 * c->npart_blocks * sizeof(double)) != hipSuccess)
     return cleanup(KV_ENOMEM, "part");
   if (hipMalloc(&c->dres, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dres");
+  {
+    // one pair of maxima per 64 x 4 block of the cell grid
+    const int64_t cb = ((nx + 63) / 64) * ((ny + 3) / 4) * nz;
+    c->cell_part_len = 2 * cb;
+    if (hipMalloc(&c->cell_part, c->cell_part_len * sizeof(double)) != hipSuccess)
+      return cleanup(KV_ENOMEM, "cell_part");
+  }
   if (hipHostMalloc(&c->hres, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(KV_ENOMEM, "hres");
   *out = c;
@@ -620,6 +649,7 @@ int kv_destroy(kv_ctx* c) {
     hipFree(c->Qt32[a]);
   }
   hipFree(c->ymix);
+  hipFree(c->cell_part);
   hipFree(c->X0);
   hipFree(c->cellA);
   hipFree(c->cellB);

@@ -56,6 +56,23 @@ struct SplitEpi {
   int64_t null3;
 };
 
+constexpr int OOB = 0x7ffffff8;  // a byte offset past every buffer: raw buffer loads return 0
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, (int)(n * (int64_t)sizeof(T)), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, int off);
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 template <typename T>
 struct SplitArgs {
   const T* in;
@@ -70,13 +87,11 @@ struct SplitArgs {
   int mtiles, ntiles;
 };
 
-constexpr int BK = 16;
-
 // One BM x BN output tile (4 waves in a 2 x 2 layout, each wave a
 // (BM/2) x (BN/2) block of 16x16 MFMA accumulators).  RIGHT kinds: m = row, n = mode (fwd) or position
 // (inv).  LEFT kinds: m = mode (fwd) or position (inv), n = line position p.
 // The inverse kinds keep two accumulator sets (even -> t, odd -> u).
-template <typename T, int KIND, int EPI, int BM, int BN>
+template <typename T, int KIND, int EPI, int BM, int BN, int BK>
 __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
@@ -117,7 +132,6 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
   if (INV) par = 0;
   const int N = a.N, H = a.H;
   const T sgn = par ? T(-1) : T(1);
-  const T* in = a.in + (RIGHT ? 0 : b * a.bstride);
   T* out = a.out + (RIGHT ? 0 : b * a.bstride);
   const int M = RIGHT ? (int)a.R : H;                 // rows of the output tile space
   const int64_t NN = RIGHT ? H : a.P;                 // columns of the output tile space
@@ -133,51 +147,57 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
   constexpr int BNT = BN / BE;                      // threads per B row
   const int bk = tid / BNT, bn = (tid % BNT) * BE;
 
+  // Operand prefetch: raw buffer loads with 32-bit byte offsets (an offset
+  // past the buffer reads 0, so edges need no branch and no load waits
+  // inside the prefetch); the butterfly partner of a forward operand is
+  // fetched separately and combined when the chunk is stashed into LDS.
+  constexpr bool AFLY = (KIND == RIGHT_FWD), BFLY = (KIND == LEFT_FWD);
+  const int64_t in_elems = RIGHT ? a.R * (int64_t)N : (int64_t)a.batch * a.bstride + (a.batch == 1 ? (int64_t)N * a.P : 0);
+  const __amdgpu_buffer_rsrc_t rin = make_rsrc(a.in, in_elems);
+  const __amdgpu_buffer_rsrc_t rq = make_rsrc(a.Qs, 2 * (int64_t)H * H);
+  const __amdgpu_buffer_rsrc_t rqt = make_rsrc(a.QsT, 2 * (int64_t)H * H);
+  const int64_t boff = RIGHT ? 0 : b * a.bstride;  // batch offset of a LEFT line block
   T ra[NS][AE], rb[NS][BE];
+  T rah[AFLY ? NS : 1][AFLY ? AE : 1], rbh[BFLY ? NS : 1][BFLY ? BE : 1];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int ps = INV ? s : par;  // parity of this operand set
 #pragma unroll
       for (int q = 0; q < AE; ++q) {
-        // ---- A(m, k)
-        {
-          const int gm = m0 + ar, gk = k0 + ak + q;
-          T v = T(0);
-          if (gm < M && gk < K) {
-            if (KIND == RIGHT_FWD) {
-              const T* row = in + (int64_t)gm * N;
-              v = row[gk] + sgn * row[N - 1 - gk];
-            } else if (KIND == RIGHT_INV) {
-              v = in[(int64_t)gm * N + ps * H + gk];
-            } else if (KIND == LEFT_FWD) {
-              v = a.QsT[(int64_t)ps * H * H + (int64_t)gm * H + gk];
-            } else {
-              v = a.Qs[(int64_t)ps * H * H + (int64_t)gm * H + gk];
-            }
-          }
-          ra[s][q] = v;
+        const int gm = m0 + ar, gk = k0 + ak + q;
+        const bool ok = gm < M && gk < K;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD) {
+          o = ok ? (gm * N + gk) * (int)sizeof(T) : OOB;
+          oh = ok ? (gm * N + N - 1 - gk) * (int)sizeof(T) : OOB;
+        } else if (KIND == RIGHT_INV) {
+          o = ok ? (gm * N + ps * H + gk) * (int)sizeof(T) : OOB;
+        } else {
+          o = ok ? ((ps * H + gm) * H + gk) * (int)sizeof(T) : OOB;
         }
+        if (KIND == RIGHT_FWD || KIND == RIGHT_INV) ra[s][q] = bload<T>(rin, o);
+        else if (KIND == LEFT_FWD) ra[s][q] = bload<T>(rqt, o);
+        else ra[s][q] = bload<T>(rq, o);
+        if (AFLY) rah[AFLY ? s : 0][AFLY ? q : 0] = bload<T>(rin, oh);
       }
 #pragma unroll
       for (int q = 0; q < BE; ++q) {
-        // ---- B(k, n)
-        {
-          const int gk = k0 + bk;
-          const int64_t gn = n0 + bn + q;
-          T v = T(0);
-          if (gk < K && gn < NN) {
-            if (KIND == RIGHT_FWD) {
-              v = a.Qs[(int64_t)ps * H * H + (int64_t)gk * H + gn];
-            } else if (KIND == RIGHT_INV) {
-              v = a.QsT[(int64_t)ps * H * H + (int64_t)gk * H + gn];
-            } else if (KIND == LEFT_FWD) {
-              v = in[(int64_t)gk * a.P + gn] + sgn * in[(int64_t)(N - 1 - gk) * a.P + gn];
-            } else {
-              v = in[(int64_t)(ps * H + gk) * a.P + gn];
-            }
-          }
-          rb[s][q] = v;
+        const int gk = k0 + bk;
+        const int64_t gn = n0 + bn + q;
+        const bool ok = gk < K && gn < NN;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD || KIND == RIGHT_INV) {
+          o = ok ? ((ps * H + gk) * H + (int)gn) * (int)sizeof(T) : OOB;
+          rb[s][q] = bload<T>(KIND == RIGHT_FWD ? rq : rqt, o);
+        } else if (KIND == LEFT_FWD) {
+          o = ok ? (int)((boff + (int64_t)gk * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          oh = ok ? (int)((boff + (int64_t)(N - 1 - gk) * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          rb[s][q] = bload<T>(rin, o);
+          rbh[BFLY ? s : 0][BFLY ? q : 0] = bload<T>(rin, oh);
+        } else {
+          o = ok ? (int)((boff + (int64_t)(ps * H + gk) * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          rb[s][q] = bload<T>(rin, o);
         }
       }
     }
@@ -186,9 +206,11 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
-      for (int q = 0; q < AE; ++q) As[s][ak + q][ar] = ra[s][q];
+      for (int q = 0; q < AE; ++q)
+        As[s][ak + q][ar] = AFLY ? ra[s][q] + sgn * rah[AFLY ? s : 0][AFLY ? q : 0] : ra[s][q];
 #pragma unroll
-      for (int q = 0; q < BE; ++q) Bs[s][bk][bn + q] = rb[s][q];
+      for (int q = 0; q < BE; ++q)
+        Bs[s][bk][bn + q] = BFLY ? rb[s][q] + sgn * rbh[BFLY ? s : 0][BFLY ? q : 0] : rb[s][q];
     }
   };
 
@@ -276,7 +298,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
     }
 }
 
-template <typename T, int KIND, int EPI, int BM, int BN>
+template <typename T, int KIND, int EPI, int BM, int BN, int BK>
 hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t s) {
   SplitArgs<T> a = a0;
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
@@ -287,7 +309,7 @@ hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t 
   a.ntiles = (int)((NN + BN - 1) / BN);
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
   const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_split_kernel<T, KIND, EPI, BM, BN><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  fd_split_kernel<T, KIND, EPI, BM, BN, BK><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
   return hipGetLastError();
 }
 
@@ -305,16 +327,28 @@ int tile_choice() {
   return t;
 }
 
+// K-chunk staged per LDS round: 16 by default, KV_FD_BK=32 for deeper chunks.
+int bk_choice() {
+  static int t = -1;
+  if (t < 0) {
+    const char* e = getenv("KV_FD_BK");
+    t = (e && atoi(e) == 32) ? 32 : 16;
+  }
+  return t;
+}
+
 template <typename T, int KIND, int EPI>
 hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
   const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
   if (sizeof(T) == 8 && a.H >= 96 && tile_choice() == 128) {
     if (inv)
-      return right ? launch_tiles<T, KIND, EPI, 128, 64>(a, ep, s) : launch_tiles<T, KIND, EPI, 64, 128>(a, ep, s);
-    return launch_tiles<T, KIND, EPI, 128, 128>(a, ep, s);
+      return right ? launch_tiles<T, KIND, EPI, 128, 64, 16>(a, ep, s)
+                   : launch_tiles<T, KIND, EPI, 64, 128, 16>(a, ep, s);
+    return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
   }
-  return launch_tiles<T, KIND, EPI, 64, 64>(a, ep, s);
+  if (a.H >= 32 && bk_choice() == 32) return launch_tiles<T, KIND, EPI, 64, 64, 32>(a, ep, s);
+  return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
 }
 
 template <typename T>

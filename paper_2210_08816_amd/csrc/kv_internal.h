@@ -51,6 +51,8 @@ struct kv_ctx {
   float* Qf32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the split bases (mixed form)
   float* Qt32[3] = {nullptr, nullptr, nullptr};
   double* ymix = nullptr;     // FP64 scratch vector for the mixed refinement sweeps
+  double* cell_part = nullptr;  // per-block maxima of the cell-grid kernels (2 per block)
+  int64_t cell_part_len = 0;
   double* X0 = nullptr;       // base flow copy
   bool has_base = false;
   double* cellA = nullptr;    // two cell-sized scratch fields for the Poisson solve

@@ -531,15 +531,15 @@ __global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const d
                                                                  float* __restrict__ bnext,
                                                                  double* __restrict__ part) {
   __shared__ double s0[256], s1[256];
-  const int t = threadIdx.x;
+  const int t = threadIdx.y * blockDim.x + threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int64_t C = (int64_t)nx * ny * nz;
   const int64_t plane = (int64_t)nx * ny;
   double mb = 0.0, mf = 0.0;
-  for (int64_t c = (int64_t)blockIdx.x * 256 + t; c < C; c += (int64_t)gridDim.x * 256) {
-    const int i = (int)(c % nx);
-    const int j = (int)((c / nx) % ny);
-    const int k = (int)(c / plane);
+  if (i < nx && j < ny) {
+    const int64_t c = k * plane + (int64_t)j * nx + i;
     const double pc = p[c];
     const Axis& AX = g.ax[0];
     const Axis& AY = g.ax[1];
@@ -564,22 +564,24 @@ __global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const d
     const double hx = AX.h[i], hy = AY.h[j], hz = AZ.h[k];
     const double net = hy * hz * (u1 - u0) + hx * hz * (v1 - v0) + hx * hy * (w1 - w0);
     if (bnext) bnext[c] = (float)(net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]));
-    mb = fmax(mb, fin_abs(net));
-    mf = fmax(mf, fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy))));
+    mb = fin_abs(net);
+    mf = fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy)));
   }
-  s0[t] = mb;
-  s1[t] = mf;
+  // wavefront maxima by lane exchange, then the 4 waves through LDS
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mb = fmax(mb, __shfl_xor(mb, o, 64));
+    mf = fmax(mf, __shfl_xor(mf, o, 64));
+  }
+  if ((t & 63) == 0) {
+    s0[t >> 6] = mb;
+    s1[t >> 6] = mf;
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) {
-      s0[t] = fmax(s0[t], s0[t + o]);
-      s1[t] = fmax(s1[t], s1[t + o]);
-    }
-    __syncthreads();
-  }
   if (t == 0) {
-    part[2 * blockIdx.x] = s0[0];
-    part[2 * blockIdx.x + 1] = s1[0];
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[2 * blk] = fmax(fmax(s0[0], s0[1]), fmax(s0[2], s0[3]));
+    part[2 * blk + 1] = fmax(fmax(s1[0], s1[1]), fmax(s1[2], s1[3]));
   }
 }
 
@@ -737,9 +739,12 @@ hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float*
 }
 
 hipError_t launch_correct_divergence(kv_ctx* c, const double* yin, const float* p, double* yout, float* bnext) {
-  const int nblk = c->npart_blocks;
-  correct_divergence_kernel<<<nblk, 256, 0, c->stream>>>(c->g, yin, p, yout, bnext, c->part);
-  max_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, 2, c->dres);
+  const Grid& g = c->g;
+  const dim3 grid = cell_grid(g);
+  const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
+  if (2 * nblk > c->cell_part_len) return hipErrorInvalidValue;
+  correct_divergence_kernel<<<grid, cell_block(g), 0, c->stream>>>(g, yin, p, yout, bnext, c->cell_part);
+  max_finish_kernel<<<1, 256, 0, c->stream>>>(c->cell_part, (int)nblk, 2, c->dres);
   return hipGetLastError();
 }
 
