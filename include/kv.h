@@ -134,7 +134,9 @@ typedef struct {
  * (Sleijpen-Fokkema form, shadow vector = initial residual), continued by
  * restarted GMRES(40) from the current iterate after a breakdown or 50
  * cycles without a 10% residual reduction.  F is projected once more before
- * the solve.  Stops when relres <= tol or after max_matvec matvecs
+ * the solve, and a converged delta is projected once more at the end (the
+ * Krylov combination is divergence-free only up to cancellation among its
+ * terms).  Stops when relres <= tol or after max_matvec matvecs
  * (KV_ENOCONV, delta holds the last iterate).  delta0: optional initial
  * iterate (device, may be NULL).  F, delta: device, n values.  info: host,
  * may be NULL.  flags: 0 (KV_MIXED is reserved). */
@@ -173,6 +175,47 @@ typedef struct {
  * converged within max_matvec: KV_ENOCONV with the last Ritz values. */
 int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
                             double* lam_im, double* resid, kv_eig_info* info);
+
+/* Transfers for the learned Newton guess (kvnn.h).  Not part of the paper's
+ * method: the paper starts each Newton solve from a converged state at a
+ * nearby Gr (Sec. 1); these calls turn converged states into training targets
+ * of a network and a network prediction back into a state.
+ *
+ * kv_cells_from_state: cell-centred fields of the packed state X (device) on
+ * the grid coarsened by factor in every axis (nx, ny, nz multiples of factor;
+ * factor 1 keeps the grid).  Per fine cell the centre values are
+ * u = (u_west + u_east)/2 (walls 0), likewise v and w, and
+ * theta = T - (1/2 - x_c) (the deviation from the conduction profile); a
+ * coarse cell takes the volume-weighted mean over its factor^3 fine cells.
+ * out (device FP32, 4 x (nz/f)(ny/f)(nx/f), [channel][z][y][x], channels
+ * u, v, w, theta) = (mean - shift[c]) / scale[c].  shift, scale: host, 4
+ * values, scale nonzero.  Non-finite X: KV_ENONFINITE. */
+int kv_cells_from_state(kv_ctx* ctx, const double* X, int factor, const double shift[4],
+                        const double scale[4], float* out);
+
+/* kv_state_from_cells: the inverse direction.  cells (device FP32,
+ * 4 x rz x ry x rx, as above) are values shift[c] + scale[c] * cells at the
+ * network cell centres xc (rx), yc (ry), zc (rz) (host, strictly increasing
+ * inside (0, 1)).  Every unknown of X (device, packed) becomes the trilinear
+ * interpolant, in physical coordinates, at its own position (faces for u, v,
+ * w; centres for T) over the node set extended by the walls 0 and 1 per
+ * axis: velocities are 0 on every wall; theta is 0 on the x-walls and takes
+ * the adjacent cell's value on the adiabatic y- and z-walls; T = theta +
+ * 1/2 - x_c.  The result is not projected (kv_project does that). */
+int kv_state_from_cells(kv_ctx* ctx, const float* cells, int rx, int ry, int rz, const double* xc,
+                        const double* yc, const double* zc, const double shift[4],
+                        const double scale[4], double* X);
+
+/* kv_state_add_cell_increment: X += S(cells) - S(cells_ref), where S is the
+ * interpolation of kv_state_from_cells (the shift and the conduction
+ * profile cancel, so only scale is needed).  With cells and cells_ref the
+ * network's predictions at Gr and at the Gr of a converged state X, this
+ * moves X by the predicted change of the state between the two Gr.  X is
+ * read and written (device, packed); cells and cells_ref are device FP32
+ * arrays as in kv_state_from_cells.  The result is not projected. */
+int kv_state_add_cell_increment(kv_ctx* ctx, const float* cells, const float* cells_ref, int rx, int ry,
+                                int rz, const double* xc, const double* yc, const double* zc,
+                                const double scale[4], double* X);
 
 /* Device time per phase of the projected Jacobian, measured with HIP events
  * on the context's stream around each phase of every kv_apply_jacobian and

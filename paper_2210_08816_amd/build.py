@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkv_hip.so")
 
-SOURCES = ["kv_capi.cpp", "kv_eig1d.cpp", "kv_stencil.hip", "kv_fd.hip", "kv_fd_split.hip", "kv_vec.hip", "kv_hess.hip"]
+SOURCES = ["kv_capi.cpp", "kv_eig1d.cpp", "kv_stencil.hip", "kv_fd.hip", "kv_fd_split.hip", "kv_vec.hip",
+           "kv_hess.hip", "kv_transfer.hip", "kvnn.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

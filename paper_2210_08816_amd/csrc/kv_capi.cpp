@@ -663,6 +663,7 @@ int kv_destroy(kv_ctx* c) {
   for (auto e : c->ev_pool) hipEventDestroy(e);
   hipFree(c->work);
   hipFree(c->hess);
+  hipFree(c->xfer);
   delete c;
   return KV_OK;
 }
@@ -945,11 +946,118 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
     inf.relres = rr;
     if (info) *info = inf;
     if (rc == KV_ENOCONV) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
-    return rc;
+    if (rc) return rc;
+    // the Krylov combination is divergence-free only up to cancellation
+    // among its (projected) terms; one more projection puts delta in null(D)
+    return project_inplace(c, x);
   }
   if (info) *info = inf;
   if (status == MAXIT) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
+  return project_inplace(c, x);
+}
+
+// ---- transfers to and from the network grid --------------------------------------------
+static bool affine_ok(const double shift[4], const double scale[4]) {
+  if (!shift || !scale) return false;
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(shift[q]) || !std::isfinite(scale[q]) || scale[q] == 0.0) return false;
+  return true;
+}
+
+int kv_cells_from_state(kv_ctx* c, const double* X, int factor, const double shift[4], const double scale[4],
+                        float* out) {
+  if (!c) return KV_EINVAL;
+  if (!X || !out) return fail(c, KV_EINVAL, "null argument");
+  if (factor < 1 || c->g.nx % factor || c->g.ny % factor || c->g.nz % factor)
+    return fail(c, KV_EINVAL, "the grid sizes must be multiples of factor");
+  if (!affine_ok(shift, scale)) return fail(c, KV_EINVAL, "shift/scale must be finite, scale nonzero");
+  int rc;
+  if ((rc = check_finite(c, X, c->g.n, "X"))) return rc;
+  HIPCHK(c, launch_cells_from_state(c, X, factor, shift, scale, out));
   return KV_OK;
+}
+
+// For positions s (ascending) on [0, 1]: q = lower node in e (size r + 2)
+// with q <= r, t = weight of node q + 1.
+static void interp_table(const std::vector<double>& e, const double* s, int ns, int* q, double* t) {
+  const int r = (int)e.size() - 2;
+  for (int i = 0; i < ns; ++i) {
+    int k = (int)(std::upper_bound(e.begin(), e.end(), s[i]) - e.begin()) - 1;
+    k = std::max(0, std::min(k, r));
+    q[i] = k;
+    const double w = (s[i] - e[k]) / (e[k + 1] - e[k]);
+    t[i] = std::max(0.0, std::min(1.0, w));
+  }
+}
+
+static int state_from_cells(kv_ctx* c, const float* cells, const float* cells_ref, int rx, int ry, int rz,
+                            const double* xc, const double* yc, const double* zc, const double shift[4],
+                            const double scale[4], double* X) {
+  if (!c) return KV_EINVAL;
+  if (!cells || !X || !xc || !yc || !zc) return fail(c, KV_EINVAL, "null argument");
+  if (rx < 1 || ry < 1 || rz < 1 || rx > 4096 || ry > 4096 || rz > 4096)
+    return fail(c, KV_EINVAL, "network grid sizes must be in [1, 4096]");
+  if (!affine_ok(shift, scale)) return fail(c, KV_EINVAL, "shift/scale must be finite, scale nonzero");
+  const int r[3] = {rx, ry, rz};
+  const double* cen[3] = {xc, yc, zc};
+  std::vector<double> e[3];
+  for (int a = 0; a < 3; ++a) {
+    e[a].push_back(0.0);
+    for (int i = 0; i < r[a]; ++i) e[a].push_back(cen[a][i]);
+    e[a].push_back(1.0);
+    for (size_t i = 1; i < e[a].size(); ++i)
+      if (!(e[a][i] > e[a][i - 1])) return fail(c, KV_EINVAL, "network centres must increase strictly inside (0, 1)");
+  }
+  // tables: per axis faces (n+1) then centres (n); ints first, then doubles
+  const int n3[3] = {c->g.nx, c->g.ny, c->g.nz};
+  int64_t nint = 0;
+  for (int a = 0; a < 3; ++a) nint += 2 * n3[a] + 1;
+  const size_t dbl_off = ((size_t)nint * sizeof(int) + 255) / 256 * 256;
+  const size_t bytes = dbl_off + (size_t)nint * sizeof(double);
+  if (c->xfer_bytes < bytes) {
+    hipFree(c->xfer);
+    c->xfer = nullptr;
+    c->xfer_bytes = 0;
+    HIPCHK(c, hipMalloc(&c->xfer, bytes));
+    c->xfer_bytes = bytes;
+  }
+  std::vector<int> hq(nint);
+  std::vector<double> ht(nint);
+  const int* qp[6];
+  const double* tp[6];
+  int64_t o = 0;
+  for (int a = 0; a < 3; ++a) {
+    const int n = n3[a];
+    std::vector<double> centres(n);
+    for (int i = 0; i < n; ++i) centres[i] = 0.5 * (c->hf[a][i] + c->hf[a][i + 1]);
+    interp_table(e[a], c->hf[a].data(), n + 1, hq.data() + o, ht.data() + o);
+    qp[2 * a] = (const int*)c->xfer + o;
+    tp[2 * a] = (const double*)((char*)c->xfer + dbl_off) + o;
+    o += n + 1;
+    interp_table(e[a], centres.data(), n, hq.data() + o, ht.data() + o);
+    qp[2 * a + 1] = (const int*)c->xfer + o;
+    tp[2 * a + 1] = (const double*)((char*)c->xfer + dbl_off) + o;
+    o += n;
+  }
+  int rc;
+  if ((rc = upload(c, c->xfer, hq.data(), nint * sizeof(int)))) return rc;
+  if ((rc = upload(c, (char*)c->xfer + dbl_off, ht.data(), nint * sizeof(double)))) return rc;
+  HIPCHK(c, launch_state_from_cells(c, cells, cells_ref, r, qp, tp, shift, scale, X));
+  return KV_OK;
+}
+
+int kv_state_from_cells(kv_ctx* c, const float* cells, int rx, int ry, int rz, const double* xc, const double* yc,
+                        const double* zc, const double shift[4], const double scale[4], double* X) {
+  return state_from_cells(c, cells, nullptr, rx, ry, rz, xc, yc, zc, shift, scale, X);
+}
+
+int kv_state_add_cell_increment(kv_ctx* c, const float* cells, const float* cells_ref, int rx, int ry, int rz,
+                                const double* xc, const double* yc, const double* zc, const double scale[4],
+                                double* X) {
+  if (!c) return KV_EINVAL;
+  if (!cells_ref) return fail(c, KV_EINVAL, "null argument");
+  const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+  return state_from_cells(c, cells, cells_ref, rx, ry, rz, xc, yc, zc, zero, scale, X);
 }
 
 // ---- Chebyshev-preconditioned Arnoldi -------------------------------------------------------

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -66,6 +67,8 @@ struct kv_ctx {
   size_t work_bytes = 0;
   double* hess = nullptr;     // device Hessenberg / Schur workspace
   size_t hess_bytes = 0;
+  void* xfer = nullptr;       // interpolation tables of kv_state_from_cells
+  size_t xfer_bytes = 0;
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events
@@ -119,6 +122,17 @@ hipError_t launch_symmetry(kv_ctx* c, const double* X);
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
 hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K,
                             hipStream_t s);
+
+// Network-grid transfers (kv_transfer.hip).  cells_from_state: out[c][K][J][I]
+// = (volume average over the f^3 fine cells of the centre value - shift[c]) / scale[c].
+hipError_t launch_cells_from_state(const kv_ctx* c, const double* X, int f, const double shift[4],
+                                   const double scale[4], float* out);
+// state_from_cells: trilinear interpolation on the extended network nodes;
+// q/t: per axis the face table then the centre table (axis-major, 6 each).
+// cells_ref non-null: X += interp(cells) - interp(cells_ref).
+hipError_t launch_state_from_cells(const kv_ctx* c, const float* cells, const float* cells_ref, const int r[3],
+                                   const int* const q[6], const double* const t[6], const double shift[4],
+                                   const double scale[4], double* X);
 
 // Hessenberg eigen-solve on the device: H (m x m, row-major, leading dim ld)
 // -> eigenvalues (wr, wi) and, for the requested columns, eigenvector

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_symmetry_measures",
-               "kv_newton_correction", "kv_arnoldi_leading_eigs", "kv_timing", "kv_last_error")
+               "kv_newton_correction", "kv_arnoldi_leading_eigs", "kv_cells_from_state",
+               "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
 
 
 class KVError(RuntimeError):
@@ -81,6 +82,10 @@ def load(path: str = LIB_PATH):
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD,
                                             ctypes.POINTER(_EigInfo)]
+    lib.kv_cells_from_state.argtypes = [P, P, ctypes.c_int, PD, PD, P]
+    lib.kv_state_from_cells.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, PD, PD, PD, PD, PD, P]
+    lib.kv_state_add_cell_increment.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, PD, PD, PD,
+                                                PD, P]
     lib.kv_timing.argtypes = [P, ctypes.c_int, PD, ctypes.POINTER(ctypes.c_int)]
     lib.kv_last_error.argtypes = [P]
     lib.kv_last_error.restype = ctypes.c_char_p
@@ -89,6 +94,22 @@ def load(path: str = LIB_PATH):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def _fptr(t, n=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (ROCm) torch tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float32 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host4(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(4))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _dptr(t, n=None):
@@ -193,6 +214,39 @@ class Context:
             self._check(rc)
         return dict(status=rc, matvecs=info.matvecs, cycles=info.cycles, used_gmres=info.used_gmres,
                     relres=info.relres)
+
+    def cells_from_state(self, X, factor, shift, scale, out):
+        """Normalized cell-centred (u, v, w, theta) of X on the grid coarsened
+        by factor, into out (float32 CUDA, 4 * ncells)."""
+        f = int(factor)
+        fits = f > 0 and self.nx % f == 0 and self.ny % f == 0 and self.nz % f == 0
+        nc = (self.nx // f) * (self.ny // f) * (self.nz // f) if fits else None
+        sh, psh = _host4(shift)
+        sc, psc = _host4(scale)
+        # a factor that does not divide the grid is left to the library to reject
+        optr = _fptr(out, 4 * nc if fits else None)
+        self._check(self._lib.kv_cells_from_state(self._h, _dptr(X, self.n), f, psh, psc, optr))
+
+    def state_from_cells(self, cells, centres, shift, scale, X):
+        """Packed state X from network fields cells (float32 CUDA,
+        4 * rz * ry * rx) at the cell centres (xc, yc, zc) (host arrays)."""
+        cen = [np.ascontiguousarray(np.asarray(c, dtype=np.float64)) for c in centres]
+        rx, ry, rz = (len(c) for c in cen)
+        sh, psh = _host4(shift)
+        sc, psc = _host4(scale)
+        pc = [c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for c in cen]
+        self._check(self._lib.kv_state_from_cells(self._h, _fptr(cells, 4 * rx * ry * rz), rx, ry, rz, *pc,
+                                                  psh, psc, _dptr(X, self.n)))
+
+    def state_add_cell_increment(self, cells, cells_ref, centres, scale, X):
+        """X += S(cells) - S(cells_ref) (S: the interpolation of state_from_cells)."""
+        cen = [np.ascontiguousarray(np.asarray(c, dtype=np.float64)) for c in centres]
+        rx, ry, rz = (len(c) for c in cen)
+        sc, psc = _host4(scale)
+        pc = [c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for c in cen]
+        nc = 4 * rx * ry * rz
+        self._check(self._lib.kv_state_add_cell_increment(self._h, _fptr(cells, nc), _fptr(cells_ref, nc), rx, ry,
+                                                          rz, *pc, psc, _dptr(X, self.n)))
 
     def arnoldi_leading_eigs(self, v0, krylov_dim, n_eigs, tol=1e-8, max_matvec=100000,
                              max_restarts=1000, cheb_degree_max=200, check=True):
