@@ -127,7 +127,9 @@ typedef struct {
   int matvecs;      /* applications of P J */
   int cycles;       /* BiCGstab(2) cycles plus GMRES restarts */
   int used_gmres;   /* 1 if the GMRES continuation ran */
-  double relres;    /* ||P J delta + F||_W / ||F||_W (recursive estimate) */
+  double relres;    /* ||P J delta + F||_W / ||F||_W (recursive estimate;
+                     * of the preconditioned system when a preconditioner is set) */
+  int precond;      /* applications of the preconditioner M^-1 */
 } kv_solve_info;
 
 /* Newton correction (Sec. 1): delta with P J(X0) delta = -F, by BiCGstab(2)
@@ -138,11 +140,32 @@ typedef struct {
  * Krylov combination is divergence-free only up to cancellation among its
  * terms).  Stops when relres <= tol or after max_matvec matvecs
  * (KV_ENOCONV, delta holds the last iterate).  delta0: optional initial
- * iterate (device, may be NULL).  F, delta: device, n values.  info: host,
- * may be NULL.  flags: 0 (KV_MIXED is reserved). */
+ * iterate (device, may be NULL, not aliasing delta).  F, delta: device, n
+ * values.  info: host, may be NULL.  flags: 0 (KV_MIXED is reserved).  With
+ * a preconditioner set (kv_set_preconditioner) the solve is right
+ * preconditioned: BiCGstab(2)/GMRES iterate on P J M^-1 and delta = delta0 +
+ * M^-1 x. */
 int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matvec,
                          unsigned flags, const double* delta0, double* delta,
                          kv_solve_info* info);
+
+/* Preconditioner of the Newton correction (an addition: the paper names no
+ * preconditioner; Sec. 1 gives BiCGstab(2) with GMRES).  KV_PC_STOKES: right
+ * preconditioning of P J by
+ *   M^-1 r = ( P (sigma - nu Lap_v)^-1 r_vel , (sigma - kappa Lap_T)^-1 r_T ),
+ * the discretization's own diffusion operators (no-slip velocity walls; T = 0
+ * on the x-walls and adiabatic y- and z-walls), each inverted by fast
+ * diagonalization (1-D eigenbases per axis, FP64 matrix cores): Stokes
+ * preconditioning in Tuckerman's sense.  Kept until changed; KV_PC_NONE
+ * switches it off.  sigma >= 0 (host).  The first KV_PC_STOKES call builds
+ * the bases (9 symmetric eigenproblems on the host) and allocates two packed
+ * vectors. */
+enum kv_preconditioner { KV_PC_NONE = 0, KV_PC_STOKES = 1 };
+int kv_set_preconditioner(kv_ctx* ctx, int kind, double sigma);
+
+/* y = M^-1 x with the preconditioner set on ctx (KV_ESTATE if none).
+ * x, y: device, packed, n values; y may equal x. */
+int kv_apply_preconditioner(kv_ctx* ctx, const double* x, double* y);
 
 typedef struct {
   int krylov_dim;       /* m, Arnoldi steps per cycle, 2..400 */

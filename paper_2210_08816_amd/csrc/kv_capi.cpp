@@ -305,6 +305,30 @@ int matvec(kv_ctx* c, const double* x, double* y) {
   return project_inplace(c, y);
 }
 
+// y = M^-1 x of the Stokes/heat preconditioner: per block the Helmholtz
+// solve (sigma - nu Lap_v) or (sigma - kappa Lap_T), then P on the velocity.
+int precond_apply(kv_ctx* c, const double* x, double* y) {
+  const Grid& g = c->g;
+  const int64_t off[4] = {g.ou, g.ov, g.ow, g.oT};
+  for (int b = 0; b < 4; ++b) {
+    const HelmBasis& bx = c->hb[0][b == 3 ? HB_CD : (b == 0 ? HB_FD : HB_CD)];
+    const HelmBasis& by = c->hb[1][b == 3 ? HB_CN : (b == 1 ? HB_FD : HB_CD)];
+    const HelmBasis& bz = c->hb[2][b == 3 ? HB_CN : (b == 2 ? HB_FD : HB_CD)];
+    const double coef = b == 3 ? g.kappa : g.nu;
+    HIPCHK(c, launch_fd_helmholtz(c, bx, by, bz, c->pc_sigma, coef, x + off[b], y + off[b]));
+  }
+  return project_inplace(c, y);
+}
+
+// The operator of the Krylov solvers: P J, or P J M^-1 while a
+// preconditioned Newton correction runs.
+int op_apply(kv_ctx* c, const double* x, double* y) {
+  if (!c->pc_active) return matvec(c, x, y);
+  int rc = precond_apply(c, x, c->pc_tmp);
+  if (rc) return rc;
+  return matvec(c, c->pc_tmp, y);
+}
+
 int check_finite(kv_ctx* c, const double* a, int64_t n, const char* what) {
   HIPCHK(c, launch_maxabs(c, a, n));
   int rc = read_results(c, 1);
@@ -347,7 +371,7 @@ int arnoldi(kv_ctx* c, double* V, int m, std::vector<double>& H, int* kout, int*
   int rc;
   for (int j = 0; j < m; ++j) {
     double* w = V + (int64_t)(j + 1) * n;
-    if ((rc = matvec(c, V + (int64_t)j * n, w))) return rc;
+    if ((rc = op_apply(c, V + (int64_t)j * n, w))) return rc;
     ++*matvecs;
     for (int pass = 0; pass < 2; ++pass) {
       HIPCHK(c, launch_mdot(c, V, n, j + 1, w));
@@ -664,6 +688,9 @@ int kv_destroy(kv_ctx* c) {
   hipFree(c->work);
   hipFree(c->hess);
   hipFree(c->xfer);
+  hipFree(c->pc_mem);
+  hipFree(c->pc_tmp);
+  hipFree(c->pc_d0);
   delete c;
   return KV_OK;
 }
@@ -763,7 +790,7 @@ static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, doub
   std::vector<double> H;
   for (;;) {
     // r = b - A x into V[0]
-    if ((rc = matvec(c, x, V))) return rc;
+    if ((rc = op_apply(c, x, V))) return rc;
     ++*used;
     if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
     double beta = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
@@ -811,6 +838,9 @@ static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, doub
   }
 }
 
+static int newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, const double* delta0,
+                             double* delta, kv_solve_info* info);
+
 int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, unsigned flags,
                          const double* delta0, double* delta, kv_solve_info* info) {
   if (!c) return KV_EINVAL;
@@ -818,6 +848,30 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
   if (flags != 0) return fail(c, KV_EINVAL, "unsupported flags");
   if (!(tol > 0) || max_matvec < 4) return fail(c, KV_EINVAL, "bad tolerance or budget");
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  if (delta0 == delta) return fail(c, KV_EINVAL, "delta0 must not alias delta");
+  c->pc_active = c->pc_kind != KV_PC_NONE;
+  const int rc = newton_correction(c, F, tol, max_matvec, delta0, delta, info);
+  c->pc_active = false;
+  return rc;
+}
+
+// With the preconditioner the Krylov iterate x lives in the preconditioned
+// space: delta = delta0 + M^-1 x.  Without it, delta = x.  Either way the
+// result is projected once more (the Krylov combination is divergence-free
+// only up to cancellation among its projected terms).
+static int finish_delta(kv_ctx* c, double* x, bool has_d0) {
+  if (c->pc_active) {
+    int rc = precond_apply(c, x, c->pc_tmp);
+    if (rc) return rc;
+    if (has_d0) rc = lincomb(c, 2, {1.0, 1.0}, {c->pc_tmp, c->pc_d0}, x);
+    else rc = lincomb(c, 1, {1.0}, {c->pc_tmp}, x);
+    if (rc) return rc;
+  }
+  return project_inplace(c, x);
+}
+
+static int newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, const double* delta0,
+                             double* delta, kv_solve_info* info) {
   const int64_t n = c->g.n;
   int rc;
   if ((rc = check_finite(c, F, n, "F"))) return rc;
@@ -830,13 +884,20 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
   double* r[3] = {r0, r1, r2};
   double* u[3] = {u0, u1, u2};
   double* x = delta;
-  kv_solve_info inf{0, 0, 0, 0.0};
+  kv_solve_info inf{0, 0, 0, 0.0, 0};
   // b = -P F
   if ((rc = lincomb(c, 1, {-1.0}, {F}, b))) return rc;
   if ((rc = project_inplace(c, b))) return rc;
   const double bnorm = std::sqrt(std::max(0.0, dot1(c, b, b, &rc)));
   if (rc) return rc;
-  if (delta0) {
+  if (delta0 && c->pc_active) {
+    // delta = delta0 + M^-1 x, x from 0: the residual of delta0 starts the solve
+    HIPCHK(c, hipMemcpyAsync(c->pc_d0, delta0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = matvec(c, c->pc_d0, r0))) return rc;
+    ++inf.matvecs;
+    if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, r0}, r0))) return rc;
+    HIPCHK(c, launch_fill(c, n, 0.0, x));
+  } else if (delta0) {
     HIPCHK(c, hipMemcpyAsync(x, delta0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if ((rc = matvec(c, x, r0))) return rc;
     ++inf.matvecs;
@@ -847,7 +908,7 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
   }
   if (bnorm == 0.0) {
     if (info) *info = inf;
-    return KV_OK;
+    return finish_delta(c, x, delta0 != nullptr);
   }
   HIPCHK(c, hipMemcpyAsync(rt, r0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, launch_fill(c, n, 0.0, u0));
@@ -880,7 +941,7 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
       rho0 = rho1;
       for (int i = 0; i <= j; ++i)
         if ((rc = lincomb(c, 2, {1.0, -beta}, {r[i], u[i]}, u[i]))) return rc;
-      if ((rc = matvec(c, u[j], u[j + 1]))) return rc;
+      if ((rc = op_apply(c, u[j], u[j + 1]))) return rc;
       ++inf.matvecs;
       const double gamma = dot1(c, u[j + 1], rt, &rc);
       if (rc) return rc;
@@ -891,7 +952,7 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
       alpha = rho0 / gamma;
       for (int i = 0; i <= j; ++i)
         if ((rc = lincomb(c, 2, {1.0, -alpha}, {r[i], u[i + 1]}, r[i]))) return rc;
-      if ((rc = matvec(c, r[j], r[j + 1]))) return rc;
+      if ((rc = op_apply(c, r[j], r[j + 1]))) return rc;
       ++inf.matvecs;
       if ((rc = lincomb(c, 2, {1.0, alpha}, {x, u[0]}, x))) return rc;
     }
@@ -944,16 +1005,146 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
     inf.matvecs = used;
     inf.cycles = cyc;
     inf.relres = rr;
+    if (c->pc_active) inf.precond = inf.matvecs - (delta0 ? 1 : 0);
     if (info) *info = inf;
+    if (rc != KV_OK && rc != KV_ENOCONV) return rc;
+    const int rf = finish_delta(c, x, delta0 != nullptr);
+    if (rf) return rf;
     if (rc == KV_ENOCONV) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
-    if (rc) return rc;
-    // the Krylov combination is divergence-free only up to cancellation
-    // among its (projected) terms; one more projection puts delta in null(D)
-    return project_inplace(c, x);
+    return KV_OK;
   }
+  if (c->pc_active) inf.precond = inf.matvecs - (delta0 ? 1 : 0);
   if (info) *info = inf;
+  const int rf = finish_delta(c, x, delta0 != nullptr);
+  if (rf) return rf;
   if (status == MAXIT) return fail(c, KV_ENOCONV, "Newton correction: matvec budget exhausted");
-  return project_inplace(c, x);
+  return KV_OK;
+}
+
+// ---- Stokes/heat preconditioner ------------------------------------------------------------
+// 1-D operator -(H^-1 K) of kind HB_* along an axis with faces f (n cells):
+// returns K (m x m, row-major) and the widths H (m values).
+static void helm_operator(const std::vector<double>& f, int kind, std::vector<double>& K, std::vector<double>& H) {
+  const int n = (int)f.size() - 1;
+  std::vector<double> h(n), d(n + 1);
+  for (int i = 0; i < n; ++i) h[i] = f[i + 1] - f[i];
+  d[0] = 0.5 * h[0];
+  d[n] = 0.5 * h[n - 1];
+  for (int i = 1; i < n; ++i) d[i] = 0.5 * (h[i - 1] + h[i]);
+  if (kind == HB_FD) {
+    const int m = n - 1;  // interior face i + 1 sits between cells i and i + 1
+    K.assign((size_t)m * m, 0.0);
+    H.resize(m);
+    for (int i = 0; i < m; ++i) {
+      H[i] = d[i + 1];
+      K[(size_t)i * m + i] = 1.0 / h[i] + 1.0 / h[i + 1];
+      if (i + 1 < m) K[(size_t)i * m + i + 1] = K[(size_t)(i + 1) * m + i] = -1.0 / h[i + 1];
+    }
+    return;
+  }
+  K.assign((size_t)n * n, 0.0);
+  H = h;
+  for (int i = 0; i + 1 < n; ++i) {  // flux between centres i and i + 1 over the gap d[i + 1]
+    const double t = 1.0 / d[i + 1];
+    K[(size_t)i * n + i] += t;
+    K[(size_t)(i + 1) * n + i + 1] += t;
+    K[(size_t)i * n + i + 1] = K[(size_t)(i + 1) * n + i] = -t;
+  }
+  if (kind == HB_CD) {  // zero wall values at half-cell distance
+    K[0] += 1.0 / d[0];
+    K[(size_t)n * n - 1] += 1.0 / d[n];
+  }
+}
+
+static int build_preconditioner(kv_ctx* c) {
+  if (c->pc_mem) return KV_OK;
+  size_t total = 0;
+  int sizes[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      const int n = (int)c->hf[a].size() - 1;
+      sizes[a][k] = k == HB_FD ? n - 1 : n;
+      total += 4 * (size_t)sizes[a][k] * sizes[a][k] + sizes[a][k];
+    }
+  std::vector<double> host(total);
+  size_t o = 0;
+  size_t offs[3][3][5];
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      const int m = sizes[a][k];
+      std::vector<double> K, H, Q, lam;
+      helm_operator(c->hf[a], k, K, H);
+      std::vector<double> s(m), is(m);
+      for (int i = 0; i < m; ++i) {
+        s[i] = std::sqrt(H[i]);
+        is[i] = 1.0 / s[i];
+      }
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) K[(size_t)i * m + j] *= is[i] * is[j];
+      jacobi_eigen(m, K, Q, lam);
+      for (double& l : lam) l = std::max(l, 0.0);
+      double* fwdB = host.data() + o;
+      double* fwdA = fwdB + (size_t)m * m;
+      double* invB = fwdA + (size_t)m * m;
+      double* invA = invB + (size_t)m * m;
+      double* lm = invA + (size_t)m * m;
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          const double q = Q[(size_t)i * m + j];  // row i = position, column j = mode
+          fwdB[(size_t)i * m + j] = s[i] * q;
+          fwdA[(size_t)j * m + i] = s[i] * q;
+          invB[(size_t)j * m + i] = is[i] * q;
+          invA[(size_t)i * m + j] = is[i] * q;
+        }
+      for (int j = 0; j < m; ++j) lm[j] = lam[j];
+      for (int q = 0; q < 5; ++q) offs[a][k][q] = o + (size_t)q * m * m;
+      o += 4 * (size_t)m * m + m;
+    }
+  const int64_t n = c->g.n;
+  if (hipMalloc(&c->pc_mem, total * sizeof(double)) != hipSuccess) {
+    c->pc_mem = nullptr;
+    return fail(c, KV_ENOMEM, "preconditioner bases");
+  }
+  if (hipMalloc(&c->pc_tmp, n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->pc_d0, n * sizeof(double)) != hipSuccess) {
+    hipFree(c->pc_mem);
+    hipFree(c->pc_tmp);
+    c->pc_mem = c->pc_tmp = nullptr;
+    return fail(c, KV_ENOMEM, "preconditioner vectors");
+  }
+  int rc = upload(c, c->pc_mem, host.data(), total * sizeof(double));
+  if (rc) return rc;
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      HelmBasis& hb = c->hb[a][k];
+      hb.n = sizes[a][k];
+      hb.fwdB = c->pc_mem + offs[a][k][0];
+      hb.fwdA = c->pc_mem + offs[a][k][1];
+      hb.invB = c->pc_mem + offs[a][k][2];
+      hb.invA = c->pc_mem + offs[a][k][3];
+      hb.lam = c->pc_mem + offs[a][k][4];
+    }
+  return KV_OK;
+}
+
+int kv_set_preconditioner(kv_ctx* c, int kind, double sigma) {
+  if (!c) return KV_EINVAL;
+  if (kind != KV_PC_NONE && kind != KV_PC_STOKES) return fail(c, KV_EINVAL, "unknown preconditioner");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return fail(c, KV_EINVAL, "sigma must be finite and >= 0");
+  if (kind == KV_PC_STOKES) {
+    const int rc = build_preconditioner(c);
+    if (rc) return rc;
+  }
+  c->pc_kind = kind;
+  c->pc_sigma = sigma;
+  return KV_OK;
+}
+
+int kv_apply_preconditioner(kv_ctx* c, const double* x, double* y) {
+  if (!c) return KV_EINVAL;
+  if (!x || !y) return fail(c, KV_EINVAL, "null argument");
+  if (c->pc_kind == KV_PC_NONE) return fail(c, KV_ESTATE, "no preconditioner set");
+  return precond_apply(c, x, y);
 }
 
 // ---- transfers to and from the network grid --------------------------------------------

@@ -24,7 +24,8 @@ struct Epi {
   const double *lx, *ly, *lz;     // per-axis eigenvalues
   const double *isx, *isy, *isz;  // 1/sqrt(h) per axis
   int nx, ny;
-  int64_t null3;                  // flat (c, b, a) index of the constant mode
+  int64_t null3;                  // flat (c, b, a) index of the constant mode (-1: none)
+  double sigma, coef;             // divide by sigma + coef (lx + ly + lz)
 };
 
 constexpr int BM = 64, BN = 64, BK = 16;
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(const double* __restrict__
           // C is (nz x nx*ny): m = z-mode c, n = b * nx + a
           const int bb = gn / ep.nx, a = gn - bb * ep.nx;
           const int64_t flat = (int64_t)gm * ((int64_t)ep.nx * ep.ny) + gn;
-          const double den = ep.lz[gm] + ep.ly[bb] + ep.lx[a];
+          const double den = ep.sigma + ep.coef * (ep.lz[gm] + ep.ly[bb] + ep.lx[a]);
           v = (flat == ep.null3) ? 0.0 : v / den;
         } else if (EPI == EPI_ISQ) {
           // C is (ny*nz x nx): m = k * ny + j, n = i
@@ -146,7 +147,7 @@ hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out) {
   const Grid& g = c->g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int64_t plane = (int64_t)nx * ny;
-  Epi ep{g.ax[0].lam, g.ax[1].lam, g.ax[2].lam, g.ax[0].isq, g.ax[1].isq, g.ax[2].isq, nx, ny, g.null3};
+  Epi ep{g.ax[0].lam, g.ax[1].lam, g.ax[2].lam, g.ax[0].isq, g.ax[1].isq, g.ax[2].isq, nx, ny, g.null3, 0.0, 1.0};
   double* A = in;
   double* Bf = c->cellB;
   hipStream_t s = c->stream;
@@ -170,6 +171,24 @@ hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out) {
   if (e) return e;
   if (c->split[0]) return launch_fd_split_pass(c, 0, true, 2, Bf, out);
   return gemm<EPI_ISQ>(Bf, nx, 0, c->Qt[0], nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
+}
+
+hipError_t launch_fd_helmholtz(const kv_ctx* c, const HelmBasis& bx, const HelmBasis& by, const HelmBasis& bz,
+                               double sigma, double coef, const double* in, double* out) {
+  const int nx = bx.n, ny = by.n, nz = bz.n;
+  const int64_t plane = (int64_t)nx * ny;
+  Epi ep{bx.lam, by.lam, bz.lam, nullptr, nullptr, nullptr, nx, ny, -1, sigma, coef};
+  double* s1 = c->cellA;
+  double* s2 = c->cellB;
+  hipStream_t s = c->stream;
+  hipError_t e;
+  // forward x, y, z (+ divide), inverse z, y, x; the H^1/2 scalings sit in the bases
+  if ((e = gemm<EPI_NONE>(in, nx, 0, bx.fwdB, nx, 0, s1, nx, 0, ny * nz, nx, nx, 1, 1, ep, s))) return e;
+  if ((e = gemm<EPI_NONE>(by.fwdA, ny, 0, s1, nx, plane, s2, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
+  if ((e = gemm<EPI_DIVIDE>(bz.fwdA, nz, 0, s2, plane, 0, s1, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
+  if ((e = gemm<EPI_NONE>(bz.invA, nz, 0, s1, plane, 0, s2, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
+  if ((e = gemm<EPI_NONE>(by.invA, ny, 0, s2, nx, plane, s1, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
+  return gemm<EPI_NONE>(s1, nx, 0, bx.invB, nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
 }
 
 hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K, hipStream_t s) {

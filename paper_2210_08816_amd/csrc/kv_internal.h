@@ -25,6 +25,17 @@ struct Axis {
   const double *h, *ih, *id, *wlo, *whi, *sq, *isq, *dd, *lam, *c;
 };
 
+// One 1-D operator H^-1 K of the Stokes/heat preconditioner (H diagonal
+// widths, K symmetric positive (semi)definite): M = H^-1/2 K H^-1/2 =
+// Q diag(lam) Q^T, with s = H^1/2 folded into the transform matrices
+// (row-major n x n):  fwdB = diag(s) Q (x pass), fwdA = Q^T diag(s) (y, z
+// passes), invB = Q^T diag(1/s), invA = diag(1/s) Q.
+struct HelmBasis {
+  int n = 0;
+  const double *fwdB = nullptr, *fwdA = nullptr, *invB = nullptr, *invA = nullptr, *lam = nullptr;
+};
+enum { HB_CN = 0, HB_CD = 1, HB_FD = 2 };  // centre Neumann, centre Dirichlet, face Dirichlet
+
 // Everything a stencil or vector kernel needs about the grid and the layout.
 struct Grid {
   int nx, ny, nz;
@@ -69,6 +80,14 @@ struct kv_ctx {
   size_t hess_bytes = 0;
   void* xfer = nullptr;       // interpolation tables of kv_state_from_cells
   size_t xfer_bytes = 0;
+  // Stokes/heat preconditioner (kv_set_preconditioner)
+  kv::HelmBasis hb[3][3];     // [axis][HB_*]
+  double* pc_mem = nullptr;   // device storage of all bases
+  double* pc_tmp = nullptr;   // one packed vector: M^-1 x inside the preconditioned operator
+  double* pc_d0 = nullptr;    // one packed vector: copy of the caller's initial iterate
+  int pc_kind = 0;            // KV_PC_NONE or KV_PC_STOKES
+  double pc_sigma = 0.0;
+  bool pc_active = false;     // set while a preconditioned solve runs
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events
@@ -122,6 +141,12 @@ hipError_t launch_symmetry(kv_ctx* c, const double* X);
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
 hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K,
                             hipStream_t s);
+
+// (sigma - coef (A_x + A_y + A_z))^-1 with A_a = -H_a^-1 K_a of the given
+// bases, on a (bz.n, by.n, bx.n) block; 6 GEMM passes with cellA/cellB as
+// scratch.  in may equal out.
+hipError_t launch_fd_helmholtz(const kv_ctx* c, const HelmBasis& bx, const HelmBasis& by, const HelmBasis& bz,
+                               double sigma, double coef, const double* in, double* out);
 
 // Network-grid transfers (kv_transfer.hip).  cells_from_state: out[c][K][J][I]
 // = (volume average over the f^3 fine cells of the centre value - shift[c]) / scale[c].

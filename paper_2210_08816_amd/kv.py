@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "libkv_hip.so")
 
 KV_OK, KV_EINVAL, KV_ENOMEM, KV_EDEVICE, KV_ENOCONV, KV_ENONFINITE, KV_ESTATE = range(7)
 KV_PROJECT, KV_MIXED = 1, 2
+KV_PC_NONE, KV_PC_STOKES = 0, 1
 STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: "KV_ENOCONV",
                 5: "KV_ENONFINITE", 6: "KV_ESTATE"}
 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_symmetry_measures",
-               "kv_newton_correction", "kv_arnoldi_leading_eigs", "kv_cells_from_state",
+               "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
+               "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
 
 
@@ -42,7 +44,7 @@ class _Params(ctypes.Structure):
 
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("matvecs", ctypes.c_int), ("cycles", ctypes.c_int), ("used_gmres", ctypes.c_int),
-                ("relres", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("precond", ctypes.c_int)]
 
 
 class _ArnoldiParams(ctypes.Structure):
@@ -80,6 +82,8 @@ def load(path: str = LIB_PATH):
     lib.kv_dot.argtypes = [P, P, P, PD]
     lib.kv_symmetry_measures.argtypes = [P, P, PD]
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
+    lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
+    lib.kv_apply_preconditioner.argtypes = [P, P, P]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD,
                                             ctypes.POINTER(_EigInfo)]
     lib.kv_cells_from_state.argtypes = [P, P, ctypes.c_int, PD, PD, P]
@@ -213,7 +217,15 @@ class Context:
         if check and rc != KV_ENOCONV:
             self._check(rc)
         return dict(status=rc, matvecs=info.matvecs, cycles=info.cycles, used_gmres=info.used_gmres,
-                    relres=info.relres)
+                    relres=info.relres, precond=info.precond)
+
+    def set_preconditioner(self, stokes=True, sigma=0.0):
+        """Stokes/heat right preconditioner for newton_correction (or none)."""
+        self._check(self._lib.kv_set_preconditioner(self._h, KV_PC_STOKES if stokes else KV_PC_NONE,
+                                                    float(sigma)))
+
+    def apply_preconditioner(self, x, y):
+        self._check(self._lib.kv_apply_preconditioner(self._h, _dptr(x, self.n), _dptr(y, self.n)))
 
     def cells_from_state(self, X, factor, shift, scale, out):
         """Normalized cell-centred (u, v, w, theta) of X on the grid coarsened
