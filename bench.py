@@ -77,6 +77,62 @@ def cpu_baseline(g_args, X0, x0, y_gpu):
             "sample": f"one P J x application (x seed 1000) on the full grid, {dt:.1f} s wall"}, errs
 
 
+# (ci, co, kernel size, resolution divisor) of the U-Net's 11 convolutions
+UNET_CONVS = [(4, 16, 3, 1), (16, 16, 3, 1), (16, 32, 3, 2), (32, 32, 3, 2), (32, 64, 3, 4), (64, 64, 3, 4),
+              (96, 32, 3, 2), (32, 32, 3, 2), (48, 16, 3, 1), (16, 16, 3, 1), (16, 4, 1, 1)]
+
+
+def unet_flops(r, batch):
+    """Algorithmic flops of one training step (forward, input gradients of
+    every convolution but the first, weight gradients) and of one forward
+    pass, for an r^3 network: 2 ci co k^3 per output voxel per product."""
+    fwd = sum(2.0 * ci * co * k ** 3 * (r // d) ** 3 for ci, co, k, d in UNET_CONVS)
+    first = 2.0 * 4 * 16 * 27 * r ** 3
+    return batch * (3 * fwd - first), fwd
+
+
+def learned_leg(torch, steps=10):
+    """Time kvnn training steps and predictions on a 64^3 network (the
+    learned Newton guess's kernels)."""
+    from synth import inputs as S
+    from paper_2210_08816_amd import kvnn
+    r, batch = 64, 2
+    f = S.faces_clustered(r)
+    cen = 0.5 * (f[1:] + f[:-1])
+    net = kvnn.Net((cen, cen, cen), (6.0, 8.5), batch_max=batch, seed=3)
+    inp = torch.empty(batch * 4 * r ** 3, dtype=torch.float32, device="cuda")
+    net.make_inputs([1e7, 1e8], inp)
+    x = inp.view(batch, 4, r, r, r)
+    # a smooth synthetic target of the state's shape
+    tgt = torch.stack([torch.sin(3 * x[:, 0]) * x[:, 3], torch.cos(2 * x[:, 1]), x[:, 2] * x[:, 0],
+                       x[:, 3] - x[:, 0] ** 2], dim=1).contiguous().view(-1)
+    for _ in range(3):
+        net.train_step(inp, tgt, batch, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(inp, tgt, batch, 1e-4)
+    torch.cuda.synchronize()
+    t_step = (time.perf_counter() - t0) / steps
+    out = torch.empty(4 * r ** 3, dtype=torch.float32, device="cuda")
+    net.predict(1e7, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.predict(1e7, out)
+    torch.cuda.synchronize()
+    t_pred = (time.perf_counter() - t0) / steps
+    step_flops, fwd_flops = unet_flops(r, batch)
+    ach = step_flops / t_step / 1e12
+    net.close()
+    return {"network": f"{r}^3 U-Net 16/32/64, batch {batch}", "params": net.num_params,
+            "train_step_ms": round(1e3 * t_step, 3), "predict_ms": round(1e3 * t_pred, 3),
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                         "what": "algorithmic convolution flops of a training step / its wall time"},
+            "predict_tflops": round(fwd_flops / t_pred / 1e12, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +143,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=("fp64", "mixed", "both"), default="both",
                     help="projection form(s) to time; the headline value is the faster form's")
+    ap.add_argument("--no-learned", action="store_true", help="skip the network timing leg")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="also run this many plain device copies of one vector (a known-size "
                          "reference for hardware byte counters)")
@@ -206,6 +263,9 @@ def main():
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_learned:
+        log("[bench] timing the learned-guess network kernels")
+        result["learned"] = learned_leg(torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one vector")
         outs = {}

@@ -52,12 +52,15 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
     return dict(converged=ok, hist=hist, matvecs=mv, iters=len(hist) - 1, seconds=time.perf_counter() - t0)
 
 
-def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12, **kw):
+def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12,
+          precond_sigma=None, **kw):
     """Continuation over increasing Gr values, from X0 (default: the
     conduction state).  A failed step is retried from the last converged
     state at the geometric midpoint in Gr, at most max_halvings times per
-    requested value.  Returns (states, infos) for the requested Gr values
-    reached; a value that cannot be reached ends the sweep."""
+    requested value.  precond_sigma: None, or the shift of the Stokes/heat
+    preconditioner of the Newton corrections.  Returns (states, infos) for
+    the requested Gr values reached; a value that cannot be reached ends the
+    sweep."""
     import torch
     from . import kv
     if X0 is None:
@@ -67,15 +70,20 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
     gr_last = None
     for Gr in grs:
         target, halvings = Gr, 0
+        spent_mv, spent_s = 0, 0.0   # over every attempt for this value
         while True:
             Xtry = X.clone()
             ctx = kv.Context(*faces, Gr=target, Pr=Pr)
+            if precond_sigma is not None:
+                ctx.set_preconditioner(True, precond_sigma)
             try:
                 ctx.project(Xtry)
                 info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, **kw)
             finally:
                 ctx.close()
             info["Gr"] = target
+            spent_mv += info["matvecs"]
+            spent_s += info["seconds"]
             log(f"[continuation] Gr={target:.4e}: converged={info['converged']} iters={info['iters']} "
                 f"matvecs={info['matvecs']} |F|={info['hist'][-1]:.2e} {info['seconds']:.1f}s")
             if info["converged"]:
@@ -89,6 +97,8 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
                 return states, infos + [info]
             halvings += 1
             target = math.sqrt(gr_last * target)
+        info["matvecs_all_attempts"] = spent_mv
+        info["seconds_all_attempts"] = spent_s
         infos.append(info)
         states.append(X.clone())
     return states, infos

@@ -1,10 +1,10 @@
 // The steady-state predictor of kvnn.h: a three-level 3-D U-Net trained by
-// hand-written forward and backward kernels.  Convolutions are direct (one
-// output voxel per lane, several output channels per lane so every loaded
-// input value feeds several FMAs); their weights are the BF16-rounded master
-// weights, products are accumulated in FP32.  Reductions (weight and bias
-// gradients, the loss) are computed in a fixed order, so results do not
-// depend on scheduling.
+// hand-written forward and backward kernels.  The 3x3x3 convolutions and
+// their input and weight gradients are implicit GEMMs on the FP32 matrix
+// cores (v_mfma_f32_16x16x4) over LDS-staged voxel tiles; the 1x1x1 head is
+// direct.  Their weights are the BF16-rounded master weights, products are
+// accumulated in FP32.  Reductions (weight and bias gradients, the loss) are
+// computed in a fixed order, so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -123,25 +123,30 @@ __global__ void __launch_bounds__(NT) conv_bwd_data(const float* __restrict__ do
 template <int KS, int COB>
 __global__ void __launch_bounds__(NT) conv_bwd_weight(const float* __restrict__ in, int ci_n,
                                                       const float* __restrict__ dout, int co_n, int batch, int R,
-                                                      float* __restrict__ part) {
+                                                      float* __restrict__ part, float* __restrict__ bpart) {
   constexpr int T = KS * KS * KS, H = KS / 2;
-  __shared__ float red[NT / 64][COB * T];
+  __shared__ float red[NT / 64][COB * (T + 1)];
   const int ci = blockIdx.x, co0 = blockIdx.y * COB, s = blockIdx.z, S = gridDim.z;
   const int V = R * R * R;
   const int total = batch * V;
   const int chunk = (total + S - 1) / S;
   const int e0 = s * chunk, e1 = min(total, e0 + chunk);
-  float acc[COB][T];
+  float acc[COB][T], accb[COB];
 #pragma unroll
-  for (int c = 0; c < COB; ++c)
+  for (int c = 0; c < COB; ++c) {
+    accb[c] = 0.f;
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[c][t] = 0.f;
+  }
   for (int e = e0 + (int)threadIdx.x; e < e1; e += NT) {
     const int b = e / V, v = e - b * V;
     const int x = v % R, y = (v / R) % R, z = v / (R * R);
     float g[COB];
 #pragma unroll
-    for (int c = 0; c < COB; ++c) g[c] = dout[((size_t)b * co_n + co0 + c) * V + v];
+    for (int c = 0; c < COB; ++c) {
+      g[c] = dout[((size_t)b * co_n + co0 + c) * V + v];
+      accb[c] += g[c];
+    }
     const float* src = in + ((size_t)b * ci_n + ci) * V;
 #pragma unroll
     for (int dz = 0; dz < KS; ++dz) {
@@ -162,24 +167,266 @@ __global__ void __launch_bounds__(NT) conv_bwd_weight(const float* __restrict__ 
       }
     }
   }
-  // wave sums (butterfly), then the waves in order
+  // wave sums (butterfly), then the waves in order; column T is the bias
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < COB; ++c)
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      float a = acc[c][t];
+    for (int t = 0; t <= T; ++t) {
+      float a = t < T ? acc[c][t] : accb[c];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-      if (lane == 0) red[wv][c * T + t] = a;
+      if (lane == 0) red[wv][c * (T + 1) + t] = a;
     }
   __syncthreads();
-  for (int q = threadIdx.x; q < COB * T; q += NT) {
+  for (int q = threadIdx.x; q < COB * (T + 1); q += NT) {
     float a = 0.f;
 #pragma unroll
     for (int k = 0; k < NT / 64; ++k) a += red[k][q];
-    const int c = q / T, t = q - c * T;
-    part[(((size_t)s * co_n + co0 + c) * ci_n + ci) * T + t] = a;
+    const int c = q / (T + 1), t = q - c * (T + 1);
+    if (t < T) part[(((size_t)s * co_n + co0 + c) * ci_n + ci) * T + t] = a;
+    else if (ci == 0) bpart[(size_t)s * co_n + co0 + c] = a;
+  }
+}
+
+// ---- voxel tiles of the 3x3x3 convolutions ---------------------------------------------
+// A block owns an 8 x 8 x 4 voxel tile.  Input channels are staged CCH at a
+// time as (8+2) x (8+2) x (4+2) halo tiles in LDS (zero outside the domain);
+// the next channels' values are loaded into registers while the current ones
+// are consumed, so every tap is an LDS read at a constant offset.
+constexpr int TX = 8, TY = 8, TZ = 4, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, HALO = HX * HY * HZ;
+constexpr int CCH = 4;                                   // input channels per LDS stage
+constexpr int PF = (CCH * HALO + NT - 1) / NT;           // staged values per lane
+
+struct TileIdx {
+  int x0, y0, z0, tx, ty, tz;
+};
+__device__ __forceinline__ TileIdx tile_of(int t, int R) {
+  const int nt = (R + TX - 1) / TX, ny = (R + TY - 1) / TY;
+  TileIdx q;
+  q.x0 = (t % nt) * TX;
+  q.y0 = ((t / nt) % ny) * TY;
+  q.z0 = (t / (nt * ny)) * TZ;
+  q.tx = threadIdx.x % TX;
+  q.ty = (threadIdx.x / TX) % TY;
+  q.tz = threadIdx.x / (TX * TY);
+  return q;
+}
+__device__ __forceinline__ int tiles_of(int R) {
+  return ((R + TX - 1) / TX) * ((R + TY - 1) / TY) * ((R + TZ - 1) / TZ);
+}
+
+// Values of channels c0 .. c0+CCH-1 on the halo of tile q (zero outside the
+// domain or past the last channel) into registers, then into LDS.
+__device__ __forceinline__ void halo_load(const float* __restrict__ src, int c0, int c_n, int R, const TileIdx& q,
+                                          float (&r)[PF]) {
+  const int V = R * R * R;
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int e = threadIdx.x + k * NT;
+    float v = 0.f;
+    if (e < CCH * HALO) {
+      const int cc = e / HALO, h = e - cc * HALO;
+      const int hx = h % HX, hy = (h / HX) % HY, hz = h / (HX * HY);
+      const int gx = q.x0 + hx - 1, gy = q.y0 + hy - 1, gz = q.z0 + hz - 1;
+      if (c0 + cc < c_n && gx >= 0 && gx < R && gy >= 0 && gy < R && gz >= 0 && gz < R)
+        v = src[(size_t)(c0 + cc) * V + (gz * R + gy) * R + gx];
+    }
+    r[k] = v;
+  }
+}
+__device__ __forceinline__ void halo_store(float* __restrict__ buf, const float (&r)[PF]) {
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < CCH * HALO) buf[e] = r[k];
+  }
+}
+
+// ---- 3x3x3 convolutions as implicit GEMMs on the FP32 matrix cores ----------------
+// v_mfma_f32_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 (l / 16) + e][l % 16], e = 0..3.
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int MO = 16;          // output channels per block (one MFMA row block)
+constexpr int KST = CCH * 27;   // GEMM k per LDS stage: CCH channels x 27 taps
+constexpr int PW = (KST * MO + NT - 1) / NT;
+
+__device__ __forceinline__ int tap_offset(int t) { return ((t / 9) * HY + (t / 3) % 3) * HX + t % 3; }
+__device__ __forceinline__ int voxel_offset(int nn) { return ((nn >> 6) * HY + ((nn >> 3) & 7)) * HX + (nn & 7); }
+
+// out[b][o][v] = act(bias[o] + sum_{i,t} wp[i][t][o] in[b][i][v + t - 1]) with
+// M = 16 output channels, N = the 256 voxels of an 8 x 8 x 4 tile (each wave
+// 64 of them as four 16-voxel column blocks), K = input channel x tap.  The
+// input halos and the matching weight slab are staged in LDS, double-buffered.
+// grid (tiles, o_n / 16, batch).
+template <bool RELU>
+__global__ void __launch_bounds__(NT) conv3_mfma(const float* __restrict__ in, int i_n, const float* __restrict__ wp,
+                                                 const float* __restrict__ bias, float* __restrict__ out, int o_n,
+                                                 int R) {
+  __shared__ float tile[2][CCH * HALO];
+  __shared__ float ws[2][KST][MO];
+  const TileIdx q = tile_of(blockIdx.x, R);
+  const int o0 = blockIdx.y * MO, b = blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ml = lane & 15, kq = lane >> 4;
+  const int V = R * R * R;
+  const float* src = in + (size_t)b * i_n * V;
+  int bofs[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) bofs[nb] = voxel_offset(wave * 64 + nb * 16 + ml);
+  v4f acc[4];
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+  float pre[PF], prew[PW];
+  auto wload = [&](int i0) {
+#pragma unroll
+    for (int k = 0; k < PW; ++k) {
+      const int e = threadIdx.x + k * NT;
+      float v = 0.f;
+      if (e < KST * MO) {
+        const int kk = e / MO, mm = e - kk * MO;
+        const int i = i0 + kk / 27, t = kk % 27;
+        if (i < i_n) v = wp[((size_t)i * 27 + t) * o_n + o0 + mm];
+      }
+      prew[k] = v;
+    }
+  };
+  auto wstore = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < PW; ++k) {
+      const int e = threadIdx.x + k * NT;
+      if (e < KST * MO) ws[buf][e / MO][e % MO] = prew[k];
+    }
+  };
+  halo_load(src, 0, i_n, R, q, pre);
+  wload(0);
+  halo_store(tile[0], pre);
+  wstore(0);
+  __syncthreads();
+  const int nch = (i_n + CCH - 1) / CCH;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    const bool more = ch + 1 < nch;
+    if (more) {
+      halo_load(src, (ch + 1) * CCH, i_n, R, q, pre);
+      wload((ch + 1) * CCH);
+    }
+    const float* tl = tile[buf];
+#pragma unroll 3
+    for (int ks = 0; ks < KST; ks += 4) {
+      const int k = ks + kq;
+      const int cc = k / 27, t = k - cc * 27;
+      const int toff = cc * HALO + tap_offset(t);
+      const float a = ws[buf][k][ml];
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, tl[toff + bofs[nb]], acc[nb], 0, 0, 0);
+    }
+    if (more) {
+      halo_store(tile[buf ^ 1], pre);
+      wstore(buf ^ 1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int nn = wave * 64 + nb * 16 + ml;
+    const int x = q.x0 + (nn & 7), y = q.y0 + ((nn >> 3) & 7), z = q.z0 + (nn >> 6);
+    if (x < R && y < R && z < R) {
+      const int v = (z * R + y) * R + x;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = o0 + 4 * kq + e;
+        float a = acc[nb][e] + (bias ? bias[o] : 0.f);
+        if (RELU) a = a > 0.f ? a : 0.f;
+        out[((size_t)b * o_n + o) * V + v] = a;
+      }
+    }
+  }
+}
+
+// Weight and bias gradients as one GEMM per tile: D[o][(i, t)] += sum_v
+// dout[b][o][v] X[(i, t)][v], M = 16 output channels, K = the tile's 256
+// voxels, N = CCH input channels x 32 columns (27 taps, a column of ones that
+// yields the bias gradient, padding).  Partial sums per slice of the
+// (batch, tile) range: part[s][co][ci][t], bpart[s][co] (ci-chunk 0).
+// grid (ci_n / CCH, co_n / 16, S).
+__global__ void __launch_bounds__(NT) conv3_wgrad_mfma(const float* __restrict__ in, int ci_n,
+                                                       const float* __restrict__ dout, int co_n, int batch, int R,
+                                                       float* __restrict__ part, float* __restrict__ bpart) {
+  __shared__ float tile[CCH * HALO];
+  __shared__ float dts[MO][TX * TY * TZ + 4];
+  const int i0 = blockIdx.x * CCH, o0 = blockIdx.y * MO, s = blockIdx.z, S = gridDim.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ml = lane & 15, kq = lane >> 4;
+  const int V = R * R * R;
+  const int nt = tiles_of(R);
+  const int total = batch * nt;
+  const int chunk = (total + S - 1) / S;
+  const int e0 = s * chunk, e1 = min(total, e0 + chunk);
+  // this lane's two B columns: n = (2 wave + j) 16 + ml -> channel cc, tap t
+  int ncc[2], nt_[2], noff[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = (2 * wave + j) * 16 + ml;
+    ncc[j] = n >> 5;
+    nt_[j] = n & 31;
+    noff[j] = ncc[j] * HALO + (nt_[j] < 27 ? tap_offset(nt_[j]) : 0);
+  }
+  v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+  for (int e = e0; e < e1; ++e) {
+    const int b = e / nt;
+    const TileIdx q = tile_of(e - b * nt, R);
+    float pre[PF];
+    halo_load(in + (size_t)b * ci_n * V, i0, ci_n, R, q, pre);
+    // dout of the 16 output channels on the tile's voxels (0 outside the domain)
+    float g[MO];
+    {
+      const int x = q.x0 + q.tx, y = q.y0 + q.ty, z = q.z0 + q.tz;
+      const bool inside = x < R && y < R && z < R;
+      const float* gp = dout + ((size_t)b * co_n + o0) * V + (size_t)((z * R + y) * R + x);
+#pragma unroll
+      for (int c = 0; c < MO; ++c) g[c] = inside ? gp[(size_t)c * V] : 0.f;
+    }
+    halo_store(tile, pre);
+#pragma unroll
+    for (int c = 0; c < MO; ++c) dts[c][threadIdx.x] = g[c];
+    __syncthreads();
+#pragma unroll 4
+    for (int kv = 0; kv < TX * TY * TZ; kv += 4) {
+      const int vx = kv + kq;
+      const int vo = voxel_offset(vx);
+      const float a = dts[ml][vx];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float bv = nt_[j] < 27 ? tile[noff[j] + vo] : (nt_[j] == 27 ? 1.f : 0.f);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int ci = i0 + ncc[j], t = nt_[j];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int o = o0 + 4 * kq + e;
+      if (t < 27 && ci < ci_n) part[(((size_t)s * co_n + o) * ci_n + ci) * 27 + t] = acc[j][e];
+      else if (t == 27 && ncc[j] == 0 && blockIdx.x == 0) bpart[(size_t)s * co_n + o] = acc[j][e];
+    }
+  }
+}
+
+// Packed copies of one 3x3x3 convolution's working weights w[co][ci][27]:
+// wf[ci][t][co] = w[co][ci][t] (forward) and wb[co][t][ci] = w[co][ci][26 - t]
+// (input gradient: the same GEMM with mirrored taps and channels swapped).
+__global__ void repack3(const float* __restrict__ w, int ci_n, int co_n, float* __restrict__ wf,
+                        float* __restrict__ wb) {
+  const int n = co_n * ci_n * 27;
+  for (int e = blockIdx.x * NT + threadIdx.x; e < n; e += gridDim.x * NT) {
+    const int t = e % 27, ci = (e / 27) % ci_n, co = e / (27 * ci_n);
+    wf[((size_t)ci * 27 + t) * co_n + co] = w[e];
+    wb[((size_t)co * 27 + (26 - t)) * ci_n + ci] = w[e];
   }
 }
 
@@ -189,27 +436,6 @@ __global__ void sum_slices(const float* __restrict__ part, int S, int64_t len, f
     float a = 0.f;
     for (int s = 0; s < S; ++s) a += part[(size_t)s * len + j];
     dw[j] = a;
-  }
-}
-
-// db[co] = sum_b sum_v dout[b][co][v]; one block per co
-__global__ void __launch_bounds__(NT) bias_grad(const float* __restrict__ dout, int co_n, int batch, int V,
-                                                float* __restrict__ db) {
-  __shared__ float red[NT / 64];
-  const int co = blockIdx.x;
-  float a = 0.f;
-  for (int b = 0; b < batch; ++b) {
-    const float* g = dout + ((size_t)b * co_n + co) * V;
-    for (int v = threadIdx.x; v < V; v += NT) a += g[v];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float s = 0.f;
-    for (int k = 0; k < NT / 64; ++k) s += red[k];
-    db[co] = s;
   }
 }
 
@@ -364,6 +590,8 @@ __global__ void fill0(float* __restrict__ p, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) p[e] = 0.f;
 }
 
+inline int tiles_of_host(int R) { return ((R + 7) / 8) * ((R + 7) / 8) * ((R + 3) / 4); }
+
 inline unsigned nblk(int64_t n) {
   return (unsigned)std::min<int64_t>(8192, std::max<int64_t>(1, (n + NT - 1) / NT));
 }
@@ -397,6 +625,9 @@ struct kvnn {
   float *act = nullptr, *grad = nullptr;
   std::vector<int64_t> off;
   float* wpart = nullptr;  // weight-gradient slice partials
+  float* bpart = nullptr;  // bias-gradient slice partials
+  float* wpk = nullptr;    // packed working weights of the 3x3x3 convolutions
+  std::vector<int64_t> pk_off;  // per convolution: offset of wf (wb follows)
   double *cen = nullptr, *lg = nullptr, *part = nullptr, *loss = nullptr;
   float* in1 = nullptr;  // inputs of kvnn_predict
   std::string err;
@@ -423,32 +654,52 @@ int wgt_slices(const Conv& c) {
   const int blocks = c.ci * (c.co / kWgtCob);
   return std::max(1, std::min(64, kWgtBlocks / blocks));
 }
+
+// slices of a 3x3x3 weight-gradient launch: enough blocks to fill the chip
+int wgrad3_slices(const Conv& c) {
+  const int blocks = ((c.ci + CCH - 1) / CCH) * (c.co / MO);
+  return std::max(1, std::min(64, kWgtBlocks / blocks));
+}
+
+hipError_t repack_all(kvnn* n) {
+  for (size_t k = 0; k < n->conv.size(); ++k) {
+    const Conv& c = n->conv[k];
+    if (c.ks != 3) continue;
+    const int64_t len = (int64_t)c.co * c.ci * 27;
+    float* wf = n->wpk + n->pk_off[k];
+    repack3<<<nblk(len), NT, 0, n->stream>>>(n->wq + c.w_off, c.ci, c.co, wf, wf + len);
+  }
+  return hipGetLastError();
+}
 int cob_of(const Conv& c) { return c.co % 8 == 0 ? 8 : 4; }
 int cib_of(const Conv& c) { return c.ci % 8 == 0 ? 8 : 4; }
 
+const float* packed_fwd(kvnn* n, const Conv& c) { return n->wpk + n->pk_off[&c - n->conv.data()]; }
+const float* packed_bwd(kvnn* n, const Conv& c) {
+  return packed_fwd(n, c) + (int64_t)c.co * c.ci * 27;
+}
+
 hipError_t conv_forward(kvnn* n, const Conv& c, const float* in, float* out, int batch, int R, bool relu) {
   const int V = R * R * R;
+  if (c.ks == 3) {
+    const dim3 grid(tiles_of_host(R), c.co / MO, batch);
+    const float* b = n->wq + c.b_off;
+    if (relu) conv3_mfma<true><<<grid, NT, 0, n->stream>>>(in, c.ci, packed_fwd(n, c), b, out, c.co, R);
+    else conv3_mfma<false><<<grid, NT, 0, n->stream>>>(in, c.ci, packed_fwd(n, c), b, out, c.co, R);
+    return hipGetLastError();
+  }
+  // the 1x1x1 head: one output voxel per lane, direct
   const int cob = cob_of(c);
   const dim3 grid((V + NT - 1) / NT, c.co / cob, batch);
   const float* w = n->wq + c.w_off;
   const float* b = n->wq + c.b_off;
-#define KVNN_FWD(KS, RL, CB) conv_fwd<KS, RL, CB><<<grid, NT, 0, n->stream>>>(in, c.ci, w, b, out, c.co, R)
-  if (c.ks == 3) {
-    if (cob == 8) {
-      if (relu) KVNN_FWD(3, true, 8);
-      else KVNN_FWD(3, false, 8);
-    } else {
-      if (relu) KVNN_FWD(3, true, 4);
-      else KVNN_FWD(3, false, 4);
-    }
+#define KVNN_FWD(RL, CB) conv_fwd<1, RL, CB><<<grid, NT, 0, n->stream>>>(in, c.ci, w, b, out, c.co, R)
+  if (cob == 8) {
+    if (relu) KVNN_FWD(true, 8);
+    else KVNN_FWD(false, 8);
   } else {
-    if (cob == 8) {
-      if (relu) KVNN_FWD(1, true, 8);
-      else KVNN_FWD(1, false, 8);
-    } else {
-      if (relu) KVNN_FWD(1, true, 4);
-      else KVNN_FWD(1, false, 4);
-    }
+    if (relu) KVNN_FWD(true, 4);
+    else KVNN_FWD(false, 4);
   }
 #undef KVNN_FWD
   return hipGetLastError();
@@ -459,24 +710,30 @@ hipError_t conv_forward(kvnn* n, const Conv& c, const float* in, float* out, int
 // gradient.
 hipError_t conv_backward(kvnn* n, const Conv& c, const float* in, const float* gout, float* gin, int batch, int R) {
   const int V = R * R * R;
+  const int64_t wlen = (int64_t)c.co * c.ci * c.ks * c.ks * c.ks;
+  if (c.ks == 3) {
+    const int S = std::min(wgrad3_slices(c), batch * tiles_of_host(R));
+    const dim3 wg((c.ci + CCH - 1) / CCH, c.co / MO, S);
+    conv3_wgrad_mfma<<<wg, NT, 0, n->stream>>>(in, c.ci, gout, c.co, batch, R, n->wpart, n->bpart);
+    sum_slices<<<nblk(wlen), NT, 0, n->stream>>>(n->wpart, S, wlen, n->gw + c.w_off);
+    sum_slices<<<1, NT, 0, n->stream>>>(n->bpart, S, c.co, n->gw + c.b_off);
+    if (gin) {
+      const dim3 dg(tiles_of_host(R), c.ci / MO, batch);
+      conv3_mfma<false><<<dg, NT, 0, n->stream>>>(gout, c.co, packed_bwd(n, c), nullptr, gin, c.ci, R);
+    }
+    return hipGetLastError();
+  }
   const int S = wgt_slices(c);
   const dim3 wg(c.ci, c.co / kWgtCob, S);
-  if (c.ks == 3) conv_bwd_weight<3, kWgtCob><<<wg, NT, 0, n->stream>>>(in, c.ci, gout, c.co, batch, R, n->wpart);
-  else conv_bwd_weight<1, kWgtCob><<<wg, NT, 0, n->stream>>>(in, c.ci, gout, c.co, batch, R, n->wpart);
-  const int64_t wlen = (int64_t)c.co * c.ci * c.ks * c.ks * c.ks;
+  conv_bwd_weight<1, kWgtCob><<<wg, NT, 0, n->stream>>>(in, c.ci, gout, c.co, batch, R, n->wpart, n->bpart);
   sum_slices<<<nblk(wlen), NT, 0, n->stream>>>(n->wpart, S, wlen, n->gw + c.w_off);
-  bias_grad<<<c.co, NT, 0, n->stream>>>(gout, c.co, batch, V, n->gw + c.b_off);
+  sum_slices<<<1, NT, 0, n->stream>>>(n->bpart, S, c.co, n->gw + c.b_off);
   if (gin) {
     const int cib = cib_of(c);
     const dim3 dg((V + NT - 1) / NT, c.ci / cib, batch);
     const float* w = n->wq + c.w_off;
-    if (c.ks == 3) {
-      if (cib == 8) conv_bwd_data<3, 8><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
-      else conv_bwd_data<3, 4><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
-    } else {
-      if (cib == 8) conv_bwd_data<1, 8><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
-      else conv_bwd_data<1, 4><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
-    }
+    if (cib == 8) conv_bwd_data<1, 8><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
+    else conv_bwd_data<1, 4><<<dg, NT, 0, n->stream>>>(gout, c.co, w, gin, c.ci, R);
   }
   return hipGetLastError();
 }
@@ -587,14 +844,18 @@ int kvnn_create(const kvnn_params* p, void* hip_stream, kvnn** out) {
   n->stream = reinterpret_cast<hipStream_t>(hip_stream);
   n->lg_mid = 0.5 * (p->lgr_lo + p->lgr_hi);
   n->lg_half = 0.5 * (p->lgr_hi - p->lgr_lo);
-  int64_t o = 0, wpart = 0;
+  int64_t o = 0, wpart = 0, bpart = 0, pk = 0;
   for (const auto& s : conv_spec) {
     Conv c{s[0], s[1], s[2], 0, 0};
     const int64_t wl = (int64_t)c.co * c.ci * c.ks * c.ks * c.ks;
     c.w_off = o;
     c.b_off = o + wl;
     o += wl + c.co;
-    wpart = std::max<int64_t>(wpart, wl * wgt_slices(c));
+    const int sl = c.ks == 3 ? wgrad3_slices(c) : wgt_slices(c);
+    wpart = std::max<int64_t>(wpart, wl * sl);
+    bpart = std::max<int64_t>(bpart, (int64_t)c.co * sl);
+    n->pk_off.push_back(pk);
+    if (c.ks == 3) pk += 2 * wl;
     n->conv.push_back(c);
   }
   n->nparam = o;
@@ -620,6 +881,8 @@ int kvnn_create(const kvnn_params* p, void* hip_stream, kvnn** out) {
       hipMalloc(&n->v, o * sizeof(float)) != hipSuccess || hipMalloc(&n->act, acc * sizeof(float)) != hipSuccess ||
       hipMalloc(&n->grad, acc * sizeof(float)) != hipSuccess ||
       hipMalloc(&n->wpart, wpart * sizeof(float)) != hipSuccess ||
+      hipMalloc(&n->bpart, bpart * sizeof(float)) != hipSuccess ||
+      hipMalloc(&n->wpk, pk * sizeof(float)) != hipSuccess ||
       hipMalloc(&n->cen, 3 * R * sizeof(double)) != hipSuccess ||
       hipMalloc(&n->lg, p->batch_max * sizeof(double)) != hipSuccess ||
       hipMalloc(&n->part, 8192 * sizeof(double)) != hipSuccess ||
@@ -631,7 +894,9 @@ int kvnn_create(const kvnn_params* p, void* hip_stream, kvnn** out) {
   fill0<<<nblk(o), NT, 0, n->stream>>>(n->m, o);
   fill0<<<nblk(o), NT, 0, n->stream>>>(n->v, o);
   quantize<<<nblk(o), NT, 0, n->stream>>>(n->w, n->wq, o);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(n->stream) != hipSuccess) return bad(KVNN_EDEVICE);
+  if (hipGetLastError() != hipSuccess || repack_all(n) != hipSuccess ||
+      hipStreamSynchronize(n->stream) != hipSuccess)
+    return bad(KVNN_EDEVICE);
   *out = n;
   return KVNN_OK;
 }
@@ -640,7 +905,7 @@ int kvnn_destroy(kvnn* n) {
   if (!n) return KVNN_OK;
   if (n->w) hipStreamSynchronize(n->stream);
   for (void* p : {(void*)n->w, (void*)n->wq, (void*)n->gw, (void*)n->m, (void*)n->v, (void*)n->act, (void*)n->grad,
-                  (void*)n->wpart, (void*)n->cen, (void*)n->lg, (void*)n->part, (void*)n->loss, (void*)n->in1})
+                  (void*)n->wpart, (void*)n->bpart, (void*)n->wpk, (void*)n->cen, (void*)n->lg, (void*)n->part, (void*)n->loss, (void*)n->in1})
     if (p) hipFree(p);
   delete n;
   return KVNN_OK;
@@ -667,6 +932,7 @@ int kvnn_set_params(kvnn* n, const float* host) {
     if (!std::isfinite(host[e])) return fail(n, KVNN_EINVAL, "non-finite parameter");
   NNCHK(n, hipMemcpyAsync(n->w, host, n->nparam * sizeof(float), hipMemcpyHostToDevice, n->stream));
   quantize<<<nblk(n->nparam), NT, 0, n->stream>>>(n->w, n->wq, n->nparam);
+  NNCHK(n, repack_all(n));
   fill0<<<nblk(n->nparam), NT, 0, n->stream>>>(n->m, n->nparam);
   fill0<<<nblk(n->nparam), NT, 0, n->stream>>>(n->v, n->nparam);
   NNCHK(n, hipGetLastError());
@@ -741,6 +1007,7 @@ int kvnn_train_step(kvnn* n, const float* in, const float* target, int batch, fl
   adam<<<nblk(n->nparam), NT, 0, n->stream>>>(n->w, n->wq, n->gw, n->m, n->v, n->nparam, lr, (float)b1,
                                               (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), 1e-8f, c1, c2);
   NNCHK(n, hipGetLastError());
+  NNCHK(n, repack_all(n));
   if (loss) {
     double h = 0.0;
     NNCHK(n, hipMemcpyAsync(&h, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));

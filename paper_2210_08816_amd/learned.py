@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import kv, kvnn
-from .continuation import newton_solve
+from .continuation import _conduction_state, newton_solve, sweep
 
 
 def coarse_centres(faces, factor):
@@ -147,7 +147,7 @@ START_KINDS = ("continuation", "learned", "learned_increment")
 
 
 def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10, max_iter=20,
-                   max_matvec=40000, kinds=START_KINDS, log=None):
+                   max_matvec=40000, kinds=START_KINDS, precond_sigma=None, log=None):
     """Newton at Gr from the nearest converged state (continuation), from the
     direct learned guess and from the learned increment, each to the same
     absolute residual tolerance.  Returns a record per start (iterations,
@@ -156,6 +156,8 @@ def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10
     import torch
     res = {}
     ctx = kv.Context(*faces, Gr=Gr, Pr=Pr)
+    if precond_sigma is not None:
+        ctx.set_preconditioner(True, precond_sigma)
     finals = []
     try:
         for kind in kinds:
@@ -189,3 +191,93 @@ def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10
     finally:
         ctx.close()
     return res
+
+
+def guess_residual(faces, Gr, X, Pr=0.71):
+    """||P N(X)||_W at Gr (the Newton residual that judges a guess)."""
+    import torch
+    ctx = kv.Context(*faces, Gr=Gr, Pr=Pr)
+    try:
+        ctx.set_base_flow(X)
+        F = torch.empty_like(X)
+        return ctx.residual(F)
+    finally:
+        ctx.close()
+
+
+def experiment(n=64, grid="clustered", factor=2, gr_lo=1e6, log_step=None, ntrain=15, held=(1, 4, 7, 10, 13),
+               epochs=6000, lr=1e-3, lr_final=1e-5, batch=2, precond_sigma=10.0, seed=3, data_seed=4,
+               tol_abs=1e-10, log=print):
+    """Training states by continuation (from the conduction state, Gr raised
+    by 1.6 per step up to gr_lo, then the training values
+    Gr_i = gr_lo 10^(i log_step)), network training, and Newton from three
+    starts at the held-out values Gr = gr_lo 10^((i + 1/2) log_step).
+    Returns a dict of everything measured."""
+    import torch
+    from synth import inputs as S  # seeded grid faces (input construction only)
+    f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
+    faces = (f, f, f)
+    log_step = log_step if log_step is not None else math.log10(300.0) / 23.0
+    train_grs = [gr_lo * 10 ** (i * log_step) for i in range(ntrain)]
+    held = [i for i in held if i + 1 < ntrain]
+    pre = []
+    g = 1e4
+    while g < gr_lo:
+        pre.append(g)
+        g *= 1.6
+    t0 = time.perf_counter()
+    states, infos = sweep(faces, pre + train_grs, max_matvec=20000, max_iter=20, precond_sigma=precond_sigma,
+                          log=log)
+    t_cont = time.perf_counter() - t0
+    if len(states) < len(pre) + len(train_grs):
+        raise RuntimeError("continuation did not reach every training value")
+    states = states[len(pre):]
+    mv_cont = sum(i["matvecs_all_attempts"] for i in infos)
+    ts = build_training_set(faces, train_grs, states, factor)
+    lgr = (math.log10(train_grs[0]), math.log10(train_grs[-1]))
+    net, hist, t_train = train(ts, lgr, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed,
+                               data_seed=data_seed, log=log)
+    out = dict(grid=f"{n}^3 {grid}", network=f"{net.res}^3", factor=factor, train_gr=train_grs,
+               continuation_seconds=t_cont, continuation_matvecs=mv_cont, train_seconds=t_train,
+               epochs=epochs, final_loss=hist[-1], precond_sigma=precond_sigma, held_out=[])
+    cond = torch.from_numpy(_conduction_state(*faces)).cuda()
+    for i in held:
+        gr = gr_lo * 10 ** ((i + 0.5) * log_step)
+        r = compare_starts(faces, gr, states[i], train_grs[i], net, ts.norm, tol_abs=tol_abs,
+                           precond_sigma=precond_sigma, log=log)
+        rec = {"Gr": gr, "nearest_Gr": train_grs[i], "state_distance": r["state_distance"],
+               "conduction_F0": guess_residual(faces, gr, cond)}
+        for k in START_KINDS:
+            v = r[k]
+            rec[k] = {"converged": v["converged"], "iters": v["iters"], "matvecs": v["matvecs"],
+                      "F0": v["hist"][0], "seconds": round(v["seconds"], 3), "hist": v["hist"]}
+        out["held_out"].append(rec)
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="learned Newton guess vs continuation (held-out Gr)")
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--grid", choices=("uniform", "clustered"), default="clustered")
+    ap.add_argument("--factor", type=int, default=2)
+    ap.add_argument("--ntrain", type=int, default=15)
+    ap.add_argument("--epochs", type=int, default=6000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=2)
+    ap.add_argument("--sigma", type=float, default=10.0, help="preconditioner shift (negative: none)")
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    res = experiment(n=a.n, grid=a.grid, factor=a.factor, ntrain=a.ntrain, epochs=a.epochs, lr=a.lr,
+                     batch=a.batch, precond_sigma=None if a.sigma < 0 else a.sigma,
+                     log=lambda m: print(m, flush=True))
+    text = json.dumps(res)
+    if a.json:
+        with open(a.json, "w") as fh:
+            fh.write(text + "\n")
+    print(text, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,67 @@
+"""What the trained network gains over the method without it (learned
+Newton guess, end to end on the GPU): steady states by continuation on a
+16^3 grid at six Gr values, the network trained on them by the library's
+kernels, and Newton at five held-out Gr values started three ways.  The
+Newton residual judges every start; all starts must reach the same state."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from synth import inputs as S  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def trained():
+    from paper_2210_08816_amd import continuation as C
+    from paper_2210_08816_amd import learned as L
+    f = S.faces_uniform(16)
+    faces = (f, f, f)
+    train = [1e4 * 2.5 ** k for k in range(6)]
+    states, infos = C.sweep(faces, train, max_matvec=20000, max_iter=20, log=lambda m: print(m, flush=True))
+    assert len(states) == len(train)
+    ts = L.build_training_set(faces, train, states, 1)
+    net, hist, sec = L.train(ts, (math.log10(train[0]), math.log10(train[-1])), epochs=8000, batch=2, lr=5e-4,
+                             lr_final=1e-5, seed=3, data_seed=4)
+    print(f"training: {sec:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
+    return faces, train, states, ts, net, hist
+
+
+def test_training_converges(trained):
+    faces, train, states, ts, net, hist = trained
+    assert hist[-1] < 1e-2 * hist[0]
+
+
+def test_learned_guess_against_continuation(trained):
+    from paper_2210_08816_amd import continuation as C
+    from paper_2210_08816_amd import learned as L
+    faces, train, states, ts, net, hist = trained
+    cond = torch.from_numpy(C._conduction_state(*faces)).cuda()
+    ratios_incr, ratios_direct = [], []
+    for k in range(len(train) - 1):
+        gr = math.sqrt(train[k] * train[k + 1])
+        r = L.compare_starts(faces, gr, states[k], train[k], net, ts.norm, tol_abs=1e-11,
+                             log=lambda m: print(m, flush=True))
+        f_cond = L.guess_residual(faces, gr, cond)
+        for kind in L.START_KINDS:
+            assert r[kind]["converged"], (gr, kind)
+        assert r["state_distance"] <= 1e-8
+        f_cont = r["continuation"]["hist"][0]
+        ratios_incr.append(r["learned_increment"]["hist"][0] / f_cont)
+        ratios_direct.append(r["learned"]["hist"][0] / f_cond)
+        print(f"Gr={gr:.3e}: F0 conduction {f_cond:.3e} continuation {f_cont:.3e} "
+              f"learned {r['learned']['hist'][0]:.3e} increment {r['learned_increment']['hist'][0]:.3e}",
+              flush=True)
+    print("increment / continuation F0:", np.round(ratios_incr, 3), flush=True)
+    print("direct / conduction F0:", np.round(ratios_direct, 3), flush=True)
+    # without any converged state the method starts from rest: the network's
+    # own prediction is a far better start
+    assert max(ratios_direct) < 0.5
+    # with the nearest converged state at hand, the learned increment starts
+    # closer to the solution at every held-out Gr
+    assert max(ratios_incr) < 1.0
+    assert float(np.exp(np.mean(np.log(ratios_incr)))) < 0.7
