@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--form", choices=("fp64", "mixed", "both"), default="both",
                     help="projection form(s) to time; the headline value is the faster form's")
     ap.add_argument("--no-learned", action="store_true", help="skip the network timing leg")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="run only the network timing leg and print its JSON (for profiling)")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="also run this many plain device copies of one vector (a known-size "
                          "reference for hardware byte counters)")
@@ -157,6 +159,9 @@ def main():
     from synth import inputs as S
     from paper_2210_08816_amd import kv
 
+    if args.learned_only:
+        print(json.dumps({"learned": learned_leg(torch)}), flush=True)
+        return
     spec = S.WORKLOADS[args.workload]
     xf, yf, zf = S.workload_grid(spec)
     n_cells = spec["n"] ** 3

@@ -1,0 +1,94 @@
+"""Linear stability of a steady state, end to end on the GPU: Newton
+continuation in Gr to a target value, then the leading eigenvalues of the
+Jacobian at the converged state by Chebyshev-preconditioned Arnoldi
+iteration (the paper's method, Sec. 1 and Sec. 3).  Reports the wall time
+and matvec count of each stage.
+
+    python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --krylov 60 --eigs 10
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+from . import kv
+from .continuation import sweep
+
+
+def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
+        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, log=print):
+    import torch
+    from synth import inputs as S  # seeded grid faces (input construction only)
+    f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
+    faces = (f, f, f)
+    grs = []
+    g = 1e4
+    while g < Gr:
+        grs.append(g)
+        g *= ratio
+    grs.append(Gr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    states, infos = sweep(faces, grs, Pr=Pr, max_matvec=20000, max_iter=20, precond_sigma=precond_sigma, log=log)
+    torch.cuda.synchronize()
+    t_cont = time.perf_counter() - t0
+    if len(states) < len(grs):
+        raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
+    X = states[-1]
+    last = infos[-1]
+    ctx = kv.Context(*faces, Gr=Gr, Pr=Pr)
+    try:
+        ctx.set_base_flow(X)
+        F = torch.empty_like(X)
+        fn = ctx.residual(F)
+        sym = ctx.symmetry_measures(X)
+        v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(ctx.n)).cuda()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
+                                                   cheb_degree_max=cheb_degree_max, check=False)
+        torch.cuda.synchronize()
+        t_eig = time.perf_counter() - t1
+    finally:
+        ctx.close()
+    return {
+        "grid": f"{n}^3 {grid}", "Gr": Gr, "Pr": Pr, "unknowns": int(X.numel()),
+        "continuation": {"steps": len(grs), "seconds": round(t_cont, 3),
+                         "matvecs": int(sum(i["matvecs_all_attempts"] for i in infos)),
+                         "last_newton_iters": last["iters"], "last_newton_matvecs": last["matvecs"],
+                         "last_newton_seconds": round(last["seconds"], 3), "residual": fn,
+                         "precond_sigma": precond_sigma},
+        "symmetry_measures": list(sym),
+        "arnoldi": {"krylov_dim": krylov, "n_eigs": n_eigs, "tol": tol, "seconds": round(t_eig, 3),
+                    "matvecs": info["matvecs"], "restarts": info["restarts"], "converged": info["converged"],
+                    "status": info["status"],
+                    "eigenvalues": [[float(v.real), float(v.imag)] for v in vals],
+                    "residuals": [float(r) for r in res]},
+    }
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--grid", choices=("uniform", "clustered"), default="clustered")
+    ap.add_argument("--gr", type=float, default=4e7)
+    ap.add_argument("--krylov", type=int, default=60)
+    ap.add_argument("--eigs", type=int, default=10)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--sigma", type=float, default=10.0, help="preconditioner shift (negative: none)")
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol,
+              precond_sigma=None if a.sigma < 0 else a.sigma, log=lambda m: print(m, flush=True))
+    text = json.dumps(res)
+    if a.json:
+        with open(a.json, "w") as fh:
+            fh.write(text + "\n")
+    print(text, flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,32 @@ def test_residual(kind, shape, Gr, K, amp):
     assert abs(norm - O.wnorm(g.weights(), ref)) <= 1e-12 * norm
 
 
+# The full-size workloads: 100^3 clustered at Gr 4e7 and 256^3 clustered at
+# Gr 2e8, the launch configuration the benchmark times (every output compared).
+FULL = [("cube100_clustered_gr4e7", 1000), ("cube256_clustered_gr2e8", 1000)]
+
+
+@pytest.mark.parametrize("workload,seed", FULL)
+def test_projected_jacobian_full_size(workload, seed):
+    from paper_2210_08816_amd import kv
+    print(f"case PJ full {workload}", flush=True)
+    spec = S.WORKLOADS[workload]
+    fx = S.workload_grid(spec)
+    g = O.Grid(*fx, Gr=spec["Gr"], Pr=spec["Pr"])
+    X0 = S.base_flow(*fx, K=spec["K"], amp=spec["amp"], seed=spec["base_seed"])
+    ctx = kv.Context(*fx, Gr=spec["Gr"], Pr=spec["Pr"])
+    ctx.set_base_flow(to_dev(X0))
+    x = S.perturbation(g.size, seed)
+    y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    ctx.apply_jacobian(to_dev(x), y, project=True)
+    got = to_host(y)
+    del y
+    ref = O.apply_jacobian(g, X0, x)
+    err = field_rel_errors(g, got, ref)
+    print("field errors", err, flush=True)
+    assert max(err) <= TOL64, err
+
+
 def test_weighted_dot_and_symmetry():
     g, X0, ctx = make("clustered", (33, 20, 17), 1e6, 3, 0.1)
     a = S.perturbation(g.size, 1)
