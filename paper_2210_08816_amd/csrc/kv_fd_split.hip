@@ -99,8 +99,11 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
   constexpr int NS = INV ? 2 : 1;  // operand sets
   constexpr int RM = BM / 32, RN = BN / 32;   // 16x16 blocks per wave
   constexpr int AE = BM * BK / 256, BE = BK * BN / 256;  // tile elements per thread
-  __shared__ T As[NS][BK][BM + 2];
-  __shared__ T Bs[NS][BK][BN + 2];
+  // forward kinds double-buffer the LDS chunks (one barrier per chunk); the
+  // inverse kinds carry two operand sets and keep one buffer (two barriers)
+  constexpr int NB = INV ? 1 : 2;
+  __shared__ T As[NB][NS][BK][BM + 2];
+  __shared__ T Bs[NB][NS][BK][BN + 2];
 
   const int pars = INV ? 1 : 2;
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * pars;
@@ -202,15 +205,15 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
       }
     }
   };
-  auto stash = [&]() {
+  auto stash = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
       for (int q = 0; q < AE; ++q)
-        As[s][ak + q][ar] = AFLY ? ra[s][q] + sgn * rah[AFLY ? s : 0][AFLY ? q : 0] : ra[s][q];
+        As[buf][s][ak + q][ar] = AFLY ? ra[s][q] + sgn * rah[AFLY ? s : 0][AFLY ? q : 0] : ra[s][q];
 #pragma unroll
       for (int q = 0; q < BE; ++q)
-        Bs[s][bk][bn + q] = BFLY ? rb[s][q] + sgn * rbh[BFLY ? s : 0][BFLY ? q : 0] : rb[s][q];
+        Bs[buf][s][bk][bn + q] = BFLY ? rb[s][q] + sgn * rbh[BFLY ? s : 0][BFLY ? q : 0] : rb[s][q];
     }
   };
 
@@ -223,8 +226,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
       for (int c = 0; c < RN; ++c) acc[s][r][c] = acc_t{0, 0, 0, 0};
 
   fetch(0);
-  stash();
+  stash(0);
   __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
     if (more) fetch(k0 + BK);
@@ -235,9 +239,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
       for (int s = 0; s < NS; ++s) {
         T af[RM], bf[RN];
 #pragma unroll
-        for (int r = 0; r < RM; ++r) af[r] = As[s][kr][wm + 16 * r + (lane & 15)];
+        for (int r = 0; r < RM; ++r) af[r] = As[buf][s][kr][wm + 16 * r + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < RN; ++c) bf[c] = Bs[s][kr][wn + 16 * c + (lane & 15)];
+        for (int c = 0; c < RN; ++c) bf[c] = Bs[buf][s][kr][wn + 16 * c + (lane & 15)];
 #pragma unroll
         for (int r = 0; r < RM; ++r)
 #pragma unroll
@@ -245,10 +249,17 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
             acc[s][r][c] = Mfma<T>::op(af[r], bf[c], acc[s][r][c]);
       }
     }
-    __syncthreads();
-    if (more) {
-      stash();
+    if (NB == 2) {
+      // the other buffer was last read before the previous barrier
+      if (more) stash(buf ^ 1);
       __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();
+      if (more) {
+        stash(0);
+        __syncthreads();
+      }
     }
   }
 
@@ -348,6 +359,10 @@ hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
     return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
   }
   if (a.H >= 32 && bk_choice() == 32) return launch_tiles<T, KIND, EPI, 64, 64, 32>(a, ep, s);
+  // FP64 inverse kinds carry two accumulator sets: a 64 x 32 tile keeps their
+  // register footprint, and so their occupancy, close to the forward kinds'
+  // (FP32 ones measured faster with the full tile)
+  if (inv && sizeof(T) == 8) return launch_tiles<T, KIND, EPI, 64, 32, 16>(a, ep, s);
   return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
 }
 

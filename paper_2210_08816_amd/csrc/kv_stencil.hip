@@ -324,45 +324,67 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 
 // ---- 2.5-D tiled version ---------------------------------------------------------
 // A block owns a TX x TY tile of (x, y) columns and a chunk of KC z-planes.  It
-// marches up in z keeping three planes (k-1, k, k+1) of every field, with a
-// one-cell halo in x and y, in an LDS ring; each plane is loaded once, as
-// coalesced x-rows, and every output row is written once.
+// marches up in z with the planes the stencil reaches (k-1, k, k+1), a
+// one-cell halo in x and y, in LDS and registers; each plane is loaded once,
+// as coalesced x-rows, and every output row is written once.
 constexpr int TX = 64, TY = 4, KC = 32;
 constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
 
+// LDS holds only what other columns read: every field on plane k; u and v
+// also on plane k-1 (the w equation reads u(i+1, k-1), v(j+1, k-1)); w also
+// on plane k+1 (the u and v equations read w(i-1, k+1), w(j-1, k+1)).  The
+// thread's own column at k-1 (w, T) and k+1 (u, v, T) is kept in registers.
+// That is 7 planes per field set (14 for J, 7 for N) instead of a 3-plane
+// ring of every field: 44 KB per block for J, so three blocks share a CU.
 template <int NF>
 struct TileAcc {
-  const double* pl[3];  // planes k-1, k, k+1: [NF fields][PY][PX] each
-  int ic, jc, kc, off;  // this thread's cell and its offset inside a plane
-  __device__ __forceinline__ double at(int f, int i, int j, int k) const {
-    return pl[k - kc + 1][f * PLANE + off + (j - jc) * PX + (i - ic)];
+  static constexpr int NSF = NF / 4;  // field sets: base and perturbation (J) or one (N)
+  const double* lds;
+  int ic, jc, kc, off;                // this thread's cell and its offset inside a plane
+  double un[NSF], vn[NSF], tn[NSF];   // own column, plane k+1
+  double wp[NSF], tp[NSF];            // own column, plane k-1
+  // LDS plane of (component, set, plane parity): u, v, w two planes each, T one
+  static __device__ __forceinline__ int slot(int comp, int s, int pp) {
+    return comp < 3 ? (comp * NSF + s) * 2 + pp : 6 * NSF + s;
   }
-  // field index: (component, s) -> 2*comp + s for NF = 8, comp for NF = 4
-  __device__ __forceinline__ int fi(int comp, int s) const { return NF == 8 ? 2 * comp + s : comp; }
-  __device__ __forceinline__ double U(int s, int i, int j, int k) const { return at(fi(0, s), i, j, k); }
-  __device__ __forceinline__ double V(int s, int i, int j, int k) const { return at(fi(1, s), i, j, k); }
-  __device__ __forceinline__ double W(int s, int i, int j, int k) const { return at(fi(2, s), i, j, k); }
-  __device__ __forceinline__ double T(int s, int i, int j, int k) const { return at(fi(3, s), i, j, k); }
+  __device__ __forceinline__ double ld(int comp, int s, int k, int i, int j) const {
+    return lds[slot(comp, s, k & 1) * PLANE + off + (j - jc) * PX + (i - ic)];
+  }
+  __device__ __forceinline__ int st(int s) const { return NSF == 2 ? s : 0; }
+  __device__ __forceinline__ double U(int s, int i, int j, int k) const {
+    return k > kc ? un[st(s)] : ld(0, st(s), k, i, j);
+  }
+  __device__ __forceinline__ double V(int s, int i, int j, int k) const {
+    return k > kc ? vn[st(s)] : ld(1, st(s), k, i, j);
+  }
+  __device__ __forceinline__ double W(int s, int i, int j, int k) const {
+    return k < kc ? wp[st(s)] : ld(2, st(s), k, i, j);
+  }
+  __device__ __forceinline__ double T(int s, int i, int j, int k) const {
+    return k > kc ? tn[st(s)] : (k < kc ? tp[st(s)] : ld(3, st(s), k, i, j));
+  }
 };
 
-// Plane kp of every field, fetched into registers (each thread owns the tile
-// entries tid and tid + 256 of every field; all loads are issued before any
-// is used), then stored into the plane's ring slot.  Outside the domain and
-// on walls the value is zero.
-constexpr int PER = (PLANE + 255) / 256;
+// A plane of every field, fetched into registers: entry 0 of each thread is
+// its own column, entry 1 (the first 140 threads) one of the 140 halo
+// columns around the 64 x 4 tile.  Outside the domain and on walls the value
+// is zero.
+constexpr int NHALO = 2 * PX + 2 * TY;
 
 template <int NF>
 struct PlaneRegs {
-  double v[NF][PER];
+  double v[NF][2];
 };
 
-// Where this thread's two tile entries live in each packed block, once per
+// Where this thread's two entries live in each packed block, once per
 // block: a plane kp of block c is at  base[c][q] + kp * stride[c]  (32-bit
-// offsets: n < 2^31), valid where the in-plane position lies in the block.
+// offsets: n < 2^31), valid where the in-plane position lies in the block;
+// pos[q] is the entry's position in an LDS plane (-1: none).
 struct FetchMap {
-  int32_t base[4][PER];
+  int32_t base[4][2];
   int32_t stride[4];
-  uint32_t ok[PER];  // bit c: in-plane position valid for block c
+  uint32_t ok[2];  // bit c: in-plane position valid for block c
+  int pos[2];
 };
 
 __device__ __forceinline__ FetchMap fetch_map(const Grid& g, int i0, int j0) {
@@ -373,10 +395,27 @@ __device__ __forceinline__ FetchMap fetch_map(const Grid& g, int i0, int j0) {
   m.stride[2] = ny * nx;
   m.stride[3] = ny * nx;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int r = threadIdx.x + 256 * q;
-    const int i = i0 - 1 + r % PX, j = j0 - 1 + r / PX;
-    const bool rin = r < PLANE;
+  for (int q = 0; q < 2; ++q) {
+    int ti, tj;
+    bool rin = true;
+    if (q == 0) {
+      ti = threadIdx.x % TX;
+      tj = threadIdx.x / TX;
+    } else {
+      const int h = threadIdx.x;
+      rin = h < NHALO;
+      if (h < PX) {
+        ti = h - 1, tj = -1;
+      } else if (h < 2 * PX) {
+        ti = h - PX - 1, tj = TY;
+      } else if (h < 2 * PX + TY) {
+        ti = -1, tj = h - 2 * PX;
+      } else {
+        ti = TX, tj = h - 2 * PX - TY;
+      }
+    }
+    const int i = i0 + ti, j = j0 + tj;
+    m.pos[q] = rin ? (tj + 1) * PX + (ti + 1) : -1;
     const bool iin = i >= 0 && i < nx, jin = j >= 0 && j < ny;
     uint32_t ok = 0;
     if (rin && jin && i >= 1 && i <= nx - 1) ok |= 1u;
@@ -398,14 +437,16 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const double* p, int6
 }
 constexpr int OOB = 0x7ffffff8;  // a byte offset past every buffer
 
+// field f of a PlaneRegs: component f / NSF, set f % NSF
 template <int NF>
 __device__ __forceinline__ void fetch_plane(const Grid& g, __amdgpu_buffer_rsrc_t rB, __amdgpu_buffer_rsrc_t rx,
                                             const FetchMap& m, int kp, PlaneRegs<NF>& R) {
+  constexpr int NSF = NF / 4;
   // plane validity per block: u, v, T need 0 <= kp < nz; w (faces) 1 <= kp <= nz-1
   const bool kin = (kp >= 0 && kp < g.nz);
   const bool win = (kp >= 1 && kp < g.nz);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
+  for (int q = 0; q < 2; ++q) {
     int off[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -414,22 +455,25 @@ __device__ __forceinline__ void fetch_plane(const Grid& g, __amdgpu_buffer_rsrc_
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      const int comp = NF == 8 ? f >> 1 : f;
-      const __amdgpu_buffer_rsrc_t r = (NF == 8 && (f & 1) == 0) ? rB : rx;
+      const int comp = f / NSF;
+      const __amdgpu_buffer_rsrc_t r = (NSF == 2 && (f % NSF) == 0) ? rB : rx;
       R.v[f][q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off[comp], 0, 0));
     }
   }
 }
 
+// Store the components in mask (bit c: component c) of plane kp.
 template <int NF>
-__device__ __forceinline__ void store_plane(double* lds, int kp, const PlaneRegs<NF>& R) {
-  const int slot = (kp + 3) % 3;
+__device__ __forceinline__ void store_plane(double* lds, const FetchMap& m, int kp, unsigned mask,
+                                            const PlaneRegs<NF>& R) {
+  constexpr int NSF = NF / 4;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int r = threadIdx.x + 256 * q;
-    if (r < PLANE) {
+  for (int q = 0; q < 2; ++q) {
+    if (m.pos[q] < 0) continue;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) lds[(slot * NF + f) * PLANE + r] = R.v[f][q];
+    for (int f = 0; f < NF; ++f) {
+      const int comp = f / NSF, s = f % NSF;
+      if ((mask >> comp) & 1u) lds[TileAcc<NF>::slot(comp, s, kp & 1) * PLANE + m.pos[q]] = R.v[f][q];
     }
   }
 }
@@ -439,6 +483,7 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
                                                              const double* __restrict__ x, double* __restrict__ y,
                                                              int tiles_x, int tiles_y, int chunks) {
   constexpr int NF = MODE ? 4 : 8;
+  constexpr int NSF = NF / 4;
   extern __shared__ double lds[];
   // XCD-aware order: blocks are dealt round-robin over 8 XCDs; give each XCD a
   // contiguous range of tiles so y-neighbouring tiles share an L2.
@@ -456,31 +501,61 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   const FetchMap fm = fetch_map(g, i0, j0);
   const __amdgpu_buffer_rsrc_t rB = vec_rsrc(B, g.n), rx = vec_rsrc(x, g.n);
   BufOut out{vec_rsrc(y, g.n), &g};
-  PlaneRegs<NF> R;
-  fetch_plane<NF>(g, rB, rx, fm, k0 - 1, R);
-  store_plane<NF>(lds, k0 - 1, R);
-  fetch_plane<NF>(g, rB, rx, fm, k0, R);
-  store_plane<NF>(lds, k0, R);
-  fetch_plane<NF>(g, rB, rx, fm, k0 + 1, R);
-  store_plane<NF>(lds, k0 + 1, R);
+  TileAcc<NF> A;
+  A.lds = lds;
+  A.ic = i;
+  A.jc = j;
+  A.off = (j - j0 + 1) * PX + (i - i0 + 1);
+  // prologue: u, v of plane k0-1 and w, T of it in registers; every field of
+  // plane k0; w of plane k0+1 (u, v, T of it in registers)
+  PlaneRegs<NF> Rn, Rf;
+  fetch_plane<NF>(g, rB, rx, fm, k0 - 1, Rf);
+  fetch_plane<NF>(g, rB, rx, fm, k0, Rn);
+  store_plane<NF>(lds, fm, k0 - 1, 0x3u, Rf);
+#pragma unroll
+  for (int s = 0; s < NSF; ++s) {
+    A.wp[s] = Rf.v[2 * NSF + s][0];
+    A.tp[s] = Rf.v[3 * NSF + s][0];
+  }
+  store_plane<NF>(lds, fm, k0, 0xfu, Rn);
+  fetch_plane<NF>(g, rB, rx, fm, k0 + 1, Rn);
+  store_plane<NF>(lds, fm, k0 + 1, 0x4u, Rn);
   __syncthreads();
   for (int k = k0; k < k1; ++k) {
     // software pipeline: plane k+2 is in flight while plane k is computed
     const bool more = k + 1 < k1;
-    if (more) fetch_plane<NF>(g, rB, rx, fm, k + 2, R);
-    if (i < g.nx && j < g.ny) {
-      TileAcc<NF> A;
-      A.pl[0] = lds + ((k + 2) % 3) * NF * PLANE;
-      A.pl[1] = lds + (k % 3) * NF * PLANE;
-      A.pl[2] = lds + ((k + 1) % 3) * NF * PLANE;
-      A.ic = i;
-      A.jc = j;
-      A.kc = k;
-      A.off = (j - j0 + 1) * PX + (i - i0 + 1);
-      point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out);
+    if (more) fetch_plane<NF>(g, rB, rx, fm, k + 2, Rf);
+#pragma unroll
+    for (int s = 0; s < NSF; ++s) {
+      A.un[s] = Rn.v[0 * NSF + s][0];
+      A.vn[s] = Rn.v[1 * NSF + s][0];
+      A.tn[s] = Rn.v[3 * NSF + s][0];
     }
+    A.kc = k;
+    double wk[NSF], tk[NSF];
+#pragma unroll
+    for (int s = 0; s < NSF; ++s) {
+      wk[s] = A.ld(2, s, k, i, j);
+      tk[s] = A.ld(3, s, k, i, j);
+    }
+    if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out);
     __syncthreads();
-    if (more) store_plane<NF>(lds, k + 2, R);   // slot of plane k-1, no longer read
+    if (more) {
+      // u, v, T of plane k+1 replace those of planes k-1 and k; w of plane
+      // k+2 replaces w of plane k
+      store_plane<NF>(lds, fm, k + 1, 0xbu, Rn);
+      store_plane<NF>(lds, fm, k + 2, 0x4u, Rf);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        Rn.v[f][0] = Rf.v[f][0];
+        Rn.v[f][1] = Rf.v[f][1];
+      }
+#pragma unroll
+      for (int s = 0; s < NSF; ++s) {
+        A.wp[s] = wk[s];
+        A.tp[s] = tk[s];
+      }
+    }
     __syncthreads();
   }
 }
@@ -709,8 +784,8 @@ hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, d
   const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, ch = (g.nz + KC - 1) / KC;
   const int64_t total = (int64_t)tx * ty * ch;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-  const size_t lds0 = 3 * 8 * PLANE * sizeof(double), lds1 = 3 * 4 * PLANE * sizeof(double);
-  // the 8-field ring needs more than the default 64 KB of dynamic LDS
+  const size_t lds0 = 14 * PLANE * sizeof(double), lds1 = 7 * PLANE * sizeof(double);
+  // raise the dynamic-LDS limit explicitly, whatever its default
   static int lds_ok = -1;
   if (lds_ok < 0)
     lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&operator_tiled_kernel<0>),
