@@ -227,20 +227,23 @@ def A_project(A: Operator, v):
 
 
 # ---- Chebyshev-preconditioned Arnoldi -----------------------------------------
-def ellipse(unwanted):
+def ellipse(unwanted, wanted_min_re):
     """Centre d, semi-axes a (real) and b (imag), and c^2 = a^2 - b^2 of an
-    ellipse symmetric about the real axis enclosing the unwanted values."""
+    ellipse symmetric about the real axis that encloses the unwanted values
+    and stays left of the wanted ones: its right end lies halfway between
+    the largest unwanted real part and the smallest wanted one, its left end
+    1% of the unwanted real range left of the smallest unwanted real part,
+    and b is the smallest semi-axis that then encloses every unwanted value."""
     re, im = unwanted.real, np.abs(unwanted.imag)
     rmin, rmax = float(re.min()), float(re.max())
-    d = 0.5 * (rmin + rmax)
-    a = max(0.5 * (rmax - rmin), 1e-300)
-    while True:
-        t = ((re - d) / a) ** 2
-        if np.all((t < 1.0) | (im == 0.0)):
-            break
-        a *= 1.1
-    ok = t < 1.0
-    b2 = float(np.max(im[ok] ** 2 / (1.0 - t[ok]), initial=0.0))
+    span = max(rmax - rmin, 1e-300)
+    gap = wanted_min_re - rmax
+    right = rmax + 0.5 * gap if gap > 0 else rmax + 1e-3 * span
+    left = rmin - 0.01 * span
+    d = 0.5 * (left + right)
+    a = 0.5 * (right - left)
+    t = ((re - d) / a) ** 2
+    b2 = float(np.max(im ** 2 / (1.0 - t), initial=0.0))
     b = math.sqrt(b2)
     return d, a, b, a * a - b2
 
@@ -294,8 +297,8 @@ def cheb_arnoldi(A: Operator, v0, m, n_eigs, tol=1e-8, max_matvec=100000,
         if len(unw) == 0:
             v = z0
         else:
-            d, a, b, c2 = ellipse(unw)
             ref = min((vals[i] for i in sel), key=lambda t: t.real)
+            d, a, b, c2 = ellipse(unw, ref.real)
             wr = ref.real - d
             deg = cheb_degree(wr, a, b, c2, cheb_degree_max)
             deg = min(deg, max(0, max_matvec - (A.matvecs - m0) - m))

@@ -488,32 +488,33 @@ int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz
   return KV_OK;
 }
 
-// ---- Chebyshev helpers (ellipse and degree), same definitions as the oracle's -------------
-void ellipse(const std::vector<std::complex<double>>& unw, double* d, double* a, double* b, double* c2) {
+// ---- Chebyshev helpers (ellipse and degree) ------------------------------------------------
+// Ellipse (centre d, real semi-axis a, imaginary semi-axis b, c^2 = a^2 - b^2)
+// symmetric about the real axis that encloses the unwanted Ritz values and
+// stays left of the wanted ones: right end halfway between the largest
+// unwanted and the smallest wanted real part, left end 1% of the unwanted
+// real range beyond the smallest unwanted real part, b the smallest
+// semi-axis that then encloses every unwanted value.
+void ellipse(const std::vector<std::complex<double>>& unw, double wanted_min_re, double* d, double* a, double* b,
+             double* c2) {
   double rmin = 1e300, rmax = -1e300;
   for (auto& z : unw) {
     rmin = std::min(rmin, z.real());
     rmax = std::max(rmax, z.real());
   }
-  *d = 0.5 * (rmin + rmax);
-  double aa = std::max(0.5 * (rmax - rmin), 1e-300);
-  for (;;) {
-    bool ok = true;
-    for (auto& z : unw) {
-      const double t = std::pow((z.real() - *d) / aa, 2);
-      if (!(t < 1.0) && z.imag() != 0.0) ok = false;
-    }
-    if (ok) break;
-    aa *= 1.1;
-  }
+  const double span = std::max(rmax - rmin, 1e-300);
+  const double gap = wanted_min_re - rmax;
+  const double right = gap > 0 ? rmax + 0.5 * gap : rmax + 1e-3 * span;
+  const double left = rmin - 0.01 * span;
+  *d = 0.5 * (left + right);
+  *a = 0.5 * (right - left);
   double b2 = 0.0;
   for (auto& z : unw) {
-    const double t = std::pow((z.real() - *d) / aa, 2);
-    if (t < 1.0) b2 = std::max(b2, z.imag() * z.imag() / (1.0 - t));
+    const double t = std::pow((z.real() - *d) / *a, 2);
+    b2 = std::max(b2, z.imag() * z.imag() / (1.0 - t));
   }
-  *a = aa;
   *b = std::sqrt(b2);
-  *c2 = aa * aa - b2;
+  *c2 = (*a) * (*a) - b2;
 }
 
 int cheb_degree(double wr, double a, double b, double c2, int dmax) {
@@ -1308,9 +1309,9 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     int deg = 0;
     double d = 0, a = 0, bb = 0, c2 = 0, wr = 0;
     if (!unw.empty()) {
-      ellipse(unw, &d, &a, &bb, &c2);
       double ref = 1e300;
       for (int i : rz.sel) ref = std::min(ref, rz.vals[i].real());
+      ellipse(unw, ref, &d, &a, &bb, &c2);
       wr = ref - d;
       deg = cheb_degree(wr, a, bb, c2, p->cheb_degree_max);
       deg = std::min(deg, std::max(0, p->max_matvec - matvecs - m));

@@ -18,26 +18,39 @@ from .continuation import sweep
 
 
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
-        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, log=print):
+        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, log=print):
+    """state: a converged packed state at Gr (host array) to start from
+    instead of continuation; save_state: file to store the converged state."""
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
     f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
     faces = (f, f, f)
-    grs = []
-    g = 1e4
-    while g < Gr:
-        grs.append(g)
-        g *= ratio
-    grs.append(Gr)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    states, infos = sweep(faces, grs, Pr=Pr, max_matvec=20000, max_iter=20, precond_sigma=precond_sigma, log=log)
-    torch.cuda.synchronize()
-    t_cont = time.perf_counter() - t0
-    if len(states) < len(grs):
-        raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
-    X = states[-1]
-    last = infos[-1]
+    cont = None
+    if state is None:
+        grs = []
+        g = 1e4
+        while g < Gr:
+            grs.append(g)
+            g *= ratio
+        grs.append(Gr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        states, infos = sweep(faces, grs, Pr=Pr, max_matvec=20000, max_iter=20, precond_sigma=precond_sigma,
+                              log=log)
+        torch.cuda.synchronize()
+        t_cont = time.perf_counter() - t0
+        if len(states) < len(grs):
+            raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
+        X = states[-1]
+        last = infos[-1]
+        cont = {"steps": len(grs), "seconds": round(t_cont, 3),
+                "matvecs": int(sum(i["matvecs_all_attempts"] for i in infos)),
+                "last_newton_iters": last["iters"], "last_newton_matvecs": last["matvecs"],
+                "last_newton_seconds": round(last["seconds"], 3), "precond_sigma": precond_sigma}
+        if save_state:
+            np.save(save_state, X.cpu().numpy())
+    else:
+        X = torch.from_numpy(np.asarray(state, dtype=np.float64)).cuda()
     ctx = kv.Context(*faces, Gr=Gr, Pr=Pr)
     try:
         ctx.set_base_flow(X)
@@ -53,13 +66,11 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
         t_eig = time.perf_counter() - t1
     finally:
         ctx.close()
+    if cont is not None:
+        cont["residual"] = fn
     return {
-        "grid": f"{n}^3 {grid}", "Gr": Gr, "Pr": Pr, "unknowns": int(X.numel()),
-        "continuation": {"steps": len(grs), "seconds": round(t_cont, 3),
-                         "matvecs": int(sum(i["matvecs_all_attempts"] for i in infos)),
-                         "last_newton_iters": last["iters"], "last_newton_matvecs": last["matvecs"],
-                         "last_newton_seconds": round(last["seconds"], 3), "residual": fn,
-                         "precond_sigma": precond_sigma},
+        "grid": f"{n}^3 {grid}", "Gr": Gr, "Pr": Pr, "unknowns": int(X.numel()), "residual": fn,
+        "continuation": cont,
         "symmetry_measures": list(sym),
         "arnoldi": {"krylov_dim": krylov, "n_eigs": n_eigs, "tol": tol, "seconds": round(t_eig, 3),
                     "matvecs": info["matvecs"], "restarts": info["restarts"], "converged": info["converged"],
@@ -78,11 +89,17 @@ def main(argv=None):
     ap.add_argument("--krylov", type=int, default=60)
     ap.add_argument("--eigs", type=int, default=10)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--degree", type=int, default=200, help="largest Chebyshev filter degree")
+    ap.add_argument("--max-matvec", type=int, default=200000)
     ap.add_argument("--sigma", type=float, default=10.0, help="preconditioner shift (negative: none)")
     ap.add_argument("--json", default=None)
+    ap.add_argument("--save-state", default=None, help="store the converged state (.npy)")
+    ap.add_argument("--load-state", default=None, help="start from a stored converged state (.npy)")
     a = ap.parse_args(argv)
-    res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol,
-              precond_sigma=None if a.sigma < 0 else a.sigma, log=lambda m: print(m, flush=True))
+    state = np.load(a.load_state) if a.load_state else None
+    res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
+              max_matvec=a.max_matvec, precond_sigma=None if a.sigma < 0 else a.sigma, state=state,
+              save_state=a.save_state, log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
         with open(a.json, "w") as fh:
