@@ -119,6 +119,10 @@ int kv_project(kv_ctx* ctx, double* y, unsigned flags, double* div_max, int* swe
 /* <a, b>_W on the device, result to host *out. */
 int kv_dot(kv_ctx* ctx, const double* a, const double* b, double* out);
 
+/* y <- a x + b y on the device (packed vectors, n values; x may equal y).
+ * a, b: host scalars. */
+int kv_axpby(kv_ctx* ctx, double a, const double* x, double b, double* y);
+
 /* Symmetry measures R_ref, R_2D, R_3D of Eqs. 7-9 (Sec. 2) of the packed
  * state X (device), over cell-centred theta = T - (1 - x).  host out[3]. */
 int kv_symmetry_measures(kv_ctx* ctx, const double* X, double out[3]);

@@ -772,6 +772,13 @@ int kv_dot(kv_ctx* c, const double* a, const double* b, double* out) {
   return rc;
 }
 
+int kv_axpby(kv_ctx* c, double a, const double* x, double b, double* y) {
+  if (!c) return KV_EINVAL;
+  if (!x || !y) return fail(c, KV_EINVAL, "null argument");
+  if (!std::isfinite(a) || !std::isfinite(b)) return fail(c, KV_EINVAL, "non-finite coefficient");
+  return lincomb(c, 2, {a, b}, {x, y}, y);
+}
+
 int kv_symmetry_measures(kv_ctx* c, const double* X, double out[3]) {
   if (!c) return KV_EINVAL;
   if (!X || !out) return fail(c, KV_EINVAL, "null argument");

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
-               "kv_apply_jacobian", "kv_project", "kv_dot", "kv_symmetry_measures",
+               "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.kv_apply_jacobian.argtypes = [P, P, P, ctypes.c_uint]
     lib.kv_project.argtypes = [P, P, ctypes.c_uint, PD, ctypes.POINTER(ctypes.c_int)]
     lib.kv_dot.argtypes = [P, P, P, PD]
+    lib.kv_axpby.argtypes = [P, D, P, D, P]
     lib.kv_symmetry_measures.argtypes = [P, P, PD]
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
@@ -194,6 +195,10 @@ class Context:
         out = ctypes.c_double()
         self._check(self._lib.kv_dot(self._h, _dptr(a, self.n), _dptr(b, self.n), ctypes.byref(out)))
         return out.value
+
+    def axpby(self, a, x, b, y):
+        """y <- a x + b y."""
+        self._check(self._lib.kv_axpby(self._h, float(a), _dptr(x, self.n), float(b), _dptr(y, self.n)))
 
     def timing(self, enable: bool):
         """Start (True) or stop (False) phase timing; returns the sums since the

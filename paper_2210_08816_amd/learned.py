@@ -120,14 +120,21 @@ def train(ts: TrainingSet, lgr_range, epochs=2000, batch=4, lr=2e-3, lr_final=2e
     return net, hist, time.perf_counter() - t0
 
 
-def guess(ctx, net, norm: Normalization, Gr, X, X_near=None, Gr_near=None):
+def guess(ctx, net, norm: Normalization, Gr, X, X_near=None, Gr_near=None, smooth_sigma=None,
+          restore_sigma=None):
     """Learned initial guess at Gr on ctx's grid, projected, into X (packed,
     float64 CUDA).
       direct    (X_near None): the interpolated prediction at Gr;
       increment (X_near, Gr_near given): the converged state X_near moved by
                 the predicted change between Gr_near and Gr,
                 X = X_near + S(NN(Gr)) - S(NN(Gr_near)); the network's error
-                common to both predictions cancels."""
+                common to both predictions cancels.
+    smooth_sigma (increment only): the change is low-pass filtered first,
+    D <- sigma M^-1 D with the Stokes/heat operator M = sigma - nu Lap
+    (factor sigma / (sigma + nu lambda) on a diffusion mode lambda): the
+    network's grid-scale error, which the 1/h^2 terms of the residual
+    amplify in thin wall cells, is damped, smooth changes pass.  The
+    context's preconditioner is set to restore_sigma afterwards (None: off)."""
     import torch
     r = net.res
     out = torch.empty(4 * r ** 3, dtype=torch.float32, device="cuda")
@@ -137,8 +144,20 @@ def guess(ctx, net, norm: Normalization, Gr, X, X_near=None, Gr_near=None):
     else:
         ref = torch.empty_like(out)
         net.predict(Gr_near, ref)
-        X.copy_(X_near)
-        ctx.state_add_cell_increment(out, ref, net.centres, norm.scale, X)
+        if smooth_sigma is None:
+            X.copy_(X_near)
+            ctx.state_add_cell_increment(out, ref, net.centres, norm.scale, X)
+        else:
+            D = torch.zeros_like(X)
+            ctx.state_add_cell_increment(out, ref, net.centres, norm.scale, D)
+            ctx.set_preconditioner(True, smooth_sigma)
+            ctx.apply_preconditioner(D, D)
+            if restore_sigma is None:
+                ctx.set_preconditioner(False)
+            else:
+                ctx.set_preconditioner(True, restore_sigma)
+            X.copy_(X_near)
+            ctx.axpby(smooth_sigma, D, 1.0, X)
     ctx.project(X)
     return X
 
@@ -147,7 +166,7 @@ START_KINDS = ("continuation", "learned", "learned_increment")
 
 
 def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10, max_iter=20,
-                   max_matvec=40000, kinds=START_KINDS, precond_sigma=None, log=None):
+                   max_matvec=40000, kinds=START_KINDS, precond_sigma=None, smooth_sigmas=(), log=None):
     """Newton at Gr from the nearest converged state (continuation), from the
     direct learned guess and from the learned increment, each to the same
     absolute residual tolerance.  Returns a record per start (iterations,
@@ -160,7 +179,7 @@ def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10
         ctx.set_preconditioner(True, precond_sigma)
     finals = []
     try:
-        for kind in kinds:
+        for kind in list(kinds) + [f"learned_increment_smooth{sg:g}" for sg in smooth_sigmas]:
             X = torch.empty_like(X_near)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -169,8 +188,12 @@ def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10
                 ctx.project(X)
             elif kind == "learned":
                 guess(ctx, net, norm, Gr, X)
-            else:
+            elif kind == "learned_increment":
                 guess(ctx, net, norm, Gr, X, X_near=X_near, Gr_near=Gr_near)
+            else:
+                sg = float(kind[len("learned_increment_smooth"):])
+                guess(ctx, net, norm, Gr, X, X_near=X_near, Gr_near=Gr_near, smooth_sigma=sg,
+                      restore_sigma=precond_sigma)
             torch.cuda.synchronize()
             tg = time.perf_counter() - t0
             rec = newton_solve(ctx, X, tol_rel=0.0, tol_abs=tol_abs, max_iter=max_iter, max_matvec=max_matvec)
@@ -207,7 +230,7 @@ def guess_residual(faces, Gr, X, Pr=0.71):
 
 def experiment(n=64, grid="clustered", factor=2, gr_lo=1e6, log_step=None, ntrain=15, held=(1, 4, 7, 10, 13),
                epochs=6000, lr=1e-3, lr_final=1e-5, batch=2, precond_sigma=10.0, seed=3, data_seed=4,
-               tol_abs=1e-10, log=print):
+               tol_abs=1e-10, smooth_sigmas=(), log=print):
     """Training states by continuation (from the conduction state, Gr raised
     by 1.6 per step up to gr_lo, then the training values
     Gr_i = gr_lo 10^(i log_step)), network training, and Newton from three
@@ -244,10 +267,10 @@ def experiment(n=64, grid="clustered", factor=2, gr_lo=1e6, log_step=None, ntrai
     for i in held:
         gr = gr_lo * 10 ** ((i + 0.5) * log_step)
         r = compare_starts(faces, gr, states[i], train_grs[i], net, ts.norm, tol_abs=tol_abs,
-                           precond_sigma=precond_sigma, log=log)
+                           precond_sigma=precond_sigma, smooth_sigmas=smooth_sigmas, log=log)
         rec = {"Gr": gr, "nearest_Gr": train_grs[i], "state_distance": r["state_distance"],
                "conduction_F0": guess_residual(faces, gr, cond)}
-        for k in START_KINDS:
+        for k in [k for k in r if k != "state_distance"]:
             v = r[k]
             rec[k] = {"converged": v["converged"], "iters": v["iters"], "matvecs": v["matvecs"],
                       "F0": v["hist"][0], "seconds": round(v["seconds"], 3), "hist": v["hist"]}
@@ -267,10 +290,12 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=2)
     ap.add_argument("--sigma", type=float, default=10.0, help="preconditioner shift (negative: none)")
+    ap.add_argument("--smooth", default="", help="comma-separated smoothing shifts of the learned increment")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
+    sm = tuple(float(v) for v in a.smooth.split(",") if v)
     res = experiment(n=a.n, grid=a.grid, factor=a.factor, ntrain=a.ntrain, epochs=a.epochs, lr=a.lr,
-                     batch=a.batch, precond_sigma=None if a.sigma < 0 else a.sigma,
+                     batch=a.batch, precond_sigma=None if a.sigma < 0 else a.sigma, smooth_sigmas=sm,
                      log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:

@@ -28,7 +28,9 @@ TOL_NET = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+    nb = np.linalg.norm(np.ravel(b))
+    d = np.linalg.norm(np.ravel(a) - np.ravel(b))
+    return float(d / nb) if nb > 0 else float(d)
 
 
 def centres(kind, r):
@@ -46,7 +48,8 @@ def fdev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-@pytest.mark.parametrize("kind,r,batch", [("clustered", 8, 2), ("uniform", 16, 1), ("clustered", 12, 2)])
+@pytest.mark.parametrize("kind,r,batch", [("clustered", 8, 2), ("uniform", 16, 1), ("clustered", 12, 2),
+                                          ("uniform", 4, 1), ("clustered", 20, 2)])
 def test_forward_and_inputs(kind, r, batch):
     print(f"case kvnn forward {kind} r={r} batch={batch}", flush=True)
     N = net(kind, r, batch_max=batch)
@@ -66,7 +69,8 @@ def test_forward_and_inputs(kind, r, batch):
     assert np.array_equal(to_host(one), to_host(out)[-4 * r ** 3:])
 
 
-@pytest.mark.parametrize("kind,r,batch", [("clustered", 8, 2), ("uniform", 16, 1)])
+@pytest.mark.parametrize("kind,r,batch", [("clustered", 8, 2), ("uniform", 16, 1), ("uniform", 4, 1),
+                                          ("clustered", 20, 2)])
 def test_backward(kind, r, batch):
     print(f"case kvnn backward {kind} r={r}", flush=True)
     N = net(kind, r, batch_max=batch, seed=11)

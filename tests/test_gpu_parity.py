@@ -110,6 +110,18 @@ def test_projected_jacobian_full_size(workload, seed):
     assert max(err) <= TOL64, err
 
 
+def test_axpby():
+    from paper_2210_08816_amd import kv
+    g, X0, ctx = make("clustered", (9, 7, 8), 1e5, 2, 0.1)
+    a = S.perturbation(g.size, 3)
+    b = S.perturbation(g.size, 4)
+    y = to_dev(b)
+    ctx.axpby(2.5, to_dev(a), -0.75, y)
+    assert np.allclose(to_host(y), 2.5 * a - 0.75 * b, rtol=1e-15, atol=1e-15)
+    with pytest.raises(kv.KVError):
+        ctx.axpby(float("nan"), y, 1.0, y)
+
+
 def test_weighted_dot_and_symmetry():
     g, X0, ctx = make("clustered", (33, 20, 17), 1e6, 3, 0.1)
     a = S.perturbation(g.size, 1)

@@ -187,7 +187,8 @@ def test_newton_correction_rejects_bad_input():
 # ---- Stokes/heat preconditioner ------------------------------------------------------
 @pytest.mark.parametrize("kind,shape,Gr,sigma", [("clustered", (7, 6, 5), 1e6, 0.0),
                                                  ("uniform", (32, 32, 32), 1e5, 2.0),
-                                                 ("clustered", (70, 9, 66), 4e7, 0.5)])
+                                                 ("clustered", (70, 9, 66), 4e7, 0.5),
+                                                 ("uniform", (2, 3, 2), 1e3, 1.0)])
 def test_preconditioner_matches_oracle(kind, shape, Gr, sigma):
     from oracle import precond as PC
     from tests.gpu_util import field_rel_errors
