@@ -73,6 +73,27 @@ __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, int off)
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// Two consecutive elements in one load (16 bytes for FP64, 8 for FP32).
+template <typename T>
+__device__ __forceinline__ void bload2(__amdgpu_buffer_rsrc_t r, int off, T& x0, T& x1);
+// (Elements are copied to scalars before the bit cast: a bit cast applied
+// to a vector element directly reads element 0 whatever the index.)
+template <>
+__device__ __forceinline__ void bload2<double>(__amdgpu_buffer_rsrc_t r, int off, double& x0, double& x1) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  const unsigned long long w0 = (unsigned long long)v[0] | ((unsigned long long)v[1] << 32);
+  const unsigned long long w1 = (unsigned long long)v[2] | ((unsigned long long)v[3] << 32);
+  x0 = __builtin_bit_cast(double, w0);
+  x1 = __builtin_bit_cast(double, w1);
+}
+template <>
+__device__ __forceinline__ void bload2<float>(__amdgpu_buffer_rsrc_t r, int off, float& x0, float& x1) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+  const unsigned w0 = v[0], w1 = v[1];
+  x0 = __builtin_bit_cast(float, w0);
+  x1 = __builtin_bit_cast(float, w1);
+}
+
 template <typename T>
 struct SplitArgs {
   const T* in;
@@ -91,7 +112,11 @@ struct SplitArgs {
 // (BM/2) x (BN/2) block of 16x16 MFMA accumulators).  RIGHT kinds: m = row, n = mode (fwd) or position
 // (inv).  LEFT kinds: m = mode (fwd) or position (inv), n = line position p.
 // The inverse kinds keep two accumulator sets (even -> t, odd -> u).
-template <typename T, int KIND, int EPI, int BM, int BN, int BK>
+//
+// VEC (every dimension the pairs run along is even: H, and the line length
+// of the LEFT kinds): operands move in element pairs, A along k and B along n,
+// so that the 64 lanes of one load cover whole contiguous row segments.
+template <typename T, int KIND, int EPI, int BM, int BN, int BK, bool VEC>
 __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
@@ -162,7 +187,7 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
   const int64_t boff = RIGHT ? 0 : b * a.bstride;  // batch offset of a LEFT line block
   T ra[NS][AE], rb[NS][BE];
   T rah[AFLY ? NS : 1][AFLY ? AE : 1], rbh[BFLY ? NS : 1][BFLY ? BE : 1];
-  auto fetch = [&](int k0) {
+  auto fetch_one = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int ps = INV ? s : par;  // parity of this operand set
@@ -205,7 +230,75 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
       }
     }
   };
-  auto stash = [&](int buf) {
+  // pair mapping (VEC): A pair p = tid + 256 h is row p / (BK/2), k 2 (p % (BK/2));
+  // B pair p is row p / (BN/2), n 2 (p % (BN/2))
+  constexpr int AKP = BK / 2, BNP = BN / 2;
+  auto fetch_vec = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ps = INV ? s : par;
+#pragma unroll
+      for (int h = 0; h < AE / 2; ++h) {
+        const int pp = tid + 256 * h;
+        const int gm = m0 + pp / AKP, gk = k0 + 2 * (pp % AKP);
+        const bool ok = gm < M && gk < K;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD) {
+          o = ok ? (gm * N + gk) * (int)sizeof(T) : OOB;
+          oh = ok ? (gm * N + N - 2 - gk) * (int)sizeof(T) : OOB;  // holds partners of gk + 1, gk
+        } else if (KIND == RIGHT_INV) {
+          o = ok ? (gm * N + ps * H + gk) * (int)sizeof(T) : OOB;
+        } else {
+          o = ok ? ((ps * H + gm) * H + gk) * (int)sizeof(T) : OOB;
+        }
+        const __amdgpu_buffer_rsrc_t r = (KIND == RIGHT_FWD || KIND == RIGHT_INV) ? rin : (KIND == LEFT_FWD ? rqt : rq);
+        bload2<T>(r, o, ra[s][2 * h], ra[s][2 * h + 1]);
+        if (AFLY) bload2<T>(rin, oh, rah[AFLY ? s : 0][AFLY ? 2 * h + 1 : 0], rah[AFLY ? s : 0][AFLY ? 2 * h : 0]);
+      }
+#pragma unroll
+      for (int h = 0; h < BE / 2; ++h) {
+        const int pp = tid + 256 * h;
+        const int gk = k0 + pp / BNP;
+        const int64_t gn = n0 + 2 * (pp % BNP);
+        const bool ok = gk < K && gn < NN;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD || KIND == RIGHT_INV) {
+          o = ok ? ((ps * H + gk) * H + (int)gn) * (int)sizeof(T) : OOB;
+          bload2<T>(KIND == RIGHT_FWD ? rq : rqt, o, rb[s][2 * h], rb[s][2 * h + 1]);
+        } else if (KIND == LEFT_FWD) {
+          o = ok ? (int)((boff + (int64_t)gk * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          oh = ok ? (int)((boff + (int64_t)(N - 1 - gk) * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          bload2<T>(rin, o, rb[s][2 * h], rb[s][2 * h + 1]);
+          bload2<T>(rin, oh, rbh[BFLY ? s : 0][BFLY ? 2 * h : 0], rbh[BFLY ? s : 0][BFLY ? 2 * h + 1 : 0]);
+        } else {
+          o = ok ? (int)((boff + (int64_t)(ps * H + gk) * a.P + gn) * (int64_t)sizeof(T)) : OOB;
+          bload2<T>(rin, o, rb[s][2 * h], rb[s][2 * h + 1]);
+        }
+      }
+    }
+  };
+  auto stash_vec = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int h = 0; h < AE / 2; ++h) {
+        const int pp = tid + 256 * h;
+        const int r = pp / AKP, k = 2 * (pp % AKP);
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          As[buf][s][k + e][r] = AFLY ? ra[s][2 * h + e] + sgn * rah[AFLY ? s : 0][AFLY ? 2 * h + e : 0] : ra[s][2 * h + e];
+      }
+#pragma unroll
+      for (int h = 0; h < BE / 2; ++h) {
+        const int pp = tid + 256 * h;
+        const int k = pp / BNP, n = 2 * (pp % BNP);
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          Bs[buf][s][k][n + e] = BFLY ? rb[s][2 * h + e] + sgn * rbh[BFLY ? s : 0][BFLY ? 2 * h + e : 0] : rb[s][2 * h + e];
+      }
+    }
+  };
+  auto stash_one = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
 #pragma unroll
@@ -216,6 +309,14 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
         Bs[buf][s][bk][bn + q] = BFLY ? rb[s][q] + sgn * rbh[BFLY ? s : 0][BFLY ? q : 0] : rb[s][q];
     }
   };
+  auto fetch = [&](int k0) {
+    if constexpr (VEC) fetch_vec(k0);
+    else fetch_one(k0);
+  };
+  auto stash = [&](int buf) {
+    if constexpr (VEC) stash_vec(buf);
+    else stash_one(buf);
+  };
 
   acc_t acc[NS][RM][RN];
 #pragma unroll
@@ -224,6 +325,35 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
     for (int r = 0; r < RM; ++r)
 #pragma unroll
       for (int c = 0; c < RN; ++c) acc[s][r][c] = acc_t{0, 0, 0, 0};
+
+  // epilogue coefficients of the tile's rows and columns, staged in LDS
+  // during the prologue (their load latency overlaps the first chunk's)
+  constexpr bool HASEPI = EPI != EPI_NONE;
+  __shared__ double Erow[HASEPI ? BM : 1], Ecol[HASEPI ? 2 : 1][HASEPI ? BN : 1];
+  if constexpr (HASEPI) {
+    if (tid < BM) {
+      const int gm = m0 + tid;
+      double v = 0.0;
+      if (gm < M) v = (EPI == EPI_DIVIDE) ? ep.lz[par * H + gm] : ep.isy[gm % ep.ny] * ep.isz[gm / ep.ny];
+      Erow[tid] = v;
+    }
+    if (tid < BN) {
+      const int64_t gn = n0 + tid;
+      double v0 = 0.0, v1 = 0.0;
+      if (gn < NN) {
+        if (EPI == EPI_DIVIDE) {
+          const int g32 = (int)gn;  // position in an (nx * ny) plane: fits 32 bits
+          const int bb = g32 / ep.nx, aa = g32 - bb * ep.nx;
+          v0 = ep.ly[bb] + ep.lx[aa];
+        } else {
+          v0 = ep.isx[gn];
+          v1 = ep.isx[N - 1 - gn];
+        }
+      }
+      Ecol[0][tid] = v0;
+      Ecol[HASEPI ? 1 : 0][tid] = v1;
+    }
+  }
 
   fetch(0);
   stash(0);
@@ -279,10 +409,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
           } else {
             const int mode = par * H + gm;
             if (EPI == EPI_DIVIDE) {
-              const int g32 = (int)gn;  // position in an (nx * ny) plane: fits 32 bits
-              const int bb = g32 / ep.nx, aa = g32 - bb * ep.nx;
               const int64_t flat = (int64_t)mode * ((int64_t)ep.nx * ep.ny) + gn;
-              v = (flat == ep.null3) ? 0.0 : v / (ep.lz[mode] + ep.ly[bb] + ep.lx[aa]);
+              v = (flat == ep.null3) ? 0.0
+                                     : v / (Erow[wm + r * 16 + Mfma<T>::row(lane, q)] + Ecol[0][wn + c * 16 + (lane & 15)]);
             }
             out[(int64_t)mode * a.P + gn] = (T)v;
           }
@@ -292,10 +421,9 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
           if (RIGHT) {
             const int i = (int)gn;
             if (EPI == EPI_ISQ) {
-              const int j = gm % ep.ny, k = gm / ep.ny;
-              const double syz = ep.isy[j] * ep.isz[k];
-              lo *= ep.isx[i] * syz;
-              hi *= ep.isx[N - 1 - i] * syz;
+              const double syz = Erow[wm + r * 16 + Mfma<T>::row(lane, q)];
+              lo *= Ecol[0][wn + c * 16 + (lane & 15)] * syz;
+              hi *= Ecol[HASEPI ? 1 : 0][wn + c * 16 + (lane & 15)] * syz;
             }
             out[(int64_t)gm * N + i] = (T)lo;
             out[(int64_t)gm * N + (N - 1 - i)] = (T)hi;
@@ -309,6 +437,16 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
     }
 }
 
+// Pair loads on by default; KV_FD_PAIRS=0 selects one element per load.
+bool pair_loads() {
+  static int t = -1;
+  if (t < 0) {
+    const char* e = getenv("KV_FD_PAIRS");
+    t = (e && atoi(e) == 0) ? 0 : 1;
+  }
+  return t == 1;
+}
+
 template <typename T, int KIND, int EPI, int BM, int BN, int BK>
 hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t s) {
   SplitArgs<T> a = a0;
@@ -320,49 +458,37 @@ hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t 
   a.ntiles = (int)((NN + BN - 1) / BN);
   const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
   const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_split_kernel<T, KIND, EPI, BM, BN, BK><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  // pairs stay inside a row and aligned when the half size and the line
+  // length are even
+  const bool vec = (a.H % 2 == 0) && (right || a.P % 2 == 0) && pair_loads();
+  if (vec)
+    fd_split_kernel<T, KIND, EPI, BM, BN, BK, true><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  else
+    fd_split_kernel<T, KIND, EPI, BM, BN, BK, false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
   return hipGetLastError();
 }
 
-// Tile size: 64 x 64 by default (it measured faster: four waves per SIMD
-// stay resident); KV_FD_TILE=128 selects large tiles when the half size fills
-// them (more MFMA work per operand
-// byte and per prologue); 64 x 64 otherwise.  The inverse kinds carry two
-// accumulator sets, so their tiles are half as wide.
-int tile_choice() {
+// Tile shapes (FP64, measured at H = 128): the forward kinds without an
+// epilogue take 128 x 128 tiles once the half size fills them (four times the
+// MFMA work per prologue and epilogue); the spectral-divide kind keeps 64 x 64
+// (its division epilogue at 128 x 128 needs registers for one wave per SIMD
+// only), and so do the inverse kinds, whose two accumulator sets double the
+// registers per output.  FP32 (mixed form) uses 64 x 64 throughout.
+// KV_FD_TILE=64 forces 64 x 64 everywhere.
+bool large_tiles_allowed() {
   static int t = -1;
   if (t < 0) {
     const char* e = getenv("KV_FD_TILE");
-    t = (e && atoi(e) == 128) ? 128 : 64;
+    t = (e && atoi(e) == 64) ? 0 : 1;
   }
-  return t;
-}
-
-// K-chunk staged per LDS round: 16 by default, KV_FD_BK=32 for deeper chunks.
-int bk_choice() {
-  static int t = -1;
-  if (t < 0) {
-    const char* e = getenv("KV_FD_BK");
-    t = (e && atoi(e) == 32) ? 32 : 16;
-  }
-  return t;
+  return t == 1;
 }
 
 template <typename T, int KIND, int EPI>
 hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
-  const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
-  if (sizeof(T) == 8 && a.H >= 96 && tile_choice() == 128) {
-    if (inv)
-      return right ? launch_tiles<T, KIND, EPI, 128, 64, 16>(a, ep, s)
-                   : launch_tiles<T, KIND, EPI, 64, 128, 16>(a, ep, s);
+  if (sizeof(T) == 8 && !inv && EPI == EPI_NONE && a.H >= 128 && large_tiles_allowed())
     return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
-  }
-  if (a.H >= 32 && bk_choice() == 32) return launch_tiles<T, KIND, EPI, 64, 64, 32>(a, ep, s);
-  // FP64 inverse kinds carry two accumulator sets: a 64 x 32 tile keeps their
-  // register footprint, and so their occupancy, close to the forward kinds'
-  // (FP32 ones measured faster with the full tile)
-  if (inv && sizeof(T) == 8) return launch_tiles<T, KIND, EPI, 64, 32, 16>(a, ep, s);
   return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
 }
 
