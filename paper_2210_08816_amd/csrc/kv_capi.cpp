@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -1284,6 +1285,10 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   std::vector<double> H;
   Ritz rz;
   bool conv = false;
+  // KV_ARNOLDI_TRACE=1: one line per restart on stderr (residual, ellipse,
+  // filter degree, wanted Ritz values)
+  const char* ev = getenv("KV_ARNOLDI_TRACE");
+  const bool trace = ev && atoi(ev) != 0;
   for (;;) {
     double vn = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
     if (rc) return rc;
@@ -1322,6 +1327,15 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
       wr = ref - d;
       deg = cheb_degree(wr, a, bb, c2, p->cheb_degree_max);
       deg = std::min(deg, std::max(0, p->max_matvec - matvecs - m));
+    }
+    if (trace) {
+      double rmx = 0.0;
+      for (double r : rz.res) rmx = std::max(rmx, r);
+      fprintf(stderr, "[arnoldi] restart %d matvecs %d res/scale %.3e  ellipse d %.4g a %.4g b %.4g  degree %d",
+              restarts, matvecs, rmx / scale, d, a, bb, deg);
+      for (size_t q = 0; q < rz.sel.size() && q < 4; ++q)
+        fprintf(stderr, "  (%.6g, %.6g)", rz.vals[rz.sel[q]].real(), rz.vals[rz.sel[q]].imag());
+      fprintf(stderr, "\n");
     }
     if (deg > 0) {
       // z1 = r1 (A - d) z0, z_{j+1} = r_{j+1} (2 (A - d) z_j - c^2 r_j z_{j-1})

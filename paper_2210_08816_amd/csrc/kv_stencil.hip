@@ -84,9 +84,18 @@ __device__ __forceinline__ Met load_met(const Axis& A, int c) {
   return m;
 }
 
+// Quantities of a control volume's top z-face, carried up a column from
+// plane k to plane k+1, where they are the bottom-face ones: the convective
+// flux (f) and the diffusive gradient term (g) of u, v, w and T.  They are
+// the same operands combined in the same order, so reusing them leaves every
+// result bit-identical.  fresh: nothing carried (first plane of a march).
+struct ZCarry {
+  double uf, ug, vf, vg, wf, wg, tf, tg;
+};
+
 template <int MODE, class Acc, class Out>
 __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j, int k, const Met& MX, const Met& MY,
-                                      const Met& MZ, const Out& y) {
+                                      const Met& MZ, const Out& y, ZCarry& zc, bool fresh) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const double s = MODE ? 0.5 : 1.0;
   const double TW = MODE ? 0.5 : 0.0, TE = MODE ? -0.5 : 0.0;
@@ -119,14 +128,21 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     }
     adv += (fN - fS) * MY.ih0;
     // z: fluxes w_hat * u_hat at z-faces k and k+1
-    double fB = 0.0, fT = 0.0, uB = 0.0, uT = 0.0;
-    if (k > 0) {
-      const double zl = MZ.wl0, zh = MZ.wh0;
-      const double UB = A.U(0, i, j, k - 1);
-      uB = A.U(1, i, j, k - 1);
-      const double Wh = xl * A.W(0, i - 1, j, k) + xh * A.W(0, i, j, k);
-      const double wh = xl * A.W(1, i - 1, j, k) + xh * A.W(1, i, j, k);
-      fB = Wh * (zl * uB + zh * uc) + wh * (zl * UB + zh * Uc);
+    double fB = 0.0, fT = 0.0, gB, uT = 0.0;
+    if (!fresh) {
+      fB = zc.uf;
+      gB = zc.ug;
+    } else {
+      double uB = 0.0;
+      if (k > 0) {
+        const double zl = MZ.wl0, zh = MZ.wh0;
+        const double UB = A.U(0, i, j, k - 1);
+        uB = A.U(1, i, j, k - 1);
+        const double Wh = xl * A.W(0, i - 1, j, k) + xh * A.W(0, i, j, k);
+        const double wh = xl * A.W(1, i - 1, j, k) + xh * A.W(1, i, j, k);
+        fB = Wh * (zl * uB + zh * uc) + wh * (zl * UB + zh * Uc);
+      }
+      gB = (uc - uB) * MZ.id0;
     }
     if (k < nz - 1) {
       const double zl = MZ.wl1, zh = MZ.wh1;
@@ -137,9 +153,12 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fT = Wh * (zl * uc + zh * uT) + wh * (zl * Uc + zh * UB);
     }
     adv += (fT - fB) * MZ.ih0;
+    const double gT = (uT - uc) * MZ.id1;
+    zc.uf = fT;
+    zc.ug = gT;
     double lap = ((up - uc) * MX.ih0 - (uc - um) * MX.ihm) * MX.id0;
     lap += ((uN - uc) * MY.id1 - (uc - uS) * MY.id0) * MY.ih0;
-    lap += ((uT - uc) * MZ.id1 - (uc - uB) * MZ.id0) * MZ.ih0;
+    lap += (gT - gB) * MZ.ih0;
     y.put(g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1), -s * adv + g.nu * lap);
   }
 
@@ -168,14 +187,21 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fE = Uh * (xl * vc + xh * vE) + uh * (xl * Vc + xh * VB);
     }
     adv += (fE - fW) * MX.ih0;
-    double fB = 0.0, fT = 0.0, vB = 0.0, vT = 0.0;
-    if (k > 0) {
-      const double zl = MZ.wl0, zh = MZ.wh0;
-      const double VB = A.V(0, i, j, k - 1);
-      vB = A.V(1, i, j, k - 1);
-      const double Wh = yl * A.W(0, i, j - 1, k) + yh * A.W(0, i, j, k);
-      const double wh = yl * A.W(1, i, j - 1, k) + yh * A.W(1, i, j, k);
-      fB = Wh * (zl * vB + zh * vc) + wh * (zl * VB + zh * Vc);
+    double fB = 0.0, fT = 0.0, gB, vT = 0.0;
+    if (!fresh) {
+      fB = zc.vf;
+      gB = zc.vg;
+    } else {
+      double vB = 0.0;
+      if (k > 0) {
+        const double zl = MZ.wl0, zh = MZ.wh0;
+        const double VB = A.V(0, i, j, k - 1);
+        vB = A.V(1, i, j, k - 1);
+        const double Wh = yl * A.W(0, i, j - 1, k) + yh * A.W(0, i, j, k);
+        const double wh = yl * A.W(1, i, j - 1, k) + yh * A.W(1, i, j, k);
+        fB = Wh * (zl * vB + zh * vc) + wh * (zl * VB + zh * Vc);
+      }
+      gB = (vc - vB) * MZ.id0;
     }
     if (k < nz - 1) {
       const double zl = MZ.wl1, zh = MZ.wh1;
@@ -186,18 +212,35 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fT = Wh * (zl * vc + zh * vT) + wh * (zl * Vc + zh * VB);
     }
     adv += (fT - fB) * MZ.ih0;
+    const double gT = (vT - vc) * MZ.id1;
+    zc.vf = fT;
+    zc.vg = gT;
     double lap = ((vp - vc) * MY.ih0 - (vc - vm) * MY.ihm) * MY.id0;
     lap += ((vE - vc) * MX.id1 - (vc - vW) * MX.id0) * MX.ih0;
-    lap += ((vT - vc) * MZ.id1 - (vc - vB) * MZ.id0) * MZ.ih0;
+    lap += (gT - gB) * MZ.ih0;
     y.put(g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i, -s * adv + g.nu * lap);
   }
 
   // ---------------- w on z-face k ----------------
   if (k >= 1) {
     const double Wc = A.W(0, i, j, k), wc = A.W(1, i, j, k);
-    const double Wm = A.W(0, i, j, k - 1), wm = A.W(1, i, j, k - 1);
     const double Wp = A.W(0, i, j, k + 1), wp = A.W(1, i, j, k + 1);
-    double adv = (0.5 * (Wc + Wp) * (wc + wp) - 0.5 * (Wm + Wc) * (wm + wc)) * MZ.id0;
+    // centre fluxes (w_bar)^2 and gradients at cells k (top) and k-1 (bottom);
+    // the face k-1 below holds a w only for k >= 2
+    const bool wfresh = fresh || k == 1;
+    double cB, gB;
+    if (!wfresh) {
+      cB = zc.wf;
+      gB = zc.wg;
+    } else {
+      const double Wm = A.W(0, i, j, k - 1), wm = A.W(1, i, j, k - 1);
+      cB = 0.5 * (Wm + Wc) * (wm + wc);
+      gB = (wc - wm) * MZ.ihm;
+    }
+    const double cT = 0.5 * (Wc + Wp) * (wc + wp), gT = (wp - wc) * MZ.ih0;
+    zc.wf = cT;
+    zc.wg = gT;
+    double adv = (cT - cB) * MZ.id0;
     const double zl = MZ.wl0, zh = MZ.wh0;
     double fW = 0.0, fE = 0.0, wW = 0.0, wE = 0.0;
     if (i > 0) {
@@ -235,7 +278,7 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       fN = Vh * (yl * wc + yh * wN) + vh * (yl * Wc + yh * WB);
     }
     adv += (fN - fS) * MY.ih0;
-    double lap = ((wp - wc) * MZ.ih0 - (wc - wm) * MZ.ihm) * MZ.id0;
+    double lap = (gT - gB) * MZ.id0;
     lap += ((wE - wc) * MX.id1 - (wc - wW) * MX.id0) * MX.ih0;
     lap += ((wN - wc) * MY.id1 - (wc - wS) * MY.id0) * MY.ih0;
     const double buoy = zl * A.T(1, i, j, k - 1) + zh * A.T(1, i, j, k);
@@ -287,7 +330,10 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     // z
     {
       double fB = 0.0, fT = 0.0, gB = 0.0, gT = 0.0;
-      if (k > 0) {
+      if (!fresh) {
+        fB = zc.tf;
+        gB = zc.tg;
+      } else if (k > 0) {
         const double zl = MZ.wl0, zh = MZ.wh0;
         const double tB = A.T(1, i, j, k - 1);
         const double Th = zl * A.T(0, i, j, k - 1) + zh * Tb;
@@ -303,6 +349,8 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
       }
       adv += (fT - fB) * MZ.ih0;
       lap += (gT - gB) * MZ.ih0;
+      zc.tf = fT;
+      zc.tg = gT;
     }
     y.put(g.oT + ((int64_t)k * ny + j) * nx + i, -s * adv + g.kappa * lap);
   }
@@ -319,7 +367,8 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
   GlobalAcc A{&g, B, x};
-  point<MODE>(g, A, i, j, k, load_met(g.ax[0], i), load_met(g.ax[1], j), load_met(g.ax[2], k), PtrOut{y});
+  ZCarry zc;
+  point<MODE>(g, A, i, j, k, load_met(g.ax[0], i), load_met(g.ax[1], j), load_met(g.ax[2], k), PtrOut{y}, zc, true);
 }
 
 // ---- 2.5-D tiled version ---------------------------------------------------------
@@ -496,8 +545,11 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   const int bz = (int)(w / ((int64_t)tiles_x * tiles_y));
   const int i0 = bx * TX, j0 = by * TY, k0 = bz * KC;
   const int k1 = min(g.nz, k0 + KC);
-  const int i = i0 + (threadIdx.x % TX), j = j0 + (threadIdx.x / TX);
+  // a wave is one x-row of the tile (TX = 64), so j is uniform per wave
+  static_assert(TX == 64, "one wave per tile row");
+  const int i = i0 + (threadIdx.x % TX), j = __builtin_amdgcn_readfirstlane(j0 + (int)(threadIdx.x / TX));
   const Met MX = load_met(g.ax[0], i), MY = load_met(g.ax[1], j);
+  ZCarry zc;
   const FetchMap fm = fetch_map(g, i0, j0);
   const __amdgpu_buffer_rsrc_t rB = vec_rsrc(B, g.n), rx = vec_rsrc(x, g.n);
   BufOut out{vec_rsrc(y, g.n), &g};
@@ -538,7 +590,7 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
       wk[s] = A.ld(2, s, k, i, j);
       tk[s] = A.ld(3, s, k, i, j);
     }
-    if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out);
+    if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out, zc, k == k0);
     __syncthreads();
     if (more) {
       // u, v, T of plane k+1 replace those of planes k-1 and k; w of plane
