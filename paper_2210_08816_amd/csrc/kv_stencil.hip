@@ -612,40 +612,39 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   }
 }
 
+// Column-marching kernels: a (64, 4) block owns a tile of (x, y) columns
+// and KD consecutive z-planes, and each thread walks up its column keeping
+// the value its plane shares with the one below (w on the face between them,
+// or p of the cell below) in a register, so that every input is read once.
+constexpr int KD = 16;
+
 // out = V^{1/2} (D y) = (net outward face flux of the velocity) / sqrt(V_c)
+template <typename OutT>
 __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const double* __restrict__ y,
-                                                                double* __restrict__ out) {
+                                                                OutT* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
+  const int k0 = blockIdx.z * KD, k1 = min(g.nz, k0 + KD);
   const Axis& AX = g.ax[0];
   const Axis& AY = g.ax[1];
   const Axis& AZ = g.ax[2];
-  const double fx = Uat(y, g, i + 1, j, k) - Uat(y, g, i, j, k);
-  const double fy = Vat(y, g, i, j + 1, k) - Vat(y, g, i, j, k);
-  const double fz = Wat(y, g, i, j, k + 1) - Wat(y, g, i, j, k);
-  const double hx = AX.h[i], hy = AY.h[j], hz = AZ.h[k];
-  const double net = hy * hz * fx + hx * hz * fy + hx * hy * fz;
-  out[((int64_t)k * g.ny + j) * g.nx + i] = net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]);
+  const double hx = AX.h[i], hy = AY.h[j], sxy = AX.isq[i] * AY.isq[j];
+  double wlo = Wat(y, g, i, j, k0);
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k) {
+    const double whi = Wat(y, g, i, j, k + 1);
+    const double fx = Uat(y, g, i + 1, j, k) - Uat(y, g, i, j, k);
+    const double fy = Vat(y, g, i, j + 1, k) - Vat(y, g, i, j, k);
+    const double fz = whi - wlo;
+    const double hz = AZ.h[k];
+    const double net = hy * hz * fx + hx * hz * fy + hx * hy * fz;
+    out[((int64_t)k * g.ny + j) * g.nx + i] = (OutT)(net * (sxy * AZ.isq[k]));
+    wlo = whi;
+  }
 }
 
 __device__ __forceinline__ double fin_abs(double v);
-
-// Mixed form: the same scaled divergence of an FP64 field, stored in FP32.
-__global__ void __launch_bounds__(256) scaled_divergence_f32_kernel(Grid g, const double* __restrict__ y,
-                                                                    float* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
-  const double fx = Uat(y, g, i + 1, j, k) - Uat(y, g, i, j, k);
-  const double fy = Vat(y, g, i, j + 1, k) - Vat(y, g, i, j, k);
-  const double fz = Wat(y, g, i, j, k + 1) - Wat(y, g, i, j, k);
-  const double hx = g.ax[0].h[i], hy = g.ax[1].h[j], hz = g.ax[2].h[k];
-  const double net = hy * hz * fx + hx * hz * fy + hx * hy * fz;
-  out[((int64_t)k * g.ny + j) * g.nx + i] = (float)(net * (g.ax[0].isq[i] * g.ax[1].isq[j] * g.ax[2].isq[k]));
-}
 
 // Mixed-form refinement sweep, fused: yout = yin - G p on the velocity (T
 // copied), and from the corrected field (every face of the cell corrected
@@ -712,19 +711,27 @@ __global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const d
   }
 }
 
-// y_vel -= G p at the interior faces owned by cell (i, j, k)
+// y_vel -= G p at the interior faces owned by cell (i, j, k), marching up
+// the column (p of the cell below kept in a register)
 __global__ void __launch_bounds__(256) gradient_correction_kernel(Grid g, const double* __restrict__ p,
                                                                   double* __restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
+  const int k0 = blockIdx.z * KD, k1 = min(g.nz, k0 + KD);
   const int nx = g.nx, ny = g.ny;
-  const int64_t c = ((int64_t)k * ny + j) * nx + i;
-  const double pc = p[c];
-  if (i >= 1) y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] -= (pc - p[c - 1]) * g.ax[0].id[i];
-  if (j >= 1) y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] -= (pc - p[c - nx]) * g.ax[1].id[j];
-  if (k >= 1) y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] -= (pc - p[c - (int64_t)nx * ny]) * g.ax[2].id[k];
+  const int64_t plane = (int64_t)nx * ny;
+  const double idx = g.ax[0].id[i], idy = g.ax[1].id[j];
+  int64_t c = (int64_t)k0 * plane + (int64_t)j * nx + i;
+  double pm = k0 >= 1 ? p[c - plane] : 0.0;
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k, c += plane) {
+    const double pc = p[c];
+    if (i >= 1) y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] -= (pc - p[c - 1]) * idx;
+    if (j >= 1) y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] -= (pc - p[c - nx]) * idy;
+    if (k >= 1) y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] -= (pc - pm) * g.ax[2].id[k];
+    pm = pc;
+  }
 }
 
 // Block maxima of |net flux| and |face flux|; non-finite values count as +inf.
@@ -821,6 +828,7 @@ __global__ void max_finish_kernel(const double* __restrict__ part, int nblk, int
 
 inline dim3 cell_block(const Grid& g) { return dim3(64, 4, 1); }
 inline dim3 cell_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
+inline dim3 march_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + KD - 1) / KD); }
 
 }  // namespace
 
@@ -855,13 +863,13 @@ hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, d
 
 hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* out) {
   const Grid& g = c->g;
-  scaled_divergence_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
+  scaled_divergence_kernel<double><<<march_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
   return hipGetLastError();
 }
 
 hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float* out) {
   const Grid& g = c->g;
-  scaled_divergence_f32_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
+  scaled_divergence_kernel<float><<<march_grid(g), cell_block(g), 0, c->stream>>>(g, y, out);
   return hipGetLastError();
 }
 
@@ -877,7 +885,7 @@ hipError_t launch_correct_divergence(kv_ctx* c, const double* yin, const float* 
 
 hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* y) {
   const Grid& g = c->g;
-  gradient_correction_kernel<<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, p, y);
+  gradient_correction_kernel<<<march_grid(g), cell_block(g), 0, c->stream>>>(g, p, y);
   return hipGetLastError();
 }
 
