@@ -242,9 +242,11 @@ int project_inplace(kv_ctx* c, double* y) {
 // Mixed form of the projection: FP32-storage fast diagonalization on the
 // FP32 matrix cores, refined on the FP64 residual.  Each sweep solves for
 // the divergence left by the previous one; corrections and the next
-// divergence are fused and ping-pong between y and a scratch vector, so the
-// sweeps come in pairs and the result lands in y.  Stops when the normalized
-// divergence max|net flux| / max|face flux| <= tol (at most 8 sweeps).
+// divergence are fused, and the sweeps alternate between y and a scratch
+// vector (an odd count ends with
+// a copy of the velocity back into y).  Stops when the normalized divergence
+// max|net flux| / max|face flux| <= tol, checked from the second sweep on (at
+// most 8 sweeps).
 constexpr double kMixedDivTol = 1e-10;
 
 int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
@@ -266,25 +268,31 @@ int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
   double div = 1.0;
   int sweeps = 0;
   while (sweeps < 8) {
-    for (int half = 0; half < 2; ++half) {
-      const double* src = half == 0 ? y : c->ymix;
-      double* dst = half == 0 ? c->ymix : y;
-      float* b = half == 0 ? F0 : F1;
-      float* bn = half == 0 ? F1 : F0;
-      {
-        PhaseMark pm(c, 2);
-        HIPCHK(c, launch_fd_solve_f32(c, b, b));
-      }
-      {
-        PhaseMark pm(c, 3);
-        HIPCHK(c, launch_correct_divergence(c, src, b, dst, bn));
-      }
-      ++sweeps;
+    // even sweeps read y and write the scratch vector, odd ones the reverse
+    const bool from_y = sweeps % 2 == 0;
+    const double* src = from_y ? y : c->ymix;
+    double* dst = from_y ? c->ymix : y;
+    float* b = from_y ? F0 : F1;
+    float* bn = from_y ? F1 : F0;
+    {
+      PhaseMark pm(c, 2);
+      HIPCHK(c, launch_fd_solve_f32(c, b, b));
     }
+    {
+      PhaseMark pm(c, 3);
+      HIPCHK(c, launch_correct_divergence(c, src, b, dst, bn));
+    }
+    ++sweeps;
+    if (sweeps < 2) continue;  // one FP32 sweep never reaches the tolerance
     if ((rc = read_results(c, 2))) return rc;
     div = c->hres[1] > 0 ? c->hres[0] / c->hres[1] : 0.0;
     if (!std::isfinite(div)) return fail(c, KV_ENONFINITE, "non-finite value in the mixed projection");
     if (div <= kMixedDivTol) break;
+  }
+  if (sweeps % 2 == 1) {
+    // the result is in the scratch vector: its velocity back into y (T of y is final)
+    PhaseMark pm(c, 3);
+    HIPCHK(c, hipMemcpyAsync(y, c->ymix, c->g.oT * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   }
   if (div_out) *div_out = div;
   if (sweeps_out) *sweeps_out = sweeps;

@@ -646,52 +646,63 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
 
 __device__ __forceinline__ double fin_abs(double v);
 
-// Mixed-form refinement sweep, fused: yout = yin - G p on the velocity (T
-// copied), and from the corrected field (every face of the cell corrected
-// locally from p, so no thread reads another's output) the net flux of the
-// cell: its scaled value feeds the next sweep (bnext, FP32, optional) and
-// block maxima of |net flux| and |face flux| give the normalized divergence.
+// Mixed-form refinement sweep, fused: yout = yin - G p on the velocity, and
+// from the corrected field (every face of the cell corrected locally from p,
+// so no thread reads another's output) the net flux of the cell: its scaled
+// value feeds the next sweep (bnext, FP32, optional) and block maxima of
+// |net flux| and |face flux| give the normalized divergence.  T is not
+// touched (the sweeps alternate between the caller's vector, whose T is
+// final, and a scratch vector whose T is never read).  Threads march up
+// z-columns like the divergence kernel; the corrected w on a cell's top face
+// is the next plane's bottom one.
 __global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const double* __restrict__ yin,
                                                                  const float* __restrict__ p,
                                                                  double* __restrict__ yout,
                                                                  float* __restrict__ bnext,
                                                                  double* __restrict__ part) {
-  __shared__ double s0[256], s1[256];
+  __shared__ double s0[4], s1[4];
   const int t = threadIdx.y * blockDim.x + threadIdx.x;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int64_t plane = (int64_t)nx * ny;
   double mb = 0.0, mf = 0.0;
   if (i < nx && j < ny) {
-    const int64_t c = k * plane + (int64_t)j * nx + i;
-    const double pc = p[c];
+    const int k0 = blockIdx.z * KD, k1 = min(nz, k0 + KD);
     const Axis& AX = g.ax[0];
     const Axis& AY = g.ax[1];
     const Axis& AZ = g.ax[2];
-    double u0 = 0.0, u1 = 0.0, v0 = 0.0, v1 = 0.0, w0 = 0.0, w1 = 0.0;
-    if (i >= 1) {
-      u0 = Uat(yin, g, i, j, k) - (pc - p[c - 1]) * AX.id[i];
-      yout[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] = u0;
+    const double idx0 = AX.id[i], idx1 = AX.id[i + 1], idy0 = AY.id[j], idy1 = AY.id[j + 1];
+    const double hx = AX.h[i], hy = AY.h[j], sxy = AX.isq[i] * AY.isq[j];
+    int64_t c = k0 * plane + (int64_t)j * nx + i;
+    double pc = p[c];
+    double w0 = 0.0;  // corrected w on the bottom face of the current cell
+    if (k0 >= 1) w0 = Wat(yin, g, i, j, k0) - (pc - p[c - plane]) * AZ.id[k0];
+    for (int k = k0; k < k1; ++k, c += plane) {
+      double u0 = 0.0, u1 = 0.0, v0 = 0.0, v1 = 0.0, w1 = 0.0, pn = 0.0;
+      if (i >= 1) {
+        u0 = Uat(yin, g, i, j, k) - (pc - p[c - 1]) * idx0;
+        yout[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] = u0;
+      }
+      if (i + 1 <= nx - 1) u1 = Uat(yin, g, i + 1, j, k) - (p[c + 1] - pc) * idx1;
+      if (j >= 1) {
+        v0 = Vat(yin, g, i, j, k) - (pc - p[c - nx]) * idy0;
+        yout[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] = v0;
+      }
+      if (j + 1 <= ny - 1) v1 = Vat(yin, g, i, j + 1, k) - (p[c + nx] - pc) * idy1;
+      if (k >= 1) yout[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = w0;
+      if (k + 1 <= nz - 1) {
+        pn = p[c + plane];
+        w1 = Wat(yin, g, i, j, k + 1) - (pn - pc) * AZ.id[k + 1];
+      }
+      const double hz = AZ.h[k];
+      const double net = hy * hz * (u1 - u0) + hx * hz * (v1 - v0) + hx * hy * (w1 - w0);
+      if (bnext) bnext[c] = (float)(net * (sxy * AZ.isq[k]));
+      mb = fmax(mb, fin_abs(net));
+      mf = fmax(mf, fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy))));
+      w0 = w1;
+      pc = pn;
     }
-    if (i + 1 <= nx - 1) u1 = Uat(yin, g, i + 1, j, k) - (p[c + 1] - pc) * AX.id[i + 1];
-    if (j >= 1) {
-      v0 = Vat(yin, g, i, j, k) - (pc - p[c - nx]) * AY.id[j];
-      yout[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] = v0;
-    }
-    if (j + 1 <= ny - 1) v1 = Vat(yin, g, i, j + 1, k) - (p[c + nx] - pc) * AY.id[j + 1];
-    if (k >= 1) {
-      w0 = Wat(yin, g, i, j, k) - (pc - p[c - plane]) * AZ.id[k];
-      yout[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] = w0;
-    }
-    if (k + 1 <= nz - 1) w1 = Wat(yin, g, i, j, k + 1) - (p[c + plane] - pc) * AZ.id[k + 1];
-    yout[g.oT + c] = yin[g.oT + c];
-    const double hx = AX.h[i], hy = AY.h[j], hz = AZ.h[k];
-    const double net = hy * hz * (u1 - u0) + hx * hz * (v1 - v0) + hx * hy * (w1 - w0);
-    if (bnext) bnext[c] = (float)(net * (AX.isq[i] * AY.isq[j] * AZ.isq[k]));
-    mb = fin_abs(net);
-    mf = fmax(fin_abs(u0 * hy * hz), fmax(fin_abs(v0 * hx * hz), fin_abs(w0 * hx * hy)));
   }
   // wavefront maxima by lane exchange, then the 4 waves through LDS
 #pragma unroll
@@ -875,7 +886,7 @@ hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float*
 
 hipError_t launch_correct_divergence(kv_ctx* c, const double* yin, const float* p, double* yout, float* bnext) {
   const Grid& g = c->g;
-  const dim3 grid = cell_grid(g);
+  const dim3 grid = march_grid(g);
   const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
   if (2 * nblk > c->cell_part_len) return hipErrorInvalidValue;
   correct_divergence_kernel<<<grid, cell_block(g), 0, c->stream>>>(g, yin, p, yout, bnext, c->cell_part);
