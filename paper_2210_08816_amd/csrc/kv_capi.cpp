@@ -319,13 +319,20 @@ int matvec(kv_ctx* c, const double* x, double* y) {
 int precond_apply(kv_ctx* c, const double* x, double* y) {
   const Grid& g = c->g;
   const int64_t off[4] = {g.ou, g.ov, g.ow, g.oT};
+  const HelmBasis *bx[4], *by[4], *bz[4];
+  double coef[4];
+  const double* in[4];
+  double *out[4], *scr[4];
   for (int b = 0; b < 4; ++b) {
-    const HelmBasis& bx = c->hb[0][b == 3 ? HB_CD : (b == 0 ? HB_FD : HB_CD)];
-    const HelmBasis& by = c->hb[1][b == 3 ? HB_CN : (b == 1 ? HB_FD : HB_CD)];
-    const HelmBasis& bz = c->hb[2][b == 3 ? HB_CN : (b == 2 ? HB_FD : HB_CD)];
-    const double coef = b == 3 ? g.kappa : g.nu;
-    HIPCHK(c, launch_fd_helmholtz(c, bx, by, bz, c->pc_sigma, coef, x + off[b], y + off[b]));
+    bx[b] = &c->hb[0][b == 3 ? HB_CD : (b == 0 ? HB_FD : HB_CD)];
+    by[b] = &c->hb[1][b == 3 ? HB_CN : (b == 1 ? HB_FD : HB_CD)];
+    bz[b] = &c->hb[2][b == 3 ? HB_CN : (b == 2 ? HB_FD : HB_CD)];
+    coef[b] = b == 3 ? g.kappa : g.nu;
+    in[b] = x + off[b];
+    out[b] = y + off[b];
+    scr[b] = c->pc_scr + off[b];
   }
+  HIPCHK(c, launch_fd_helmholtz4(c, bx, by, bz, c->pc_sigma, coef, in, out, scr));
   return project_inplace(c, y);
 }
 
@@ -701,6 +708,7 @@ int kv_destroy(kv_ctx* c) {
   hipFree(c->pc_mem);
   hipFree(c->pc_tmp);
   hipFree(c->pc_d0);
+  hipFree(c->pc_scr);
   delete c;
   return KV_OK;
 }
@@ -1123,10 +1131,13 @@ static int build_preconditioner(kv_ctx* c) {
     return fail(c, KV_ENOMEM, "preconditioner bases");
   }
   if (hipMalloc(&c->pc_tmp, n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->pc_d0, n * sizeof(double)) != hipSuccess) {
+      hipMalloc(&c->pc_d0, n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->pc_scr, n * sizeof(double)) != hipSuccess) {
     hipFree(c->pc_mem);
     hipFree(c->pc_tmp);
-    c->pc_mem = c->pc_tmp = nullptr;
+    hipFree(c->pc_d0);
+    hipFree(c->pc_scr);
+    c->pc_mem = c->pc_tmp = c->pc_d0 = c->pc_scr = nullptr;
     return fail(c, KV_ENOMEM, "preconditioner vectors");
   }
   int rc = upload(c, c->pc_mem, host.data(), total * sizeof(double));

@@ -30,37 +30,65 @@ struct Epi {
 
 constexpr int BM = 64, BN = 64, BK = 16;
 
-// C[b] = A[b] * B[b], row-major, 256 threads = 4 waves, 64x64 tile per block,
-// each wave a 32x32 quarter as 2x2 MFMA 16x16 accumulators.  Work items are
+// One batched product C[b] = A[b] * B[b] (row-major) of a launch.
+struct GemmProb {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t lda, sA, ldb, sB, ldc, sC;
+  int M, N, K, mtiles, ntiles, batch, a_is_big;
+  int64_t first;  // first work item of this product in the launch
+  Epi ep;
+};
+constexpr int MAXP = 4;
+struct GemmSet {
+  GemmProb p[MAXP];
+  int np;
+  int64_t total;  // work items (64x64 output tiles) over all products
+};
+
+// Up to four independent products (the four blocks of a packed vector) in
+// one launch, 256 threads = 4 waves, 64x64 tile per block, each wave a 32x32
+// quarter as 2x2 MFMA 16x16 accumulators.  Within a product, work items are
 // laid out so that the blocks sharing the large operand's tile are
 // consecutive on one XCD (blocks are dealt round-robin over the 8 XCDs).
 template <int EPI>
-__global__ void __launch_bounds__(256) fd_gemm_kernel(const double* __restrict__ A, int64_t lda, int64_t sA,
-                                                      const double* __restrict__ B, int64_t ldb, int64_t sB,
-                                                      double* __restrict__ C, int64_t ldc, int64_t sC,
-                                                      int M, int N, int K, int mtiles, int ntiles, int batch,
-                                                      int a_is_big, Epi ep) {
+__global__ void __launch_bounds__(256) fd_gemm_kernel(GemmSet gs) {
   __shared__ double As[BK][BM + 2];  // [k][m]
   __shared__ double Bs[BK][BN + 2];  // [k][n]
-  const int64_t total = (int64_t)mtiles * ntiles * batch;
-  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t per_xcd = (gs.total + 7) / 8;
   const int64_t f = blockIdx.x;
-  const int64_t w = (f % 8) * per_xcd + f / 8;
-  if (w >= total) return;
+  int64_t w = (f % 8) * per_xcd + f / 8;
+  if (w >= gs.total) return;
+  int q = 0;
+#pragma unroll
+  for (int t = 1; t < MAXP; ++t)
+    if (t < gs.np && w >= gs.p[t].first) q = t;
+  GemmProb P;
+  switch (q) {  // constant indices: the fields stay scalar kernel-argument loads
+    case 0: P = gs.p[0]; break;
+    case 1: P = gs.p[1]; break;
+    case 2: P = gs.p[2]; break;
+    default: P = gs.p[3]; break;
+  }
+  w -= P.first;
+  const int M = P.M, N = P.N, K = P.K, mtiles = P.mtiles, ntiles = P.ntiles;
+  const int64_t lda = P.lda, ldb = P.ldb, ldc = P.ldc;
+  const Epi& ep = P.ep;
   int mt, nt;
   int64_t b;
-  if (a_is_big) {  // A tile shared by the ntiles blocks of one row of tiles
+  if (P.a_is_big) {  // A tile shared by the ntiles blocks of one row of tiles
     nt = (int)(w % ntiles);
     mt = (int)((w / ntiles) % mtiles);
     b = w / ((int64_t)ntiles * mtiles);
-  } else {         // B tile shared by the mtiles blocks of one column of tiles
+  } else {           // B tile shared by the mtiles blocks of one column of tiles
     mt = (int)(w % mtiles);
     nt = (int)((w / mtiles) % ntiles);
     b = w / ((int64_t)ntiles * mtiles);
   }
-  A += b * sA;
-  B += b * sB;
-  C += b * sC;
+  const double* __restrict__ A = P.A + b * P.sA;
+  const double* __restrict__ B = P.B + b * P.sB;
+  double* __restrict__ C = P.C + b * P.sC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = mt * BM, n0 = nt * BN;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -129,16 +157,52 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(const double* __restrict__
   }
 }
 
+GemmProb prob(const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C,
+              int64_t ldc, int64_t sC, int M, int N, int K, int batch, int a_is_big, const Epi& ep) {
+  GemmProb p{};
+  p.A = A;
+  p.B = B;
+  p.C = C;
+  p.lda = lda;
+  p.sA = sA;
+  p.ldb = ldb;
+  p.sB = sB;
+  p.ldc = ldc;
+  p.sC = sC;
+  p.M = M;
+  p.N = N;
+  p.K = K;
+  p.mtiles = (M + BM - 1) / BM;
+  p.ntiles = (N + BN - 1) / BN;
+  p.batch = batch;
+  p.a_is_big = a_is_big;
+  p.ep = ep;
+  return p;
+}
+
+template <int EPI>
+hipError_t gemm_set(const GemmProb* ps, int np, hipStream_t s) {
+  GemmSet gs{};
+  gs.np = np;
+  int64_t total = 0;
+  for (int q = 0; q < np; ++q) {
+    gs.p[q] = ps[q];
+    gs.p[q].first = total;
+    total += (int64_t)ps[q].mtiles * ps[q].ntiles * ps[q].batch;
+  }
+  gs.total = total;
+  if (total == 0) return hipSuccess;
+  const int64_t blocks = ((total + 7) / 8) * 8;
+  fd_gemm_kernel<EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(gs);
+  return hipGetLastError();
+}
+
 template <int EPI>
 hipError_t gemm(const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB,
                 double* C, int64_t ldc, int64_t sC, int M, int N, int K, int batch, int a_is_big,
                 const Epi& ep, hipStream_t s) {
-  const int mt = (M + BM - 1) / BM, nt = (N + BN - 1) / BN;
-  const int64_t total = (int64_t)mt * nt * batch;
-  const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_gemm_kernel<EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(A, lda, sA, B, ldb, sB, C, ldc, sC, M, N,
-                                                                   K, mt, nt, batch, a_is_big, ep);
-  return hipGetLastError();
+  const GemmProb p = prob(A, lda, sA, B, ldb, sB, C, ldc, sC, M, N, K, batch, a_is_big, ep);
+  return gemm_set<EPI>(&p, 1, s);
 }
 
 }  // namespace
@@ -173,22 +237,38 @@ hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out) {
   return gemm<EPI_ISQ>(Bf, nx, 0, c->Qt[0], nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
 }
 
-hipError_t launch_fd_helmholtz(const kv_ctx* c, const HelmBasis& bx, const HelmBasis& by, const HelmBasis& bz,
-                               double sigma, double coef, const double* in, double* out) {
-  const int nx = bx.n, ny = by.n, nz = bz.n;
-  const int64_t plane = (int64_t)nx * ny;
-  Epi ep{bx.lam, by.lam, bz.lam, nullptr, nullptr, nullptr, nx, ny, -1, sigma, coef};
-  double* s1 = c->cellA;
-  double* s2 = c->cellB;
+// The four Helmholtz solves of a packed vector (one per block u, v, w, T,
+// each on its own grid and bases), pass by pass: each of the six passes is
+// one launch over the four products.  The passes alternate between out and
+// scr (in is read by the first pass only, so in == out is allowed).
+hipError_t launch_fd_helmholtz4(const kv_ctx* c, const HelmBasis* const bx[4], const HelmBasis* const by[4],
+                                const HelmBasis* const bz[4], double sigma, const double coef[4],
+                                const double* const in[4], double* const out[4], double* const scr[4]) {
   hipStream_t s = c->stream;
+  GemmProb ps[4];
   hipError_t e;
   // forward x, y, z (+ divide), inverse z, y, x; the H^1/2 scalings sit in the bases
-  if ((e = gemm<EPI_NONE>(in, nx, 0, bx.fwdB, nx, 0, s1, nx, 0, ny * nz, nx, nx, 1, 1, ep, s))) return e;
-  if ((e = gemm<EPI_NONE>(by.fwdA, ny, 0, s1, nx, plane, s2, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
-  if ((e = gemm<EPI_DIVIDE>(bz.fwdA, nz, 0, s2, plane, 0, s1, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
-  if ((e = gemm<EPI_NONE>(bz.invA, nz, 0, s1, plane, 0, s2, plane, 0, nz, (int)plane, nz, 1, 0, ep, s))) return e;
-  if ((e = gemm<EPI_NONE>(by.invA, ny, 0, s2, nx, plane, s1, nx, plane, ny, nx, ny, nz, 0, ep, s))) return e;
-  return gemm<EPI_NONE>(s1, nx, 0, bx.invB, nx, 0, out, nx, 0, ny * nz, nx, nx, 1, 1, ep, s);
+  for (int pass = 0; pass < 6; ++pass) {
+    for (int q = 0; q < 4; ++q) {
+      const HelmBasis &X = *bx[q], &Y = *by[q], &Z = *bz[q];
+      const int nx = X.n, ny = Y.n, nz = Z.n;
+      const int64_t plane = (int64_t)nx * ny;
+      const Epi ep{X.lam, Y.lam, Z.lam, nullptr, nullptr, nullptr, nx, ny, -1, sigma, coef[q]};
+      const double* src = pass == 0 ? in[q] : (pass % 2 ? scr[q] : out[q]);
+      double* dst = pass % 2 ? out[q] : scr[q];
+      switch (pass) {
+        case 0: ps[q] = prob(src, nx, 0, X.fwdB, nx, 0, dst, nx, 0, ny * nz, nx, nx, 1, 1, ep); break;
+        case 1: ps[q] = prob(Y.fwdA, ny, 0, src, nx, plane, dst, nx, plane, ny, nx, ny, nz, 0, ep); break;
+        case 2: ps[q] = prob(Z.fwdA, nz, 0, src, plane, 0, dst, plane, 0, nz, (int)plane, nz, 1, 0, ep); break;
+        case 3: ps[q] = prob(Z.invA, nz, 0, src, plane, 0, dst, plane, 0, nz, (int)plane, nz, 1, 0, ep); break;
+        case 4: ps[q] = prob(Y.invA, ny, 0, src, nx, plane, dst, nx, plane, ny, nx, ny, nz, 0, ep); break;
+        default: ps[q] = prob(src, nx, 0, X.invB, nx, 0, dst, nx, 0, ny * nz, nx, nx, 1, 1, ep); break;
+      }
+    }
+    e = pass == 2 ? gemm_set<EPI_DIVIDE>(ps, 4, s) : gemm_set<EPI_NONE>(ps, 4, s);
+    if (e) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K, hipStream_t s) {

@@ -85,6 +85,7 @@ struct kv_ctx {
   double* pc_mem = nullptr;   // device storage of all bases
   double* pc_tmp = nullptr;   // one packed vector: M^-1 x inside the preconditioned operator
   double* pc_d0 = nullptr;    // one packed vector: copy of the caller's initial iterate
+  double* pc_scr = nullptr;   // one packed vector: intermediate passes of the Helmholtz solves
   int pc_kind = 0;            // KV_PC_NONE or KV_PC_STOKES
   double pc_sigma = 0.0;
   bool pc_active = false;     // set while a preconditioned solve runs
@@ -145,8 +146,9 @@ hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, 
 // (sigma - coef (A_x + A_y + A_z))^-1 with A_a = -H_a^-1 K_a of the given
 // bases, on a (bz.n, by.n, bx.n) block; 6 GEMM passes with cellA/cellB as
 // scratch.  in may equal out.
-hipError_t launch_fd_helmholtz(const kv_ctx* c, const HelmBasis& bx, const HelmBasis& by, const HelmBasis& bz,
-                               double sigma, double coef, const double* in, double* out);
+hipError_t launch_fd_helmholtz4(const kv_ctx* c, const HelmBasis* const bx[4], const HelmBasis* const by[4],
+                                const HelmBasis* const bz[4], double sigma, const double coef[4],
+                                const double* const in[4], double* const out[4], double* const scr[4]);
 
 // Network-grid transfers (kv_transfer.hip).  cells_from_state: out[c][K][J][I]
 // = (volume average over the f^3 fine cells of the centre value - shift[c]) / scale[c].

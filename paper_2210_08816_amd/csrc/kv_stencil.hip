@@ -372,11 +372,11 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 }
 
 // ---- 2.5-D tiled version ---------------------------------------------------------
-// A block owns a TX x TY tile of (x, y) columns and a chunk of KC z-planes.  It
+// A block owns a TX x TY tile of (x, y) columns and a chunk of kc z-planes.  It
 // marches up in z with the planes the stencil reaches (k-1, k, k+1), a
 // one-cell halo in x and y, in LDS and registers; each plane is loaded once,
 // as coalesced x-rows, and every output row is written once.
-constexpr int TX = 64, TY = 4, KC = 32;
+constexpr int TX = 64, TY = 4;
 constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
 
 // LDS holds only what other columns read: every field on plane k; u and v
@@ -530,7 +530,7 @@ __device__ __forceinline__ void store_plane(double* lds, const FetchMap& m, int 
 template <int MODE>
 __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const double* __restrict__ B,
                                                              const double* __restrict__ x, double* __restrict__ y,
-                                                             int tiles_x, int tiles_y, int chunks) {
+                                                             int tiles_x, int tiles_y, int chunks, int kc) {
   constexpr int NF = MODE ? 4 : 8;
   constexpr int NSF = NF / 4;
   extern __shared__ double lds[];
@@ -543,8 +543,8 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   const int bx = (int)(w % tiles_x);
   const int by = (int)((w / tiles_x) % tiles_y);
   const int bz = (int)(w / ((int64_t)tiles_x * tiles_y));
-  const int i0 = bx * TX, j0 = by * TY, k0 = bz * KC;
-  const int k1 = min(g.nz, k0 + KC);
+  const int i0 = bx * TX, j0 = by * TY, k0 = bz * kc;
+  const int k1 = min(g.nz, k0 + kc);
   // a wave is one x-row of the tile (TX = 64), so j is uniform per wave
   static_assert(TX == 64, "one wave per tile row");
   const int i = i0 + (threadIdx.x % TX), j = __builtin_amdgcn_readfirstlane(j0 + (int)(threadIdx.x / TX));
@@ -852,7 +852,13 @@ hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, d
       operator_kernel<1><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, x, x, y);
     return hipGetLastError();
   }
-  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY, ch = (g.nz + KC - 1) / KC;
+  // z-chunk: 32 planes, shortened on small grids until about 1024 blocks
+  // exist (four per CU; one block is 4 waves), but not below 4 planes, since
+  // every chunk also loads the plane below and the two above it
+  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
+  int kc = 32;
+  while (kc > 4 && (int64_t)tx * ty * ((g.nz + kc - 1) / kc) < 1024) kc /= 2;
+  const int ch = (g.nz + kc - 1) / kc;
   const int64_t total = (int64_t)tx * ty * ch;
   const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
   const size_t lds0 = 14 * PLANE * sizeof(double), lds1 = 7 * PLANE * sizeof(double);
@@ -863,11 +869,11 @@ hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, d
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds0) == hipSuccess;
   if (mode == 0) {
     if (lds_ok)
-      operator_tiled_kernel<0><<<blocks, 256, lds0, c->stream>>>(g, X0, x, y, tx, ty, ch);
+      operator_tiled_kernel<0><<<blocks, 256, lds0, c->stream>>>(g, X0, x, y, tx, ty, ch, kc);
     else
       operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
   } else {
-    operator_tiled_kernel<1><<<blocks, 256, lds1, c->stream>>>(g, x, x, y, tx, ty, ch);
+    operator_tiled_kernel<1><<<blocks, 256, lds1, c->stream>>>(g, x, x, y, tx, ty, ch, kc);
   }
   return hipGetLastError();
 }

@@ -22,6 +22,8 @@ GRIDS = [
     ("clustered", (7, 6, 5), 2e5, 2, 0.1),        # odd, unequal, smaller than one tile
     ("clustered", (70, 9, 66), 4e7, 4, 0.1),      # one full tile plus ragged tails
     ("uniform", (2, 3, 2), 1e3, 1, 0.1),          # minimal sizes
+    ("clustered", (36, 20, 44), 4e7, 3, 0.1),     # even half sizes (pair loads), ragged FD tiles on every axis
+    ("clustered", (7, 12, 8), 2e5, 2, 0.1),       # y pass: even half size, odd line length (single loads)
 ]
 
 
@@ -158,6 +160,7 @@ MIXED_GRIDS = [
     ("uniform", (32, 32, 32), 1e5, 3, 0.05),
     ("clustered", (24, 18, 20), 4e7, 4, 0.1),
     ("clustered", (64, 64, 64), 2e8, 6, 0.1),
+    ("clustered", (36, 20, 44), 4e7, 3, 0.1),     # FP32 pair loads with ragged FD tiles
 ]
 TOL_MIXED = 1e-5
 
