@@ -437,14 +437,11 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
     }
 }
 
-// Pair loads on by default; KV_FD_PAIRS=0 selects one element per load.
+// Pair loads on by default; KV_FD_PAIRS=0 selects one element per load
+// (read at every launch, so tests can cover both paths in one process).
 bool pair_loads() {
-  static int t = -1;
-  if (t < 0) {
-    const char* e = getenv("KV_FD_PAIRS");
-    t = (e && atoi(e) == 0) ? 0 : 1;
-  }
-  return t == 1;
+  const char* e = getenv("KV_FD_PAIRS");
+  return !(e && atoi(e) == 0);
 }
 
 template <typename T, int KIND, int EPI, int BM, int BN, int BK>
@@ -473,22 +470,29 @@ hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t 
 // MFMA work per prologue and epilogue); the spectral-divide kind keeps 64 x 64
 // (its division epilogue at 128 x 128 needs registers for one wave per SIMD
 // only), and so do the inverse kinds, whose two accumulator sets double the
-// registers per output.  FP32 (mixed form) uses 64 x 64 throughout.
-// KV_FD_TILE=64 forces 64 x 64 everywhere.
-bool large_tiles_allowed() {
-  static int t = -1;
-  if (t < 0) {
-    const char* e = getenv("KV_FD_TILE");
-    t = (e && atoi(e) == 64) ? 0 : 1;
-  }
-  return t == 1;
+// registers per output.  Small grids take 32 x 32 tiles when 64 x 64 ones
+// would leave fewer than about four blocks per CU.  FP32 (mixed form) follows
+// the same rules without the 128 x 128 case.  KV_FD_TILE=64 or 32 forces one
+// shape (read at every launch, for tests and measurements).
+int forced_tile() {
+  const char* e = getenv("KV_FD_TILE");
+  if (!e) return 0;
+  const int t = atoi(e);
+  return (t == 64 || t == 32) ? t : 0;
 }
 
 template <typename T, int KIND, int EPI>
 hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
-  if (sizeof(T) == 8 && !inv && EPI == EPI_NONE && a.H >= 128 && large_tiles_allowed())
+  const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  const int forced = forced_tile();
+  if (forced == 64) return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
+  if (forced == 32) return launch_tiles<T, KIND, EPI, 32, 32, 16>(a, ep, s);
+  if (sizeof(T) == 8 && !inv && EPI == EPI_NONE && a.H >= 128)
     return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
+  const int64_t M = right ? a.R : a.H, NN = right ? a.H : a.P;
+  const int64_t tiles64 = ((M + 63) / 64) * ((NN + 63) / 64) * a.batch * (inv ? 1 : 2);
+  if (tiles64 < 1024) return launch_tiles<T, KIND, EPI, 32, 32, 16>(a, ep, s);
   return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
 }
 

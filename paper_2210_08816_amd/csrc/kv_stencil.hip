@@ -613,10 +613,12 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
 }
 
 // Column-marching kernels: a (64, 4) block owns a tile of (x, y) columns
-// and KD consecutive z-planes, and each thread walks up its column keeping
+// and a run of consecutive z-planes (the planes split evenly over gridDim.z:
+// 16 per block on large grids, fewer on small ones so that enough blocks
+// exist), and each thread walks up its column keeping
 // the value its plane shares with the one below (w on the face between them,
 // or p of the cell below) in a register, so that every input is read once.
-constexpr int KD = 16;
+__device__ __forceinline__ int march_planes(int nz) { return (nz + (int)gridDim.z - 1) / (int)gridDim.z; }
 
 // out = V^{1/2} (D y) = (net outward face flux of the velocity) / sqrt(V_c)
 template <typename OutT>
@@ -625,7 +627,8 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = blockIdx.z * KD, k1 = min(g.nz, k0 + KD);
+  const int kd = march_planes(g.nz);
+  const int k0 = blockIdx.z * kd, k1 = min(g.nz, k0 + kd);
   const Axis& AX = g.ax[0];
   const Axis& AY = g.ax[1];
   const Axis& AZ = g.ax[2];
@@ -668,7 +671,8 @@ __global__ void __launch_bounds__(256) correct_divergence_kernel(Grid g, const d
   const int64_t plane = (int64_t)nx * ny;
   double mb = 0.0, mf = 0.0;
   if (i < nx && j < ny) {
-    const int k0 = blockIdx.z * KD, k1 = min(nz, k0 + KD);
+    const int kd = march_planes(nz);
+    const int k0 = blockIdx.z * kd, k1 = min(nz, k0 + kd);
     const Axis& AX = g.ax[0];
     const Axis& AY = g.ax[1];
     const Axis& AZ = g.ax[2];
@@ -729,7 +733,8 @@ __global__ void __launch_bounds__(256) gradient_correction_kernel(Grid g, const 
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = blockIdx.z * KD, k1 = min(g.nz, k0 + KD);
+  const int kd = march_planes(g.nz);
+  const int k0 = blockIdx.z * kd, k1 = min(g.nz, k0 + kd);
   const int nx = g.nx, ny = g.ny;
   const int64_t plane = (int64_t)nx * ny;
   const double idx = g.ax[0].id[i], idy = g.ax[1].id[j];
@@ -839,7 +844,13 @@ __global__ void max_finish_kernel(const double* __restrict__ part, int nblk, int
 
 inline dim3 cell_block(const Grid& g) { return dim3(64, 4, 1); }
 inline dim3 cell_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz); }
-inline dim3 march_grid(const Grid& g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + KD - 1) / KD); }
+// 16 planes per block, fewer until about 1024 blocks exist
+inline dim3 march_grid(const Grid& g) {
+  const int64_t tiles = (int64_t)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+  int kd = 16;
+  while (kd > 1 && tiles * ((g.nz + kd - 1) / kd) < 1024) kd /= 2;
+  return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kd - 1) / kd);
+}
 
 }  // namespace
 

@@ -86,6 +86,26 @@ def test_residual(kind, shape, Gr, K, amp):
     assert abs(norm - O.wnorm(g.weights(), ref)) <= 1e-12 * norm
 
 
+# The split FD passes choose their tile shape and load width from the sizes
+# (32 x 32 on small grids, 64 x 64 and 128 x 128 on large ones, element pairs
+# when the half size and line length are even).  KV_FD_TILE and KV_FD_PAIRS
+# force each variant, so the shapes used only at full size are checked here
+# on small ragged grids too.
+FD_VARIANTS = [("KV_FD_TILE", "64"), ("KV_FD_TILE", "32"), ("KV_FD_PAIRS", "0")]
+
+
+@pytest.mark.parametrize("var,val", FD_VARIANTS)
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", [GRIDS[0], GRIDS[2], GRIDS[4]])
+def test_projection_fd_variants(monkeypatch, var, val, kind, shape, Gr, K, amp):
+    print(f"case FD variant {var}={val} {kind} {shape}", flush=True)
+    monkeypatch.setenv(var, val)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    y0 = S.perturbation(g.size, 11)
+    y = to_dev(y0)
+    ctx.project(y)
+    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL64
+
+
 # The full-size workloads: 100^3 clustered at Gr 4e7 and 256^3 clustered at
 # Gr 2e8, the launch configuration the benchmark times (every output compared).
 FULL = [("cube100_clustered_gr4e7", 1000), ("cube256_clustered_gr2e8", 1000)]
@@ -177,6 +197,20 @@ def test_mixed_projected_jacobian(kind, shape, Gr, K, amp):
     err = field_rel_errors(g, got, ref)
     print("mixed field errors", err, flush=True)
     assert max(err) <= TOL_MIXED, err
+    assert O.div_measure(g, got) <= 1e-10
+
+
+@pytest.mark.parametrize("var,val", FD_VARIANTS)
+def test_mixed_fd_variants(monkeypatch, var, val):
+    kind, shape, Gr, K, amp = MIXED_GRIDS[3]
+    print(f"case mixed FD variant {var}={val} {kind} {shape}", flush=True)
+    monkeypatch.setenv(var, val)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    x = S.perturbation(g.size, 1000)
+    y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    ctx.apply_jacobian(to_dev(x), y, project=True, mixed=True)
+    got = to_host(y)
+    assert max(field_rel_errors(g, got, O.apply_jacobian(g, X0, x))) <= TOL_MIXED
     assert O.div_measure(g, got) <= 1e-10
 
 
