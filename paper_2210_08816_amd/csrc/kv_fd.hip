@@ -28,7 +28,7 @@ struct Epi {
   double sigma, coef;             // divide by sigma + coef (lx + ly + lz)
 };
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;
 
 // One batched product C[b] = A[b] * B[b] (row-major) of a launch.
 struct GemmProb {
@@ -48,12 +48,15 @@ struct GemmSet {
 };
 
 // Up to four independent products (the four blocks of a packed vector) in
-// one launch, 256 threads = 4 waves, 64x64 tile per block, each wave a 32x32
-// quarter as 2x2 MFMA 16x16 accumulators.  Within a product, work items are
+// one launch, 256 threads = 4 waves, TILE x TILE output tile per block (64,
+// or 32 on small grids), each wave a quarter as (TILE/32)^2 MFMA 16x16
+// accumulators.  Within a product, work items are
 // laid out so that the blocks sharing the large operand's tile are
 // consecutive on one XCD (blocks are dealt round-robin over the 8 XCDs).
-template <int EPI>
+template <int EPI, int TILE>
 __global__ void __launch_bounds__(256) fd_gemm_kernel(GemmSet gs) {
+  constexpr int BM = TILE, BN = TILE, R = TILE / 32;  // R x R accumulators per wave
+  constexpr int AE = BM * BK / 256, BE = BK * BN / 256;  // tile elements per thread
   __shared__ double As[BK][BM + 2];  // [k][m]
   __shared__ double Bs[BK][BN + 2];  // [k][n]
   const int64_t per_xcd = (gs.total + 7) / 8;
@@ -91,16 +94,20 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(GemmSet gs) {
   double* __restrict__ C = P.C + b * P.sC;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = mt * BM, n0 = nt * BN;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  v4d acc[R][R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < R; ++c) acc[r][c] = v4d{0, 0, 0, 0};
 
-  const int ar = tid >> 2, ak = (tid & 3) * 4;     // A tile: row, first k
-  const int bk = tid >> 4, bn = (tid & 15) * 4;    // B tile: k, first n
+  const int ar = tid / (BK / AE), ak = (tid % (BK / AE)) * AE;  // A tile: row, first k
+  const int bk = tid / (BN / BE), bn = (tid % (BN / BE)) * BE;  // B tile: k, first n
   for (int k0 = 0; k0 < K; k0 += BK) {
     {
       const int gm = m0 + ar;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < AE; ++q) {
         const int gk = k0 + ak + q;
         As[ak + q][ar] = (gm < M && gk < K) ? A[(int64_t)gm * lda + gk] : 0.0;
       }
@@ -108,7 +115,7 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(GemmSet gs) {
     {
       const int gk = k0 + bk;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < BE; ++q) {
         const int gn = n0 + bn + q;
         Bs[bk][bn + q] = (gk < K && gn < N) ? B[(int64_t)gk * ldb + gn] : 0.0;
       }
@@ -117,44 +124,45 @@ __global__ void __launch_bounds__(256) fd_gemm_kernel(GemmSet gs) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      const double a0 = As[kr][wm + (lane & 15)];
-      const double a1 = As[kr][wm + 16 + (lane & 15)];
-      const double b0 = Bs[kr][wn + (lane & 15)];
-      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
-      acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-      acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+      double af[R], bf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) af[r] = As[kr][wm + 16 * r + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < R; ++c) bf[c] = Bs[kr][wn + 16 * c + (lane & 15)];
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[r][c], 0, 0, 0);
     }
     __syncthreads();
   }
 
   // D[i][j] of a 16x16 block: lane = j + 16 * (i % 4), element i / 4.
-  const v4d* accs[4] = {&acc00, &acc01, &acc10, &acc11};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int r = t >> 1, cblk = t & 1;
-    const int gn = n0 + wn + cblk * 16 + (lane & 15);
+  for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gm = m0 + wm + r * 16 + (lane >> 4) + 4 * q;
-      if (gm < M && gn < N) {
-        double v = (*accs[t])[q];
-        if (EPI == EPI_DIVIDE) {
-          // C is (nz x nx*ny): m = z-mode c, n = b * nx + a
-          const int bb = gn / ep.nx, a = gn - bb * ep.nx;
-          const int64_t flat = (int64_t)gm * ((int64_t)ep.nx * ep.ny) + gn;
-          const double den = ep.sigma + ep.coef * (ep.lz[gm] + ep.ly[bb] + ep.lx[a]);
-          v = (flat == ep.null3) ? 0.0 : v / den;
-        } else if (EPI == EPI_ISQ) {
-          // C is (ny*nz x nx): m = k * ny + j, n = i
-          const int j = gm % ep.ny, k = gm / ep.ny;
-          v *= ep.isx[gn] * ep.isy[j] * ep.isz[k];
+    for (int cblk = 0; cblk < R; ++cblk) {
+      const int gn = n0 + wn + cblk * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gm = m0 + wm + r * 16 + (lane >> 4) + 4 * q;
+        if (gm < M && gn < N) {
+          double v = acc[r][cblk][q];
+          if (EPI == EPI_DIVIDE) {
+            // C is (nz x nx*ny): m = z-mode c, n = b * nx + a
+            const int bb = gn / ep.nx, a = gn - bb * ep.nx;
+            const int64_t flat = (int64_t)gm * ((int64_t)ep.nx * ep.ny) + gn;
+            const double den = ep.sigma + ep.coef * (ep.lz[gm] + ep.ly[bb] + ep.lx[a]);
+            v = (flat == ep.null3) ? 0.0 : v / den;
+          } else if (EPI == EPI_ISQ) {
+            // C is (ny*nz x nx): m = k * ny + j, n = i
+            const int j = gm % ep.ny, k = gm / ep.ny;
+            v *= ep.isx[gn] * ep.isy[j] * ep.isz[k];
+          }
+          C[(int64_t)gm * ldc + gn] = v;
         }
-        C[(int64_t)gm * ldc + gn] = v;
       }
     }
-  }
 }
 
 GemmProb prob(const double* A, int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double* C,
@@ -172,28 +180,37 @@ GemmProb prob(const double* A, int64_t lda, int64_t sA, const double* B, int64_t
   p.M = M;
   p.N = N;
   p.K = K;
-  p.mtiles = (M + BM - 1) / BM;
-  p.ntiles = (N + BN - 1) / BN;
   p.batch = batch;
   p.a_is_big = a_is_big;
   p.ep = ep;
   return p;
 }
 
+// Tiles of 64 x 64, or 32 x 32 when 64 x 64 ones would give fewer than about
+// four blocks per CU (KV_FD_TILE forces either).
 template <int EPI>
 hipError_t gemm_set(const GemmProb* ps, int np, hipStream_t s) {
+  int64_t tiles64 = 0;
+  for (int q = 0; q < np; ++q) tiles64 += (int64_t)((ps[q].M + 63) / 64) * ((ps[q].N + 63) / 64) * ps[q].batch;
+  const int forced = fd_forced_tile();
+  const int tile = forced ? forced : (tiles64 < 1024 ? 32 : 64);
   GemmSet gs{};
   gs.np = np;
   int64_t total = 0;
   for (int q = 0; q < np; ++q) {
     gs.p[q] = ps[q];
+    gs.p[q].mtiles = (ps[q].M + tile - 1) / tile;
+    gs.p[q].ntiles = (ps[q].N + tile - 1) / tile;
     gs.p[q].first = total;
-    total += (int64_t)ps[q].mtiles * ps[q].ntiles * ps[q].batch;
+    total += (int64_t)gs.p[q].mtiles * gs.p[q].ntiles * ps[q].batch;
   }
   gs.total = total;
   if (total == 0) return hipSuccess;
   const int64_t blocks = ((total + 7) / 8) * 8;
-  fd_gemm_kernel<EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(gs);
+  if (tile == 32)
+    fd_gemm_kernel<EPI, 32><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(gs);
+  else
+    fd_gemm_kernel<EPI, 64><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(gs);
   return hipGetLastError();
 }
 
@@ -269,11 +286,6 @@ hipError_t launch_fd_helmholtz4(const kv_ctx* c, const HelmBasis* const bx[4], c
     if (e) return e;
   }
   return hipSuccess;
-}
-
-hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K, hipStream_t s) {
-  Epi ep{};
-  return gemm<EPI_NONE>(A, K, 0, B, N, 0, C, N, 0, M, N, K, 1, M >= N, ep, s);
 }
 
 }  // namespace kv

@@ -473,19 +473,13 @@ hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t 
 // registers per output.  Small grids take 32 x 32 tiles when 64 x 64 ones
 // would leave fewer than about four blocks per CU.  FP32 (mixed form) follows
 // the same rules without the 128 x 128 case.  KV_FD_TILE=64 or 32 forces one
-// shape (read at every launch, for tests and measurements).
-int forced_tile() {
-  const char* e = getenv("KV_FD_TILE");
-  if (!e) return 0;
-  const int t = atoi(e);
-  return (t == 64 || t == 32) ? t : 0;
-}
+// shape (fd_forced_tile, read at every launch, for tests and measurements).
 
 template <typename T, int KIND, int EPI>
 hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
   const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
-  const int forced = forced_tile();
+  const int forced = fd_forced_tile();
   if (forced == 64) return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
   if (forced == 32) return launch_tiles<T, KIND, EPI, 32, 32, 16>(a, ep, s);
   if (sizeof(T) == 8 && !inv && EPI == EPI_NONE && a.H >= 128)
@@ -534,6 +528,13 @@ hipError_t split_pass(const kv_ctx* c, int axis, bool inverse, int epi, const T*
 }
 
 }  // namespace
+
+int fd_forced_tile() {
+  const char* e = getenv("KV_FD_TILE");
+  if (!e) return 0;
+  const int t = atoi(e);
+  return (t == 64 || t == 32) ? t : 0;
+}
 
 // One axis pass of the split transform.  axis 0 (x): RIGHT kinds on rows of
 // length nx; axis 1 (y): LEFT kinds on lines of nx, batched over z; axis 2

@@ -140,8 +140,9 @@ hipError_t launch_div_measure(kv_ctx* c, const double* y);
 hipError_t launch_symmetry(kv_ctx* c, const double* X);
 
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
-hipError_t launch_gemm_test(const double* A, const double* B, double* C, int M, int N, int K,
-                            hipStream_t s);
+// KV_FD_TILE=64 or 32: the tile shape every FD and Helmholtz GEMM pass must
+// use (0: chosen from the sizes); read at each launch.
+int fd_forced_tile();
 
 // (sigma - coef (A_x + A_y + A_z))^-1 with A_a = -H_a^-1 K_a of the given
 // bases, on a (bz.n, by.n, bx.n) block; 6 GEMM passes with cellA/cellB as

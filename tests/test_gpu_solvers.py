@@ -213,6 +213,24 @@ def test_preconditioner_matches_oracle(kind, shape, Gr, sigma):
     assert torch.equal(yy, y)
 
 
+@pytest.mark.parametrize("tile", ["64", "32"])
+def test_preconditioner_tile_shapes(monkeypatch, tile):
+    """The Helmholtz GEMM passes with each tile shape forced (the sizes
+    choose 32 x 32 on grids this small, 64 x 64 on large ones)."""
+    from oracle import precond as PC
+    from tests.gpu_util import field_rel_errors
+    monkeypatch.setenv("KV_FD_TILE", tile)
+    fx = [faces("clustered", n) for n in (70, 9, 66)]
+    g = O.Grid(*fx, Gr=4e7, Pr=0.71)
+    X0 = S.base_flow(*fx, K=2, amp=0.05, seed=71)
+    ctx = context(fx, 4e7, 0.71, X0)
+    r = S.perturbation(g.size, 73)
+    y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+    ctx.set_preconditioner(True, 0.5)
+    ctx.apply_preconditioner(to_dev(r), y)
+    assert max(field_rel_errors(g, to_host(y), PC.apply(g, r, 0.5))) <= 1e-12
+
+
 @pytest.mark.parametrize("kind,shape,Gr,amp,noise,tol", [
     ("clustered", (7, 6, 5), 1e4, 0.05, 0.01, 1e-10),
     ("clustered", (24, 24, 24), 1e4, 0.02, 0.0, 1e-8)])
