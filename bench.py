@@ -225,17 +225,26 @@ def main():
             roofline, secondary = roof_fd, roof_st
         else:
             roofline, secondary = roof_st, roof_fd
+        t_meas = dt / args.steps
+        extra = {}
         if mixed:
             # HBM bytes per cell: stencil 96, FP32 divergence 28 (read y 24,
             # write 4), per sweep six FP32 transform passes (8 B each) and the
-            # fused correction + divergence (read y 24, p 4; write y 24, T copy
-            # 16, b 4)
-            t_roof = (96.0 + 28.0 + sweeps * (48.0 + 72.0)) * n_cells / (HBM_PEAK_GBS * 1e9)
+            # fused correction + divergence (read y 24, p 4; write y 24, b 4)
+            t_roof = (96.0 + 28.0 + sweeps * (48.0 + 56.0)) * n_cells / (HBM_PEAK_GBS * 1e9)
         else:
             t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
                       + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
+            # the same step priced with dense (unsplit) axis transforms, 2N
+            # flop per cell per pass at the FP64 peak, and the stencil with
+            # its divergence fused (104 B) plus the correction (56 B) at the
+            # HBM peak: the roofline of the method without the even/odd split
+            t_dense = ((104.0 + 56.0) * n_cells / (HBM_PEAK_GBS * 1e9)
+                       + max(6 * 16.0 * n_cells / (HBM_PEAK_GBS * 1e9), 12 * fd_flops / (FP64_PEAK_TFLOPS * 1e12)))
+            extra = {"dense_transform_model_ms": round(1e3 * t_dense, 4),
+                     "dense_transform_model_frac": round(t_dense / t_meas, 4)}
         return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "roofline": roofline,
-                "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / (dt / args.steps), 4),
+                "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / t_meas, 4), **extra,
                 "sweeps_per_vector": round(sweeps, 3),
                 "phases_ms_per_vector": {"stencil": round(per_vec[0], 5), "divergence": round(per_vec[1], 5),
                                          "fd_transforms": round(per_vec[2], 5),
@@ -265,6 +274,8 @@ def main():
         "roofline": head["roofline"],
         "roofline_secondary": head["roofline_secondary"],
         "step_roofline_frac": head["step_roofline_frac"],
+        **({"dense_transform_model_frac": head["dense_transform_model_frac"]}
+           if "dense_transform_model_frac" in head else {}),
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
         "device": torch.cuda.get_device_name(0),
     }
