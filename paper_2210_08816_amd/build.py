@@ -21,6 +21,11 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     # packed FP32 arithmetic is kept off for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: without it the compiler keeps the
+    # FD kernels' loop-carried accumulators in VGPRs and copies them into and
+    # out of the AGPRs around every K chunk (twice the registers and 128 extra
+    # moves per chunk in the inverse passes)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

@@ -378,6 +378,10 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
           for (int c = 0; c < RN; ++c)
             acc[s][r][c] = Mfma<T>::op(af[r], bf[c], acc[s][r][c]);
       }
+      // inverse kinds: keep each k-step's fragment reads with its products
+      // (hoisting all four steps' reads of both operand sets costs about 64
+      // VGPRs and occupancy)
+      if (INV) __builtin_amdgcn_sched_barrier(0);
     }
     if (NB == 2) {
       // the other buffer was last read before the previous barrier
