@@ -116,8 +116,15 @@ struct SplitArgs {
 // VEC (every dimension the pairs run along is even: H, and the line length
 // of the LEFT kinds): operands move in element pairs, A along k and B along n,
 // so that the 64 lanes of one load cover whole contiguous row segments.
+//
+// Waves per SIMD the compiler must fit: 4 for the 64 x 64 inverse tiles (128
+// VGPRs; left alone it takes 154 and runs 3, and 4 measured 3-5% faster per
+// pass), no constraint otherwise.
+constexpr int split_waves(int kind, int bm, int bn) { return ((kind == 1 || kind == 3) && bm == 64 && bn == 64) ? 4 : 1; }
+
 template <typename T, int KIND, int EPI, int BM, int BN, int BK, bool VEC>
-__global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(split_waves(KIND, BM, BN))))
+fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
   constexpr bool RIGHT = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
@@ -379,8 +386,8 @@ __global__ void __launch_bounds__(256) fd_split_kernel(SplitArgs<T> a, SplitEpi 
             acc[s][r][c] = Mfma<T>::op(af[r], bf[c], acc[s][r][c]);
       }
       // inverse kinds: keep each k-step's fragment reads with its products
-      // (hoisting all four steps' reads of both operand sets costs about 64
-      // VGPRs and occupancy)
+      // (hoisting the reads of later steps costs registers: 72 -> 56 VGPRs
+      // on the 32 x 32 tiles)
       if (INV) __builtin_amdgcn_sched_barrier(0);
     }
     if (NB == 2) {
