@@ -119,8 +119,11 @@ struct SplitArgs {
 //
 // Waves per SIMD the compiler must fit: 4 for the 64 x 64 inverse tiles (128
 // VGPRs; left alone it takes 154 and runs 3, and 4 measured 3-5% faster per
-// pass), no constraint otherwise.
-constexpr int split_waves(int kind, int bm, int bn) { return ((kind == 1 || kind == 3) && bm == 64 && bn == 64) ? 4 : 1; }
+// pass), 2 for the 128 x 128 forward tiles (the LDS holds two such blocks per
+// CU), no constraint otherwise.
+constexpr int split_waves(int kind, int bm, int bn) {
+  return ((kind == 1 || kind == 3) && bm == 64 && bn == 64) ? 4 : ((bm == 128 && bn == 128) ? 2 : 1);
+}
 
 template <typename T, int KIND, int EPI, int BM, int BN, int BK, bool VEC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(split_waves(KIND, BM, BN))))
@@ -478,14 +481,13 @@ hipError_t launch_tiles(const SplitArgs<T>& a0, const SplitEpi& ep, hipStream_t 
 
 // Tile shapes (FP64, measured at H = 128): the forward kinds without an
 // epilogue take 128 x 128 tiles once the half size fills them (four times the
-// MFMA work per prologue and epilogue); the spectral-divide kind keeps 64 x 64
-// (its division epilogue at 128 x 128 needs registers for one wave per SIMD
-// only), and so do the inverse kinds, whose two accumulator sets double the
-// registers per output.  Small grids take 32 x 32 tiles when 64 x 64 ones
+// MFMA work per prologue and epilogue of a 64 x 64 tile); the spectral-divide
+// kind keeps 64 x 64 (at 128 x 128 it fits two waves per SIMD, but the whole
+// projection measured 5 us slower); the inverse kinds keep 64 x 64, because
+// their two accumulator sets double the registers per output.  Small grids take 32 x 32 tiles when 64 x 64 ones
 // would leave fewer than about four blocks per CU.  FP32 (mixed form) follows
 // the same rules without the 128 x 128 case.  KV_FD_TILE=64 or 32 forces one
 // shape (fd_forced_tile, read at every launch, for tests and measurements).
-
 template <typename T, int KIND, int EPI>
 hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
@@ -493,8 +495,9 @@ hipError_t launch(const SplitArgs<T>& a, const SplitEpi& ep, hipStream_t s) {
   const int forced = fd_forced_tile();
   if (forced == 64) return launch_tiles<T, KIND, EPI, 64, 64, 16>(a, ep, s);
   if (forced == 32) return launch_tiles<T, KIND, EPI, 32, 32, 16>(a, ep, s);
-  if (sizeof(T) == 8 && !inv && EPI == EPI_NONE && a.H >= 128)
-    return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
+  if constexpr (sizeof(T) == 8 && KIND != RIGHT_INV && KIND != LEFT_INV && EPI == EPI_NONE) {
+    if (a.H >= 128) return launch_tiles<T, KIND, EPI, 128, 128, 16>(a, ep, s);
+  }
   const int64_t M = right ? a.R : a.H, NN = right ? a.H : a.P;
   const int64_t tiles64 = ((M + 63) / 64) * ((NN + 63) / 64) * a.batch * (inv ? 1 : 2);
   if (tiles64 < 1024) return launch_tiles<T, KIND, EPI, 32, 32, 16>(a, ep, s);
