@@ -91,6 +91,36 @@ def unet_flops(r, batch):
     return batch * (3 * fwd - first), fwd
 
 
+def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
+    """One restart-free Arnoldi cycle of Krylov dimension m (m projected
+    Jacobians and classical Gram-Schmidt twice) on the bench context.  The
+    Gram-Schmidt time is the cycle's wall time less m projected Jacobians at
+    the measured per-vector time, so it also carries the cycle's host
+    synchronizations and the Hessenberg eigensolve.  Its algorithmic bytes
+    follow the kernels: at step j (nv = j + 1 basis vectors) each of the two
+    passes reads the nv vectors and w once per group of 8 (multi-dot), reads
+    the nv vectors and w and writes w (update); the norm and the scaling of w
+    add three vector volumes."""
+    best = None
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.arnoldi_leading_eigs(v0, m, 4, max_restarts=0, check=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if r > 0:  # the first call allocates the basis
+            best = dt if best is None else min(best, dt)
+    vols = sum(2 * (2 * (j + 1) + (j + 1 + 7) // 8 + 2) + 3 for j in range(m))
+    cgs_bytes = vols * 8.0 * n
+    cgs_s = max(best - m * matvec_ms * 1e-3, 1e-9)
+    ach = cgs_bytes / cgs_s / 1e9
+    return {"krylov_dim": m, "cycle_ms": round(1e3 * best, 3), "matvec_ms": round(m * matvec_ms, 3),
+            "cgs2_ms": round(1e3 * cgs_s, 3), "cgs2_bytes": int(cgs_bytes),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                         "what": "Gram-Schmidt algorithmic bytes / (cycle time - matvec time)"}}
+
+
 def learned_leg(torch, steps=10):
     """Time kvnn training steps and predictions on a 64^3 network (the
     learned Newton guess's kernels)."""
@@ -144,6 +174,7 @@ def main():
     ap.add_argument("--form", choices=("fp64", "mixed", "both"), default="both",
                     help="projection form(s) to time; the headline value is the faster form's")
     ap.add_argument("--no-learned", action="store_true", help="skip the network timing leg")
+    ap.add_argument("--no-arnoldi", action="store_true", help="skip the Arnoldi-cycle timing leg")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the network timing leg and print its JSON (for profiling)")
     ap.add_argument("--copy-ref", type=int, default=0,
@@ -279,6 +310,9 @@ def main():
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
         "device": torch.cuda.get_device_name(0),
     }
+    if "fp64" in forms and not args.no_arnoldi:
+        log("[bench] timing one Arnoldi cycle (CGS2)")
+        result["arnoldi_cycle"] = arnoldi_leg(torch, ctx, xs[0], n, forms["fp64"]["ms_per_step"])
     if not args.no_learned:
         log("[bench] timing the learned-guess network kernels")
         result["learned"] = learned_leg(torch)
