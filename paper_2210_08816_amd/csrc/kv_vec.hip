@@ -22,26 +22,28 @@ struct RowInfo {
 
 // Row r of the packed vector: block u (nz*ny rows of nx-1), v (nz*(ny-1) rows
 // of nx), w ((nz-1)*ny rows of nx), T (nz*ny rows of nx).
-__device__ __forceinline__ RowInfo row_info(const Grid& g, int64_t r) {
+// (Row indices fit 32 bits: at most 4 * 4096^2 rows.)
+__device__ __forceinline__ RowInfo row_info(const Grid& g, int64_t r64) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int64_t R0 = (int64_t)nz * ny, R1 = (int64_t)nz * (ny - 1), R2 = (int64_t)(nz - 1) * ny;
+  const int R0 = nz * ny, R1 = nz * (ny - 1), R2 = (nz - 1) * ny;
+  int r = (int)r64;
   if (r < R0) {
-    const int k = (int)(r / ny), j = (int)(r % ny);
-    return {g.ou + r * (nx - 1), nx - 1, g.ax[0].dd + 1, g.ax[1].h[j] * g.ax[2].h[k]};
+    const int k = r / ny, j = r - k * ny;
+    return {g.ou + (int64_t)r * (nx - 1), nx - 1, g.ax[0].dd + 1, g.ax[1].h[j] * g.ax[2].h[k]};
   }
   r -= R0;
   if (r < R1) {
-    const int k = (int)(r / (ny - 1)), jj = (int)(r % (ny - 1));
-    return {g.ov + r * nx, nx, g.ax[0].h, g.ax[1].dd[jj + 1] * g.ax[2].h[k]};
+    const int k = r / (ny - 1), jj = r - k * (ny - 1);
+    return {g.ov + (int64_t)r * nx, nx, g.ax[0].h, g.ax[1].dd[jj + 1] * g.ax[2].h[k]};
   }
   r -= R1;
   if (r < R2) {
-    const int kk = (int)(r / ny), j = (int)(r % ny);
-    return {g.ow + r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].dd[kk + 1]};
+    const int kk = r / ny, j = r - kk * ny;
+    return {g.ow + (int64_t)r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].dd[kk + 1]};
   }
   r -= R2;
-  const int k = (int)(r / ny), j = (int)(r % ny);
-  return {g.oT + r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].h[k]};
+  const int k = r / ny, j = r - k * ny;
+  return {g.oT + (int64_t)r * nx, nx, g.ax[0].h, g.ax[1].h[j] * g.ax[2].h[k]};
 }
 
 __device__ __forceinline__ int64_t total_rows(const Grid& g) {
@@ -136,6 +138,8 @@ __global__ void __launch_bounds__(256) mupdate_kernel(int64_t n, const double* _
   __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     double acc = w[e];
+    // eight loads in flight per thread
+#pragma unroll 8
     for (int q = 0; q < nv; ++q) acc -= hs[q] * V[q * ldv + e];
     w[e] = acc;
   }
