@@ -199,7 +199,9 @@ typedef struct {
  * invert).  The Hessenberg eigenproblem is solved on the GPU by Francis
  * double-shift QR.  lam_re, lam_im, resid: host arrays of n_eigs+1 values;
  * resid gets the Ritz residual norms.  info: host, may be NULL.  Not
- * converged within max_matvec: KV_ENOCONV with the last Ritz values. */
+ * converged within max_matvec: KV_ENOCONV with the last Ritz values.  A
+ * Hessenberg QR that does not converge also gives KV_ENOCONV, with no values
+ * (info->n_out = 0; matvecs and restarts count the work done). */
 int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
                             double* lam_im, double* resid, kv_eig_info* info);
 

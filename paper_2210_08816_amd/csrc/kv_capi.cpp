@@ -1314,8 +1314,10 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     if (!(vn > 0) || !std::isfinite(vn)) return fail(c, KV_ENONFINITE, "zero or non-finite start vector");
     if ((rc = lincomb(c, 1, {1.0 / vn}, {V}, V))) return rc;
     int k = 0;
-    if ((rc = arnoldi(c, V, m, H, &k, &matvecs))) return rc;
-    if ((rc = ritz(c, H, m, k, p->n_eigs, rz))) return rc;
+    if ((rc = arnoldi(c, V, m, H, &k, &matvecs)) || (rc = ritz(c, H, m, k, p->n_eigs, rz))) {
+      if (info) *info = kv_eig_info{0, matvecs, restarts, 0};  // the work done so far
+      return rc;
+    }
     double scale = 0.0;
     for (int i : rz.sel) scale = std::max(scale, std::abs(rz.vals[i]));
     conv = true;

@@ -5,7 +5,7 @@
 // One wavefront does all of it, FP64:
 //   1. Francis implicit double-shift QR on the active window (eigenvalues
 //      only), deflating when |h_{l,l-1}| <= eps (|h_{l-1,l-1}| + |h_{l,l}|);
-//      ad-hoc shifts after 10 and 20 iterations without deflation.  Each
+//      ad-hoc shifts after every 10 iterations without deflation.  Each
 //      3x3 reflector is formed redundantly by every lane and applied to the
 //      rows / columns with one matrix element per lane.
 //   2. For each requested eigenvalue, inverse iteration on H - lambda I in
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
     ++total;
     // double shift: eigenvalues of the trailing 2x2 (sum s, product t)
     double s, t;
-    if (its == 10 || its == 20) {
+    if (its % 10 == 0) {  // every tenth iteration without a deflation
       const double e = fabs(h(hi, hi - 1)) + fabs(h(hi - 1, hi - 2));
       s = 1.5 * e;
       t = e * e;
