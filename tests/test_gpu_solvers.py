@@ -112,6 +112,25 @@ def test_single_arnoldi_cycle_ritz_values():
     assert np.allclose(res, ref_res, rtol=1e-5, atol=1e-10 * scale)
 
 
+def test_single_arnoldi_cycle_krylov_dim_200():
+    """One 200-step cycle: the GPU Hessenberg QR on a 200 x 200 matrix
+    (exceptional shifts beyond the 20th stalled iteration), against the
+    oracle's Ritz values."""
+    fx = [faces("clustered", 12)] * 3
+    g = O.Grid(*fx, Gr=1e5, Pr=0.71)
+    X0 = S.base_flow(*fx, K=3, amp=0.1, seed=5)
+    v0 = S.perturbation(g.size, 78)
+    ctx = context(fx, 1e5, 0.71, X0)
+    vals, res, info = ctx.arnoldi_leading_eigs(to_dev(v0), krylov_dim=200, n_eigs=4, max_restarts=0,
+                                               max_matvec=200)
+    assert info["matvecs"] == 200 and len(vals) >= 4
+    A = SV.Operator(g, X0)
+    ref, ref_res = SV.arnoldi_ritz(A, v0, 200, 4)
+    scale = np.max(np.abs(ref))
+    assert len(vals) == len(ref)
+    assert np.max(np.abs(vals - ref)) <= 1e-8 * scale, (vals, ref)
+
+
 def dense_saddle_eigs(g, X0):
     def dense(fn, nin):
         cols = []
