@@ -494,8 +494,11 @@ __device__ __forceinline__ void fetch_plane(const Grid& g, __amdgpu_buffer_rsrc_
   // plane validity per block: u, v, T need 0 <= kp < nz; w (faces) 1 <= kp <= nz-1
   const bool kin = (kp >= 0 && kp < g.nz);
   const bool win = (kp >= 1 && kp < g.nz);
+  // waves none of whose lanes holds a halo column skip the halo loads
+  const bool halo_wave = (int)(threadIdx.x >> 6) <= (NHALO - 1) / 64;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
+    if (q == 1 && !halo_wave) break;
     int off[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
