@@ -74,9 +74,9 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
         while True:
             Xtry = X.clone()
             ctx = kv.Context(*faces, Gr=target, Pr=Pr)
-            if precond_sigma is not None:
-                ctx.set_preconditioner(True, precond_sigma)
             try:
+                if precond_sigma is not None:
+                    ctx.set_preconditioner(True, precond_sigma)
                 ctx.project(Xtry)
                 info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, **kw)
             finally:

@@ -175,10 +175,10 @@ def compare_starts(faces, Gr, X_near, Gr_near, net, norm, Pr=0.71, tol_abs=1e-10
     import torch
     res = {}
     ctx = kv.Context(*faces, Gr=Gr, Pr=Pr)
-    if precond_sigma is not None:
-        ctx.set_preconditioner(True, precond_sigma)
     finals = []
     try:
+        if precond_sigma is not None:
+            ctx.set_preconditioner(True, precond_sigma)
         for kind in list(kinds) + [f"learned_increment_smooth{sg:g}" for sg in smooth_sigmas]:
             X = torch.empty_like(X_near)
             torch.cuda.synchronize()
