@@ -291,10 +291,13 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=2)
     ap.add_argument("--sigma", type=float, default=10.0, help="preconditioner shift (negative: none)")
     ap.add_argument("--smooth", default="", help="comma-separated smoothing shifts of the learned increment")
+    ap.add_argument("--held", default="1,4,7,10,13",
+                    help="comma-separated i: held-out values Gr_lo 10^((i + 1/2) step)")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     sm = tuple(float(v) for v in a.smooth.split(",") if v)
-    res = experiment(n=a.n, grid=a.grid, factor=a.factor, ntrain=a.ntrain, epochs=a.epochs, lr=a.lr,
+    held = tuple(int(v) for v in a.held.split(",") if v)
+    res = experiment(n=a.n, grid=a.grid, factor=a.factor, ntrain=a.ntrain, held=held, epochs=a.epochs, lr=a.lr,
                      batch=a.batch, precond_sigma=None if a.sigma < 0 else a.sigma, smooth_sigmas=sm,
                      log=lambda m: print(m, flush=True))
     text = json.dumps(res)
