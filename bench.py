@@ -38,6 +38,17 @@ def algorithmic_bytes_per_cell_fp64():
     return {"stencil": 104.0, "stencil_io": 96.0, "fd": 96.0, "correction": 56.0, "divergence": 32.0}
 
 
+def dense_transform_model_s(n_cells, n_axis):
+    """Roofline time of one projected Krylov vector with dense (unsplit) axis
+    transforms: the stencil with its divergence fused (104 B per cell) and
+    the gradient correction (56 B) at the HBM peak, plus six transform passes,
+    each the larger of 16 B per cell at the HBM peak and 2 n_axis flop per
+    cell at the FP64 peak."""
+    hbm = HBM_PEAK_GBS * 1e9
+    return ((104.0 + 56.0) * n_cells / hbm
+            + max(6 * 16.0 * n_cells / hbm, 12.0 * n_axis * n_cells / (FP64_PEAK_TFLOPS * 1e12)))
+
+
 def profiled_traffic(kernel, source):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel's source changed since it was taken."""
@@ -266,12 +277,8 @@ def main():
         else:
             t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
                       + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
-            # the same step priced with dense (unsplit) axis transforms, 2N
-            # flop per cell per pass at the FP64 peak, and the stencil with
-            # its divergence fused (104 B) plus the correction (56 B) at the
-            # HBM peak: the roofline of the method without the even/odd split
-            t_dense = ((104.0 + 56.0) * n_cells / (HBM_PEAK_GBS * 1e9)
-                       + max(6 * 16.0 * n_cells / (HBM_PEAK_GBS * 1e9), 12 * fd_flops / (FP64_PEAK_TFLOPS * 1e12)))
+            # the same step priced as the method without the even/odd split
+            t_dense = dense_transform_model_s(n_cells, spec["n"])
             extra = {"dense_transform_model_ms": round(1e3 * t_dense, 4),
                      "dense_transform_model_frac": round(t_dense / t_meas, 4)}
         return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "roofline": roofline,

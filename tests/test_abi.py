@@ -48,3 +48,14 @@ def test_null_context_is_rejected():
     assert nn.kvnn_num_params(None, None) == kvnn.KVNN_EINVAL
     assert nn.kvnn_create(None, None, None) == kvnn.KVNN_EINVAL
     assert nn.kvnn_last_error(None)
+
+
+def test_bench_dense_transform_model_at_256():
+    """The bench's dense-transform roofline model at 256^3: 160 B per cell at
+    8 TB/s (0.3355 ms) plus six axis passes at 2 * 256 flop per cell and
+    78.6 TFLOP/s (0.6557 ms, above their 96 B per cell at 8 TB/s): 0.991 ms."""
+    import bench
+    c = 256 ** 3
+    t = bench.dense_transform_model_s(c, 256)
+    assert abs(t - (160.0 * c / 8e12 + 12.0 * 256 * c / 78.6e12)) < 1e-15
+    assert abs(t * 1e3 - 0.991) < 5e-4
