@@ -93,16 +93,17 @@ __global__ void __launch_bounds__(256) wdots_kernel(Grid g, Ptr4 a, Ptr4 b, doub
   }
 }
 
-// Block multi-dot for classical Gram-Schmidt: part[q][blk] for q < nv <= 8
+// Block multi-dot for classical Gram-Schmidt: part[q][blk] for q < nv <= MD
 // against the vectors V + q * ldv; w * weight is formed once per element.
-__global__ void __launch_bounds__(256) mdot8_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
-                                                    const double* __restrict__ w, double* __restrict__ part,
-                                                    int qbase) {
+constexpr int MD = 16;
+__global__ void __launch_bounds__(256) mdot_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
+                                                   const double* __restrict__ w, double* __restrict__ part,
+                                                   int qbase) {
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double acc[8];
+  double acc[MD];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int q = 0; q < MD; ++q) acc[q] = 0.0;
   const int64_t nrows = total_rows(g);
   for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
     const RowInfo ri = row_info(g, r);
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(256) mdot8_kernel(Grid g, const double* __rest
       const int64_t idx = ri.off + e;
       const double ww = ri.wx[e] * ri.wyz * w[idx];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < MD; ++q)
         if (q < nv) acc[q] += ww * V[q * ldv + idx];
     }
   }
@@ -223,9 +224,9 @@ hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const doub
 hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
   const int nblk = c->npart_blocks;
-  for (int q0 = 0; q0 < nvec; q0 += 8) {
-    const int nv = (nvec - q0 < 8) ? nvec - q0 : 8;
-    mdot8_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
+  for (int q0 = 0; q0 < nvec; q0 += MD) {
+    const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
+    mdot_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
   }
   sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, c->dres);
   return hipGetLastError();
