@@ -109,7 +109,7 @@ def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
     the measured per-vector time, so it also carries the cycle's host
     synchronizations and the Hessenberg eigensolve.  Its algorithmic bytes
     follow the kernels: at step j (nv = j + 1 basis vectors) each of the two
-    passes reads the nv vectors and w once per group of 8 (multi-dot), reads
+    passes reads the nv vectors and w once per group of 16 (multi-dot), reads
     the nv vectors and w and writes w (update); the norm and the scaling of w
     add three vector volumes."""
     best = None
@@ -121,7 +121,7 @@ def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
         dt = time.perf_counter() - t0
         if r > 0:  # the first call allocates the basis
             best = dt if best is None else min(best, dt)
-    vols = sum(2 * (2 * (j + 1) + (j + 1 + 7) // 8 + 2) + 3 for j in range(m))
+    vols = sum(2 * (2 * (j + 1) + (j + 1 + 15) // 16 + 2) + 3 for j in range(m))
     cgs_bytes = vols * 8.0 * n
     cgs_s = max(best - m * matvec_ms * 1e-3, 1e-9)
     ach = cgs_bytes / cgs_s / 1e9
