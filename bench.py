@@ -193,7 +193,7 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(one solve per GPU is the sharding plan); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
