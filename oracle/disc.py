@@ -338,3 +338,38 @@ def symmetry_measures(g: Grid, X):
     r_2d = np.max(np.abs(theta + theta[::-1, :, ::-1]))
     r_3d = np.max(np.abs(theta + theta[::-1, ::-1, ::-1]))
     return float(r_ref), float(r_2d), float(r_3d)
+
+
+# ---- symmetry classes of perturbations (Sec. 2, Eqs. 7-9) --------------------
+# The cube with its boundary conditions is invariant under two commuting
+# mirror maps, and their product:
+#   reflection   y -> 1 - y:          (u, v, w, T) -> ( u, -v,  w,  T)
+#   2-D rotation (x, z) -> (1-x, 1-z): (u, v, w, T) -> (-u,  v, -w, -T)
+#   3-D centro-symmetry, the product:  (u, v, w, T) -> (-u, -v, -w, -T)
+# with T the centred temperature (its wall values +-1/2 swap under x -> 1-x),
+# each field read at the mirrored point.  Eqs. 7-9 measure a state's distance
+# from these symmetries.  On a mirror-symmetric grid a mirrored interior face
+# or cell is the reversed index along that axis.  At a state with all three
+# symmetries the Jacobian commutes with the maps, so its eigenvectors split
+# into four classes by the sign (+1 kept, -1 broken) each map takes on them.
+SYM_AXES = {"ref": (1,), "rot": (0, 2)}
+SYM_SIGNS = {"ref": (1.0, -1.0, 1.0, 1.0), "rot": (-1.0, 1.0, -1.0, -1.0)}
+
+
+def symmetry_map(g: Grid, x, which):
+    """S x for which in {"ref", "rot"} (the maps above); needs a mirror-
+    symmetric grid along the mirrored axes."""
+    flip = tuple(2 - a for a in SYM_AXES[which])   # numpy axes of (z, y, x)
+    return Grid.pack([s * np.flip(f, axis=flip) for f, s in zip(g.unpack(x), SYM_SIGNS[which])])
+
+
+def symmetry_project(g: Grid, x, e_ref, e_rot):
+    """Projection onto a symmetry class: the product of (I + e S) / 2 over
+    the reflection and the 2-D rotation, e = +1 (symmetric), -1
+    (antisymmetric) or 0 (that map not restricted).  The class of the 3-D
+    centro-symmetry is then e_ref * e_rot."""
+    y = np.array(x, dtype=np.float64)
+    for which, e in (("ref", e_ref), ("rot", e_rot)):
+        if e:
+            y = 0.5 * (y + e * symmetry_map(g, y, which))
+    return y

@@ -333,6 +333,92 @@ def test_symmetry_measures_vanish_on_symmetric_field():
     assert min(O.symmetry_measures(g, X)) > 1e-3
 
 
+CLASSES = [(1, 1), (1, -1), (-1, 1), (-1, -1)]
+
+
+def brute_symmetry_map(g, x, which):
+    """S x found by matching physical positions: each unknown takes the value
+    of the same field at the mirrored point (searched over all unknowns of
+    that field), times the field's sign under the map."""
+    mir = {"ref": (1,), "rot": (0, 2)}[which]
+    sign = {"ref": (1, -1, 1, 1), "rot": (-1, 1, -1, -1)}[which]
+    out = np.empty(g.size)
+    for a, f in enumerate(g.unpack(x)):
+        coords = []
+        for ax in range(3):   # interior faces along the field's own axis, centres otherwise
+            coords.append(g.faces[ax][1:-1] if ax == a else g.c[ax])
+        pts = [(k, j, i) for k in range(f.shape[0]) for j in range(f.shape[1]) for i in range(f.shape[2])]
+        pos = {tuple(round(coords[ax][(i, j, k)[ax]], 12) for ax in range(3)): (k, j, i) for (k, j, i) in pts}
+        res = np.empty(f.shape)
+        for (k, j, i) in pts:
+            p = [coords[ax][(i, j, k)[ax]] for ax in range(3)]
+            for ax in mir:
+                p[ax] = 1.0 - p[ax]
+            res[k, j, i] = sign[a] * f[pos[tuple(round(t, 12) for t in p)]]
+        out[g.off[a]:g.off[a + 1]] = res.ravel()
+    return out
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered"])
+def test_symmetry_map_against_mirrored_positions(kind):
+    g = grid(5, 4, 3, kind)
+    x = S.perturbation(g.size, 31)
+    for which in ("ref", "rot"):
+        assert np.array_equal(O.symmetry_map(g, x, which), brute_symmetry_map(g, x, which))
+
+
+def test_symmetry_maps_commute_with_the_equations():
+    """The maps are symmetries of the discrete problem: N(S X) = S N(X) and
+    P S = S P (a wrong sign on any field breaks the advection or buoyancy
+    coupling), each map is an involution, and their product maps every field
+    to minus its centro-symmetric image (Eq. 9)."""
+    g = grid(8, 7, 6, "clustered", Gr=2e5)
+    X = S.base_flow(*g.faces, K=3, amp=0.05, seed=5) + 0.1 * S.perturbation(g.size, 6)
+    y = S.perturbation(g.size, 7)
+    for which in ("ref", "rot"):
+        Sm = lambda v: O.symmetry_map(g, v, which)  # noqa: E731
+        assert rel(O.nonlinear(g, Sm(X)), Sm(O.nonlinear(g, X))) < 1e-13
+        assert rel(O.project(g, Sm(y)), Sm(O.project(g, y))) < 1e-12
+        assert np.array_equal(Sm(Sm(y)), y)
+    c = O.symmetry_map(g, O.symmetry_map(g, y, "rot"), "ref")
+    assert np.array_equal(c, g.pack([-f[::-1, ::-1, ::-1] for f in g.unpack(y)]))
+
+
+def test_symmetry_classes_project_and_split():
+    """The four class projections are W-orthogonal projections that sum to the
+    identity; at a state with all three symmetries they commute with J and P."""
+    g = grid(8, 7, 6, "clustered", Gr=2e5)
+    w = g.weights()
+    x = S.perturbation(g.size, 8)
+    parts = [O.symmetry_project(g, x, er, eo) for er, eo in CLASSES]
+    assert rel(sum(parts), x) < 1e-15
+    for a in range(4):
+        assert rel(O.symmetry_project(g, parts[a], *CLASSES[a]), parts[a]) < 1e-15
+        for b in range(a):
+            assert abs(O.wdot(w, parts[a], parts[b])) < 1e-14 * O.wdot(w, x, x)
+    assert np.array_equal(O.symmetry_project(g, x, 0, 0), x)
+    assert rel(O.symmetry_project(g, x, 1, 0) + O.symmetry_project(g, x, -1, 0), x) < 1e-15
+    X0 = O.symmetry_project(g, S.base_flow(*g.faces, K=3, amp=0.05, seed=5), 1, 1)
+    for cl in CLASSES:
+        Pi = lambda v: O.symmetry_project(g, v, *cl)  # noqa: E731
+        assert rel(Pi(O.jacobian(g, X0, x)), O.jacobian(g, X0, Pi(x))) < 1e-13
+        assert rel(Pi(O.project(g, x)), O.project(g, Pi(x))) < 1e-12
+
+
+def test_symmetry_classes_against_the_measures():
+    """Eqs. 7-9: a state in class (+,+) has all three measures zero; adding a
+    class (e_ref, e_rot) perturbation keeps exactly the measures whose map has
+    sign +1 on it (the centro-symmetry's sign is e_ref e_rot) at zero."""
+    g = grid(8, 8, 8, "clustered")
+    Xs = O.symmetry_project(g, S.base_flow(*g.faces, K=3, amp=0.1, seed=17), 1, 1)
+    assert max(O.symmetry_measures(g, Xs)) < 1e-14
+    x = S.perturbation(g.size, 19)
+    for er, eo in CLASSES:
+        m = O.symmetry_measures(g, Xs + 0.1 * O.symmetry_project(g, x, er, eo))
+        for val, e in zip(m, (er, eo, er * eo)):
+            assert (val < 1e-14) if e == 1 else (val > 1e-3), (er, eo, m)
+
+
 def test_workload_grids():
     f = S.faces_clustered(256)
     assert f[0] == 0.0 and f[-1] == 1.0 and np.all(np.diff(f) > 0)
