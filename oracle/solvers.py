@@ -248,13 +248,33 @@ def ellipse(unwanted, wanted_min_re):
     return d, a, b, a * a - b2
 
 
+def growth_rate(z, a, b, c2):
+    """Growth per degree of the Chebyshev polynomial of the ellipse at z
+    (measured from the centre) against its size on the ellipse:
+    |z + sqrt(z^2 - c^2)| / (a + b), the root of larger modulus."""
+    s = np.sqrt(complex(z) ** 2 - c2)
+    return max(abs(complex(z) + s), abs(complex(z) - s)) / (a + b)
+
+
 def cheb_degree(wr, a, b, c2, dmax, gain=1e6):
     """Smallest degree whose Chebyshev growth at wr over the ellipse exceeds gain."""
-    s = np.sqrt(complex(wr * wr - c2))
-    ratio = max(abs(wr + s), abs(wr - s)) / (a + b)
+    ratio = growth_rate(wr, a, b, c2)
     if ratio <= 1.0 + 1e-12:
         return 0
     return int(min(dmax, max(1, math.ceil(math.log(gain) / math.log(ratio)))))
+
+
+def restart_weights(wanted, d, a, b, c2, wr, degree):
+    """Weights of the wanted Ritz vectors in the restart vector: the inverse
+    of each one's predicted growth under the filter, relative to the least
+    growing one, growth_rate(lam - d)^degree.  Unweighted, a wanted value far
+    right of the ellipse outgrows the others by many orders, and the others
+    sink to round-off in the filtered vector (their Ritz residuals stall, or
+    the next cycle ends in a breakdown without them)."""
+    if degree == 0:
+        return np.ones(len(wanted))
+    lg = np.array([degree * math.log(growth_rate(lam - d, a, b, c2)) for lam in wanted])
+    return np.maximum(np.exp(lg.min() - lg), 1e-300)
 
 
 def cheb_filter(A: Operator, z0, d, c2, wr, degree):
@@ -271,42 +291,122 @@ def cheb_filter(A: Operator, z0, d, c2, wr, degree):
     return z
 
 
+class Deflated:
+    """B x = (I - Q Q^T W) A x: A with a locked invariant subspace span(Q)
+    (rows of Q, W-orthonormal) taken out.  On the W-orthogonal complement of
+    span(Q) the eigenvalues of B are those of A less the locked ones
+    (Schur deflation), so a converged eigenvalue can neither be found again
+    nor outgrow the others under the filter."""
+
+    def __init__(self, A: Operator, Q):
+        self.A, self.Q = A, Q
+        self.g, self.fd, self.w = A.g, A.fd, A.w
+
+    @property
+    def matvecs(self):
+        return self.A.matvecs
+
+    def orth(self, y):
+        for _ in range(2):                               # CGS2 against Q
+            if len(self.Q):
+                y = y - (self.Q @ (self.w * y)) @ self.Q
+        return y
+
+    def __call__(self, x):
+        return self.orth(self.A(x))
+
+    def norm(self, a):
+        return self.A.norm(a)
+
+
+def lift(A: Operator, Q, y, theta):
+    """Eigenvector of A from an eigenvector y of the deflated operator
+    (theta its eigenvalue): x = y + Q^T t with (theta - R) t = Q W A y and
+    R = Q W A Q^T the locked block.  Not counted as matvecs."""
+    if len(Q) == 0:
+        return y
+    m0 = A.matvecs
+    R = np.array([[A.dot(qi, A(qj)) for qj in Q] for qi in Q])
+    Ay = A(y.real) + 1j * A(y.imag)
+    rhs = Q @ (A.w * Ay)
+    A.matvecs = m0
+    t = np.linalg.solve(theta * np.eye(len(Q)) - R, rhs)
+    return y + t @ Q
+
+
 def cheb_arnoldi(A: Operator, v0, m, n_eigs, tol=1e-8, max_matvec=100000,
                  cheb_degree_max=200, max_restarts=1000):
-    """Leading eigenvalues of A.  Returns (vals, res, vecs, info)."""
+    """Leading eigenvalues of A.  Returns (vals, res, vecs, info).
+
+    Restarted Arnoldi with a Chebyshev-filtered restart vector, and locking:
+    a wanted Ritz value (a conjugate pair whole) whose residual meets the
+    tolerance is locked -- its real invariant subspace joins Q and later
+    cycles and filters work on the deflated operator (Deflated), asking for
+    the remaining wanted values only.  Values are locked in leading order
+    (a converged value waits while one right of it is still open), so the
+    locked values are always the leading ones found."""
     m0 = A.matvecs
+    n = len(v0)
+    Q = np.zeros((0, n))
+    lk_vals, lk_res, lk_vecs = [], [], []
     v = A_project(A, v0)
     restarts = 0
     while True:
-        V, H, k = arnoldi(A, v, m)
+        B = Deflated(A, Q)
+        V, H, k = arnoldi(B, B.orth(v), m)
         vals, S, res = ritz(H, k)
-        sel = wanted_set(vals, n_eigs)
-        scale = max(abs(vals[i]) for i in sel)
-        conv = all(res[i] <= tol * scale for i in sel) or k < m
-        if conv or A.matvecs - m0 >= max_matvec or restarts >= max_restarts:
-            Y = (V[:k].T @ S[:, sel]).T                 # Ritz vectors as rows
-            return (vals[sel], res[sel], Y,
-                    dict(matvecs=A.matvecs - m0, restarts=restarts, converged=conv))
-        # restart vector: sum of real and imaginary parts of wanted Ritz vectors
-        coef = np.zeros(k)
+        sel = wanted_set(vals, n_eigs - len(lk_vals))
+        scale = max([abs(vals[i]) for i in sel] + [abs(x) for x in lk_vals])
+        done = []                      # converged prefix of sel, in leading order
         for i in sel:
-            coef += S[:, i].real + S[:, i].imag
-        z0 = V[:k].T @ coef
-        z0 = z0 / A.norm(z0)
+            if not res[i] <= tol * scale:
+                break
+            done.append(i)
+        conv = len(done) == len(sel) or k < m
+        stop = conv or A.matvecs - m0 >= max_matvec or restarts >= max_restarts
+        for i in (sel if stop else done):
+            if vals[i].imag < 0 and any(abs(vals[j] - np.conj(vals[i])) <= 1e-12 * abs(vals[i]) for j in sel):
+                continue                                 # the +Im member locks the pair
+            y = lift(A, Q, V[:k].T @ S[:, i], vals[i])
+            members = [(vals[i], y)] + ([(np.conj(vals[i]), np.conj(y))] if vals[i].imag > 0 else [])
+            for lam, vec in members:
+                lk_vals.append(lam)
+                lk_res.append(res[i])
+                lk_vecs.append(vec)
+            if not stop:
+                for q in ([y.real, y.imag] if vals[i].imag > 0 else [y.real]):
+                    q = Deflated(A, Q).orth(q)
+                    Q = np.vstack([Q, q / A.norm(q)])
+        if stop or len(lk_vals) >= n_eigs:
+            idx = wanted_set(np.array(lk_vals), n_eigs)
+            info = dict(matvecs=A.matvecs - m0, restarts=restarts, converged=conv or len(lk_vals) >= n_eigs,
+                        locked=len(Q))
+            return (np.array(lk_vals)[idx], np.array(lk_res)[idx], np.array(lk_vecs)[idx], info)
+        rest = [i for i in sel if i not in done]
+        # filter: an ellipse around the unwanted Ritz values and a degree
         unw = np.array([vals[i] for i in range(k) if i not in sel])
-        if len(unw) == 0:
-            v = z0
-        else:
-            ref = min((vals[i] for i in sel), key=lambda t: t.real)
+        deg = 0
+        if len(unw):
+            ref = min((vals[i] for i in rest), key=lambda t: t.real)
             d, a, b, c2 = ellipse(unw, ref.real)
             wr = ref.real - d
             deg = cheb_degree(wr, a, b, c2, cheb_degree_max)
             deg = min(deg, max(0, max_matvec - (A.matvecs - m0) - m))
-            v = cheb_filter(A, z0, d, c2, wr, deg)
+        # restart vector: sum of the real and imaginary parts of the wanted
+        # Ritz vectors still open, each weighted against its growth under the
+        # filter
+        wts = restart_weights([vals[i] for i in rest], d, a, b, c2, wr, deg) if deg else np.ones(len(rest))
+        coef = np.zeros(k)
+        for i, wt in zip(rest, wts):
+            coef += wt * (S[:, i].real + S[:, i].imag)
+        B = Deflated(A, Q)
+        z0 = B.orth(V[:k].T @ coef)
+        z0 = z0 / A.norm(z0)
+        v = cheb_filter(B, z0, d, c2, wr, deg) if deg else z0
         # A = P J has the eigenvalue 0 on gradient fields, right of the wanted
         # set; the filter's "- d z" term carries round-off there, so the start
         # vector is put back into range(P) before the next Arnoldi cycle.
-        v = A_project(A, v)
+        v = B.orth(A_project(A, v))
         v = v / A.norm(v)
         restarts += 1
 

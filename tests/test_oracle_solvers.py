@@ -183,3 +183,80 @@ def test_breakdown_falls_back_to_gmres():
     b = -SV.A_project(A, F)
     x, binfo = SV.bicgstab2(A, b, tol=1e-10, max_matvec=3000, stall_cycles=0)
     assert binfo["status"] in ("stagnation", "converged")
+
+
+def test_chebyshev_growth_rate_and_restart_weights():
+    """growth_rate is the per-degree growth of the filter polynomial: on a
+    scalar operator the filter's value at two points outside the ellipse
+    approaches (rate_1 / rate_2)^degree (real and complex points, b < a and
+    b > a).  The restart weights undo that growth."""
+    class Scalar:
+        def __init__(self, lam):
+            self.lam = lam
+
+        def __call__(self, v):
+            return self.lam * v
+
+    for a, b in ((1.0, 0.5), (1.0, 2.0)):
+        c2 = a * a - b * b
+        for lam in (3.0, 1.5 + 2.5j, -4.0):
+            deg = 200
+            wr = 2.0 * a + 0.5
+            p = SV.cheb_filter(Scalar(lam), np.array([1.0 + 0j]), 0.0, c2, wr, deg)[0]
+            # the filter is normalized to 1 at wr
+            est = deg * np.log(SV.growth_rate(lam, a, b, c2) / SV.growth_rate(wr, a, b, c2))
+            assert abs(np.log(abs(p)) - est) < 1.5, (a, b, lam, np.log(abs(p)), est)
+    # restart weights: filtering the weighted wanted components of a diagonal
+    # operator leaves them of comparable size (within the same constant)
+    lam = np.array([8.0, 3.0, 1.5 + 2.5j, 1.5 - 2.5j])
+    a, b = 1.0, 0.5
+    c2 = a * a - b * b
+    wr, deg = 2.5, 150
+    wts = SV.restart_weights(lam, 0.0, a, b, c2, wr, deg)
+    assert wts.max() == 1.0 and wts[0] < 1e-40
+    out = SV.cheb_filter(Scalar(lam), wts.astype(complex), 0.0, c2, wr, deg)
+    assert np.max(np.abs(np.log(np.abs(out) / np.abs(out[1])))) < 3.0, out
+    assert np.array_equal(SV.restart_weights(lam, 0.0, a, b, c2, wr, 0), np.ones(4))
+
+
+class ClassOperator(SV.Operator):
+    """P J restricted to a symmetry class: the class projection after P J."""
+
+    def __init__(self, g, X0, cls):
+        super().__init__(g, X0)
+        self.cls = cls
+
+    def __call__(self, x):
+        return O.symmetry_project(self.g, super().__call__(x), *self.cls)
+
+
+def test_locked_cheb_arnoldi_in_a_symmetry_class():
+    """At a symmetric base flow, Arnoldi on one symmetry class returns the
+    leading eigenvalues of the saddle problem whose eigenvectors lie in that
+    class.  Here the leading pair converges cycles before the next one and is
+    locked, and the returned vectors are eigenvectors of A."""
+    f = [S.faces_clustered(n) for n in (5, 7, 5)]
+    g = O.Grid(*f, Gr=2e4, Pr=0.71)
+    X0 = O.symmetry_project(g, S.base_flow(*f, K=2, amp=0.3, seed=21), 1, 1)
+    J, D, G = saddle(g, X0)
+    D, G = D[:-1], G[:, :-1]
+    n, C = g.size, g.ncell - 1
+    lam, vec = sl.eig(np.block([[J, -G], [D, np.zeros((C, C))]]),
+                      np.block([[np.eye(n), np.zeros((n, C))], [np.zeros((C, n + C))]]))
+    cls = (-1, 1)
+    keep = [q for q in range(len(lam)) if np.isfinite(lam[q]) and np.linalg.norm(
+        O.symmetry_project(g, vec[:n, q].real, *cls) + 1j * O.symmetry_project(g, vec[:n, q].imag, *cls)
+        - vec[:n, q]) <= 1e-6 * np.linalg.norm(vec[:n, q])]
+    ref = lam[keep][np.argsort(-lam[keep].real, kind="stable")]
+    A = ClassOperator(g, X0, cls)
+    vals, res, Y, info = SV.cheb_arnoldi(A, O.symmetry_project(g, S.perturbation(g.size, 77), *cls), m=30,
+                                         n_eigs=4, tol=1e-11, max_matvec=20000, cheb_degree_max=300)
+    assert info["converged"] and info["locked"] >= 2, info
+    scale = np.max(np.abs(ref[:4]))
+    assert closest_match(vals, ref[:6]) < 1e-8 * scale
+    assert closest_match(ref[:4], vals) < 1e-8 * scale
+    for i in range(len(vals)):
+        y = Y[i]
+        r = A(y.real) + 1j * A(y.imag) - vals[i] * y
+        assert np.sqrt(A.norm(r.real) ** 2 + A.norm(r.imag) ** 2) <= 1e-8 * scale * np.sqrt(
+            A.norm(y.real) ** 2 + A.norm(y.imag) ** 2)
