@@ -127,6 +127,30 @@ int kv_axpby(kv_ctx* ctx, double a, const double* x, double b, double* y);
  * state X (device), over cell-centred theta = T - (1 - x).  host out[3]. */
 int kv_symmetry_measures(kv_ctx* ctx, const double* X, double out[3]);
 
+/* Symmetry classes of perturbations (Sec. 2, Eqs. 7-9; Sec. 4.1 tells the
+ * two leading eigenmodes apart by them).  The cube is invariant under the reflection
+ * y -> 1-y, (u,v,w,T) -> (u,-v,w,T), the 2-D rotation (x,z) -> (1-x,1-z),
+ * (u,v,w,T) -> (-u,v,-w,-T), and their product, the 3-D centro-symmetry,
+ * (u,v,w,T) -> -(u,v,w,T), each field read at the mirrored point (T centred).
+ * A perturbation is EVEN under a map S if S x = x and ODD if S x = -x; its
+ * centro-symmetry sign is the product of the other two.  At a base flow with
+ * all three symmetries P J commutes with the maps and each eigenvector lies
+ * in one class.  Give at most one bit per map; a map with no bit is free. */
+enum kv_symmetry_class {
+  KV_SYM_REF_EVEN = 1u << 4,  /* reflection kept */
+  KV_SYM_REF_ODD = 1u << 5,   /* reflection broken (antisymmetric) */
+  KV_SYM_ROT_EVEN = 1u << 6,  /* 2-D rotation kept */
+  KV_SYM_ROT_ODD = 1u << 7    /* 2-D rotation broken (antisymmetric) */
+};
+
+/* y = Pi x, Pi the W-orthogonal projection onto the class given by sym: the
+ * product over the restricted maps of (I + e S)/2, e = +1 (EVEN) or -1 (ODD).
+ * x, y: device, packed, n values; y may equal x.  KV_EINVAL on bad bits or
+ * when a restricted map mirrors an axis whose cell widths are not mirror-
+ * symmetric (to 1e-12 of the largest width).  Needs no base flow.  Memory
+ * bound: one read and one write of the vector. */
+int kv_symmetry_project(kv_ctx* ctx, const double* x, double* y, unsigned sym);
+
 typedef struct {
   int matvecs;      /* applications of P J */
   int cycles;       /* BiCGstab(2) cycles plus GMRES restarts */
@@ -180,7 +204,10 @@ typedef struct {
   double tol;           /* converged when every wanted Ritz residual
                            <= tol * max |wanted Ritz value| */
   const double* v0;     /* device, n values: start vector (projected first) */
-  unsigned flags;       /* 0 (KV_MIXED is reserved) */
+  unsigned flags;       /* 0, or KV_SYM_* bits: restrict the Krylov space
+                           to that symmetry class (v0, every P J x and every
+                           restart vector projected onto it); meaningful at
+                           a base flow with all three symmetries */
 } kv_arnoldi_params;
 
 typedef struct {

@@ -362,6 +362,9 @@ def cheb_arnoldi(A: Operator, v0, m, n_eigs, tol=1e-8, max_matvec=100000,
             if not res[i] <= tol * scale:
                 break
             done.append(i)
+        if done and len(done) < len(sel) and vals[done[-1]].imag > 0 and \
+                abs(vals[sel[len(done)]] - np.conj(vals[done[-1]])) <= 1e-12 * max(1.0, abs(vals[done[-1]])):
+            done.append(sel[len(done)])    # a pair stays whole
         conv = len(done) == len(sel) or k < m
         stop = conv or A.matvecs - m0 >= max_matvec or restarts >= max_restarts
         for i in (sel if stop else done):
@@ -379,8 +382,7 @@ def cheb_arnoldi(A: Operator, v0, m, n_eigs, tol=1e-8, max_matvec=100000,
                     Q = np.vstack([Q, q / A.norm(q)])
         if stop or len(lk_vals) >= n_eigs:
             idx = wanted_set(np.array(lk_vals), n_eigs)
-            info = dict(matvecs=A.matvecs - m0, restarts=restarts, converged=conv or len(lk_vals) >= n_eigs,
-                        locked=len(Q))
+            info = dict(matvecs=A.matvecs - m0, restarts=restarts, converged=conv or not stop, locked=len(Q))
             return (np.array(lk_vals)[idx], np.array(lk_res)[idx], np.array(lk_vecs)[idx], info)
         rest = [i for i in sel if i not in done]
         # filter: an ellipse around the unwanted Ritz values and a degree

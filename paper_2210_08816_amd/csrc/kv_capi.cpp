@@ -308,11 +308,70 @@ int apply_operator(kv_ctx* c, const double* x, double* y) {
   return KV_OK;
 }
 
+// y <- (I - Q Q^T W) y over the locked vectors Q (classical Gram-Schmidt
+// twice, no host synchronization); nothing while none are locked.
+int deflate(kv_ctx* c, double* y) {
+  for (int pass = 0; c->nlock > 0 && pass < 2; ++pass) {
+    HIPCHK(c, launch_mdot(c, c->lockQ, c->g.n, c->nlock, y));
+    HIPCHK(c, launch_mupdate(c, c->lockQ, c->g.n, c->nlock, c->dres, y));
+  }
+  return KV_OK;
+}
+
 int matvec(kv_ctx* c, const double* x, double* y) {
   int rc = apply_operator(c, x, y);
   if (rc) return rc;
-  return project_inplace(c, y);
+  if ((rc = project_inplace(c, y))) return rc;
+  if (c->sym_ref || c->sym_rot) HIPCHK(c, launch_symmetry_class(c, y, y, c->sym_ref, c->sym_rot));
+  return deflate(c, y);
 }
+
+// Class signs (+1 symmetric, -1 antisymmetric, 0 free) from KV_SYM_* bits;
+// false on an unknown bit or both signs of one map.
+bool sym_class(unsigned sym, int* e_ref, int* e_rot) {
+  const unsigned all = KV_SYM_REF_EVEN | KV_SYM_REF_ODD | KV_SYM_ROT_EVEN | KV_SYM_ROT_ODD;
+  if (sym & ~all) return false;
+  if ((sym & KV_SYM_REF_EVEN) && (sym & KV_SYM_REF_ODD)) return false;
+  if ((sym & KV_SYM_ROT_EVEN) && (sym & KV_SYM_ROT_ODD)) return false;
+  *e_ref = (sym & KV_SYM_REF_EVEN) ? 1 : (sym & KV_SYM_REF_ODD) ? -1 : 0;
+  *e_rot = (sym & KV_SYM_ROT_EVEN) ? 1 : (sym & KV_SYM_ROT_ODD) ? -1 : 0;
+  return true;
+}
+
+// Widths mirror-symmetric about the axis midpoint (to 1e-12 of the largest).
+bool mirror_axis(const kv_ctx* c, int a) {
+  const std::vector<double>& f = c->hf[a];
+  const int n = (int)f.size() - 1;
+  double hmax = 0.0;
+  for (int i = 0; i < n; ++i) hmax = std::max(hmax, f[i + 1] - f[i]);
+  for (int i = 0; i < n; ++i)
+    if (std::fabs((f[i + 1] - f[i]) - (f[n - i] - f[n - 1 - i])) > 1e-12 * hmax) return false;
+  return true;
+}
+
+int check_sym(kv_ctx* c, unsigned sym, int* e_ref, int* e_rot) {
+  if (!sym_class(sym, e_ref, e_rot)) return fail(c, KV_EINVAL, "bad symmetry-class flags");
+  if ((*e_ref && !mirror_axis(c, 1)) || (*e_rot && !(mirror_axis(c, 0) && mirror_axis(c, 2))))
+    return fail(c, KV_EINVAL, "symmetry class needs a grid mirror-symmetric along the mirrored axes");
+  return KV_OK;
+}
+
+// Keeps matvec in a symmetry class and deflated by the locked vectors for
+// one eigen-solve, cleared on every exit.
+struct EigScope {
+  kv_ctx* c;
+  EigScope(kv_ctx* cc, int er, int eo, const double* Q) : c(cc) {
+    c->sym_ref = er;
+    c->sym_rot = eo;
+    c->lockQ = Q;
+    c->nlock = 0;
+  }
+  ~EigScope() {
+    c->sym_ref = c->sym_rot = 0;
+    c->lockQ = nullptr;
+    c->nlock = 0;
+  }
+};
 
 // y = M^-1 x of the Stokes/heat preconditioner: per block the Helmholtz
 // solve (sigma - nu Lap_v) or (sigma - kappa Lap_T), then P on the velocity.
@@ -533,9 +592,16 @@ void ellipse(const std::vector<std::complex<double>>& unw, double wanted_min_re,
   *c2 = (*a) * (*a) - b2;
 }
 
+// Growth per degree of the ellipse's Chebyshev polynomial at z (from the
+// centre) against its size on the ellipse: the larger root of w^2 - 2zw + c^2.
+double growth_rate(std::complex<double> z, double a, double b, double c2) {
+  const std::complex<double> s = std::sqrt(z * z - c2);
+  return std::max(std::abs(z + s), std::abs(z - s)) / (a + b);
+}
+
+// Smallest degree with growth 1e6 at wr, at most dmax.
 int cheb_degree(double wr, double a, double b, double c2, int dmax) {
-  const std::complex<double> s = std::sqrt(std::complex<double>(wr * wr - c2, 0.0));
-  const double ratio = std::max(std::abs(wr + s), std::abs(wr - s)) / (a + b);
+  const double ratio = growth_rate(wr, a, b, c2);
   if (ratio <= 1.0 + 1e-12) return 0;
   const int d = (int)std::ceil(std::log(1e6) / std::log(ratio));
   return std::min(dmax, std::max(1, d));
@@ -794,6 +860,15 @@ int kv_axpby(kv_ctx* c, double a, const double* x, double b, double* y) {
   if (!x || !y) return fail(c, KV_EINVAL, "null argument");
   if (!std::isfinite(a) || !std::isfinite(b)) return fail(c, KV_EINVAL, "non-finite coefficient");
   return lincomb(c, 2, {a, b}, {x, y}, y);
+}
+
+int kv_symmetry_project(kv_ctx* c, const double* x, double* y, unsigned sym) {
+  if (!c) return KV_EINVAL;
+  if (!x || !y) return fail(c, KV_EINVAL, "null argument");
+  int er = 0, eo = 0, rc;
+  if ((rc = check_sym(c, sym, &er, &eo))) return rc;
+  HIPCHK(c, launch_symmetry_class(c, x, y, er, eo));
+  return KV_OK;
 }
 
 int kv_symmetry_measures(kv_ctx* c, const double* X, double out[3]) {
@@ -1284,28 +1359,40 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
                             double* resid, kv_eig_info* info) {
   if (!c) return KV_EINVAL;
   if (!p || !lam_re || !lam_im || !p->v0) return fail(c, KV_EINVAL, "null argument");
-  if (p->flags != 0) return fail(c, KV_EINVAL, "unsupported flags");
+  int sym_ref = 0, sym_rot = 0, rc;
+  if ((rc = check_sym(c, p->flags, &sym_ref, &sym_rot))) return rc;
   const int m = p->krylov_dim;
   if (m < 2 || m > 400 || p->n_eigs < 1 || p->n_eigs >= m || p->max_matvec < m || p->max_restarts < 0)
     return fail(c, KV_EINVAL, "bad Arnoldi parameters");
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   const int64_t n = c->g.n;
-  int rc;
   if ((rc = check_finite(c, p->v0, n, "v0"))) return rc;
-  // workspace: V (m+1 vectors) + z_prev, z, tmp
-  if ((rc = ensure_work(c, (size_t)m + 4))) return rc;
+  // workspace: V (m+1 vectors) + z_prev, z, tmp + up to n_eigs+1 locked vectors
+  if ((rc = ensure_work(c, (size_t)m + 5 + p->n_eigs))) return rc;
   double* V = c->work;
   double* zp = c->work + (int64_t)(m + 1) * n;
   double* zc = zp + n;
   double* tmp = zc + n;
+  double* L = tmp + n;
+  EigScope scope(c, sym_ref, sym_rot, L);
+  // the start vector in range(P), in the class, W-orthogonal to the locked vectors
+  auto settle = [&](double* v) -> int {
+    int r;
+    if ((r = project_inplace(c, v))) return r;
+    if (sym_ref || sym_rot) HIPCHK(c, launch_symmetry_class(c, v, v, sym_ref, sym_rot));
+    return deflate(c, v);
+  };
   HIPCHK(c, hipMemcpyAsync(V, p->v0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  if ((rc = project_inplace(c, V))) return rc;
+  if ((rc = settle(V))) return rc;
   int matvecs = 0, restarts = 0;
   std::vector<double> H;
   Ritz rz;
   bool conv = false;
+  // locked eigenvalues and their residual estimates when locked
+  std::vector<std::complex<double>> lk_vals;
+  std::vector<double> lk_res;
   // KV_ARNOLDI_TRACE=1: one line per restart on stderr (residual, ellipse,
-  // filter degree, wanted Ritz values)
+  // filter degree, wanted Ritz values, locked count)
   const char* ev = getenv("KV_ARNOLDI_TRACE");
   const bool trace = ev && atoi(ev) != 0;
   for (;;) {
@@ -1314,28 +1401,55 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     if (!(vn > 0) || !std::isfinite(vn)) return fail(c, KV_ENONFINITE, "zero or non-finite start vector");
     if ((rc = lincomb(c, 1, {1.0 / vn}, {V}, V))) return rc;
     int k = 0;
-    if ((rc = arnoldi(c, V, m, H, &k, &matvecs)) || (rc = ritz(c, H, m, k, p->n_eigs, rz))) {
+    if ((rc = arnoldi(c, V, m, H, &k, &matvecs)) ||
+        (rc = ritz(c, H, m, k, p->n_eigs - (int)lk_vals.size(), rz))) {
       if (info) *info = kv_eig_info{0, matvecs, restarts, 0};  // the work done so far
       return rc;
     }
     double scale = 0.0;
     for (int i : rz.sel) scale = std::max(scale, std::abs(rz.vals[i]));
-    conv = true;
-    for (double r : rz.res)
-      if (!(r <= p->tol * scale)) conv = false;
-    if (k < m) conv = true;  // invariant subspace found
-    if (conv || matvecs >= p->max_matvec || restarts >= p->max_restarts) break;
-    // restart vector: sum of the real and imaginary parts of the wanted Ritz vectors
-    std::vector<double> coef(k, 0.0);
-    for (size_t q = 0; q < rz.sel.size(); ++q)
-      for (int r = 0; r < k; ++r) coef[r] += rz.vecs[q][r].real() + rz.vecs[q][r].imag();
-    for (int r = 0; r < k; ++r) coef[r] = -coef[r];
-    HIPCHK(c, launch_fill(c, n, 0.0, zc));
-    if ((rc = upload(c, c->dres, coef.data(), k * sizeof(double)))) return rc;
-    HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, zc));
-    double zn = std::sqrt(std::max(0.0, dot1(c, zc, zc, &rc)));
-    if (rc) return rc;
-    if ((rc = lincomb(c, 1, {1.0 / zn}, {zc}, zc))) return rc;
+    for (const auto& v : lk_vals) scale = std::max(scale, std::abs(v));
+    // converged prefix of the wanted set in leading order; a pair stays whole
+    // (its members' residual estimates agree to round-off)
+    size_t ndone = 0;
+    while (ndone < rz.sel.size() && rz.res[ndone] <= p->tol * scale) ++ndone;
+    if (ndone > 0 && ndone < rz.sel.size() && rz.vals[rz.sel[ndone - 1]].imag() > 0 &&
+        std::abs(rz.vals[rz.sel[ndone]] - std::conj(rz.vals[rz.sel[ndone - 1]])) <=
+            1e-12 * std::max(1.0, std::abs(rz.vals[rz.sel[ndone - 1]])))
+      ++ndone;
+    conv = ndone == rz.sel.size() || k < m;  // k < m: invariant subspace found
+    const bool stop = conv || matvecs >= p->max_matvec || restarts >= p->max_restarts;
+    // lock: converged values (or, at the end, all wanted ones) join the output;
+    // before a restart their real invariant subspaces join L
+    const size_t nout = stop ? rz.sel.size() : ndone;
+    for (size_t q = 0; q < nout; ++q) {
+      lk_vals.push_back(rz.vals[rz.sel[q]]);
+      lk_res.push_back(rz.res[q]);
+      if (stop || rz.vals[rz.sel[q]].imag() < 0) continue;  // a pair locks once, by its +Im member
+      const int parts = rz.vals[rz.sel[q]].imag() > 0 ? 2 : 1;
+      for (int part = 0; part < parts; ++part) {
+        double* dst = L + (int64_t)c->nlock * n;
+        std::vector<double> coef(k);
+        for (int r = 0; r < k; ++r) coef[r] = -(part == 0 ? rz.vecs[q][r].real() : rz.vecs[q][r].imag());
+        HIPCHK(c, launch_fill(c, n, 0.0, dst));
+        if ((rc = upload(c, c->dres, coef.data(), k * sizeof(double)))) return rc;
+        HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, dst));
+        if ((rc = deflate(c, dst))) return rc;
+        const double ln = std::sqrt(std::max(0.0, dot1(c, dst, dst, &rc)));
+        if (rc) return rc;
+        if (!(ln > 0) || !std::isfinite(ln)) return fail(c, KV_ENONFINITE, "degenerate locked vector");
+        if ((rc = lincomb(c, 1, {1.0 / ln}, {dst}, dst))) return rc;
+        ++c->nlock;
+      }
+    }
+    if (stop) break;
+    if ((int)lk_vals.size() >= p->n_eigs) {  // every wanted value locked
+      conv = true;
+      break;
+    }
+    // the wanted values still open
+    std::vector<int> rest(rz.sel.begin() + ndone, rz.sel.end());
+    // filter: an ellipse around the unwanted Ritz values and a degree
     std::vector<std::complex<double>> unw;
     for (int i = 0; i < k; ++i)
       if (std::find(rz.sel.begin(), rz.sel.end(), i) == rz.sel.end()) unw.push_back(rz.vals[i]);
@@ -1343,23 +1457,51 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     double d = 0, a = 0, bb = 0, c2 = 0, wr = 0;
     if (!unw.empty()) {
       double ref = 1e300;
-      for (int i : rz.sel) ref = std::min(ref, rz.vals[i].real());
+      for (int i : rest) ref = std::min(ref, rz.vals[i].real());
       ellipse(unw, ref, &d, &a, &bb, &c2);
       wr = ref - d;
       deg = cheb_degree(wr, a, bb, c2, p->cheb_degree_max);
       deg = std::min(deg, std::max(0, p->max_matvec - matvecs - m));
     }
+    // restart vector: sum of the real and imaginary parts of the open wanted
+    // Ritz vectors, each weighted by the inverse of its growth under the
+    // filter, growth_rate(lambda - d)^deg, relative to the least growing one;
+    // unweighted, a value far right of the ellipse outgrows the others by
+    // many orders and they sink to round-off in the filtered vector
+    std::vector<double> wts(rest.size(), 1.0);
+    if (deg > 0) {
+      std::vector<double> lg(rest.size());
+      double lmin = 1e300;
+      for (size_t q = 0; q < rest.size(); ++q) {
+        lg[q] = deg * std::log(growth_rate(rz.vals[rest[q]] - d, a, bb, c2));
+        lmin = std::min(lmin, lg[q]);
+      }
+      for (size_t q = 0; q < rest.size(); ++q) wts[q] = std::max(std::exp(lmin - lg[q]), 1e-300);
+    }
+    std::vector<double> coef(k, 0.0);
+    for (size_t q = 0; q < rest.size(); ++q)
+      for (int r = 0; r < k; ++r)
+        coef[r] += wts[q] * (rz.vecs[ndone + q][r].real() + rz.vecs[ndone + q][r].imag());
+    for (int r = 0; r < k; ++r) coef[r] = -coef[r];
+    HIPCHK(c, launch_fill(c, n, 0.0, zc));
+    if ((rc = upload(c, c->dres, coef.data(), k * sizeof(double)))) return rc;
+    HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, zc));
+    if ((rc = deflate(c, zc))) return rc;
+    double zn = std::sqrt(std::max(0.0, dot1(c, zc, zc, &rc)));
+    if (rc) return rc;
+    if ((rc = lincomb(c, 1, {1.0 / zn}, {zc}, zc))) return rc;
     if (trace) {
       double rmx = 0.0;
       for (double r : rz.res) rmx = std::max(rmx, r);
-      fprintf(stderr, "[arnoldi] restart %d matvecs %d res/scale %.3e  ellipse d %.4g a %.4g b %.4g  degree %d",
-              restarts, matvecs, rmx / scale, d, a, bb, deg);
+      fprintf(stderr, "[arnoldi] restart %d matvecs %d res/scale %.3e  ellipse d %.4g a %.4g b %.4g  degree %d  locked %d",
+              restarts, matvecs, rmx / scale, d, a, bb, deg, (int)lk_vals.size());
       for (size_t q = 0; q < rz.sel.size() && q < 4; ++q)
         fprintf(stderr, "  (%.6g, %.6g)", rz.vals[rz.sel[q]].real(), rz.vals[rz.sel[q]].imag());
       fprintf(stderr, "\n");
     }
     if (deg > 0) {
-      // z1 = r1 (A - d) z0, z_{j+1} = r_{j+1} (2 (A - d) z_j - c^2 r_j z_{j-1})
+      // z1 = r1 (A - d) z0, z_{j+1} = r_{j+1} (2 (A - d) z_j - c^2 r_j z_{j-1}),
+      // A deflated by the locked vectors (inside matvec)
       double rj = 1.0 / wr;
       HIPCHK(c, hipMemcpyAsync(zp, zc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
       if ((rc = matvec(c, zp, tmp))) return rc;
@@ -1378,16 +1520,17 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     // back into range(P): the filter's -d z term carries round-off onto gradient
     // fields, where A has the eigenvalue 0 (right of the wanted set)
     HIPCHK(c, hipMemcpyAsync(V, zc, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if ((rc = project_inplace(c, V))) return rc;
+    if ((rc = settle(V))) return rc;
     ++restarts;
   }
-  const int nout = (int)rz.sel.size();
-  for (int q = 0; q < nout; ++q) {
-    lam_re[q] = rz.vals[rz.sel[q]].real();
-    lam_im[q] = rz.vals[rz.sel[q]].imag();
-    if (resid) resid[q] = rz.res[q];
+  // the n_eigs leading of the locked values (a pair kept whole)
+  const std::vector<int> out = wanted_set(lk_vals, p->n_eigs);
+  for (size_t q = 0; q < out.size(); ++q) {
+    lam_re[q] = lk_vals[out[q]].real();
+    lam_im[q] = lk_vals[out[q]].imag();
+    if (resid) resid[q] = lk_res[out[q]];
   }
-  if (info) *info = kv_eig_info{nout, matvecs, restarts, conv ? 1 : 0};
+  if (info) *info = kv_eig_info{(int)out.size(), matvecs, restarts, conv ? 1 : 0};
   if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");
   return KV_OK;
 }

@@ -89,6 +89,9 @@ struct kv_ctx {
   int pc_kind = 0;            // KV_PC_NONE or KV_PC_STOKES
   double pc_sigma = 0.0;
   bool pc_active = false;     // set while a preconditioned solve runs
+  int sym_ref = 0, sym_rot = 0;  // symmetry class kept by matvec while a restricted Arnoldi runs
+  const double* lockQ = nullptr;  // locked W-orthonormal vectors matvec deflates while Arnoldi runs
+  int nlock = 0;
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events
@@ -123,7 +126,7 @@ hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* 
 // Weighted dot products over the packed layout.  npair <= 4 pairs (a_i, b_i);
 // results land in c->dres[0..npair).
 hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b);
-// res[i] = <V_i, w>_W for i < nvec (V row stride ldv), results in c->dres (nvec <= 64)
+// res[i] = <V_i, w>_W for i < nvec (V row stride ldv), results in c->dres (nvec <= 1024)
 hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w);
 // w -= sum_i h[i] V_i, h on the device (nvec values)
 hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w);
@@ -138,6 +141,8 @@ hipError_t launch_maxabs(kv_ctx* c, const double* a, int64_t n);
 hipError_t launch_div_measure(kv_ctx* c, const double* y);
 // dres[0..3) = R_ref, R_2D, R_3D of X
 hipError_t launch_symmetry(kv_ctx* c, const double* X);
+// y = projection of x onto a symmetry class; e_ref, e_rot in {-1, 0, +1}; y may equal x
+hipError_t launch_symmetry_class(kv_ctx* c, const double* x, double* y, int e_ref, int e_rot);
 
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
 // KV_FD_TILE=64 or 32: the tile shape every FD and Helmholtz GEMM pass must

@@ -828,6 +828,44 @@ __global__ void __launch_bounds__(256) symmetry_kernel(Grid g, const double* __r
     for (int q = 0; q < 3; ++q) part[3 * blockIdx.x + q] = s[q][0];
 }
 
+// Projection onto a symmetry class of perturbations (Sec. 2, Eqs. 7-9), one
+// packed field of extents (ex, ey, ez), x fastest.  R mirrors y, O mirrors x
+// and z; on a mirror-symmetric grid a mirrored face or cell is the reversed
+// index.  cr, co: the class sign times the field's sign under R, O (0 for a
+// map that is not restricted).  One thread owns the orbit {p, Rp, Op, ROp},
+// reads all of it before writing it, and no two threads share an orbit, so
+// y may equal x.  Points fixed by a map (middle rows) come out as the
+// definition gives: zero where the class is odd there.
+__global__ void __launch_bounds__(256) symmetry_class_kernel(const double* x, double* y, int ex, int ey, int ez,
+                                                             double cr, double co) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int j = blockIdx.y * 4 + threadIdx.y;
+  const int k = blockIdx.z;
+  const int im = ex - 1 - i, jm = ey - 1 - j, km = ez - 1 - k;
+  if (i >= ex || j > jm || k > km || (k == km && i > im)) return;
+  const int64_t pp = ((int64_t)k * ey + j) * ex + i;
+  const int64_t pr = ((int64_t)k * ey + jm) * ex + i;
+  const int64_t po = ((int64_t)km * ey + j) * ex + im;
+  const int64_t pro = ((int64_t)km * ey + jm) * ex + im;
+  double a = x[pp], b = x[pr], c = x[po], d = x[pro];
+  if (cr != 0.0) {
+    a = 0.5 * (a + cr * b);
+    b = cr * a;
+    c = 0.5 * (c + cr * d);
+    d = cr * c;
+  }
+  if (co != 0.0) {
+    a = 0.5 * (a + co * c);
+    c = co * a;
+    b = 0.5 * (b + co * d);
+    d = co * b;
+  }
+  y[pp] = a;
+  y[pr] = b;
+  y[po] = c;
+  y[pro] = d;
+}
+
 __global__ void max_finish_kernel(const double* __restrict__ part, int nblk, int nq, double* __restrict__ out) {
   __shared__ double s[256];
   const int t = threadIdx.x;
@@ -931,6 +969,23 @@ hipError_t launch_symmetry(kv_ctx* c, const double* X) {
   const int nblk = c->npart_blocks;
   symmetry_kernel<<<nblk, 256, 0, c->stream>>>(c->g, X, c->g.ax[0].c, c->part);
   max_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, 3, c->dres);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetry_class(kv_ctx* c, const double* x, double* y, int e_ref, int e_rot) {
+  const Grid& g = c->g;
+  const int ext[4][3] = {{g.nx - 1, g.ny, g.nz}, {g.nx, g.ny - 1, g.nz}, {g.nx, g.ny, g.nz - 1}, {g.nx, g.ny, g.nz}};
+  const int64_t off[4] = {g.ou, g.ov, g.ow, g.oT};
+  // field signs under the reflection y -> 1-y and the rotation (x,z) -> (1-x,1-z)
+  const double s_ref[4] = {1.0, -1.0, 1.0, 1.0};
+  const double s_rot[4] = {-1.0, 1.0, -1.0, -1.0};
+  for (int f = 0; f < 4; ++f) {
+    const int ex = ext[f][0], ey = ext[f][1], ez = ext[f][2];
+    if (ex <= 0 || ey <= 0 || ez <= 0) continue;
+    const dim3 grid((ex + 63) / 64, ((ey + 1) / 2 + 3) / 4, (ez + 1) / 2);
+    symmetry_class_kernel<<<grid, dim3(64, 4, 1), 0, c->stream>>>(x + off[f], y + off[f], ex, ey, ez,
+                                                                   e_ref * s_ref[f], e_rot * s_rot[f]);
+  }
   return hipGetLastError();
 }
 

@@ -19,12 +19,24 @@ LIB_PATH = os.path.join(HERE, "libkv_hip.so")
 KV_OK, KV_EINVAL, KV_ENOMEM, KV_EDEVICE, KV_ENOCONV, KV_ENONFINITE, KV_ESTATE = range(7)
 KV_PROJECT, KV_MIXED = 1, 2
 KV_PC_NONE, KV_PC_STOKES = 0, 1
+KV_SYM_REF_EVEN, KV_SYM_REF_ODD, KV_SYM_ROT_EVEN, KV_SYM_ROT_ODD = 1 << 4, 1 << 5, 1 << 6, 1 << 7
+
+
+def sym_flags(cls):
+    """KV_SYM_* bits of a symmetry class (e_ref, e_rot), each +1 (kept),
+    -1 (broken) or 0 (free); None is the unrestricted space."""
+    if cls is None:
+        return 0
+    e_ref, e_rot = cls
+    bits = {1: KV_SYM_REF_EVEN, -1: KV_SYM_REF_ODD, 0: 0}[e_ref]
+    return bits | {1: KV_SYM_ROT_EVEN, -1: KV_SYM_ROT_ODD, 0: 0}[e_rot]
 STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: "KV_ENOCONV",
                 5: "KV_ENONFINITE", 6: "KV_ESTATE"}
 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
+               "kv_symmetry_project",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -82,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.kv_dot.argtypes = [P, P, P, PD]
     lib.kv_axpby.argtypes = [P, D, P, D, P]
     lib.kv_symmetry_measures.argtypes = [P, P, PD]
+    lib.kv_symmetry_project.argtypes = [P, P, P, ctypes.c_uint]
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
@@ -214,6 +227,13 @@ class Context:
         self._check(self._lib.kv_symmetry_measures(self._h, _dptr(X, self.n), out))
         return tuple(out)
 
+    def symmetry_project(self, x, y=None, cls=(1, 1)):
+        """y = projection of x onto the symmetry class cls = (e_ref, e_rot)
+        (see sym_flags); in place when y is None."""
+        y = x if y is None else y
+        self._check(self._lib.kv_symmetry_project(self._h, _dptr(x, self.n), _dptr(y, self.n), sym_flags(cls)))
+        return y
+
     def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True):
         info = _SolveInfo()
         d0 = _dptr(delta0, self.n) if delta0 is not None else None
@@ -266,9 +286,11 @@ class Context:
                                                           rz, *pc, psc, _dptr(X, self.n)))
 
     def arnoldi_leading_eigs(self, v0, krylov_dim, n_eigs, tol=1e-8, max_matvec=100000,
-                             max_restarts=1000, cheb_degree_max=200, check=True):
+                             max_restarts=1000, cheb_degree_max=200, sym=None, check=True):
+        """sym: a symmetry class (e_ref, e_rot) to restrict the Krylov space
+        to (see sym_flags), or None."""
         p = _ArnoldiParams(int(krylov_dim), int(n_eigs), int(max_matvec), int(max_restarts),
-                           int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, 0)
+                           int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, sym_flags(sym))
         re = (ctypes.c_double * (n_eigs + 1))()
         im = (ctypes.c_double * (n_eigs + 1))()
         res = (ctypes.c_double * (n_eigs + 1))()

@@ -2,9 +2,12 @@
 continuation in Gr to a target value, then the leading eigenvalues of the
 Jacobian at the converged state by Chebyshev-preconditioned Arnoldi
 iteration (the paper's method, Sec. 1 and Sec. 3).  Reports the wall time
-and matvec count of each stage.
+and matvec count of each stage.  With --sym the Arnoldi iteration runs once
+per symmetry class of perturbations (Sec. 2, Eqs. 7-9), its Krylov space
+restricted to the class.
 
     python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --krylov 60 --eigs 10
+    python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --sym all
 """
 from __future__ import annotations
 
@@ -18,9 +21,11 @@ from .continuation import sweep
 
 
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
-        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, log=print):
+        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, log=print):
     """state: a converged packed state at Gr (host array) to start from
-    instead of continuation; save_state: file to store the converged state."""
+    instead of continuation; save_state: file to store the converged state;
+    sym: None (one unrestricted Arnoldi run) or a list of symmetry classes
+    (e_ref, e_rot), one restricted run each."""
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
     f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
@@ -56,14 +61,22 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
         ctx.set_base_flow(X)
         F = torch.empty_like(X)
         fn = ctx.residual(F)
-        sym = ctx.symmetry_measures(X)
+        meas = ctx.symmetry_measures(X)
         v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(ctx.n)).cuda()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
-                                                   cheb_degree_max=cheb_degree_max, check=False)
-        torch.cuda.synchronize()
-        t_eig = time.perf_counter() - t1
+        runs = []
+        for cls in (sym or [None]):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
+                                                       cheb_degree_max=cheb_degree_max, sym=cls, check=False)
+            torch.cuda.synchronize()
+            t_eig = time.perf_counter() - t1
+            runs.append({"symmetry_class": list(cls) if cls else None, "krylov_dim": krylov, "n_eigs": n_eigs,
+                         "tol": tol, "seconds": round(t_eig, 3), "matvecs": info["matvecs"],
+                         "restarts": info["restarts"], "converged": info["converged"], "status": info["status"],
+                         "eigenvalues": [[float(v.real), float(v.imag)] for v in vals],
+                         "residuals": [float(r) for r in res]})
+            log(json.dumps(runs[-1]))
     finally:
         ctx.close()
     if cont is not None:
@@ -71,13 +84,24 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
     return {
         "grid": f"{n}^3 {grid}", "Gr": Gr, "Pr": Pr, "unknowns": int(X.numel()), "residual": fn,
         "continuation": cont,
-        "symmetry_measures": list(sym),
-        "arnoldi": {"krylov_dim": krylov, "n_eigs": n_eigs, "tol": tol, "seconds": round(t_eig, 3),
-                    "matvecs": info["matvecs"], "restarts": info["restarts"], "converged": info["converged"],
-                    "status": info["status"],
-                    "eigenvalues": [[float(v.real), float(v.imag)] for v in vals],
-                    "residuals": [float(r) for r in res]},
+        "symmetry_measures": list(meas),
+        "arnoldi": runs[0] if sym is None else runs,
     }
+
+
+def parse_sym(text):
+    """'all' or '+-,--' style sign pairs (reflection, 2-D rotation) -> classes."""
+    if not text:
+        return None
+    if text == "all":
+        return [(1, 1), (1, -1), (-1, 1), (-1, -1)]
+    sign = {"+": 1, "-": -1, "0": 0}
+    out = []
+    for pair in text.split(","):
+        if len(pair) != 2 or any(ch not in sign for ch in pair):
+            raise ValueError(f"bad symmetry class {pair!r}")
+        out.append((sign[pair[0]], sign[pair[1]]))
+    return out
 
 
 def main(argv=None):
@@ -95,11 +119,14 @@ def main(argv=None):
     ap.add_argument("--json", default=None)
     ap.add_argument("--save-state", default=None, help="store the converged state (.npy)")
     ap.add_argument("--load-state", default=None, help="start from a stored converged state (.npy)")
+    ap.add_argument("--sym", default=None,
+                    help="symmetry classes for restricted Arnoldi runs: 'all', or a comma list of sign pairs "
+                         "(reflection, 2-D rotation) such as '+-,--'")
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
               max_matvec=a.max_matvec, precond_sigma=None if a.sigma < 0 else a.sigma, state=state,
-              save_state=a.save_state, log=lambda m: print(m, flush=True))
+              save_state=a.save_state, sym=parse_sym(a.sym), log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
         with open(a.json, "w") as fh:

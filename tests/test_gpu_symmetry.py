@@ -1,0 +1,204 @@
+"""GPU parity of the symmetry-class projection and of Arnoldi restricted to a
+symmetry class (Sec. 2, Eqs. 7-9; the two leading modes of Sec. 4.1 differ
+by class).
+
+The projection is sign flips, one add and a halving per restricted map, in
+the oracle's order, so it is compared bit for bit, out of place and in place.
+Restricted Arnoldi is compared with the eigenvalues of the dense saddle-point
+problem whose eigenvectors lie in the class (to 1e-8 of the largest wanted
+modulus), at a base flow made symmetric by the oracle's projection.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+torch = pytest.importorskip("torch")
+
+from oracle import disc as O  # noqa: E402
+from synth import inputs as S  # noqa: E402
+from tests.gpu_util import faces, to_dev, to_host  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = [(e_ref, e_rot) for e_ref in (1, -1, 0) for e_rot in (1, -1, 0)]
+
+
+def make_ctx(fx, Gr=2e4, Pr=0.71):
+    from paper_2210_08816_amd import kv
+    return kv.Context(*fx, Gr=Gr, Pr=Pr)
+
+
+# several 64-wide tiles with a ragged tail, odd extents (middle rows and
+# planes fixed by a map), a minimal grid
+@pytest.mark.parametrize("kind,shape", [
+    ("clustered", (8, 7, 6)),
+    ("uniform", (7, 12, 8)),
+    ("clustered", (131, 9, 17)),
+    ("uniform", (66, 33, 5)),
+    ("clustered", (2, 2, 2)),
+])
+def test_symmetry_project_bit_exact(kind, shape):
+    fx = [faces(kind, n) for n in shape]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    ctx = make_ctx(fx)
+    try:
+        x = S.perturbation(g.size, 41)
+        xd = to_dev(x)
+        for cls in CLASSES:
+            print(f"symmetry class {cls} on {shape} {kind}", flush=True)
+            ref = O.symmetry_project(g, x, *cls)
+            y = torch.full_like(xd, np.nan)
+            ctx.symmetry_project(xd, y, cls)
+            assert np.array_equal(to_host(y), ref), cls
+            z = xd.clone()
+            ctx.symmetry_project(z, None, cls)
+            assert np.array_equal(to_host(z), ref), cls
+        assert np.array_equal(to_host(xd), x)
+    finally:
+        ctx.close()
+
+
+def test_symmetry_project_at_256():
+    """The 256^3 clustered grid of the Krylov-vector throughput workload."""
+    fx = [S.faces_clustered(256)] * 3
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    ctx = make_ctx(fx)
+    try:
+        x = S.perturbation(g.size, 43)
+        xd = to_dev(x)
+        for cls in [(1, -1), (-1, -1)]:
+            ctx.symmetry_project(xd, None, cls)
+            x = O.symmetry_project(g, x, *cls)
+            assert np.array_equal(to_host(xd), x), cls
+    finally:
+        ctx.close()
+
+
+def test_symmetry_project_rejects_bad_input():
+    from paper_2210_08816_amd import kv
+    fx = [S.faces_uniform(6)] * 3
+    ctx = make_ctx(fx)
+    x = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
+    try:
+        for bits in (kv.KV_SYM_REF_EVEN | kv.KV_SYM_REF_ODD, kv.KV_SYM_ROT_EVEN | kv.KV_SYM_ROT_ODD, 1 << 9):
+            rc = ctx._lib.kv_symmetry_project(ctx._h, x.data_ptr(), x.data_ptr(), bits)
+            assert rc == kv.KV_EINVAL, bits
+    finally:
+        ctx.close()
+    # y-axis widths not mirror-symmetric: the reflection is refused, the rotation is not
+    fy = np.array([0.0, 0.1, 0.3, 0.6, 1.0])
+    fx = [S.faces_uniform(6), fy, S.faces_uniform(4)]
+    ctx = make_ctx(fx)
+    x = torch.zeros(ctx.n, dtype=torch.float64, device="cuda")
+    try:
+        assert ctx._lib.kv_symmetry_project(ctx._h, x.data_ptr(), x.data_ptr(), kv.KV_SYM_REF_EVEN) == kv.KV_EINVAL
+        ctx.symmetry_project(x, None, (0, -1))
+    finally:
+        ctx.close()
+
+
+def saddle_eigs_by_class(g, X0):
+    """Finite eigenvalues of the saddle-point problem J x - G p = lam x,
+    D x = 0, each with the class (e_ref, e_rot) its eigenvector lies in
+    (None if it lies in no single class)."""
+    def dense(fn, nin):
+        cols = []
+        for i in range(nin):
+            e = np.zeros(nin)
+            e[i] = 1.0
+            cols.append(np.ravel(fn(e)))
+        return np.array(cols).T
+    J = dense(lambda v: O.jacobian(g, X0, v), g.size)
+    D = dense(lambda v: O.divergence(g, v), g.size)[:-1]
+    G = dense(lambda p: O.gradient(g, p.reshape(g.shapes[3])), g.ncell)[:, :-1]
+    n, C = g.size, g.ncell - 1
+    Am = np.block([[J, -G], [D, np.zeros((C, C))]])
+    Bm = np.zeros_like(Am)
+    Bm[:n, :n] = np.eye(n)
+    lam, vec = sl.eig(Am, Bm)
+    keep = np.isfinite(lam)
+    lam, vec = lam[keep], vec[:n, keep]
+    cls = []
+    for q in range(len(lam)):
+        v = vec[:, q]
+        nv = np.linalg.norm(v)
+        found = None
+        for c in [(1, 1), (1, -1), (-1, 1), (-1, -1)]:
+            pv = O.symmetry_project(g, v.real, *c) + 1j * O.symmetry_project(g, v.imag, *c)
+            if np.linalg.norm(pv - v) <= 1e-6 * nv:
+                found = c
+        cls.append(found)
+    return lam, cls
+
+
+def closest(a, b):
+    return max(np.min(np.abs(np.asarray(b) - x)) for x in a)
+
+
+# in (5, 7, 5), class (-1, 1), the leading pair converges cycles before the
+# next one and is locked
+@pytest.mark.parametrize("kind,shape", [("clustered", (6, 6, 4)), ("clustered", (5, 7, 5)), ("uniform", (7, 6, 5))])
+def test_arnoldi_restricted_to_each_class(kind, shape):
+    fx = [faces(kind, n) for n in shape]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    X0 = O.symmetry_project(g, S.base_flow(*fx, K=2, amp=0.3, seed=21), 1, 1)
+    assert max(O.symmetry_measures(g, X0)) < 1e-14
+    lam, cls = saddle_eigs_by_class(g, X0)
+    assert sum(c is None for c in cls) == 0
+    ctx = make_ctx(fx)
+    try:
+        ctx.set_base_flow(to_dev(X0))
+        for c in [(1, 1), (1, -1), (-1, 1), (-1, -1)]:
+            print(f"restricted Arnoldi, class {c}, {shape} {kind}", flush=True)
+            ref = np.array([lam[q] for q in range(len(lam)) if cls[q] == c])
+            ref = ref[np.argsort(-ref.real, kind="stable")]
+            vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=30,
+                                                       n_eigs=4, tol=1e-11, max_matvec=20000,
+                                                       cheb_degree_max=300, sym=c)
+            assert info["converged"], (c, info)
+            scale = np.max(np.abs(ref[:4]))
+            assert closest(vals, ref[:6]) <= 1e-8 * scale, (c, vals, ref[:6])
+            assert closest(ref[:4], vals) <= 1e-8 * scale, (c, vals, ref[:6])
+    finally:
+        ctx.close()
+
+
+def test_arnoldi_rejects_bad_symmetry_flags():
+    from paper_2210_08816_amd import kv
+    fx = [S.faces_uniform(6)] * 3
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    ctx = make_ctx(fx)
+    try:
+        ctx.set_base_flow(to_dev(S.conduction_state(*fx)))
+        vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 7)), 10, 2, max_restarts=0,
+                                                   check=False, sym=None)
+        assert info["status"] == kv.KV_OK
+        v0 = to_dev(S.perturbation(g.size, 7))
+        p = kv._ArnoldiParams(10, 2, 1000, 0, 100, 1e-8, v0.data_ptr(), kv.KV_SYM_REF_EVEN | kv.KV_SYM_REF_ODD)
+        re = (ctypes.c_double * 3)()
+        assert ctx._lib.kv_arnoldi_leading_eigs(ctx._h, ctypes.byref(p), re, re, re, None) == kv.KV_EINVAL
+    finally:
+        ctx.close()
+
+
+def test_arnoldi_budget_exhausted_reports_no_convergence():
+    """A run stopped by its matvec budget (or restart cap) before the
+    tolerance is met says so: KV_ENOCONV, converged False, the last Ritz
+    values out."""
+    from paper_2210_08816_amd import kv
+    fx = [faces("clustered", n) for n in (6, 6, 4)]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    X0 = O.symmetry_project(g, S.base_flow(*fx, K=2, amp=0.3, seed=21), 1, 1)
+    ctx = make_ctx(fx)
+    try:
+        ctx.set_base_flow(to_dev(X0))
+        for sym in (None, (-1, 1)):
+            vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=10,
+                                                       n_eigs=4, tol=1e-14, max_matvec=40, cheb_degree_max=5,
+                                                       sym=sym, check=False)
+            assert info["status"] == kv.KV_ENOCONV and not info["converged"], (sym, info)
+            assert info["n_out"] >= 4 and np.all(np.isfinite(vals)), (sym, info, vals)
+    finally:
+        ctx.close()
