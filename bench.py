@@ -132,6 +132,26 @@ def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
                          "what": "Gram-Schmidt algorithmic bytes / (cycle time - matvec time)"}}
 
 
+def symmetry_leg(torch, ctx, x, n, reps=50):
+    """In-place projections of one vector onto a symmetry class (the step
+    that a class-restricted Arnoldi run adds after every P J x).  Algorithmic
+    bytes: one read and one write of the vector, 16 B per unknown."""
+    y = x.clone()
+    for _ in range(3):
+        ctx.symmetry_project(y, None, (-1, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.symmetry_project(y, None, (-1, 1))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ach = 16.0 * n / dt / 1e9
+    return {"call_ms": round(1e3 * dt, 4), "bytes": 16 * n,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "symmetry_class_kernel (4 launches, one per field)"}}
+
+
 def learned_leg(torch, steps=10):
     """Time kvnn training steps and predictions on a 64^3 network (the
     learned Newton guess's kernels)."""
@@ -320,6 +340,8 @@ def main():
     if "fp64" in forms and not args.no_arnoldi:
         log("[bench] timing one Arnoldi cycle (CGS2)")
         result["arnoldi_cycle"] = arnoldi_leg(torch, ctx, xs[0], n, forms["fp64"]["ms_per_step"])
+        log("[bench] timing the symmetry-class projection")
+        result["symmetry_project"] = symmetry_leg(torch, ctx, xs[0], n)
     if not args.no_learned:
         log("[bench] timing the learned-guess network kernels")
         result["learned"] = learned_leg(torch)
