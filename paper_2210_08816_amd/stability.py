@@ -121,7 +121,7 @@ def main(argv=None):
     ap.add_argument("--load-state", default=None, help="start from a stored converged state (.npy)")
     ap.add_argument("--sym", default=None,
                     help="symmetry classes for restricted Arnoldi runs: 'all', or a comma list of sign pairs "
-                         "(reflection, 2-D rotation) such as '+-,--'")
+                         "(reflection, 2-D rotation) such as --sym=+-,-- (with '=' when the list starts with '-')")
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
