@@ -219,18 +219,31 @@ typedef struct {
 
 /* Leading eigenvalues (largest real part first, +Im before -Im within a
  * conjugate pair) of A = P J(X0) on divergence-free vectors, by restarted
- * Arnoldi (classical Gram-Schmidt twice, FP64) whose restart vector, the sum
- * of the real and imaginary parts of the wanted Ritz vectors, is filtered by
- * a Chebyshev polynomial on the ellipse around the unwanted Ritz values
- * (Sec. 1 and Sec. 3: Chebyshev-preconditioned Arnoldi, no shift-and-
- * invert).  The Hessenberg eigenproblem is solved on the GPU by Francis
- * double-shift QR.  lam_re, lam_im, resid: host arrays of n_eigs+1 values;
- * resid gets the Ritz residual norms.  info: host, may be NULL.  Not
- * converged within max_matvec: KV_ENOCONV with the last Ritz values.  A
- * Hessenberg QR that does not converge also gives KV_ENOCONV, with no values
- * (info->n_out = 0; matvecs and restarts count the work done). */
+ * Arnoldi (classical Gram-Schmidt twice, FP64) whose restart vector is
+ * filtered by a Chebyshev polynomial on the ellipse around the unwanted Ritz
+ * values (Sec. 1 and Sec. 3: Chebyshev-preconditioned Arnoldi, no shift-and-
+ * invert).  The restart vector sums the real and imaginary parts of the
+ * wanted Ritz vectors still open, each weighted by the inverse of its
+ * predicted growth under the filter; converged values are locked in leading
+ * order and their invariant subspaces deflated from later cycles and
+ * filters.  The Hessenberg eigenproblem is solved on the GPU by Francis
+ * double-shift QR.
+ *   lam_re, lam_im, resid: host arrays of n_eigs+1 values; resid gets the
+ *     Ritz residual norms (for a locked value, when it was locked).
+ *   evecs: NULL, or device, (n_eigs+1) rows of n values: the eigenvector of
+ *     output value q in row q, unit W-norm, sign not fixed; a conjugate pair
+ *     q, q+1 as the real part (row q) and imaginary part (row q+1) of the
+ *     eigenvector of the +Im member, turned so the two are W-orthogonal and
+ *     the real part the longer.  Vectors of locked values are lifted from the
+ *     deflated operator to A (a few extra P J x, counted in info->matvecs),
+ *     and the workspace grows by n_eigs+1 vectors.
+ *   info: host, may be NULL.
+ * Not converged within max_matvec (or max_restarts > 0 restarts): KV_ENOCONV
+ * with the last Ritz values (and their vectors).  A Hessenberg QR that does
+ * not converge also gives KV_ENOCONV, with no values (info->n_out = 0;
+ * matvecs and restarts count the work done). */
 int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
-                            double* lam_im, double* resid, kv_eig_info* info);
+                            double* lam_im, double* resid, double* evecs, kv_eig_info* info);
 
 /* Transfers for the learned Newton guess (kvnn.h).  Not part of the paper's
  * method: the paper starts each Newton solve from a converged state at a

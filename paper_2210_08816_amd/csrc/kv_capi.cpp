@@ -609,6 +609,117 @@ int cheb_degree(double wr, double a, double b, double c2, int dmax) {
 
 }  // namespace
 
+// Solves M t = b in place (b <- t) for a small dense complex M (row-major,
+// nn x nn) by Gaussian elimination with partial pivoting; false if singular.
+static bool solve_small(std::vector<std::complex<double>> M, std::vector<std::complex<double>>& b, int nn) {
+  for (int col = 0; col < nn; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < nn; ++r)
+      if (std::abs(M[(size_t)r * nn + col]) > std::abs(M[(size_t)piv * nn + col])) piv = r;
+    if (!(std::abs(M[(size_t)piv * nn + col]) > 0)) return false;
+    if (piv != col) {
+      for (int cc = 0; cc < nn; ++cc) std::swap(M[(size_t)piv * nn + cc], M[(size_t)col * nn + cc]);
+      std::swap(b[piv], b[col]);
+    }
+    for (int r = col + 1; r < nn; ++r) {
+      const std::complex<double> f = M[(size_t)r * nn + col] / M[(size_t)col * nn + col];
+      for (int cc = col; cc < nn; ++cc) M[(size_t)r * nn + cc] -= f * M[(size_t)col * nn + cc];
+      b[r] -= f * b[col];
+    }
+  }
+  for (int r = nn - 1; r >= 0; --r) {
+    for (int cc = r + 1; cc < nn; ++cc) b[r] -= M[(size_t)r * nn + cc] * b[cc];
+    b[r] /= M[(size_t)r * nn + r];
+  }
+  return true;
+}
+
+// Eigenvectors of the output values into evecs (rows of n values; a pair as
+// its real part, then its imaginary part).  A value found with nl vectors of
+// L deflated has a Ritz vector y of the deflated operator; its eigenvector of
+// A is x = y + L t with (theta - R) t = L^T W A y, R = L^T W A L over those nl
+// vectors (A L = L R for the locked invariant subspaces).  Each x is scaled
+// to unit W-norm; a complex x is turned by a phase so that its real and
+// imaginary parts are W-orthogonal, the real part the longer.  zp, zc, tmp:
+// scratch vectors.  Adds the matvecs used to *matvecs.
+static int write_eigenvectors(kv_ctx* c, const double* L, const std::vector<int>& out,
+                              const std::vector<std::complex<double>>& vals, const std::vector<const double*>& src_re,
+                              const std::vector<const double*>& src_im, const std::vector<int>& nl, double* evecs,
+                              double* zp, double* zc, double* tmp, int* matvecs) {
+  const int64_t n = c->g.n;
+  const int nL = c->nlock;
+  int rc;
+  c->nlock = 0;  // A itself below, not deflated
+  std::vector<double> R((size_t)nL * nL, 0.0);
+  bool need_R = false;
+  for (int v : nl) need_R = need_R || v > 0;
+  for (int j = 0; need_R && j < nL; ++j) {
+    if ((rc = matvec(c, L + (int64_t)j * n, tmp))) return rc;
+    ++*matvecs;
+    HIPCHK(c, launch_mdot(c, L, n, nL, tmp));
+    if ((rc = read_results(c, nL))) return rc;
+    for (int i = 0; i < nL; ++i) R[(size_t)i * nL + j] = c->hres[i];
+  }
+  for (size_t q = 0; q < out.size(); ++q) {
+    const std::complex<double> th = vals[out[q]];
+    if (th.imag() < 0) continue;  // written with its +Im member
+    const bool cplx = th.imag() > 0;
+    HIPCHK(c, hipMemcpyAsync(zp, src_re[q], n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (cplx) HIPCHK(c, hipMemcpyAsync(zc, src_im[q], n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    const int k = nl[q];
+    if (k > 0) {
+      std::vector<std::complex<double>> rhs(k), M((size_t)k * k);
+      for (int part = 0; part < (cplx ? 2 : 1); ++part) {
+        if ((rc = matvec(c, part == 0 ? zp : zc, tmp))) return rc;
+        ++*matvecs;
+        HIPCHK(c, launch_mdot(c, L, n, k, tmp));
+        if ((rc = read_results(c, k))) return rc;
+        for (int i = 0; i < k; ++i) rhs[i] += part == 0 ? std::complex<double>(c->hres[i], 0.0)
+                                                       : std::complex<double>(0.0, c->hres[i]);
+      }
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) M[(size_t)i * k + j] = (i == j ? th : 0.0) - R[(size_t)i * nL + j];
+      if (!solve_small(M, rhs, k)) return fail(c, KV_ENOCONV, "eigenvector lift: singular locked block");
+      std::vector<double> cr(k), ci(k);
+      for (int i = 0; i < k; ++i) {
+        cr[i] = -rhs[i].real();
+        ci[i] = -rhs[i].imag();
+      }
+      if ((rc = upload(c, c->dres, cr.data(), k * sizeof(double)))) return rc;
+      HIPCHK(c, launch_mupdate(c, L, n, k, c->dres, zp));
+      if (cplx) {
+        if ((rc = upload(c, c->dres, ci.data(), k * sizeof(double)))) return rc;
+        HIPCHK(c, launch_mupdate(c, L, n, k, c->dres, zc));
+      }
+    }
+    const double a = dot1(c, zp, zp, &rc);
+    if (rc) return rc;
+    double* row = evecs + (int64_t)q * n;
+    if (!cplx) {
+      if (!(a > 0)) return fail(c, KV_ENONFINITE, "zero eigenvector");
+      if ((rc = lincomb(c, 1, {1.0 / std::sqrt(a)}, {zp}, row))) return rc;
+      continue;
+    }
+    const double b = dot1(c, zc, zc, &rc);
+    if (rc) return rc;
+    const double ab = dot1(c, zp, zc, &rc);
+    if (rc) return rc;
+    if (!(a + b > 0)) return fail(c, KV_ENONFINITE, "zero eigenvector");
+    double phi = 0.5 * std::atan2(-2.0 * ab, a - b);
+    double cs = std::cos(phi), sn = std::sin(phi);
+    if (a * cs * cs - 2.0 * ab * sn * cs + b * sn * sn < a * sn * sn + 2.0 * ab * sn * cs + b * cs * cs) {
+      phi += 1.5707963267948966;  // pi / 2
+      cs = std::cos(phi);
+      sn = std::sin(phi);
+    }
+    const double inv = 1.0 / std::sqrt(a + b);
+    if ((rc = lincomb(c, 2, {cs * inv, -sn * inv}, {zp, zc}, row))) return rc;
+    if ((rc = lincomb(c, 2, {sn * inv, cs * inv}, {zp, zc}, row + n))) return rc;
+  }
+  c->nlock = nL;
+  return KV_OK;
+}
+
 // =============================================================================================
 extern "C" {
 
@@ -1356,7 +1467,7 @@ int kv_state_add_cell_increment(kv_ctx* c, const float* cells, const float* cell
 
 // ---- Chebyshev-preconditioned Arnoldi -------------------------------------------------------
 int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_re, double* lam_im,
-                            double* resid, kv_eig_info* info) {
+                            double* resid, double* evecs, kv_eig_info* info) {
   if (!c) return KV_EINVAL;
   if (!p || !lam_re || !lam_im || !p->v0) return fail(c, KV_EINVAL, "null argument");
   int sym_ref = 0, sym_rot = 0, rc;
@@ -1367,13 +1478,17 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   const int64_t n = c->g.n;
   if ((rc = check_finite(c, p->v0, n, "v0"))) return rc;
-  // workspace: V (m+1 vectors) + z_prev, z, tmp + up to n_eigs+1 locked vectors
-  if ((rc = ensure_work(c, (size_t)m + 5 + p->n_eigs))) return rc;
+  // workspace: V (m+1 vectors) + z_prev, z, tmp + up to n_eigs+1 locked
+  // vectors (+ as many lock-time Ritz vectors when eigenvectors are asked for)
+  const int nslot = p->n_eigs + 1;
+  if ((rc = ensure_work(c, (size_t)m + 4 + (size_t)nslot * (evecs ? 2 : 1)))) return rc;
   double* V = c->work;
   double* zp = c->work + (int64_t)(m + 1) * n;
   double* zc = zp + n;
   double* tmp = zc + n;
   double* L = tmp + n;
+  double* Ys = L + (int64_t)nslot * n;  // lock-time Ritz vectors (real, imaginary part), if evecs
+  int nys = 0;
   EigScope scope(c, sym_ref, sym_rot, L);
   // the start vector in range(P), in the class, W-orthogonal to the locked vectors
   auto settle = [&](double* v) -> int {
@@ -1388,9 +1503,13 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   std::vector<double> H;
   Ritz rz;
   bool conv = false;
-  // locked eigenvalues and their residual estimates when locked
+  // output values (locked, then the last cycle's wanted ones), their residual
+  // estimates, where their Ritz vector is (Ys slot of its real part, or -1:
+  // the last cycle's basis, entry lk_q of the Ritz data) and how many locked
+  // vectors were deflated when it was found
   std::vector<std::complex<double>> lk_vals;
   std::vector<double> lk_res;
+  std::vector<int> lk_slot, lk_q, lk_nl;
   // KV_ARNOLDI_TRACE=1: one line per restart on stderr (residual, ellipse,
   // filter degree, wanted Ritz values, locked count)
   const char* ev = getenv("KV_ARNOLDI_TRACE");
@@ -1423,17 +1542,23 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     // before a restart their real invariant subspaces join L
     const size_t nout = stop ? rz.sel.size() : ndone;
     for (size_t q = 0; q < nout; ++q) {
+      const bool minus = rz.vals[rz.sel[q]].imag() < 0;
       lk_vals.push_back(rz.vals[rz.sel[q]]);
       lk_res.push_back(rz.res[q]);
-      if (stop || rz.vals[rz.sel[q]].imag() < 0) continue;  // a pair locks once, by its +Im member
+      lk_q.push_back((int)q);
+      lk_nl.push_back(minus && !lk_nl.empty() ? lk_nl.back() : c->nlock);
+      lk_slot.push_back(stop ? -1 : (minus && !lk_slot.empty() ? lk_slot.back() : (evecs ? nys : -1)));
+      if (stop || minus) continue;  // a pair locks once, by its +Im member
       const int parts = rz.vals[rz.sel[q]].imag() > 0 ? 2 : 1;
       for (int part = 0; part < parts; ++part) {
         double* dst = L + (int64_t)c->nlock * n;
+        double* ys = evecs ? Ys + (int64_t)(nys + part) * n : dst;
         std::vector<double> coef(k);
         for (int r = 0; r < k; ++r) coef[r] = -(part == 0 ? rz.vecs[q][r].real() : rz.vecs[q][r].imag());
-        HIPCHK(c, launch_fill(c, n, 0.0, dst));
+        HIPCHK(c, launch_fill(c, n, 0.0, ys));
         if ((rc = upload(c, c->dres, coef.data(), k * sizeof(double)))) return rc;
-        HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, dst));
+        HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, ys));
+        if (ys != dst) HIPCHK(c, hipMemcpyAsync(dst, ys, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         if ((rc = deflate(c, dst))) return rc;
         const double ln = std::sqrt(std::max(0.0, dot1(c, dst, dst, &rc)));
         if (rc) return rc;
@@ -1441,6 +1566,7 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
         if ((rc = lincomb(c, 1, {1.0 / ln}, {dst}, dst))) return rc;
         ++c->nlock;
       }
+      if (evecs) nys += parts;
     }
     if (stop) break;
     if ((int)lk_vals.size() >= p->n_eigs) {  // every wanted value locked
@@ -1529,6 +1655,35 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     lam_re[q] = lk_vals[out[q]].real();
     lam_im[q] = lk_vals[out[q]].imag();
     if (resid) resid[q] = lk_res[out[q]];
+  }
+  if (evecs) {
+    std::vector<const double*> src_re(out.size(), nullptr), src_im(out.size(), nullptr);
+    std::vector<int> nl(out.size(), 0);
+    // the last cycle's Ritz vectors, still in V, go to the Ys slots left free
+    for (size_t q = 0; q < out.size(); ++q) {
+      const int e = out[q];
+      nl[q] = lk_nl[e];
+      if (lk_slot[e] < 0 && lk_vals[e].imag() >= 0) {
+        const int parts = lk_vals[e].imag() > 0 ? 2 : 1;
+        if (nys + parts > nslot) return fail(c, KV_EINVAL, "eigenvector workspace exhausted");
+        for (int part = 0; part < parts; ++part) {
+          double* ys = Ys + (int64_t)(nys + part) * n;
+          std::vector<double> coef(rz.vecs[lk_q[e]].size());
+          for (size_t r = 0; r < coef.size(); ++r)
+            coef[r] = -(part == 0 ? rz.vecs[lk_q[e]][r].real() : rz.vecs[lk_q[e]][r].imag());
+          HIPCHK(c, launch_fill(c, n, 0.0, ys));
+          if ((rc = upload(c, c->dres, coef.data(), coef.size() * sizeof(double)))) return rc;
+          HIPCHK(c, launch_mupdate(c, V, n, (int)coef.size(), c->dres, ys));
+        }
+        lk_slot[e] = nys;
+        nys += parts;
+      } else if (lk_slot[e] < 0) {
+        lk_slot[e] = lk_slot[out[q - 1]];  // the -Im member follows its +Im member
+      }
+      src_re[q] = Ys + (int64_t)lk_slot[e] * n;
+      src_im[q] = lk_vals[e].imag() != 0.0 ? src_re[q] + n : nullptr;
+    }
+    if ((rc = write_eigenvectors(c, L, out, lk_vals, src_re, src_im, nl, evecs, zp, zc, tmp, &matvecs))) return rc;
   }
   if (info) *info = kv_eig_info{(int)out.size(), matvecs, restarts, conv ? 1 : 0};
   if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");

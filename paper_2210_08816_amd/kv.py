@@ -98,7 +98,7 @@ def load(path: str = LIB_PATH):
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
-    lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD,
+    lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD, P,
                                             ctypes.POINTER(_EigInfo)]
     lib.kv_cells_from_state.argtypes = [P, P, ctypes.c_int, PD, PD, P]
     lib.kv_state_from_cells.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, PD, PD, PD, PD, PD, P]
@@ -286,16 +286,19 @@ class Context:
                                                           rz, *pc, psc, _dptr(X, self.n)))
 
     def arnoldi_leading_eigs(self, v0, krylov_dim, n_eigs, tol=1e-8, max_matvec=100000,
-                             max_restarts=1000, cheb_degree_max=200, sym=None, check=True):
+                             max_restarts=1000, cheb_degree_max=200, sym=None, evecs=None, check=True):
         """sym: a symmetry class (e_ref, e_rot) to restrict the Krylov space
-        to (see sym_flags), or None."""
+        to (see sym_flags), or None.  evecs: None, or a float64 CUDA tensor of
+        (n_eigs + 1) * n values that receives the eigenvectors, one per row
+        (a conjugate pair as the real and imaginary part of the +Im member's)."""
         p = _ArnoldiParams(int(krylov_dim), int(n_eigs), int(max_matvec), int(max_restarts),
                            int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, sym_flags(sym))
         re = (ctypes.c_double * (n_eigs + 1))()
         im = (ctypes.c_double * (n_eigs + 1))()
         res = (ctypes.c_double * (n_eigs + 1))()
         info = _EigInfo()
-        rc = self._lib.kv_arnoldi_leading_eigs(self._h, ctypes.byref(p), re, im, res, ctypes.byref(info))
+        ev = _dptr(evecs, (n_eigs + 1) * self.n) if evecs is not None else None
+        rc = self._lib.kv_arnoldi_leading_eigs(self._h, ctypes.byref(p), re, im, res, ev, ctypes.byref(info))
         if check and rc != KV_ENOCONV:
             self._check(rc)
         k = info.n_out

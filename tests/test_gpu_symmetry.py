@@ -17,6 +17,7 @@ import scipy.linalg as sl
 torch = pytest.importorskip("torch")
 
 from oracle import disc as O  # noqa: E402
+from oracle import solvers as SV  # noqa: E402
 from synth import inputs as S  # noqa: E402
 from tests.gpu_util import faces, to_dev, to_host  # noqa: E402
 
@@ -178,7 +179,7 @@ def test_arnoldi_rejects_bad_symmetry_flags():
         v0 = to_dev(S.perturbation(g.size, 7))
         p = kv._ArnoldiParams(10, 2, 1000, 0, 100, 1e-8, v0.data_ptr(), kv.KV_SYM_REF_EVEN | kv.KV_SYM_REF_ODD)
         re = (ctypes.c_double * 3)()
-        assert ctx._lib.kv_arnoldi_leading_eigs(ctx._h, ctypes.byref(p), re, re, re, None) == kv.KV_EINVAL
+        assert ctx._lib.kv_arnoldi_leading_eigs(ctx._h, ctypes.byref(p), re, re, re, None, None) == kv.KV_EINVAL
     finally:
         ctx.close()
 
@@ -202,3 +203,81 @@ def test_arnoldi_budget_exhausted_reports_no_convergence():
             assert info["n_out"] >= 4 and np.all(np.isfinite(vals)), (sym, info, vals)
     finally:
         ctx.close()
+
+
+class ClassOperator(SV.Operator):
+    """The oracle's P J followed by a class projection (host)."""
+
+    def __init__(self, g, X0, cls):
+        super().__init__(g, X0)
+        self.cls = cls
+
+    def __call__(self, x):
+        return O.symmetry_project(self.g, super().__call__(x), *self.cls)
+
+
+def check_eigenvectors(A, w, vals, ev, scale):
+    """Rows of ev against A on the host: residual, unit W-norm, the pair
+    convention (real and imaginary parts W-orthogonal, the real part longer).
+    Returns the complex eigenvectors."""
+    xs, q = [], 0
+    while q < len(vals):
+        if vals[q].imag > 0:
+            re, im = ev[q], ev[q + 1]
+            assert abs(np.dot(w * re, im)) < 1e-10 and np.dot(w * re, re) >= np.dot(w * im, im) - 1e-12
+            x = re + 1j * im
+            xs += [x, np.conj(x)]
+            q += 2
+        else:
+            x = ev[q] + 0j
+            xs.append(x)
+            q += 1
+    for lam, x in zip(vals, xs):
+        nx = np.sqrt(np.dot(w, np.abs(x) ** 2))
+        assert abs(nx - 1.0) < 1e-12, nx
+        r = A(x.real) + 1j * A(x.imag) - lam * x
+        assert np.sqrt(np.dot(w, np.abs(r) ** 2)) <= 1e-8 * scale, (lam, np.sqrt(np.dot(w, np.abs(r) ** 2)))
+    return xs
+
+
+@pytest.mark.parametrize("case", ["unrestricted", "class_locked"])
+def test_arnoldi_eigenvectors(case):
+    """Eigenvectors returned by the library are eigenvectors of A (checked
+    with the oracle's operator) and match the oracle's Ritz vectors up to a
+    complex scale; in the class case the leading pair is locked cycles
+    before the rest, so its vector is lifted from the deflated operator."""
+    if case == "unrestricted":
+        fx = [faces("clustered", n) for n in (6, 5, 4)]
+        g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+        X0 = S.base_flow(*fx, K=2, amp=0.3, seed=21)
+        cls, m = None, 40
+        A = SV.Operator(g, X0)
+        v0 = S.perturbation(g.size, 77)
+    else:
+        fx = [faces("clustered", n) for n in (5, 7, 5)]
+        g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+        X0 = O.symmetry_project(g, S.base_flow(*fx, K=2, amp=0.3, seed=21), 1, 1)
+        cls, m = (-1, 1), 30
+        A = ClassOperator(g, X0, cls)
+        v0 = O.symmetry_project(g, S.perturbation(g.size, 77), *cls)
+    ctx = make_ctx(fx)
+    try:
+        ctx.set_base_flow(to_dev(X0))
+        ev = torch.full((5, g.size), np.nan, dtype=torch.float64, device="cuda")
+        vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=m, n_eigs=4,
+                                                   tol=1e-11, max_matvec=20000, cheb_degree_max=300, sym=cls,
+                                                   evecs=ev)
+    finally:
+        ctx.close()
+    assert info["converged"], info
+    scale = np.max(np.abs(vals))
+    xs = check_eigenvectors(A, g.weights(), vals, to_host(ev), scale)
+    # the oracle's run, on its own operator
+    ovals, ores, Y, oinfo = SV.cheb_arnoldi(A, v0, m, 4, tol=1e-11, max_matvec=20000, cheb_degree_max=300)
+    assert oinfo["converged"]
+    w = g.weights()
+    for lam, x in zip(vals, xs):
+        j = int(np.argmin(np.abs(ovals - lam)))
+        y = Y[j]
+        cos = abs(np.dot(w * np.conj(x), y)) / np.sqrt(np.dot(w, np.abs(x) ** 2) * np.dot(w, np.abs(y) ** 2))
+        assert cos > 1 - 1e-10, (lam, ovals[j], cos)
