@@ -245,6 +245,17 @@ typedef struct {
 int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
                             double* lam_im, double* resid, double* evecs, kv_eig_info* info);
 
+/* Eigenvalues of a small upper Hessenberg matrix on the GPU: the Ritz
+ * values of an Arnoldi cycle (Sec. 1) come from this Francis double-shift QR
+ * (one wavefront; an exceptional shift pair every tenth iteration without a
+ * deflation).  H: host, m x m row-major, entries below the first subdiagonal
+ * ignored; 1 <= m <= 400.  wr, wi: host, m values each, in the order the QR
+ * deflates them (a complex pair as +Im, -Im in consecutive entries).
+ * KV_ENONFINITE on a non-finite entry, KV_ENOCONV when the QR does not
+ * converge (more than 30 max(10, m) iterations without a deflation, or 120
+ * max(10, m) in all).  Needs no base flow. */
+int kv_hessenberg_eigenvalues(kv_ctx* ctx, const double* H, int m, double* wr, double* wi);
+
 /* Transfers for the learned Newton guess (kvnn.h).  Not part of the paper's
  * method: the paper starts each Newton solve from a converged state at a
  * nearby Gr (Sec. 1); these calls turn converged states into training targets

@@ -1690,6 +1690,33 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   return KV_OK;
 }
 
+int kv_hessenberg_eigenvalues(kv_ctx* c, const double* H, int m, double* wr, double* wi) {
+  if (!c) return KV_EINVAL;
+  if (!H || !wr || !wi) return fail(c, KV_EINVAL, "null argument");
+  if (m < 1 || m > 400) return fail(c, KV_EINVAL, "m must be in 1..400");
+  std::vector<double> Hk((size_t)m * m, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int cc = std::max(0, r - 1); cc < m; ++cc) {
+      const double v = H[(size_t)r * m + cc];
+      if (!std::isfinite(v)) return fail(c, KV_ENONFINITE, "non-finite Hessenberg entry");
+      Hk[(size_t)r * m + cc] = v;
+    }
+  int rc;
+  const size_t mm = (size_t)m * m;
+  if ((rc = ensure_hess(c, (mm + 2 * (size_t)m + 2) * sizeof(double)))) return rc;
+  double *dH = c->hess, *dwr = dH + mm, *dwi = dwr + m;
+  int* dinfo = reinterpret_cast<int*>(dwi + m);
+  if ((rc = upload(c, dH, Hk.data(), mm * sizeof(double)))) return rc;
+  HIPCHK(c, launch_hessenberg_values(c->stream, dH, m, dwr, dwi, dinfo));
+  int info = 0;
+  HIPCHK(c, hipMemcpyAsync(wr, dwr, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(wi, dwi, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
+  return KV_OK;
+}
+
 int kv_timing(kv_ctx* c, int enable, double ms[4], int calls[2]) {
   if (!c) return KV_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -46,11 +46,16 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
   int status = 0;
   while (hi >= 0) {
     // find the start l of the unreduced active block ending at hi
+    // (after 100 iterations without a deflation the test relaxes to
+    // sqrt(eps): a nearly defective cluster, whose subdiagonal decays only
+    // linearly, is taken as converged; its values carry the cluster's own
+    // ill-conditioning, eps^(1/p) for p coalescing values)
+    const double tol = its < 100 ? eps : 1.4901161193847656e-08;
     int l = hi;
     while (l > 0) {
       double sc = fabs(h(l - 1, l - 1)) + fabs(h(l, l));
       if (sc == 0.0) sc = anorm;
-      if (fabs(h(l, l - 1)) <= eps * sc) break;
+      if (fabs(h(l, l - 1)) <= tol * sc) break;
       --l;
     }
     if (l == hi) {
@@ -84,21 +89,57 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
       its = 0;
       continue;
     }
-    if (total > 40 * m) {
+    // iteration limits as LAPACK's small-bulge QR: 30 max(10, m) per
+    // deflation, and a bound on the total
+    const int lim = 30 * (m > 10 ? m : 10);
+    if (its > lim || total > 4 * lim) {
       status = 1;
       break;
     }
     ++its;
     ++total;
-    // double shift: eigenvalues of the trailing 2x2 (sum s, product t)
-    double s, t;
-    if (its % 10 == 0) {  // every tenth iteration without a deflation
+    // double shift (sum s, product t) from a 2x2: the trailing one, or every
+    // tenth iteration without a deflation an exceptional pair
+    // [g + 0.75e, -0.4375e; e, g + 0.75e] centred at the bottom (tenth) or top
+    // (twentieth) diagonal entry of the block, as in LAPACK's small-bulge QR.
+    // Complex eigenvalues of the 2x2 give a conjugate pair; real ones give
+    // the one nearer its last diagonal entry twice.
+    double h11, h12, h21, h22;
+    if (its % 20 == 0) {
+      const double e = fabs(h(l + 1, l)) + fabs(h(l + 2, l + 1));
+      h11 = h22 = h(l, l) + 0.75 * e;
+      h12 = -0.4375 * e;
+      h21 = e;
+    } else if (its % 10 == 0) {
       const double e = fabs(h(hi, hi - 1)) + fabs(h(hi - 1, hi - 2));
-      s = 1.5 * e;
-      t = e * e;
+      h11 = h22 = h(hi, hi) + 0.75 * e;
+      h12 = -0.4375 * e;
+      h21 = e;
     } else {
-      s = h(hi - 1, hi - 1) + h(hi, hi);
-      t = h(hi - 1, hi - 1) * h(hi, hi) - h(hi - 1, hi) * h(hi, hi - 1);
+      h11 = h(hi - 1, hi - 1);
+      h12 = h(hi - 1, hi);
+      h21 = h(hi, hi - 1);
+      h22 = h(hi, hi);
+    }
+    double s = 0.0, t = 0.0;
+    const double sc = fabs(h11) + fabs(h12) + fabs(h21) + fabs(h22);
+    if (sc != 0.0) {
+      h11 /= sc;
+      h12 /= sc;
+      h21 /= sc;
+      h22 /= sc;
+      const double tr = 0.5 * (h11 + h22);
+      const double det = (h11 - tr) * (h22 - tr) - h12 * h21;
+      const double rtd = sqrt(fabs(det));
+      if (det >= 0.0) {
+        s = 2.0 * tr * sc;
+        t = (tr * sc) * (tr * sc) + (rtd * sc) * (rtd * sc);
+      } else {
+        const double r1 = tr + rtd, r2 = tr - rtd;
+        const double rr = (fabs(r1 - h22) <= fabs(r2 - h22) ? r1 : r2) * sc;
+        s = 2.0 * rr;
+        t = rr * rr;
+      }
     }
     // first column of (H - s1 I)(H - s2 I) restricted to the block
     double x = h(l, l) * h(l, l) + h(l, l + 1) * h(l + 1, l) - s * h(l, l) + t;

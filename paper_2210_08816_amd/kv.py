@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
-               "kv_symmetry_project",
+               "kv_symmetry_project", "kv_hessenberg_eigenvalues",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -95,6 +95,7 @@ def load(path: str = LIB_PATH):
     lib.kv_axpby.argtypes = [P, D, P, D, P]
     lib.kv_symmetry_measures.argtypes = [P, P, PD]
     lib.kv_symmetry_project.argtypes = [P, P, P, ctypes.c_uint]
+    lib.kv_hessenberg_eigenvalues.argtypes = [P, PD, ctypes.c_int, PD, PD]
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
@@ -233,6 +234,19 @@ class Context:
         y = x if y is None else y
         self._check(self._lib.kv_symmetry_project(self._h, _dptr(x, self.n), _dptr(y, self.n), sym_flags(cls)))
         return y
+
+    def hessenberg_eigenvalues(self, H, check=True):
+        """Eigenvalues of the upper Hessenberg part of the host matrix H
+        (m x m) by the library's GPU QR, in deflation order."""
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        m = H.shape[0]
+        wr = (ctypes.c_double * m)()
+        wi = (ctypes.c_double * m)()
+        rc = self._lib.kv_hessenberg_eigenvalues(self._h, H.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m,
+                                                 wr, wi)
+        if check:
+            self._check(rc)
+        return np.array([complex(wr[i], wi[i]) for i in range(m)]), rc
 
     def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True):
         info = _SolveInfo()

@@ -281,3 +281,67 @@ def test_preconditioned_newton_correction(kind, shape, Gr, amp, noise, tol):
     info2 = ctx.newton_correction(F, d_again, tol=max(tol, 1e-6), max_matvec=20000, delta0=d_pc)
     assert info2["status"] == 0 and info2["matvecs"] <= 5
     assert A.norm(to_host(d_again) - d) <= 1e-5 * A.norm(d)
+
+
+def hessenberg_cases():
+    """Upper Hessenberg test matrices: random (m = 1, 2, 3, 7, 60, 200, 400),
+    the cyclic shift (eigenvalues the 60th roots of unity, zero diagonal, on
+    which plain Francis shifts make no progress), one already split, and
+    Hessenberg forms of stiff matrices with a cluster of complex values near
+    the imaginary axis (the Ritz spectra of the convection operator), and of
+    matrices with a 3x3 Jordan block."""
+    rng = np.random.default_rng(5)
+    for m in (1, 2, 3, 7, 60, 200, 400):
+        yield f"random{m}", np.triu(rng.standard_normal((m, m)), -1)
+    P = np.zeros((60, 60))
+    P[0, -1] = 1.0
+    P[np.arange(1, 60), np.arange(59)] = 1.0
+    yield "cyclic60", P
+    H = np.triu(rng.standard_normal((12, 12)), -1)
+    H[6, 5] = 0.0
+    yield "split12", H
+    for seed in range(3):
+        r = np.random.default_rng(100 + seed)
+        D = np.zeros((60, 60))
+        D[:40, :40] = np.diag(-r.uniform(0.0, 2000.0, 40))
+        for i in range(10):
+            a, b = -0.05 - r.uniform(0, 0.1), r.uniform(0, 2)
+            D[40 + 2 * i:42 + 2 * i, 40 + 2 * i:42 + 2 * i] = [[a, b], [-b, a]]
+        X = r.standard_normal((60, 60))
+        yield f"stiff{seed}", sl.hessenberg(X @ D @ np.linalg.inv(X))
+    for seed in range(2):
+        r = np.random.default_rng(200 + seed)
+        D = np.diag(-r.uniform(0.1, 5.0, 40))
+        D[0, 0] = D[1, 1] = D[2, 2] = -10.0
+        D[0, 1] = D[1, 2] = 1.0          # a 3x3 Jordan block at -10
+        X = r.standard_normal((40, 40))
+        yield f"jordan{seed}", sl.hessenberg(X @ D @ np.linalg.inv(X))
+
+
+def test_hessenberg_eigenvalues_match_numpy():
+    """The GPU Francis QR (the Ritz values of every Arnoldi cycle) against
+    numpy's eigenvalues of the same matrices, to 1e-10 of ||H||_F in both
+    directions; complex pairs come as +Im, -Im."""
+    from paper_2210_08816_amd import kv
+    fx = [S.faces_uniform(4)] * 3
+    ctx = kv.Context(*fx, Gr=1e4, Pr=0.71)
+    try:
+        for name, H in hessenberg_cases():
+            print(f"hessenberg {name}", flush=True)
+            vals, rc = ctx.hessenberg_eigenvalues(H)
+            ref = np.linalg.eigvals(H)
+            # a defective triple value is fixed only to about eps^(1/3)
+            tol = (1e-4 if name.startswith("jordan") else 1e-10) * max(np.linalg.norm(H), 1e-300)
+            assert closest(vals, ref) <= tol and closest(ref, vals) <= tol, name
+            for i in range(len(vals) - 1):
+                if vals[i].imag > 0:
+                    assert vals[i + 1] == np.conj(vals[i]), name
+        bad = np.eye(3)
+        bad[0, 2] = np.nan
+        assert ctx.hessenberg_eigenvalues(bad, check=False)[1] == kv.KV_ENONFINITE
+        for m in (0, 401):
+            rc = ctx._lib.kv_hessenberg_eigenvalues(ctx._h, np.zeros(max(m, 1) ** 2).ctypes.data_as(
+                kv.ctypes.POINTER(kv.ctypes.c_double)), m, (kv.ctypes.c_double * 1)(), (kv.ctypes.c_double * 1)())
+            assert rc == kv.KV_EINVAL
+    finally:
+        ctx.close()
