@@ -738,18 +738,52 @@ __global__ void __launch_bounds__(256) gradient_correction_kernel(Grid g, const 
   if (i >= g.nx || j >= g.ny) return;
   const int kd = march_planes(g.nz);
   const int k0 = blockIdx.z * kd, k1 = min(g.nz, k0 + kd);
+  if (k0 >= k1) return;
   const int nx = g.nx, ny = g.ny;
   const int64_t plane = (int64_t)nx * ny;
+  const int64_t su = (int64_t)(nx - 1) * ny, sv = (int64_t)(ny - 1) * nx;
   const double idx = g.ax[0].id[i], idy = g.ax[1].id[j];
+  const bool du = i >= 1, dv = j >= 1;
+  double* yu = y + g.ou;
+  double* yv = y + g.ov;
+  double* yw = y + g.ow;
   int64_t c = (int64_t)k0 * plane + (int64_t)j * nx + i;
+  int64_t iu = (int64_t)k0 * su + (int64_t)j * (nx - 1) + (i - 1);
+  int64_t iv = (int64_t)k0 * sv + (int64_t)(j - 1) * nx + i;
+  int64_t iw = (int64_t)(k0 - 1) * plane + (int64_t)j * nx + i;
+  // plane k's operands are loaded one plane ahead: the loads of plane k+1 are
+  // issued before the stores of plane k (they touch other faces)
   double pm = k0 >= 1 ? p[c - plane] : 0.0;
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k, c += plane) {
-    const double pc = p[c];
-    if (i >= 1) y[g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1)] -= (pc - p[c - 1]) * idx;
-    if (j >= 1) y[g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i] -= (pc - p[c - nx]) * idy;
-    if (k >= 1) y[g.ow + ((int64_t)(k - 1) * ny + j) * nx + i] -= (pc - pm) * g.ax[2].id[k];
+  double pc = p[c], px = du ? p[c - 1] : 0.0, py = dv ? p[c - nx] : 0.0;
+  double u = du ? yu[iu] : 0.0, v = dv ? yv[iv] : 0.0, w = k0 >= 1 ? yw[iw] : 0.0;
+  for (int k = k0; k < k1; ++k) {
+    double pc1 = 0.0, px1 = 0.0, py1 = 0.0, u1 = 0.0, v1 = 0.0, w1 = 0.0;
+    if (k + 1 < k1) {
+      pc1 = p[c + plane];
+      if (du) {
+        px1 = p[c + plane - 1];
+        u1 = yu[iu + su];
+      }
+      if (dv) {
+        py1 = p[c + plane - nx];
+        v1 = yv[iv + sv];
+      }
+      w1 = yw[iw + plane];
+    }
+    if (du) yu[iu] = u - (pc - px) * idx;
+    if (dv) yv[iv] = v - (pc - py) * idy;
+    if (k >= 1) yw[iw] = w - (pc - pm) * g.ax[2].id[k];
     pm = pc;
+    pc = pc1;
+    px = px1;
+    py = py1;
+    u = u1;
+    v = v1;
+    w = w1;
+    c += plane;
+    iu += su;
+    iv += sv;
+    iw += plane;
   }
 }
 
