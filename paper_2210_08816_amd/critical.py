@@ -1,0 +1,182 @@
+"""Critical Grashof number of the steady branch: the Gr at which the real
+part of the leading eigenvalue of the Jacobian crosses zero (Sec. 4.1 finds
+the primary steady-oscillatory transition this way, Table 1).
+
+The steady state is followed by Newton continuation in Gr and the leading
+eigenvalue is computed at each state by Chebyshev-preconditioned Arnoldi,
+optionally restricted to one symmetry class of perturbations (Sec. 2; the two
+leading modes of Sec. 4.1 differ by class).  The crossing is bracketed on a
+geometric Gr sweep, then located by regula falsi in log Gr (Illinois
+variant), each new Gr solved by Newton from the nearest converged state.
+Every step runs in the library's kernels; this module sequences the calls.
+
+    python -m paper_2210_08816_amd.critical --n 24 --gr-lo 1e7 --gr-hi 2e8 --sym=-+
+"""
+from __future__ import annotations
+
+import json
+import math
+import time
+
+
+def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=None):
+    """Bracket and locate Gr with sigma(Gr) = 0 for Gr in [gr_lo, gr_hi].
+
+    sigma(Gr) returns (value, info) for increasing Gr calls during the sweep
+    (then for Gr inside the bracket); value None means the eigenvalue did not
+    converge there, and such a point is skipped; info['stop'] true means the
+    steady branch could not be followed to that Gr, which ends the sweep.  The sweep goes from gr_lo
+    up by ratio (the last step clipped to gr_hi) until the sign changes from
+    negative to non-negative.  Then regula falsi in log Gr, the retained end
+    halved in weight after two moves of the same end (Illinois), until the
+    bracket is within a factor 1 + rtol.  Returns a dict: 'gr' (None if no
+    crossing in the range, or if the first converged value is not negative),
+    'bracket', 'history' [(Gr, value, info), ...]."""
+    hist = []
+
+    stop = []
+
+    def ev(gr):
+        val, info = sigma(gr)
+        hist.append((gr, val, info))
+        if info.get("stop"):
+            stop.append(gr)
+        if log:
+            log(f"[critical] Gr={gr:.6e} sigma={val}")
+        return val
+
+    a, fa = None, None
+    gr = gr_lo
+    while True:
+        f = ev(gr)
+        if f is not None:
+            if f >= 0.0 and a is None:   # the branch is not stable where the sweep starts
+                return {"gr": None, "bracket": None, "history": hist, "note": "unstable at the start"}
+            if f >= 0.0:
+                b, fb = gr, f
+                break
+            a, fa = gr, f
+        if stop:
+            return {"gr": None, "bracket": None, "history": hist, "note": f"branch not followed to Gr = {stop[0]:.6g}"}
+        if gr >= gr_hi or len(hist) >= max_evals:
+            return {"gr": None, "bracket": None, "history": hist}
+        gr = min(gr * ratio, gr_hi)
+    if fb == 0.0:
+        return {"gr": b, "bracket": (a, b), "history": hist}
+    la, lb = math.log(a), math.log(b)
+    side = 0
+    while lb - la > math.log1p(rtol) and len(hist) < max_evals:
+        lc = lb - fb * (lb - la) / (fb - fa)
+        lc = min(max(lc, la + 1e-3 * (lb - la)), lb - 1e-3 * (lb - la))
+        fc = ev(math.exp(lc))
+        if fc is None and not stop:          # not converged: bisect instead
+            lc = 0.5 * (la + lb)
+            fc = ev(math.exp(lc))
+        if fc is None:
+            break
+        if fc == 0.0:
+            return {"gr": math.exp(lc), "bracket": (math.exp(lc), math.exp(lc)), "history": hist}
+        if fc < 0.0:
+            la, fa = lc, fc
+            if side == -1:
+                fb *= 0.5
+            side = -1
+        else:
+            lb, fb = lc, fc
+            if side == 1:
+                fa *= 0.5
+            side = 1
+    gr_c = math.exp(lb - fb * (lb - la) / (fb - fa))
+    return {"gr": gr_c, "bracket": (math.exp(la), math.exp(lb)), "history": hist}
+
+
+def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
+        tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
+        newton_max_matvec=20000, log=print):
+    """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
+    the Arnoldi tolerance (relative to the largest wanted modulus): the sign
+    of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
+    newton_max_matvec: budget of each Newton correction."""
+    import numpy as np
+    import torch
+    from synth import inputs as S  # seeded grid faces (input construction only)
+    from . import kv
+    from .continuation import sweep
+    f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
+    faces = (f, f, f)
+    grs, g = [], 1e4
+    while g < gr_lo:
+        grs.append(g)
+        g *= ratio
+    grs.append(gr_lo)
+    t0 = time.perf_counter()
+    states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
+                          log=lambda m: None)
+    if len(states) < len(grs):
+        raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
+    known = [(gr_lo, states[-1])]   # converged states, nearest one starts each new Newton solve
+    v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(states[-1].numel())).cuda()
+    counts = {"newton_matvecs": 0, "arnoldi_matvecs": 0}
+
+    def sigma(gr):
+        near = min(known, key=lambda t: abs(math.log(t[0] / gr)))
+        X = near[1]
+        if near[0] != gr:
+            st, inf = sweep(faces, [gr], Pr=Pr, X0=near[1], max_matvec=newton_max_matvec, max_iter=20,
+                            precond_sigma=precond_sigma, log=lambda m: None)
+            counts["newton_matvecs"] += sum(i.get("matvecs_all_attempts", i["matvecs"]) for i in inf)
+            if not st:
+                return None, {"newton": "not converged", "stop": True}
+            X = st[-1]
+            known.append((gr, X))
+        ctx = kv.Context(*faces, Gr=gr, Pr=Pr)
+        try:
+            ctx.set_base_flow(X)
+            vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
+                                                       cheb_degree_max=cheb_degree_max, sym=sym, check=False)
+        finally:
+            ctx.close()
+        counts["arnoldi_matvecs"] += info["matvecs"]
+        lead = [[float(v.real), float(v.imag)] for v in vals[:2]]
+        if not info["converged"] or len(vals) == 0:
+            return None, {"arnoldi": "not converged", "values": lead}
+        return float(vals[0].real), {"values": lead, "matvecs": info["matvecs"]}
+
+    out = find_crossing(sigma, gr_lo, gr_hi, ratio=ratio, rtol=rtol, log=log)
+    return {"grid": f"{n}^3 {grid}", "Pr": Pr, "symmetry_class": list(sym) if sym else None,
+            "gr_critical": out["gr"], "bracket": out["bracket"], "note": out.get("note"),
+            "history": [{"Gr": gr, "re_lambda1": val, **info} for gr, val, info in out["history"]],
+            "seconds": round(time.perf_counter() - t0, 3), **counts}
+
+
+def main(argv=None):
+    import argparse
+    from .stability import parse_sym
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, default=24)
+    ap.add_argument("--grid", choices=("uniform", "clustered"), default="clustered")
+    ap.add_argument("--gr-lo", type=float, default=1e7)
+    ap.add_argument("--gr-hi", type=float, default=2e8)
+    ap.add_argument("--ratio", type=float, default=1.6)
+    ap.add_argument("--sym", default=None, help="one symmetry class, e.g. --sym=-+ (reflection, 2-D rotation)")
+    ap.add_argument("--krylov", type=int, default=60)
+    ap.add_argument("--max-matvec", type=int, default=60000, help="Arnoldi budget per Gr")
+    ap.add_argument("--tol", type=float, default=1e-5, help="Arnoldi tolerance")
+    ap.add_argument("--newton-max-matvec", type=int, default=20000, help="budget of each Newton correction")
+    ap.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+    cls = parse_sym(a.sym)
+    if cls is not None and len(cls) != 1:
+        raise SystemExit("--sym takes one class")
+    res = run(n=a.n, grid=a.grid, gr_lo=a.gr_lo, gr_hi=a.gr_hi, ratio=a.ratio, sym=cls[0] if cls else None,
+              krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
+              log=lambda m: print(m, flush=True))
+    text = json.dumps(res)
+    if a.json:
+        with open(a.json, "w") as fh:
+            fh.write(text + "\n")
+    print(text, flush=True)
+
+
+if __name__ == "__main__":
+    main()
