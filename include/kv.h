@@ -177,6 +177,14 @@ int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matve
                          unsigned flags, const double* delta0, double* delta,
                          kv_solve_info* info);
 
+/* Restart length m of the GMRES(m) that continues a stalled BiCGstab(2) in
+ * kv_newton_correction (Sec. 1: BiCGstab(2) combined with GMRES); 10 <= m <=
+ * 400, default 40.  A longer restart keeps the few eigenvalues of P J near
+ * the imaginary axis, which a steady branch close to a Hopf point has, in the
+ * Krylov space (restarting discards them); the workspace grows to m + 9
+ * vectors.  Kept until changed. */
+int kv_set_gmres_restart(kv_ctx* ctx, int m);
+
 /* Preconditioner of the Newton correction (an addition: the paper names no
  * preconditioner; Sec. 1 gives BiCGstab(2) with GMRES).  KV_PC_STOKES: right
  * preconditioning of P J by

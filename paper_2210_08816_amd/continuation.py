@@ -53,12 +53,14 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
 
 
 def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12,
-          precond_sigma=None, **kw):
+          precond_sigma=None, gmres_restart=None, **kw):
     """Continuation over increasing Gr values, from X0 (default: the
     conduction state).  A failed step is retried from the last converged
     state at the geometric midpoint in Gr, at most max_halvings times per
     requested value.  precond_sigma: None, or the shift of the Stokes/heat
-    preconditioner of the Newton corrections.  Returns (states, infos) for
+    preconditioner of the Newton corrections; gmres_restart: None (the
+    library's default) or the restart length of their GMRES continuation.
+    Returns (states, infos) for
     the requested Gr values reached; a value that cannot be reached ends the
     sweep."""
     import torch
@@ -77,6 +79,8 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
             try:
                 if precond_sigma is not None:
                     ctx.set_preconditioner(True, precond_sigma)
+                if gmres_restart is not None:
+                    ctx.set_gmres_restart(gmres_restart)
                 ctx.project(Xtry)
                 info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, **kw)
             finally:

@@ -92,11 +92,12 @@ def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=N
 
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
         tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
-        newton_max_matvec=20000, log=print):
+        newton_max_matvec=20000, gmres_restart=None, log=print):
     """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
     the Arnoldi tolerance (relative to the largest wanted modulus): the sign
     of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
-    newton_max_matvec: budget of each Newton correction."""
+    newton_max_matvec: budget of each Newton correction; gmres_restart: the
+    restart length of its GMRES continuation (None: the library default)."""
     import numpy as np
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
@@ -111,7 +112,7 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
     grs.append(gr_lo)
     t0 = time.perf_counter()
     states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
-                          log=lambda m: None)
+                          gmres_restart=gmres_restart, log=lambda m: None)
     if len(states) < len(grs):
         raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
     known = [(gr_lo, states[-1])]   # converged states, nearest one starts each new Newton solve
@@ -123,7 +124,7 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         X = near[1]
         if near[0] != gr:
             st, inf = sweep(faces, [gr], Pr=Pr, X0=near[1], max_matvec=newton_max_matvec, max_iter=20,
-                            precond_sigma=precond_sigma, log=lambda m: None)
+                            precond_sigma=precond_sigma, gmres_restart=gmres_restart, log=lambda m: None)
             counts["newton_matvecs"] += sum(i.get("matvecs_all_attempts", i["matvecs"]) for i in inf)
             if not st:
                 return None, {"newton": "not converged", "stop": True}
@@ -138,9 +139,10 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
             ctx.close()
         counts["arnoldi_matvecs"] += info["matvecs"]
         lead = [[float(v.real), float(v.imag)] for v in vals[:2]]
+        resid = [float(r) for r in res[:2]]
         if not info["converged"] or len(vals) == 0:
-            return None, {"arnoldi": "not converged", "values": lead}
-        return float(vals[0].real), {"values": lead, "matvecs": info["matvecs"]}
+            return None, {"arnoldi": "not converged", "values": lead, "residuals": resid}
+        return float(vals[0].real), {"values": lead, "residuals": resid, "matvecs": info["matvecs"]}
 
     out = find_crossing(sigma, gr_lo, gr_hi, ratio=ratio, rtol=rtol, log=log)
     return {"grid": f"{n}^3 {grid}", "Pr": Pr, "symmetry_class": list(sym) if sym else None,
@@ -163,6 +165,7 @@ def main(argv=None):
     ap.add_argument("--max-matvec", type=int, default=60000, help="Arnoldi budget per Gr")
     ap.add_argument("--tol", type=float, default=1e-5, help="Arnoldi tolerance")
     ap.add_argument("--newton-max-matvec", type=int, default=20000, help="budget of each Newton correction")
+    ap.add_argument("--gmres-restart", type=int, default=None, help="GMRES restart length of the Newton corrections")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     cls = parse_sym(a.sym)
@@ -170,6 +173,7 @@ def main(argv=None):
         raise SystemExit("--sym takes one class")
     res = run(n=a.n, grid=a.grid, gr_lo=a.gr_lo, gr_hi=a.gr_hi, ratio=a.ratio, sym=cls[0] if cls else None,
               krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
+              gmres_restart=a.gmres_restart,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:

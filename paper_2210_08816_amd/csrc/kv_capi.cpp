@@ -1086,9 +1086,9 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
   const int64_t n = c->g.n;
   int rc;
   if ((rc = check_finite(c, F, n, "F"))) return rc;
-  // BiCGstab(2) vectors and the GMRES(40) basis, reserved together so that the
+  // BiCGstab(2) vectors and the GMRES(m) basis, reserved together so that the
   // fallback never reallocates live vectors
-  if ((rc = ensure_work(c, 8 + 41))) return rc;
+  if ((rc = ensure_work(c, 8 + (size_t)c->gmres_m + 1))) return rc;
   double* W = c->work;
   double *b = W, *rt = W + n, *r0 = W + 2 * n, *r1 = W + 3 * n, *r2 = W + 4 * n;
   double *u0 = W + 5 * n, *u1 = W + 6 * n, *u2 = W + 7 * n;
@@ -1212,7 +1212,7 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
     inf.used_gmres = 1;
     int used = inf.matvecs, cyc = inf.cycles;
     double rr = inf.relres;
-    rc = gmres_solve(c, b, bnorm, x, tol, 40, max_matvec, &used, &cyc, &rr);
+    rc = gmres_solve(c, b, bnorm, x, tol, c->gmres_m, max_matvec, &used, &cyc, &rr);
     inf.matvecs = used;
     inf.cycles = cyc;
     inf.relres = rr;
@@ -1338,6 +1338,13 @@ static int build_preconditioner(kv_ctx* c) {
       hb.invA = c->pc_mem + offs[a][k][3];
       hb.lam = c->pc_mem + offs[a][k][4];
     }
+  return KV_OK;
+}
+
+int kv_set_gmres_restart(kv_ctx* c, int m) {
+  if (!c) return KV_EINVAL;
+  if (m < 10 || m > 400) return fail(c, KV_EINVAL, "GMRES restart length must be in 10..400");
+  c->gmres_m = m;
   return KV_OK;
 }
 

@@ -89,6 +89,7 @@ struct kv_ctx {
   int pc_kind = 0;            // KV_PC_NONE or KV_PC_STOKES
   double pc_sigma = 0.0;
   bool pc_active = false;     // set while a preconditioned solve runs
+  int gmres_m = 40;           // restart length of the GMRES continuation of the Newton correction
   int sym_ref = 0, sym_rot = 0;  // symmetry class kept by matvec while a restricted Arnoldi runs
   const double* lockQ = nullptr;  // locked W-orthonormal vectors matvec deflates while Arnoldi runs
   int nlock = 0;

@@ -36,7 +36,7 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
-               "kv_symmetry_project", "kv_hessenberg_eigenvalues",
+               "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.kv_hessenberg_eigenvalues.argtypes = [P, PD, ctypes.c_int, PD, PD]
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
+    lib.kv_set_gmres_restart.argtypes = [P, ctypes.c_int]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD, P,
                                             ctypes.POINTER(_EigInfo)]
@@ -262,6 +263,10 @@ class Context:
         """Stokes/heat right preconditioner for newton_correction (or none)."""
         self._check(self._lib.kv_set_preconditioner(self._h, KV_PC_STOKES if stokes else KV_PC_NONE,
                                                     float(sigma)))
+
+    def set_gmres_restart(self, m):
+        """Restart length of the GMRES continuation of newton_correction."""
+        self._check(self._lib.kv_set_gmres_restart(self._h, int(m)))
 
     def apply_preconditioner(self, x, y):
         self._check(self._lib.kv_apply_preconditioner(self._h, _dptr(x, self.n), _dptr(y, self.n)))

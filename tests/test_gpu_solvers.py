@@ -345,3 +345,28 @@ def test_hessenberg_eigenvalues_match_numpy():
             assert rc == kv.KV_EINVAL
     finally:
         ctx.close()
+
+
+def test_gmres_restart_setting():
+    """The GMRES restart length is checked and kept; a Newton correction with a
+    non-default length still meets the oracle's residual certificate."""
+    from paper_2210_08816_amd import kv
+    shape = (7, 6, 5)
+    fx = [faces("clustered", n) for n in shape]
+    g = O.Grid(*fx, Gr=1e4, Pr=0.71)
+    X0 = O.project(g, S.base_flow(*fx, K=3, amp=0.05, seed=31) + 0.01 * S.perturbation(g.size, 32))
+    ctx = context(fx, 1e4, 0.71, X0)
+    try:
+        for m in (9, 401):
+            assert ctx._lib.kv_set_gmres_restart(ctx._h, m) == kv.KV_EINVAL
+        ctx.set_gmres_restart(120)
+        F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        delta = torch.empty_like(F)
+        info = ctx.newton_correction(F, delta, tol=1e-10, max_matvec=4000)
+        assert info["status"] == 0, info
+        A = SV.Operator(g, X0)
+        Fo = SV.A_project(A, O.residual(g, X0))
+        assert A.norm(A(to_host(delta)) + Fo) / A.norm(Fo) <= 1e-9
+    finally:
+        ctx.close()
