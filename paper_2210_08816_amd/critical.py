@@ -10,7 +10,7 @@ geometric Gr sweep, then located by regula falsi in log Gr (Illinois
 variant), each new Gr solved by Newton from the nearest converged state.
 Every step runs in the library's kernels; this module sequences the calls.
 
-    python -m paper_2210_08816_amd.critical --n 24 --gr-lo 1e7 --gr-hi 2e8 --sym=-+
+    python -m paper_2210_08816_amd.critical --n 32 --gr-lo 4.2e7 --gr-hi 5.9e7 --sym mp --krylov 120 --gmres-restart 150
 """
 from __future__ import annotations
 
@@ -160,7 +160,8 @@ def main(argv=None):
     ap.add_argument("--gr-lo", type=float, default=1e7)
     ap.add_argument("--gr-hi", type=float, default=2e8)
     ap.add_argument("--ratio", type=float, default=1.6)
-    ap.add_argument("--sym", default=None, help="one symmetry class, e.g. --sym=-+ (reflection, 2-D rotation)")
+    ap.add_argument("--sym", default=None, help="one symmetry class as two signs (reflection, 2-D rotation), "
+                                                "p = kept, m = broken, e.g. --sym mp")
     ap.add_argument("--krylov", type=int, default=60)
     ap.add_argument("--max-matvec", type=int, default=60000, help="Arnoldi budget per Gr")
     ap.add_argument("--tol", type=float, default=1e-5, help="Arnoldi tolerance")

@@ -8,6 +8,7 @@ restricted to the class.
 
     python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --krylov 60 --eigs 10
     python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --sym all
+    python -m paper_2210_08816_amd.stability --n 64 --gr 4e7 --sym mp,mm
 """
 from __future__ import annotations
 
@@ -90,12 +91,16 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
 
 
 def parse_sym(text):
-    """'all' or '+-,--' style sign pairs (reflection, 2-D rotation) -> classes."""
-    if not text:
+    """'all', or comma-separated classes, each two signs (reflection, 2-D
+    rotation): '+' or 'p' kept, '-' or 'm' broken, '0' free; e.g. 'mp,mm'
+    (the letters avoid argparse reading a leading '--' as an option end)."""
+    if text is None:
         return None
+    if not isinstance(text, str) or not text:
+        raise ValueError("empty symmetry class (write broken/kept as m/p, e.g. --sym mm)")
     if text == "all":
         return [(1, 1), (1, -1), (-1, 1), (-1, -1)]
-    sign = {"+": 1, "-": -1, "0": 0}
+    sign = {"+": 1, "p": 1, "-": -1, "m": -1, "0": 0}
     out = []
     for pair in text.split(","):
         if len(pair) != 2 or any(ch not in sign for ch in pair):
@@ -121,7 +126,7 @@ def main(argv=None):
     ap.add_argument("--load-state", default=None, help="start from a stored converged state (.npy)")
     ap.add_argument("--sym", default=None,
                     help="symmetry classes for restricted Arnoldi runs: 'all', or a comma list of sign pairs "
-                         "(reflection, 2-D rotation) such as --sym=+-,-- (with '=' when the list starts with '-')")
+                         "(reflection, 2-D rotation), p = kept and m = broken, such as --sym pm,mm")
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,

@@ -64,3 +64,18 @@ def test_branch_lost_ends_the_sweep():
     out = find_crossing(sigma, 1e7, 1e9, ratio=1.6)
     assert out["gr"] is None and out["note"].startswith("branch not followed")
     assert calls[-1] > 5e7 and len([c for c in calls if c > 5e7]) == 1
+
+
+def test_symmetry_class_arguments():
+    """Classes on the command line: letters or signs; a value argparse has
+    eaten ('--sym=--' arrives as an empty list) is an error, not 'no class'."""
+    import argparse
+    import pytest
+    from paper_2210_08816_amd.stability import parse_sym
+    assert parse_sym("mm") == [(-1, -1)] and parse_sym("mp,pm") == [(-1, 1), (1, -1)]
+    assert parse_sym("-+") == [(-1, 1)] and parse_sym(None) is None and len(parse_sym("all")) == 4
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sym", default=None)
+    for bad in (ap.parse_args(["--sym=--"]).sym, "", "mx", "m"):
+        with pytest.raises(ValueError):
+            parse_sym(bad)
