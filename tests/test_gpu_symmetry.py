@@ -281,3 +281,46 @@ def test_arnoldi_eigenvectors(case):
         y = Y[j]
         cos = abs(np.dot(w * np.conj(x), y)) / np.sqrt(np.dot(w, np.abs(x) ** 2) * np.dot(w, np.abs(y) ** 2))
         assert cos > 1 - 1e-10, (lam, ovals[j], cos)
+
+
+def test_ritz_vectors_at_256():
+    """At the 256^3 workload size (no dense reference exists), one Arnoldi
+    cycle's returned Ritz vectors satisfy a property that holds at any size:
+    || A y - theta y ||_W equals the Ritz residual estimate h_{m+1,m} |e_m^T s|
+    of the Hessenberg data (unit W-norm vectors), for each output value."""
+    from paper_2210_08816_amd import kv
+    fx = [S.faces_clustered(256)] * 3
+    g = O.Grid(*fx, Gr=2e8, Pr=0.71)
+    ctx = kv.Context(*fx, Gr=2e8, Pr=0.71)
+    try:
+        ctx.set_base_flow(to_dev(S.base_flow(*fx, K=6, amp=0.1, seed=2)))
+        ev = torch.empty(5, g.size, dtype=torch.float64, device="cuda")
+        vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=20, n_eigs=4,
+                                                   max_restarts=0, evecs=ev, check=False)
+        assert info["n_out"] >= 4
+        Ay = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        Az = torch.empty_like(Ay)
+        q = 0
+        while q < len(vals):
+            lam = vals[q]
+            if lam.imag > 0:
+                re, im = ev[q], ev[q + 1]
+                ctx.apply_jacobian(re, Ay, project=True)
+                ctx.apply_jacobian(im, Az, project=True)
+                # A (re + i im) - lam (re + i im), split into real and imaginary parts
+                rr = Ay - lam.real * re + lam.imag * im
+                ri = Az - lam.imag * re - lam.real * im
+                rn = (ctx.dot(rr, rr) + ctx.dot(ri, ri)) ** 0.5
+                yn = (ctx.dot(re, re) + ctx.dot(im, im)) ** 0.5
+                step = 2
+            else:
+                ctx.apply_jacobian(ev[q], Ay, project=True)
+                rr = Ay - lam.real * ev[q]
+                rn, yn = ctx.dot(rr, rr) ** 0.5, ctx.dot(ev[q], ev[q]) ** 0.5
+                step = 1
+            print(f"value {lam}: residual {rn:.6e}, estimate {res[q]:.6e}", flush=True)
+            assert abs(yn - 1.0) < 1e-10
+            assert abs(rn - res[q]) <= 1e-6 * max(res[q], 1e-12 * abs(lam)), (lam, rn, res[q])
+            q += step
+    finally:
+        ctx.close()
