@@ -162,7 +162,8 @@ typedef struct {
 
 /* Newton correction (Sec. 1): delta with P J(X0) delta = -F, by BiCGstab(2)
  * (Sleijpen-Fokkema form, shadow vector = initial residual), continued by
- * restarted GMRES(40) from the current iterate after a breakdown or 50
+ * restarted GMRES(m) (m = 40 unless kv_set_gmres_restart changed it) from
+ * the current iterate after a breakdown or 50
  * cycles without a 10% residual reduction.  F is projected once more before
  * the solve, and a converged delta is projected once more at the end (the
  * Krylov combination is divergence-free only up to cancellation among its
