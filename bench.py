@@ -152,6 +152,27 @@ def symmetry_leg(torch, ctx, x, n, reps=50):
                          "kernel": "symmetry_class_kernel (4 launches, one per field)"}}
 
 
+def hessenberg_leg(ctx, sizes=(20, 60, 200), reps=5):
+    """Wall time of the GPU Francis QR on random upper Hessenberg matrices of
+    the Krylov dimensions Arnoldi uses (one wavefront; host upload and the
+    copy of the values back included).  It is latency-bound: what matters is
+    its share of an Arnoldi cycle."""
+    import numpy as np
+    out = {}
+    rng = np.random.default_rng(5)
+    for m in sizes:
+        H = np.triu(rng.standard_normal((m, m)), -1)
+        ctx.hessenberg_eigenvalues(H)
+        best = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            ctx.hessenberg_eigenvalues(H)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out[str(m)] = round(1e3 * best, 3)
+    return {"ms_by_dimension": out}
+
+
 def learned_leg(torch, steps=10):
     """Time kvnn training steps and predictions on a 64^3 network (the
     learned Newton guess's kernels)."""
@@ -342,6 +363,8 @@ def main():
         result["arnoldi_cycle"] = arnoldi_leg(torch, ctx, xs[0], n, forms["fp64"]["ms_per_step"])
         log("[bench] timing the symmetry-class projection")
         result["symmetry_project"] = symmetry_leg(torch, ctx, xs[0], n)
+        log("[bench] timing the Hessenberg QR")
+        result["hessenberg_qr"] = hessenberg_leg(ctx)
     if not args.no_learned:
         log("[bench] timing the learned-guess network kernels")
         result["learned"] = learned_leg(torch)
