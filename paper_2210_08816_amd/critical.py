@@ -105,10 +105,12 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
     from .continuation import sweep
     f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
     faces = (f, f, f)
+    # continuation from rest to gr_lo in steps of 1.6 (the bracketing ratio
+    # may be much finer)
     grs, g = [], 1e4
     while g < gr_lo:
         grs.append(g)
-        g *= ratio
+        g *= 1.6
     grs.append(gr_lo)
     t0 = time.perf_counter()
     states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
