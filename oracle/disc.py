@@ -25,8 +25,8 @@ the second-order conservative staggered (MAC) finite-volume scheme:
   * conservative convective fluxes, two-point diffusive fluxes, wall values
     imposed at half-cell distance.
 N(X) is the steady right-hand side without the pressure term; the pressure is
-handled by the discrete Leray projection P = I - G L^+ D (the "divergence free
-Krylov vectors satisfying all the boundary conditions" of Sec. 3).
+handled by the discrete Leray projection P = I - G L^+ D, which gives the
+divergence-free Krylov vectors that meet every boundary condition (Sec. 3).
 
 Arrays are numpy (z, y, x) with x fastest, i.e. the packed layout of synth.
 """

@@ -17,7 +17,10 @@ Readings (the paper gives no parameters; its refs [21], [22] are absent):
   * Arnoldi with classical Gram-Schmidt applied twice (CGS2).
   * Chebyshev-Arnoldi in the style of Saad (1984): restarted Arnoldi whose
     restart vector is filtered by a Chebyshev polynomial on the ellipse
-    enclosing the unwanted Ritz values.
+    enclosing the unwanted Ritz values; the restart vector weights each
+    wanted Ritz vector against its growth under the filter, and converged
+    values are locked in leading order (Schur deflation of their invariant
+    subspaces).
 """
 from __future__ import annotations
 
