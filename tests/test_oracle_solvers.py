@@ -260,3 +260,46 @@ def test_locked_cheb_arnoldi_in_a_symmetry_class():
         r = A(y.real) + 1j * A(y.imag) - vals[i] * y
         assert np.sqrt(A.norm(r.real) ** 2 + A.norm(r.imag) ** 2) <= 1e-8 * scale * np.sqrt(
             A.norm(y.real) ** 2 + A.norm(y.imag) ** 2)
+
+
+def test_lift_from_deflated_operator():
+    """lift(): with Q an orthonormal basis of an invariant subspace of M (its
+    leading real Schur vectors), every eigenvector y of the deflated operator
+    (I - Q Q^T) M on the complement of span(Q) lifts to an eigenvector of M
+    with the same eigenvalue; the Deflated operator has the remaining
+    eigenvalues of M (and 0 on span(Q))."""
+    class Dense:
+        def __init__(self, M):
+            self.M, self.w, self.matvecs = M, np.ones(M.shape[0]), 0
+            self.g = self.fd = None
+
+        def __call__(self, x):
+            self.matvecs += 1
+            return self.M @ x
+
+        def dot(self, a, b):
+            return float(np.dot(a, b))
+
+        def norm(self, a):
+            return float(np.sqrt(np.dot(a, a)))
+
+    rng = np.random.default_rng(3)
+    n, k = 12, 4
+    M = rng.standard_normal((n, n))
+    T, Z = sl.schur(M, output="real")
+    if abs(T[k, k - 1]) > 0:          # do not split a 2x2 block
+        k += 1
+    Q = Z[:, :k].T                     # rows: W-orthonormal (W = I) basis
+    A = Dense(M)
+    B = SV.Deflated(A, Q)
+    Bm = np.array([B(e) for e in np.eye(n)]).T
+    A.matvecs = 0
+    lamB, vecB = np.linalg.eig(Bm)
+    lamM = np.linalg.eigvals(M)
+    for lam, y in zip(lamB, vecB.T):
+        if abs(lam) < 1e-10:
+            continue                   # span(Q) itself
+        assert np.min(np.abs(lamM - lam)) < 1e-10
+        x = SV.lift(A, Q, y, lam)
+        assert np.linalg.norm(M @ x - lam * x) <= 1e-10 * np.linalg.norm(x)
+    assert A.matvecs == 0              # lift does not count matvecs
