@@ -41,9 +41,14 @@
  *   - Return value: KV_OK or an error code; nothing throws across the ABI.
  *     kv_last_error(ctx) gives a message for the last failed call.
  *   - Calls that need a base flow return KV_ESTATE before kv_set_base_flow.
- *   - The library allocates its own device scratch with hipMalloc inside
- *     kv_create (cell fields, metrics) and lazily inside the solvers (Krylov
- *     bases); kv_destroy frees it.
+ *   - The library allocates device memory only in kv_create (metrics,
+ *     fast-diagonalization bases, two cell fields, reduction partials) and
+ *     kv_set_preconditioner (the preconditioner's bases); kv_destroy frees
+ *     it.  Every vector-sized scratch of a call (Krylov bases, solver
+ *     vectors, the mixed form's scratch vector, the preconditioner's vectors)
+ *     comes from a caller-owned workspace (kv_workspace_size,
+ *     kv_set_workspace), so the caller's allocator (e.g. torch's) owns all
+ *     memory that grows with the solver settings.
  *   - A context is not thread safe; calls on one context must not overlap.
  */
 #ifndef KV_H
@@ -93,6 +98,36 @@ int kv_destroy(kv_ctx* ctx);
 
 /* Packed size n and block offsets off[0..4] (u, v, w, T, end). host out. */
 int kv_layout(const kv_ctx* ctx, int64_t* n, int64_t off[5]);
+
+/* Caller-owned workspace.  The calls below carve their vector-sized scratch
+ * from one device buffer that the caller allocates and keeps alive:
+ *   KV_WS_PROJECT_MIXED         kv_apply_jacobian / kv_project with KV_MIXED
+ *                               (1 packed vector)
+ *   KV_WS_APPLY_PRECONDITIONER  kv_apply_preconditioner (1 vector)
+ *   KV_WS_NEWTON                kv_newton_correction: 8 BiCGstab(2) vectors,
+ *                               the GMRES(m) basis (m + 1, m of
+ *                               kv_set_gmres_restart) and, with a
+ *                               preconditioner set, 3 more vectors
+ *   KV_WS_ARNOLDI               kv_arnoldi_leading_eigs: the Krylov basis
+ *                               (krylov_dim + 1), 3 filter vectors, 2 (n_eigs
+ *                               + 1) locked and Ritz vectors, and the
+ *                               Hessenberg / Ritz-vector area
+ * kv_workspace_size writes the bytes op needs (host out; krylov_dim and
+ * n_eigs are read for KV_WS_ARNOLDI only; the Newton size depends on the
+ * current GMRES restart and preconditioner, so query after setting them).
+ * kv_set_workspace records dev_ptr (device, 8-byte aligned, bytes long;
+ * NULL and 0 detach it); the library never frees it, and it must outlive
+ * every call that uses it.  A call whose op needs more than is set returns
+ * KV_EINVAL and does nothing.  One workspace serves every op (calls on a
+ * context do not overlap).  Errors: KV_EINVAL (unknown op, bad sizes). */
+enum kv_workspace_op {
+  KV_WS_PROJECT_MIXED = 1,
+  KV_WS_APPLY_PRECONDITIONER = 2,
+  KV_WS_NEWTON = 3,
+  KV_WS_ARNOLDI = 4
+};
+int kv_workspace_size(const kv_ctx* ctx, int op, int krylov_dim, int n_eigs, size_t* bytes);
+int kv_set_workspace(kv_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Store the base flow X0 (device, packed, n values; copied).  Sec. 1: the
  * Jacobian is taken about the steady flow.  KV_ENONFINITE if X0 holds a NaN
@@ -182,9 +217,17 @@ int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matve
  * kv_newton_correction (Sec. 1: BiCGstab(2) combined with GMRES); 10 <= m <=
  * 400, default 40.  A longer restart keeps the few eigenvalues of P J near
  * the imaginary axis, which a steady branch close to a Hopf point has, in the
- * Krylov space (restarting discards them); the workspace grows to m + 9
- * vectors.  Kept until changed. */
+ * Krylov space (restarting discards them); the KV_WS_NEWTON workspace grows
+ * to m + 9 vectors.  Kept until changed. */
 int kv_set_gmres_restart(kv_ctx* ctx, int m);
+
+/* Stagnation limit of the BiCGstab(2) part of kv_newton_correction (Sec. 1:
+ * BiCGstab(2) combined with GMRES): after this many cycles without a 10%
+ * drop of the residual norm below its best value the solve continues as
+ * restarted GMRES(m) from the current iterate.  0 <= cycles <= 100000,
+ * default 50; 0 hands the solve to GMRES before the first BiCGstab(2) cycle.
+ * Kept until changed. */
+int kv_set_bicgstab_stall(kv_ctx* ctx, int cycles);
 
 /* Preconditioner of the Newton correction (an addition: the paper names no
  * preconditioner; Sec. 1 gives BiCGstab(2) with GMRES).  KV_PC_STOKES: right
@@ -195,8 +238,8 @@ int kv_set_gmres_restart(kv_ctx* ctx, int m);
  * diagonalization (1-D eigenbases per axis, FP64 matrix cores): Stokes
  * preconditioning in Tuckerman's sense.  Kept until changed; KV_PC_NONE
  * switches it off.  sigma >= 0 (host).  The first KV_PC_STOKES call builds
- * the bases (9 symmetric eigenproblems on the host) and allocates two packed
- * vectors. */
+ * the bases (9 symmetric eigenproblems on the host); the solve's three
+ * extra vectors come from the KV_WS_NEWTON workspace. */
 enum kv_preconditioner { KV_PC_NONE = 0, KV_PC_STOKES = 1 };
 int kv_set_preconditioner(kv_ctx* ctx, int kind, double sigma);
 
@@ -224,6 +267,12 @@ typedef struct {
   int matvecs;
   int restarts;
   int converged;  /* 1 if the tolerance was met */
+  int relaxed_qr; /* cycles whose Hessenberg QR took a deflation only the
+                     relaxed test allows (after 100 iterations without one
+                     the test |h_{k,k-1}| <= eps (|h_kk| + |h_{k-1,k-1}|)
+                     relaxes to sqrt(eps): a nearly defective Ritz cluster,
+                     whose values are then fixed only to about sqrt(eps)
+                     relative); 0 when every deflation met eps */
 } kv_eig_info;
 
 /* Leading eigenvalues (largest real part first, +Im before -Im within a
@@ -257,7 +306,9 @@ int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam
 /* Eigenvalues of a small upper Hessenberg matrix on the GPU: the Ritz
  * values of an Arnoldi cycle (Sec. 1) come from this Francis double-shift QR
  * (one wavefront; an exceptional shift pair every tenth iteration without a
- * deflation).  H: host, m x m row-major, entries below the first subdiagonal
+ * deflation; after 100 iterations without a deflation the deflation test
+ * relaxes from eps to sqrt(eps), which kv_eig_info.relaxed_qr counts in
+ * Arnoldi).  H: host, m x m row-major, entries below the first subdiagonal
  * ignored; 1 <= m <= 400.  wr, wi: host, m values each, in the order the QR
  * deflates them (a complex pair as +Im, -Im in consecutive entries).
  * KV_ENONFINITE on a non-finite entry, KV_ENOCONV when the QR does not

@@ -72,6 +72,9 @@ def bicgstab2(A: Operator, b, x0=None, tol=1e-8, max_matvec=10000,
         if res <= tol * bnorm:
             status = "converged"
             break
+        if cycles - best_cycle >= stall_cycles:         # no 10% drop for that long
+            status = "stagnation"
+            break
         if A.matvecs - m0 + 4 > max_matvec:
             status = "maxit"
             break
@@ -117,9 +120,6 @@ def bicgstab2(A: Operator, b, x0=None, tol=1e-8, max_matvec=10000,
                            status="breakdown")
         if res < 0.9 * best:
             best, best_cycle = res, cycles
-        elif cycles - best_cycle >= stall_cycles:
-            status = "stagnation"
-            break
     return x, dict(relres=res / bnorm, matvecs=A.matvecs - m0, cycles=cycles,
                    status=status)
 
@@ -151,11 +151,13 @@ def gmres(A: Operator, b, x0=None, tol=1e-8, m=40, max_matvec=10000):
 
 
 def newton_correction(A: Operator, F, tol=1e-8, max_matvec=10000, delta0=None,
-                      gmres_m=40):
+                      gmres_m=40, stall_cycles=50):
     """delta with P J delta = -F: BiCGstab(2), continued by GMRES(m) from the
-    current iterate after a breakdown or stagnation."""
+    current iterate after a breakdown or stagnation (stall_cycles cycles
+    without a 10% residual drop; 0 hands over before the first cycle)."""
     F = A_project(A, F)
-    delta, info = bicgstab2(A, -F, x0=delta0, tol=tol, max_matvec=max_matvec)
+    delta, info = bicgstab2(A, -F, x0=delta0, tol=tol, max_matvec=max_matvec,
+                            stall_cycles=stall_cycles)
     info["used_gmres"] = 0
     if info["status"] in ("breakdown", "stagnation"):
         left = max_matvec - info["matvecs"]

@@ -47,17 +47,18 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
         mv += info["matvecs"]
         if info["status"] != 0:
             break
-        X += d
+        ctx.axpby(1.0, d, 1.0, X)  # X <- X + delta on the device
     torch.cuda.synchronize()
     return dict(converged=ok, hist=hist, matvecs=mv, iters=len(hist) - 1, seconds=time.perf_counter() - t0)
 
 
 def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12,
-          precond_sigma=None, gmres_restart=None, **kw):
+          precond_sigma=None, gmres_restart=None, gr0=None, **kw):
     """Continuation over increasing Gr values, from X0 (default: the
-    conduction state).  A failed step is retried from the last converged
-    state at the geometric midpoint in Gr, at most max_halvings times per
-    requested value.  precond_sigma: None, or the shift of the Stokes/heat
+    conduction state) converged at Gr = gr0 (None: X0 is not a converged
+    state).  A failed step is retried from the last converged state at the
+    geometric midpoint in Gr, at most max_halvings times per requested value
+    (a first step from an X0 without gr0 is not retried).  precond_sigma: None, or the shift of the Stokes/heat
     preconditioner of the Newton corrections; gmres_restart: None (the
     library's default) or the restart length of their GMRES continuation.
     Returns (states, infos) for
@@ -69,7 +70,7 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
         X0 = _conduction_state(*faces)
     X = torch.as_tensor(X0, dtype=torch.float64).cuda().clone()
     states, infos = [], []
-    gr_last = None
+    gr_last = gr0
     for Gr in grs:
         target, halvings = Gr, 0
         spent_mv, spent_s = 0, 0.0   # over every attempt for this value

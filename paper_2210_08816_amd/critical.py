@@ -19,7 +19,7 @@ import math
 import time
 
 
-def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=None):
+def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=None, same_mode=None):
     """Bracket and locate Gr with sigma(Gr) = 0 for Gr in [gr_lo, gr_hi].
 
     sigma(Gr) returns (value, info) for increasing Gr calls during the sweep
@@ -29,21 +29,37 @@ def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=N
     up by ratio (the last step clipped to gr_hi) until the sign changes from
     negative to non-negative.  Then regula falsi in log Gr, the retained end
     halved in weight after two moves of the same end (Illinois), until the
-    bracket is within a factor 1 + rtol.  Returns a dict: 'gr' (None if no
-    crossing in the range, or if the first converged value is not negative),
-    'bracket', 'history' [(Gr, value, info), ...]."""
-    hist = []
+    bracket is within a factor 1 + rtol.
 
+    same_mode(info_a, info_b), if given, tells whether the leading values of
+    two points belong to one eigenmode; a bracket whose ends are different
+    modes is not a crossing, and a refinement point of another mode than the
+    end it would replace counts as not converged.
+
+    Returns a dict: 'gr' (the interpolated crossing, or None if there is no
+    crossing in the range, the first converged value is not negative, the
+    bracket ends are different modes, or the refinement stopped before the
+    bracket was within 1 + rtol), 'converged' (True only in the last case's
+    opposite: a bracket within 1 + rtol of one mode), 'gr_estimate' (the
+    interpolation in the bracket, also when not converged), 'bracket',
+    'history' [(Gr, value, info), ...] and 'note' when gr is None."""
+    hist = []
     stop = []
+    infos = {}
 
     def ev(gr):
         val, info = sigma(gr)
         hist.append((gr, val, info))
+        infos[gr] = info
         if info.get("stop"):
             stop.append(gr)
         if log:
             log(f"[critical] Gr={gr:.6e} sigma={val}")
         return val
+
+    def none(note, bracket=None, est=None):
+        return {"gr": None, "converged": False, "gr_estimate": est, "bracket": bracket, "history": hist,
+                "note": note}
 
     a, fa = None, None
     gr = gr_lo
@@ -51,43 +67,73 @@ def find_crossing(sigma, gr_lo, gr_hi, ratio=1.6, rtol=1e-3, max_evals=40, log=N
         f = ev(gr)
         if f is not None:
             if f >= 0.0 and a is None:   # the branch is not stable where the sweep starts
-                return {"gr": None, "bracket": None, "history": hist, "note": "unstable at the start"}
+                return none("unstable at the start")
             if f >= 0.0:
                 b, fb = gr, f
                 break
             a, fa = gr, f
         if stop:
-            return {"gr": None, "bracket": None, "history": hist, "note": f"branch not followed to Gr = {stop[0]:.6g}"}
+            return none(f"branch not followed to Gr = {stop[0]:.6g}")
         if gr >= gr_hi or len(hist) >= max_evals:
-            return {"gr": None, "bracket": None, "history": hist}
+            return none("no crossing in the range")
         gr = min(gr * ratio, gr_hi)
+    if same_mode is not None and not same_mode(infos[a], infos[b]):
+        return none("the bracket ends are different eigenmodes", (a, b))
     if fb == 0.0:
-        return {"gr": b, "bracket": (a, b), "history": hist}
+        return {"gr": b, "converged": True, "gr_estimate": b, "bracket": (a, b), "history": hist}
     la, lb = math.log(a), math.log(b)
+    ends = [a, b]                  # the bracket ends' own Gr (keys of infos)
     side = 0
+
+    def mode_ok(gr_c, fc):
+        if fc is None or same_mode is None:
+            return fc
+        end = ends[0] if fc < 0.0 else ends[1]
+        return fc if same_mode(infos[end], infos[gr_c]) else None
+
     while lb - la > math.log1p(rtol) and len(hist) < max_evals:
         lc = lb - fb * (lb - la) / (fb - fa)
         lc = min(max(lc, la + 1e-3 * (lb - la)), lb - 1e-3 * (lb - la))
-        fc = ev(math.exp(lc))
-        if fc is None and not stop:          # not converged: bisect instead
+        gc = math.exp(lc)
+        fc = mode_ok(gc, ev(gc))
+        if fc is None and not stop:          # not converged or another mode: bisect instead
             lc = 0.5 * (la + lb)
-            fc = ev(math.exp(lc))
+            gc = math.exp(lc)
+            fc = mode_ok(gc, ev(gc))
         if fc is None:
             break
         if fc == 0.0:
-            return {"gr": math.exp(lc), "bracket": (math.exp(lc), math.exp(lc)), "history": hist}
+            return {"gr": gc, "converged": True, "gr_estimate": gc, "bracket": (gc, gc), "history": hist}
         if fc < 0.0:
             la, fa = lc, fc
+            ends[0] = gc
             if side == -1:
                 fb *= 0.5
             side = -1
         else:
             lb, fb = lc, fc
+            ends[1] = gc
             if side == 1:
                 fa *= 0.5
             side = 1
     gr_c = math.exp(lb - fb * (lb - la) / (fb - fa))
-    return {"gr": gr_c, "bracket": (math.exp(la), math.exp(lb)), "history": hist}
+    bracket = (ends[0], ends[1])
+    if lb - la > math.log1p(rtol):
+        return none(f"refinement stopped with the bracket [{bracket[0]:.6g}, {bracket[1]:.6g}] wider than "
+                    f"1 + rtol", bracket, gr_c)
+    return {"gr": gr_c, "converged": True, "gr_estimate": gr_c, "bracket": bracket, "history": hist}
+
+
+def same_mode_by_frequency(info_a, info_b, rel=0.25, abs_tol=0.02):
+    """One eigenmode at two Gr: the leading values' |Im lambda| agree within
+    rel of the larger plus abs_tol (the frequency of a mode moves slowly with
+    Gr; a switch to another mode of the cluster near the axis changes it by
+    much more, e.g. 0.043 against 0.67 on the 32^3 grid)."""
+    va, vb = info_a.get("values"), info_b.get("values")
+    if not va or not vb:
+        return False
+    ia, ib = abs(va[0][1]), abs(vb[0][1])
+    return abs(ia - ib) <= rel * max(ia, ib) + abs_tol
 
 
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
@@ -125,7 +171,7 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         near = min(known, key=lambda t: abs(math.log(t[0] / gr)))
         X = near[1]
         if near[0] != gr:
-            st, inf = sweep(faces, [gr], Pr=Pr, X0=near[1], max_matvec=newton_max_matvec, max_iter=20,
+            st, inf = sweep(faces, [gr], Pr=Pr, X0=near[1], gr0=near[0], max_matvec=newton_max_matvec, max_iter=20,
                             precond_sigma=precond_sigma, gmres_restart=gmres_restart, log=lambda m: None)
             counts["newton_matvecs"] += sum(i.get("matvecs_all_attempts", i["matvecs"]) for i in inf)
             if not st:
@@ -146,9 +192,10 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
             return None, {"arnoldi": "not converged", "values": lead, "residuals": resid}
         return float(vals[0].real), {"values": lead, "residuals": resid, "matvecs": info["matvecs"]}
 
-    out = find_crossing(sigma, gr_lo, gr_hi, ratio=ratio, rtol=rtol, log=log)
+    out = find_crossing(sigma, gr_lo, gr_hi, ratio=ratio, rtol=rtol, log=log, same_mode=same_mode_by_frequency)
     return {"grid": f"{n}^3 {grid}", "Pr": Pr, "symmetry_class": list(sym) if sym else None,
-            "gr_critical": out["gr"], "bracket": out["bracket"], "note": out.get("note"),
+            "gr_critical": out["gr"], "converged": out["converged"], "gr_estimate": out["gr_estimate"],
+            "bracket": out["bracket"], "note": out.get("note"),
             "history": [{"Gr": gr, "re_lambda1": val, **info} for gr, val, info in out["history"]],
             "seconds": round(time.perf_counter() - t0, 3), **counts}
 

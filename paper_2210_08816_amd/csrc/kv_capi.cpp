@@ -249,18 +249,15 @@ int project_inplace(kv_ctx* c, double* y) {
 // most 8 sweeps).
 constexpr double kMixedDivTol = 1e-10;
 
+int ws_bind(kv_ctx* c, int op, int m, int neig);
+
 int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
   const int64_t C = c->ncell;
-  if (!c->ymix) {
-    if (hipMalloc(&c->ymix, c->g.n * sizeof(double)) != hipSuccess) {
-      c->ymix = nullptr;
-      return fail(c, KV_ENOMEM, "cannot allocate the mixed-form scratch vector");
-    }
-  }
+  int rc = ws_bind(c, KV_WS_PROJECT_MIXED, 0, 0);
+  if (rc) return rc;
   // FP32 fields inside the two FP64 cell buffers
   float* F0 = reinterpret_cast<float*>(c->cellA);
   float* F1 = F0 + C;
-  int rc;
   {
     PhaseMark pm(c, 1);
     HIPCHK(c, launch_scaled_divergence_f32(c, y, F0));
@@ -412,27 +409,62 @@ int check_finite(kv_ctx* c, const double* a, int64_t n, const char* what) {
   return KV_OK;
 }
 
-int ensure_work(kv_ctx* c, size_t nvec) {
-  const size_t bytes = nvec * (size_t)c->g.n * sizeof(double);
-  if (bytes <= c->work_bytes) return KV_OK;
-  if (c->work) hipFree(c->work);
-  c->work = nullptr;
-  c->work_bytes = 0;
-  if (hipMalloc(&c->work, bytes) != hipSuccess) {
-    c->work = nullptr;
-    return fail(c, KV_ENOMEM, "cannot allocate solver workspace");
-  }
-  c->work_bytes = bytes;
-  return KV_OK;
+// ---- caller workspace ------------------------------------------------------------------
+// Doubles of the Hessenberg / Ritz-vector area for k Arnoldi steps and nsel
+// wanted values: H_k and a copy, eigenvalues, selected values, coefficient
+// vectors, info, and a k x k complex matrix plus a right-hand side per value.
+size_t hess_area(int k, int nsel) {
+  const size_t kk = (size_t)k * k;
+  return 4 * kk + 4 * (size_t)k + 2 + 2 * (size_t)nsel * (kk + (size_t)k);
 }
 
-int ensure_hess(kv_ctx* c, size_t bytes) {
-  if (bytes <= c->hess_bytes) return KV_OK;
-  if (c->hess) hipFree(c->hess);
-  c->hess = nullptr;
-  c->hess_bytes = 0;
-  if (hipMalloc(&c->hess, bytes) != hipSuccess) return fail(c, KV_ENOMEM, "cannot allocate Hessenberg workspace");
-  c->hess_bytes = bytes;
+// Packed vectors an operation carves from the workspace (see ws_bind).
+size_t ws_vectors(const kv_ctx* c, int op, int m, int neig) {
+  switch (op) {
+    case KV_WS_PROJECT_MIXED: return 1;
+    case KV_WS_APPLY_PRECONDITIONER: return 1;
+    case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0);
+    case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1);
+    default: return 0;
+  }
+}
+
+size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
+  size_t bytes = ws_vectors(c, op, m, neig) * (size_t)c->g.n * sizeof(double);
+  if (op == KV_WS_ARNOLDI) bytes += hess_area(m, neig + 1) * sizeof(double);
+  return bytes;
+}
+
+// Points the per-call scratch of an operation into the caller's workspace
+// (KV_EINVAL when none is set or it is too small).  Layouts, in packed
+// vectors of n doubles:
+//   PROJECT_MIXED          ymix
+//   APPLY_PRECONDITIONER   pc_scr
+//   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr
+//   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) | Hessenberg area
+int ws_bind(kv_ctx* c, int op, int m, int neig) {
+  const size_t need = ws_need(c, op, m, neig);
+  if (!c->ws || c->ws_bytes < need) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "workspace too small: the call needs %zu bytes, %zu are set (kv_workspace_size, kv_set_workspace)",
+             need, c->ws ? c->ws_bytes : (size_t)0);
+    return fail(c, KV_EINVAL, msg);
+  }
+  const int64_t n = c->g.n;
+  switch (op) {
+    case KV_WS_PROJECT_MIXED: c->ymix = c->ws; break;
+    case KV_WS_APPLY_PRECONDITIONER: c->pc_scr = c->ws; break;
+    case KV_WS_NEWTON:
+      if (c->pc_kind != KV_PC_NONE) {
+        double* p = c->ws + (int64_t)(8 + c->gmres_m + 1) * n;
+        c->pc_tmp = p;
+        c->pc_d0 = p + n;
+        c->pc_scr = p + 2 * n;
+      }
+      break;
+    case KV_WS_ARNOLDI: c->hess = c->ws + (int64_t)(m + 4 + 2 * (neig + 1)) * n; break;
+    default: return fail(c, KV_EINVAL, "unknown workspace operation");
+  }
   return KV_OK;
 }
 
@@ -503,11 +535,8 @@ std::vector<int> wanted_set(const std::vector<std::complex<double>>& v, int k) {
 int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out) {
   // device layout: Hk (k*k) | Hcopy (k*k) | wr k | wi k | lr, li (k each) | vr, vi (k*k) | info | cwork
   const size_t kk = (size_t)k * k;
-  const size_t nd = 2 * kk + 4 * (size_t)k + 2 * kk + 2;
-  const size_t cw = 2 * ((size_t)k * kk + (size_t)k * k);  // complex work for up to k vectors
   int rc;
-  if ((rc = ensure_hess(c, (nd + cw) * sizeof(double)))) return rc;
-  double* d = c->hess;
+  double* d = c->hess;  // hess_area(k, n_eigs + 1) doubles, bound by the Arnoldi call
   double *dH = d, *dHc = d + kk, *dwr = d + 2 * kk, *dwi = dwr + k, *dlr = dwi + k, *dli = dlr + k;
   double *dvr = dli + k, *dvi = dvr + kk;
   int* dinfo = reinterpret_cast<int*>(dvi + kk);
@@ -524,7 +553,8 @@ int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz
   HIPCHK(c, hipMemcpyAsync(wi.data(), dwi, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (info) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
+  if (info & 1) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
+  if (info & 2) ++c->relaxed_qr;  // a nearly defective cluster deflated at sqrt(eps)
   out.vals.resize(k);
   for (int i = 0; i < k; ++i) out.vals[i] = {wr[i], wi[i]};
   out.sel = wanted_set(out.vals, n_eigs);
@@ -851,6 +881,15 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   }
   if (hipHostMalloc(&c->hres, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(KV_ENOMEM, "hres");
+  // kv_hessenberg_eigenvalues (m <= 400) and the interpolation tables of
+  // kv_state_from_cells: small, fixed by the limits and the grid
+  if (hipMalloc(&c->hess_small, (400 * 400 + 2 * 400 + 2) * sizeof(double)) != hipSuccess)
+    return cleanup(KV_ENOMEM, "hess_small");
+  {
+    const int64_t nint = (2 * nx + 1) + (2 * ny + 1) + (2 * nz + 1);
+    c->xfer_bytes = ((size_t)nint * sizeof(int) + 255) / 256 * 256 + (size_t)nint * sizeof(double);
+    if (hipMalloc(&c->xfer, c->xfer_bytes) != hipSuccess) return cleanup(KV_ENOMEM, "xfer");
+  }
   *out = c;
   return KV_OK;
 }
@@ -866,7 +905,6 @@ int kv_destroy(kv_ctx* c) {
     hipFree(c->Qf32[a]);
     hipFree(c->Qt32[a]);
   }
-  hipFree(c->ymix);
   hipFree(c->cell_part);
   hipFree(c->X0);
   hipFree(c->cellA);
@@ -879,13 +917,9 @@ int kv_destroy(kv_ctx* c) {
     hipEventDestroy(m.second.second);
   }
   for (auto e : c->ev_pool) hipEventDestroy(e);
-  hipFree(c->work);
-  hipFree(c->hess);
+  hipFree(c->hess_small);
   hipFree(c->xfer);
   hipFree(c->pc_mem);
-  hipFree(c->pc_tmp);
-  hipFree(c->pc_d0);
-  hipFree(c->pc_scr);
   delete c;
   return KV_OK;
 }
@@ -997,7 +1031,7 @@ static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, doub
                        int* used, int* cycles, double* relres) {
   const int64_t n = c->g.n;
   int rc;
-  double* V = c->work + 8 * n;  // caller reserved 8 + m + 1 vectors
+  double* V = c->ws + 8 * n;  // after the 8 BiCGstab(2) vectors (ws_bind, KV_WS_NEWTON)
   std::vector<double> H;
   for (;;) {
     // r = b - A x into V[0]
@@ -1086,10 +1120,10 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
   const int64_t n = c->g.n;
   int rc;
   if ((rc = check_finite(c, F, n, "F"))) return rc;
-  // BiCGstab(2) vectors and the GMRES(m) basis, reserved together so that the
-  // fallback never reallocates live vectors
-  if ((rc = ensure_work(c, 8 + (size_t)c->gmres_m + 1))) return rc;
-  double* W = c->work;
+  // BiCGstab(2) vectors and the GMRES(m) basis (and the preconditioner's
+  // vectors) from the caller's workspace
+  if ((rc = ws_bind(c, KV_WS_NEWTON, 0, 0))) return rc;
+  double* W = c->ws;
   double *b = W, *rt = W + n, *r0 = W + 2 * n, *r1 = W + 3 * n, *r2 = W + 4 * n;
   double *u0 = W + 5 * n, *u1 = W + 6 * n, *u2 = W + 7 * n;
   double* r[3] = {r0, r1, r2};
@@ -1133,6 +1167,10 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
   for (;;) {
     if (res <= tol * bnorm) {
       status = CONV;
+      break;
+    }
+    if (inf.cycles - best_cycle >= c->stall_cycles) {
+      status = STAG;
       break;
     }
     if (inf.matvecs + 4 > max_matvec) {
@@ -1202,9 +1240,6 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
     if (res < 0.9 * best) {
       best = res;
       best_cycle = inf.cycles;
-    } else if (inf.cycles - best_cycle >= 50) {
-      status = STAG;
-      break;
     }
   }
   inf.relres = res / bnorm;
@@ -1212,7 +1247,11 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
     inf.used_gmres = 1;
     int used = inf.matvecs, cyc = inf.cycles;
     double rr = inf.relres;
-    rc = gmres_solve(c, b, bnorm, x, tol, c->gmres_m, max_matvec, &used, &cyc, &rr);
+    // With the preconditioner and an initial iterate the Krylov unknown x
+    // solves P J M^-1 x = b - P J delta0, whose right-hand side is the
+    // initial residual: the shadow vector rt still holds it.
+    const double* rhs = (c->pc_active && delta0) ? rt : b;
+    rc = gmres_solve(c, rhs, bnorm, x, tol, c->gmres_m, max_matvec, &used, &cyc, &rr);
     inf.matvecs = used;
     inf.cycles = cyc;
     inf.relres = rr;
@@ -1311,20 +1350,9 @@ static int build_preconditioner(kv_ctx* c) {
       for (int q = 0; q < 5; ++q) offs[a][k][q] = o + (size_t)q * m * m;
       o += 4 * (size_t)m * m + m;
     }
-  const int64_t n = c->g.n;
   if (hipMalloc(&c->pc_mem, total * sizeof(double)) != hipSuccess) {
     c->pc_mem = nullptr;
     return fail(c, KV_ENOMEM, "preconditioner bases");
-  }
-  if (hipMalloc(&c->pc_tmp, n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->pc_d0, n * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->pc_scr, n * sizeof(double)) != hipSuccess) {
-    hipFree(c->pc_mem);
-    hipFree(c->pc_tmp);
-    hipFree(c->pc_d0);
-    hipFree(c->pc_scr);
-    c->pc_mem = c->pc_tmp = c->pc_d0 = c->pc_scr = nullptr;
-    return fail(c, KV_ENOMEM, "preconditioner vectors");
   }
   int rc = upload(c, c->pc_mem, host.data(), total * sizeof(double));
   if (rc) return rc;
@@ -1348,6 +1376,32 @@ int kv_set_gmres_restart(kv_ctx* c, int m) {
   return KV_OK;
 }
 
+int kv_workspace_size(const kv_ctx* c, int op, int krylov_dim, int n_eigs, size_t* bytes) {
+  if (!c || !bytes) return KV_EINVAL;
+  if (op < KV_WS_PROJECT_MIXED || op > KV_WS_ARNOLDI) return KV_EINVAL;
+  if (op == KV_WS_ARNOLDI && (krylov_dim < 2 || krylov_dim > 400 || n_eigs < 1 || n_eigs >= krylov_dim))
+    return KV_EINVAL;
+  *bytes = ws_need(c, op, krylov_dim, n_eigs);
+  return KV_OK;
+}
+
+int kv_set_workspace(kv_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return KV_EINVAL;
+  if ((dev_ptr == nullptr) != (bytes == 0)) return fail(c, KV_EINVAL, "workspace pointer and size must both be set or both be 0");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 8) return fail(c, KV_EINVAL, "workspace must be 8-byte aligned");
+  c->ws = static_cast<double*>(dev_ptr);
+  c->ws_bytes = bytes;
+  c->ymix = c->pc_tmp = c->pc_d0 = c->pc_scr = c->hess = nullptr;
+  return KV_OK;
+}
+
+int kv_set_bicgstab_stall(kv_ctx* c, int cycles) {
+  if (!c) return KV_EINVAL;
+  if (cycles < 0 || cycles > 100000) return fail(c, KV_EINVAL, "stall cycles must be in 0..100000");
+  c->stall_cycles = cycles;
+  return KV_OK;
+}
+
 int kv_set_preconditioner(kv_ctx* c, int kind, double sigma) {
   if (!c) return KV_EINVAL;
   if (kind != KV_PC_NONE && kind != KV_PC_STOKES) return fail(c, KV_EINVAL, "unknown preconditioner");
@@ -1365,6 +1419,8 @@ int kv_apply_preconditioner(kv_ctx* c, const double* x, double* y) {
   if (!c) return KV_EINVAL;
   if (!x || !y) return fail(c, KV_EINVAL, "null argument");
   if (c->pc_kind == KV_PC_NONE) return fail(c, KV_ESTATE, "no preconditioner set");
+  int rc = ws_bind(c, KV_WS_APPLY_PRECONDITIONER, 0, 0);
+  if (rc) return rc;
   return precond_apply(c, x, y);
 }
 
@@ -1426,13 +1482,7 @@ static int state_from_cells(kv_ctx* c, const float* cells, const float* cells_re
   for (int a = 0; a < 3; ++a) nint += 2 * n3[a] + 1;
   const size_t dbl_off = ((size_t)nint * sizeof(int) + 255) / 256 * 256;
   const size_t bytes = dbl_off + (size_t)nint * sizeof(double);
-  if (c->xfer_bytes < bytes) {
-    hipFree(c->xfer);
-    c->xfer = nullptr;
-    c->xfer_bytes = 0;
-    HIPCHK(c, hipMalloc(&c->xfer, bytes));
-    c->xfer_bytes = bytes;
-  }
+  if (c->xfer_bytes < bytes) return fail(c, KV_EINVAL, "interpolation tables exceed their create-time size");
   std::vector<int> hq(nint);
   std::vector<double> ht(nint);
   const int* qp[6];
@@ -1488,15 +1538,16 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   // workspace: V (m+1 vectors) + z_prev, z, tmp + up to n_eigs+1 locked
   // vectors (+ as many lock-time Ritz vectors when eigenvectors are asked for)
   const int nslot = p->n_eigs + 1;
-  if ((rc = ensure_work(c, (size_t)m + 4 + (size_t)nslot * (evecs ? 2 : 1)))) return rc;
-  double* V = c->work;
-  double* zp = c->work + (int64_t)(m + 1) * n;
+  if ((rc = ws_bind(c, KV_WS_ARNOLDI, m, p->n_eigs))) return rc;
+  double* V = c->ws;
+  double* zp = c->ws + (int64_t)(m + 1) * n;
   double* zc = zp + n;
   double* tmp = zc + n;
   double* L = tmp + n;
   double* Ys = L + (int64_t)nslot * n;  // lock-time Ritz vectors (real, imaginary part), if evecs
   int nys = 0;
   EigScope scope(c, sym_ref, sym_rot, L);
+  c->relaxed_qr = 0;
   // the start vector in range(P), in the class, W-orthogonal to the locked vectors
   auto settle = [&](double* v) -> int {
     int r;
@@ -1529,7 +1580,7 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     int k = 0;
     if ((rc = arnoldi(c, V, m, H, &k, &matvecs)) ||
         (rc = ritz(c, H, m, k, p->n_eigs - (int)lk_vals.size(), rz))) {
-      if (info) *info = kv_eig_info{0, matvecs, restarts, 0};  // the work done so far
+      if (info) *info = kv_eig_info{0, matvecs, restarts, 0, c->relaxed_qr};  // the work done so far
       return rc;
     }
     double scale = 0.0;
@@ -1692,7 +1743,7 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     }
     if ((rc = write_eigenvectors(c, L, out, lk_vals, src_re, src_im, nl, evecs, zp, zc, tmp, &matvecs))) return rc;
   }
-  if (info) *info = kv_eig_info{(int)out.size(), matvecs, restarts, conv ? 1 : 0};
+  if (info) *info = kv_eig_info{(int)out.size(), matvecs, restarts, conv ? 1 : 0, c->relaxed_qr};
   if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");
   return KV_OK;
 }
@@ -1710,8 +1761,7 @@ int kv_hessenberg_eigenvalues(kv_ctx* c, const double* H, int m, double* wr, dou
     }
   int rc;
   const size_t mm = (size_t)m * m;
-  if ((rc = ensure_hess(c, (mm + 2 * (size_t)m + 2) * sizeof(double)))) return rc;
-  double *dH = c->hess, *dwr = dH + mm, *dwi = dwr + m;
+  double *dH = c->hess_small, *dwr = dH + mm, *dwi = dwr + m;  // (400^2 + 2 400 + 2) doubles
   int* dinfo = reinterpret_cast<int*>(dwi + m);
   if ((rc = upload(c, dH, Hk.data(), mm * sizeof(double)))) return rc;
   HIPCHK(c, launch_hessenberg_values(c->stream, dH, m, dwr, dwi, dinfo));
@@ -1720,7 +1770,7 @@ int kv_hessenberg_eigenvalues(kv_ctx* c, const double* H, int m, double* wr, dou
   HIPCHK(c, hipMemcpyAsync(wi, dwi, m * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (info) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
+  if (info & 1) return fail(c, KV_ENOCONV, "Hessenberg QR did not converge");
   return KV_OK;
 }
 

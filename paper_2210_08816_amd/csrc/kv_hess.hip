@@ -55,7 +55,10 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
     while (l > 0) {
       double sc = fabs(h(l - 1, l - 1)) + fabs(h(l, l));
       if (sc == 0.0) sc = anorm;
-      if (fabs(h(l, l - 1)) <= tol * sc) break;
+      if (fabs(h(l, l - 1)) <= tol * sc) {
+        if (fabs(h(l, l - 1)) > eps * sc) status |= 2;  // deflated by the relaxed test only
+        break;
+      }
       --l;
     }
     if (l == hi) {
@@ -93,7 +96,7 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
     // deflation, and a bound on the total
     const int lim = 30 * (m > 10 ? m : 10);
     if (its > lim || total > 4 * lim) {
-      status = 1;
+      status |= 1;
       break;
     }
     ++its;

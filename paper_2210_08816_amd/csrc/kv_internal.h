@@ -62,7 +62,7 @@ struct kv_ctx {
   int split[3] = {0, 0, 0};   // 1: mirror-symmetric axis, Qf/Qt hold the even/odd half bases
   float* Qf32[3] = {nullptr, nullptr, nullptr};  // FP32 copies of the split bases (mixed form)
   float* Qt32[3] = {nullptr, nullptr, nullptr};
-  double* ymix = nullptr;     // FP64 scratch vector for the mixed refinement sweeps
+  double* ymix = nullptr;     // FP64 scratch vector of the mixed refinement sweeps (in the workspace)
   double* cell_part = nullptr;  // per-block maxima of the cell-grid kernels (2 per block)
   int64_t cell_part_len = 0;
   double* X0 = nullptr;       // base flow copy
@@ -73,26 +73,31 @@ struct kv_ctx {
   double* dres = nullptr;     // reduction results on the device (64 doubles)
   double* hres = nullptr;     // pinned host mirror of dres
   int npart_blocks = 0;
-  // solver workspace (lazily allocated)
-  double* work = nullptr;
-  size_t work_bytes = 0;
-  double* hess = nullptr;     // device Hessenberg / Schur workspace
-  size_t hess_bytes = 0;
-  void* xfer = nullptr;       // interpolation tables of kv_state_from_cells
+  // caller-owned workspace (kv_set_workspace): solver vectors, Krylov
+  // bases, the mixed-form scratch vector and the Ritz-vector work area are
+  // carved from it per call; the library never allocates them
+  double* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* hess = nullptr;     // Hessenberg / Ritz-vector area inside the workspace (Arnoldi)
+  double* hess_small = nullptr;  // owned: kv_hessenberg_eigenvalues, m <= 400
+  void* xfer = nullptr;       // owned: interpolation tables of kv_state_from_cells
   size_t xfer_bytes = 0;
   // Stokes/heat preconditioner (kv_set_preconditioner)
   kv::HelmBasis hb[3][3];     // [axis][HB_*]
   double* pc_mem = nullptr;   // device storage of all bases
-  double* pc_tmp = nullptr;   // one packed vector: M^-1 x inside the preconditioned operator
-  double* pc_d0 = nullptr;    // one packed vector: copy of the caller's initial iterate
-  double* pc_scr = nullptr;   // one packed vector: intermediate passes of the Helmholtz solves
+  // workspace vectors of a preconditioned call:
+  double* pc_tmp = nullptr;   // M^-1 x inside the preconditioned operator
+  double* pc_d0 = nullptr;    // copy of the caller's initial iterate
+  double* pc_scr = nullptr;   // intermediate passes of the Helmholtz solves
   int pc_kind = 0;            // KV_PC_NONE or KV_PC_STOKES
   double pc_sigma = 0.0;
   bool pc_active = false;     // set while a preconditioned solve runs
   int gmres_m = 40;           // restart length of the GMRES continuation of the Newton correction
+  int stall_cycles = 50;      // BiCGstab(2) cycles without a 10% residual drop before GMRES takes over
   int sym_ref = 0, sym_rot = 0;  // symmetry class kept by matvec while a restricted Arnoldi runs
   const double* lockQ = nullptr;  // locked W-orthonormal vectors matvec deflates while Arnoldi runs
   int nlock = 0;
+  int relaxed_qr = 0;         // Arnoldi cycles whose Hessenberg QR deflated by the relaxed test
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events

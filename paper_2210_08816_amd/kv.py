@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libkv_hip.so")
 KV_OK, KV_EINVAL, KV_ENOMEM, KV_EDEVICE, KV_ENOCONV, KV_ENONFINITE, KV_ESTATE = range(7)
 KV_PROJECT, KV_MIXED = 1, 2
 KV_PC_NONE, KV_PC_STOKES = 0, 1
+KV_WS_PROJECT_MIXED, KV_WS_APPLY_PRECONDITIONER, KV_WS_NEWTON, KV_WS_ARNOLDI = 1, 2, 3, 4
 KV_SYM_REF_EVEN, KV_SYM_REF_ODD, KV_SYM_ROT_EVEN, KV_SYM_ROT_ODD = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 
 
@@ -34,9 +35,10 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
                 5: "KV_ENONFINITE", 6: "KV_ESTATE"}
 
 # every extern "C" symbol declared in include/kv.h
-ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_set_base_flow", "kv_residual",
+ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_set_workspace",
+               "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
-               "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart",
+               "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -67,7 +69,7 @@ class _ArnoldiParams(ctypes.Structure):
 
 class _EigInfo(ctypes.Structure):
     _fields_ = [("n_out", ctypes.c_int), ("matvecs", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("converged", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("relaxed_qr", ctypes.c_int)]
 
 
 _lib = None
@@ -87,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.kv_create.argtypes = [ctypes.POINTER(_Params), P, ctypes.POINTER(P)]
     lib.kv_destroy.argtypes = [P]
     lib.kv_layout.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.kv_workspace_size.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    lib.kv_set_workspace.argtypes = [P, P, ctypes.c_size_t]
     lib.kv_set_base_flow.argtypes = [P, P]
     lib.kv_residual.argtypes = [P, P, PD]
     lib.kv_apply_jacobian.argtypes = [P, P, P, ctypes.c_uint]
@@ -99,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.kv_newton_correction.argtypes = [P, P, D, ctypes.c_int, ctypes.c_uint, P, P, ctypes.POINTER(_SolveInfo)]
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
     lib.kv_set_gmres_restart.argtypes = [P, ctypes.c_int]
+    lib.kv_set_bicgstab_stall.argtypes = [P, ctypes.c_int]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD, P,
                                             ctypes.POINTER(_EigInfo)]
@@ -158,6 +163,9 @@ class Context:
                     float(Gr), float(Pr))
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._ws = None           # torch-owned workspace (kv_set_workspace)
+        self._ws_bytes = 0
         h = ctypes.c_void_p()
         rc = self._lib.kv_create(ctypes.byref(p), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
         if rc != KV_OK:
@@ -178,6 +186,37 @@ class Context:
         if getattr(self, "_h", None):
             self._lib.kv_destroy(self._h)
             self._h = None
+        self._ws = None
+
+    # ---- workspace: torch allocates, the library carves its scratch from it ------------
+    def workspace_size(self, op, krylov_dim=0, n_eigs=0):
+        """Bytes of workspace op (KV_WS_*) needs."""
+        b = ctypes.c_size_t()
+        rc = self._lib.kv_workspace_size(self._h, int(op), int(krylov_dim), int(n_eigs), ctypes.byref(b))
+        if rc != KV_OK:
+            raise KVError(rc, f"kv_workspace_size(op={op}, krylov_dim={krylov_dim}, n_eigs={n_eigs})")
+        return int(b.value)
+
+    def set_workspace(self, buf):
+        """Hand the library a caller-owned float64 CUDA tensor as its
+        workspace (kept referenced here while it is set)."""
+        import torch
+        if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+            raise TypeError("expected a contiguous CUDA tensor")
+        nbytes = buf.numel() * buf.element_size()
+        self._check(self._lib.kv_set_workspace(self._h, ctypes.c_void_p(buf.data_ptr()), nbytes))
+        self._ws, self._ws_bytes = buf, nbytes
+
+    def _ensure_workspace(self, op, krylov_dim=0, n_eigs=0):
+        import torch
+        need = self.workspace_size(op, krylov_dim, n_eigs)
+        if self._ws is not None and self._ws_bytes >= need:
+            return
+        # work queued on the context's stream may still use the old buffer
+        self.stream.synchronize()
+        self._check(self._lib.kv_set_workspace(self._h, None, 0))
+        self._ws = None
+        self.set_workspace(torch.empty((need + 7) // 8, dtype=torch.float64, device=self.device))
 
     def __del__(self):
         try:
@@ -196,12 +235,16 @@ class Context:
 
     def apply_jacobian(self, x, y, project=True, mixed=False):
         flags = (KV_PROJECT if project else 0) | (KV_MIXED if mixed else 0)
+        if mixed and project:
+            self._ensure_workspace(KV_WS_PROJECT_MIXED)
         self._check(self._lib.kv_apply_jacobian(self._h, _dptr(x, self.n), _dptr(y, self.n), flags))
 
     def project(self, y, mixed=False):
         dm = ctypes.c_double()
         sw = ctypes.c_int()
         flags = KV_PROJECT | (KV_MIXED if mixed else 0)
+        if mixed:
+            self._ensure_workspace(KV_WS_PROJECT_MIXED)
         self._check(self._lib.kv_project(self._h, _dptr(y, self.n), flags, ctypes.byref(dm),
                                          ctypes.byref(sw)))
         return dm.value, sw.value
@@ -251,6 +294,7 @@ class Context:
 
     def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True):
         info = _SolveInfo()
+        self._ensure_workspace(KV_WS_NEWTON)
         d0 = _dptr(delta0, self.n) if delta0 is not None else None
         rc = self._lib.kv_newton_correction(self._h, _dptr(F, self.n), float(tol), int(max_matvec), 0, d0,
                                             _dptr(delta, self.n), ctypes.byref(info))
@@ -268,7 +312,13 @@ class Context:
         """Restart length of the GMRES continuation of newton_correction."""
         self._check(self._lib.kv_set_gmres_restart(self._h, int(m)))
 
+    def set_bicgstab_stall(self, cycles):
+        """Cycles without a 10% residual drop after which the BiCGstab(2) part
+        of newton_correction hands over to GMRES (0: GMRES from the start)."""
+        self._check(self._lib.kv_set_bicgstab_stall(self._h, int(cycles)))
+
     def apply_preconditioner(self, x, y):
+        self._ensure_workspace(KV_WS_APPLY_PRECONDITIONER)
         self._check(self._lib.kv_apply_preconditioner(self._h, _dptr(x, self.n), _dptr(y, self.n)))
 
     def cells_from_state(self, X, factor, shift, scale, out):
@@ -310,6 +360,7 @@ class Context:
         to (see sym_flags), or None.  evecs: None, or a float64 CUDA tensor of
         (n_eigs + 1) * n values that receives the eigenvectors, one per row
         (a conjugate pair as the real and imaginary part of the +Im member's)."""
+        self._ensure_workspace(KV_WS_ARNOLDI, krylov_dim, n_eigs)
         p = _ArnoldiParams(int(krylov_dim), int(n_eigs), int(max_matvec), int(max_restarts),
                            int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, sym_flags(sym))
         re = (ctypes.c_double * (n_eigs + 1))()
@@ -323,4 +374,5 @@ class Context:
         k = info.n_out
         vals = np.array([complex(re[i], im[i]) for i in range(k)])
         return vals, np.array(res[:k]), dict(status=rc, n_out=k, matvecs=info.matvecs,
-                                              restarts=info.restarts, converged=bool(info.converged))
+                                              restarts=info.restarts, converged=bool(info.converged),
+                                              relaxed_qr=info.relaxed_qr)

@@ -3,7 +3,7 @@ regula falsi in log Gr, pinned on closed-form sigma(Gr) curves (the GPU
 side, continuation and Arnoldi, is covered by the solver tests)."""
 import math
 
-from paper_2210_08816_amd.critical import find_crossing
+from paper_2210_08816_amd.critical import find_crossing, same_mode_by_frequency
 
 
 def curve(fn, skip=()):
@@ -48,6 +48,7 @@ def test_no_crossing_and_unstable_start():
     out = find_crossing(sigma, 1e6, 1e8, ratio=1.6)
     assert out["gr"] is None and out["bracket"] is None
     assert calls[-1] == 1e8                              # the last step is clipped to the range end
+    assert out["converged"] is False
     sigma, calls = curve(lambda gr: 0.1)
     out = find_crossing(sigma, 1e6, 1e8)
     assert out["gr"] is None and out["note"] == "unstable at the start" and len(calls) == 1
@@ -79,3 +80,54 @@ def test_symmetry_class_arguments():
     for bad in (ap.parse_args(["--sym=--"]).sym, "", "mx", "m"):
         with pytest.raises(ValueError):
             parse_sym(bad)
+
+
+def test_aborted_refinement_is_not_a_result():
+    """Refinement points that do not converge (the regula-falsi point and its
+    bisection fallback) stop the refinement; the bracket is then wider than
+    1 + rtol, so no critical value is returned, only an estimate."""
+    root = 3.3e7
+    f = lambda gr: 0.02 * math.log(gr / root)  # noqa: E731
+    calls = []
+
+    def sigma(gr):
+        calls.append(gr)
+        if len(calls) > 4:                    # every point after the bracket fails
+            return None, {"arnoldi": "not converged"}
+        return f(gr), {}
+    out = find_crossing(sigma, 1e7, 2e8, ratio=1.6, rtol=1e-6)
+    assert out["gr"] is None and out["converged"] is False
+    assert out["note"].startswith("refinement stopped")
+    a, b = out["bracket"]
+    assert b / a > 1.0 + 1e-6 and a <= root <= b and a <= out["gr_estimate"] <= b
+    ok = find_crossing(curve(f)[0], 1e7, 2e8, ratio=1.6, rtol=1e-6)
+    assert ok["converged"] is True and abs(ok["gr"] / root - 1.0) < 1e-9
+
+
+def test_mode_switch_is_not_a_crossing():
+    """Two modes of the near-axis cluster: mode 1 (Im 0.67) leads below
+    4e7 and stays stable; mode 2 (Im 0.043) leads above and is unstable.  A
+    bracket across the switch is not a crossing of one mode; inside a
+    one-mode bracket a point that returns the other mode counts as not
+    converged."""
+    def sigma_switch(gr):
+        if gr < 4e7:
+            return -0.01, {"values": [[-0.01, 0.67]]}
+        return 0.005, {"values": [[0.005, 0.043]]}
+    out = find_crossing(sigma_switch, 1e7, 2e8, ratio=1.6, same_mode=same_mode_by_frequency)
+    assert out["gr"] is None and out["converged"] is False and "different eigenmodes" in out["note"]
+    # without the check the switch would be taken for a crossing
+    assert find_crossing(sigma_switch, 1e7, 2e8, ratio=1.6)["gr"] is not None
+
+    root = 3.3e7
+
+    def sigma_one(gr):
+        val = 0.02 * math.log(gr / root)
+        if 3.0e7 < gr < 3.2e7:          # another mode leads in a window below the root
+            return -0.2, {"values": [[-0.2, 0.9]]}
+        return val, {"values": [[val, 0.05]]}
+    out = find_crossing(sigma_one, 1e7, 2e8, ratio=1.6, rtol=1e-6, same_mode=same_mode_by_frequency)
+    assert out["converged"] and abs(out["gr"] / root - 1.0) < 1e-6
+    assert same_mode_by_frequency({"values": [[0, 0.05]]}, {"values": [[0, 0.055]]})
+    assert not same_mode_by_frequency({"values": [[0, 0.043]]}, {"values": [[0, 0.67]]})
+    assert not same_mode_by_frequency({"values": []}, {"values": [[0, 0.1]]})

@@ -12,7 +12,7 @@ def test_finder_on_a_stable_range():
     from paper_2210_08816_amd.critical import run
     out = run(n=8, grid="clustered", gr_lo=1e5, gr_hi=2.25e5, ratio=1.5, sym=(1, -1), krylov=20, n_eigs=2,
               tol=1e-8, max_matvec=6000, log=lambda m: print(m, flush=True))
-    assert out["gr_critical"] is None and out["note"] is None
+    assert out["gr_critical"] is None and out["converged"] is False and out["note"] == "no crossing in the range"
     grs = [h["Gr"] for h in out["history"]]
     assert grs == pytest.approx([1e5, 1.5e5, 2.25e5])
     for h in out["history"]:

@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import disc as O  # noqa: E402
 from synth import inputs as S  # noqa: E402
-from tests.gpu_util import faces, field_rel_errors, to_dev, to_host  # noqa: E402
+from tests.gpu_util import assert_parity, faces, to_dev, to_host  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,7 @@ def test_jacobian_unprojected(kind, shape, Gr, K, amp):
     x = S.perturbation(g.size, 1000)
     y = torch.empty(g.size, dtype=torch.float64, device="cuda")
     ctx.apply_jacobian(to_dev(x), y, project=False)
-    err = field_rel_errors(g, to_host(y), O.jacobian(g, X0, x))
-    assert max(err) <= TOL64, err
+    assert_parity(g, to_host(y), O.jacobian(g, X0, x), TOL64, label="J")
 
 
 @pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS)
@@ -59,8 +58,7 @@ def test_projected_jacobian(kind, shape, Gr, K, amp):
         ctx.apply_jacobian(to_dev(x), y, project=True)
         got = to_host(y)
         ref = O.apply_jacobian(g, X0, x)
-        err = field_rel_errors(g, got, ref)
-        assert max(err) <= TOL64, err
+        assert_parity(g, got, ref, TOL64, label="PJ")
         assert O.div_measure(g, got) < 1e-11
 
 
@@ -72,7 +70,7 @@ def test_project_and_divergence(kind, shape, Gr, K, amp):
     dm, sweeps = ctx.project(y)
     got = to_host(y)
     assert sweeps == 1
-    assert max(field_rel_errors(g, got, O.project(g, y0))) <= TOL64
+    assert_parity(g, got, O.project(g, y0), TOL64, label="P")
     assert dm < 1e-11 and abs(dm - O.div_measure(g, got)) <= 1e-3 * max(dm, 1e-300) + 1e-16
 
 
@@ -82,7 +80,7 @@ def test_residual(kind, shape, Gr, K, amp):
     F = torch.empty(g.size, dtype=torch.float64, device="cuda")
     norm = ctx.residual(F)
     ref = O.residual(g, X0)
-    assert max(field_rel_errors(g, to_host(F), ref)) <= TOL64
+    assert_parity(g, to_host(F), ref, TOL64, label="F")
     assert abs(norm - O.wnorm(g.weights(), ref)) <= 1e-12 * norm
 
 
@@ -103,7 +101,7 @@ def test_projection_fd_variants(monkeypatch, var, val, kind, shape, Gr, K, amp):
     y0 = S.perturbation(g.size, 11)
     y = to_dev(y0)
     ctx.project(y)
-    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL64
+    assert_parity(g, to_host(y), O.project(g, y0), TOL64, label=f"P {var}={val}")
 
 
 # The full-size workloads: 100^3 clustered at Gr 4e7 and 256^3 clustered at
@@ -127,9 +125,7 @@ def test_projected_jacobian_full_size(workload, seed):
     got = to_host(y)
     del y
     ref = O.apply_jacobian(g, X0, x)
-    err = field_rel_errors(g, got, ref)
-    print("field errors", err, flush=True)
-    assert max(err) <= TOL64, err
+    assert_parity(g, got, ref, TOL64, label=f"PJ {workload}")
 
 
 def test_axpby():
@@ -194,9 +190,7 @@ def test_mixed_projected_jacobian(kind, shape, Gr, K, amp):
     ctx.apply_jacobian(to_dev(x), y, project=True, mixed=True)
     got = to_host(y)
     ref = O.apply_jacobian(g, X0, x)
-    err = field_rel_errors(g, got, ref)
-    print("mixed field errors", err, flush=True)
-    assert max(err) <= TOL_MIXED, err
+    assert_parity(g, got, ref, TOL_MIXED, label="mixed PJ")
     assert O.div_measure(g, got) <= 1e-10
 
 
@@ -210,7 +204,7 @@ def test_mixed_fd_variants(monkeypatch, var, val):
     y = torch.empty(g.size, dtype=torch.float64, device="cuda")
     ctx.apply_jacobian(to_dev(x), y, project=True, mixed=True)
     got = to_host(y)
-    assert max(field_rel_errors(g, got, O.apply_jacobian(g, X0, x))) <= TOL_MIXED
+    assert_parity(g, got, O.apply_jacobian(g, X0, x), TOL_MIXED, label=f"mixed {var}={val}")
     assert O.div_measure(g, got) <= 1e-10
 
 
@@ -222,7 +216,7 @@ def test_mixed_project_reports_sweeps(kind, shape, Gr, K, amp):
     dm, sweeps = ctx.project(y, mixed=True)
     assert sweeps >= 2 and sweeps % 2 == 0
     assert dm <= 1e-10
-    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL_MIXED
+    assert_parity(g, to_host(y), O.project(g, y0), TOL_MIXED, label="mixed P")
 
 
 def test_mixed_falls_back_on_unsplit_grid():
@@ -232,4 +226,4 @@ def test_mixed_falls_back_on_unsplit_grid():
     y = to_dev(y0)
     dm, sweeps = ctx.project(y, mixed=True)
     assert sweeps == 1
-    assert max(field_rel_errors(g, to_host(y), O.project(g, y0))) <= TOL64
+    assert_parity(g, to_host(y), O.project(g, y0), TOL64, label="P unsplit")

@@ -210,7 +210,7 @@ def test_newton_correction_rejects_bad_input():
                                                  ("uniform", (2, 3, 2), 1e3, 1.0)])
 def test_preconditioner_matches_oracle(kind, shape, Gr, sigma):
     from oracle import precond as PC
-    from tests.gpu_util import field_rel_errors
+    from tests.gpu_util import assert_parity
     print(f"case precond {kind} {shape}", flush=True)
     fx = [faces(kind, n) for n in shape]
     g = O.Grid(*fx, Gr=Gr, Pr=0.71)
@@ -225,7 +225,7 @@ def test_preconditioner_matches_oracle(kind, shape, Gr, sigma):
     ctx.set_preconditioner(True, sigma)
     ctx.apply_preconditioner(to_dev(r), y)
     ref = PC.apply(g, r, sigma)
-    assert max(field_rel_errors(g, to_host(y), ref)) <= 1e-12
+    assert_parity(g, to_host(y), ref, 1e-12, label="M^-1")
     # in place
     yy = to_dev(r)
     ctx.apply_preconditioner(yy, yy)
@@ -237,7 +237,7 @@ def test_preconditioner_tile_shapes(monkeypatch, tile):
     """The Helmholtz GEMM passes with each tile shape forced (the sizes
     choose 32 x 32 on grids this small, 64 x 64 on large ones)."""
     from oracle import precond as PC
-    from tests.gpu_util import field_rel_errors
+    from tests.gpu_util import assert_parity
     monkeypatch.setenv("KV_FD_TILE", tile)
     fx = [faces("clustered", n) for n in (70, 9, 66)]
     g = O.Grid(*fx, Gr=4e7, Pr=0.71)
@@ -247,7 +247,7 @@ def test_preconditioner_tile_shapes(monkeypatch, tile):
     y = torch.empty(g.size, dtype=torch.float64, device="cuda")
     ctx.set_preconditioner(True, 0.5)
     ctx.apply_preconditioner(to_dev(r), y)
-    assert max(field_rel_errors(g, to_host(y), PC.apply(g, r, 0.5))) <= 1e-12
+    assert_parity(g, to_host(y), PC.apply(g, r, 0.5), 1e-12, label="M^-1 tiles")
 
 
 @pytest.mark.parametrize("kind,shape,Gr,amp,noise,tol", [
@@ -368,5 +368,127 @@ def test_gmres_restart_setting():
         A = SV.Operator(g, X0)
         Fo = SV.A_project(A, O.residual(g, X0))
         assert A.norm(A(to_host(delta)) + Fo) / A.norm(Fo) <= 1e-9
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("precond,with_delta0", [(False, False), (False, True), (True, False), (True, True)])
+def test_forced_gmres_handover(precond, with_delta0):
+    """A stagnation limit of 0 hands the Newton correction to the GPU GMRES
+    continuation before the first BiCGstab(2) cycle, on both sides.  The
+    GPU correction (with and without the Stokes/heat right preconditioner,
+    from zero and from a nonzero initial iterate) is certified by the
+    oracle's own operator, and the oracle's forced hand-over reaches the same
+    unique correction."""
+    from paper_2210_08816_amd import kv
+    print(f"case forced gmres precond={precond} delta0={with_delta0}", flush=True)
+    shape = (7, 6, 5)
+    fx = [faces("clustered", n) for n in shape]
+    g = O.Grid(*fx, Gr=1e4, Pr=0.71)
+    X0 = O.project(g, S.base_flow(*fx, K=3, amp=0.05, seed=31) + 0.01 * S.perturbation(g.size, 32))
+    ctx = context(fx, 1e4, 0.71, X0)
+    try:
+        for bad in (-1, 100001):
+            assert ctx._lib.kv_set_bicgstab_stall(ctx._h, bad) == kv.KV_EINVAL
+        ctx.set_bicgstab_stall(0)
+        ctx.set_gmres_restart(100)      # GMRES(40) stagnates on this system without the preconditioner
+        if precond:
+            ctx.set_preconditioner(True, 0.0)
+        F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        d0_host = O.project(g, S.perturbation(g.size, 33)) * 1e-3 if with_delta0 else None
+        delta = torch.empty_like(F)
+        tol = 1e-10
+        info = ctx.newton_correction(F, delta, tol=tol, max_matvec=4000,
+                                     delta0=to_dev(d0_host) if with_delta0 else None)
+        assert info["status"] == 0 and info["used_gmres"] == 1, info
+        A = SV.Operator(g, X0)
+        Fo = SV.A_project(A, O.residual(g, X0))
+        d = to_host(delta)
+        assert A.norm(A(d) + Fo) / A.norm(Fo) <= 10 * tol
+        assert O.div_measure(g, d) < 1e-10
+        d_ref, rinfo = SV.newton_correction(A, O.residual(g, X0), tol=1e-12, max_matvec=4000,
+                                            delta0=d0_host, stall_cycles=0, gmres_m=100)
+        assert rinfo["used_gmres"] == 1 and rinfo["status"] == "converged"
+        assert A.norm(d - d_ref) <= 1e-7 * A.norm(d_ref)
+    finally:
+        ctx.close()
+
+
+def test_workspace_is_caller_owned():
+    """Vector-sized scratch comes from the caller's (torch) workspace:
+    kv_workspace_size reports each op's bytes, calls with no workspace or a
+    too-small one return KV_EINVAL and leave their outputs alone, and a
+    workspace of exactly the reported size serves the call."""
+    import ctypes
+    from paper_2210_08816_amd import kv
+    shape = (7, 6, 5)
+    fx = [faces("clustered", n) for n in shape]
+    g = O.Grid(*fx, Gr=1e4, Pr=0.71)
+    X0 = O.project(g, S.base_flow(*fx, K=3, amp=0.05, seed=31) + 0.01 * S.perturbation(g.size, 32))
+    ctx = context(fx, 1e4, 0.71, X0)
+    try:
+        n = g.size
+        vec = 8 * n
+        assert ctx.workspace_size(kv.KV_WS_PROJECT_MIXED) == vec
+        assert ctx.workspace_size(kv.KV_WS_APPLY_PRECONDITIONER) == vec
+        assert ctx.workspace_size(kv.KV_WS_NEWTON) == (8 + 40 + 1) * vec
+        ctx.set_gmres_restart(60)
+        assert ctx.workspace_size(kv.KV_WS_NEWTON) == (8 + 60 + 1) * vec
+        ctx.set_preconditioner(True, 1.0)
+        assert ctx.workspace_size(kv.KV_WS_NEWTON) == (8 + 60 + 1 + 3) * vec
+        ctx.set_preconditioner(False)
+        m, k = 20, 4
+        kk = m * m
+        hess = 4 * kk + 4 * m + 2 + 2 * (k + 1) * (kk + m)
+        assert ctx.workspace_size(kv.KV_WS_ARNOLDI, m, k) == (m + 4 + 2 * (k + 1)) * vec + 8 * hess
+        for bad in ((0, 0, 0), (5, 0, 0), (kv.KV_WS_ARNOLDI, 20, 20), (kv.KV_WS_ARNOLDI, 1, 1)):
+            b = ctypes.c_size_t()
+            assert ctx._lib.kv_workspace_size(ctx._h, *bad, ctypes.byref(b)) == kv.KV_EINVAL
+        F = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        delta = torch.full_like(F, 7.0)
+        info = kv._SolveInfo()
+        call = lambda: ctx._lib.kv_newton_correction(  # noqa: E731
+            ctx._h, ctypes.c_void_p(F.data_ptr()), 1e-10, 4000, 0, None, ctypes.c_void_p(delta.data_ptr()),
+            ctypes.byref(info))
+        # no workspace set
+        assert ctx._lib.kv_set_workspace(ctx._h, None, 0) == kv.KV_OK
+        assert call() == kv.KV_EINVAL
+        assert "workspace" in ctx._lib.kv_last_error(ctx._h).decode()
+        need = ctx.workspace_size(kv.KV_WS_NEWTON)
+        small = torch.empty(need // 8 - 1, dtype=torch.float64, device="cuda")
+        assert ctx._lib.kv_set_workspace(ctx._h, ctypes.c_void_p(small.data_ptr()), need - 8) == kv.KV_OK
+        assert call() == kv.KV_EINVAL
+        torch.cuda.synchronize()
+        assert bool((delta == 7.0).all())               # nothing ran
+        # mismatched pointer / size
+        assert ctx._lib.kv_set_workspace(ctx._h, None, 64) == kv.KV_EINVAL
+        exact = torch.empty(need // 8, dtype=torch.float64, device="cuda")
+        assert ctx._lib.kv_set_workspace(ctx._h, ctypes.c_void_p(exact.data_ptr()), need) == kv.KV_OK
+        assert call() == kv.KV_OK
+        A = SV.Operator(g, X0)
+        Fo = SV.A_project(A, O.residual(g, X0))
+        assert A.norm(A(to_host(delta)) + Fo) / A.norm(Fo) <= 1e-9
+        # the mixed projection and the preconditioner check theirs too
+        assert ctx._lib.kv_set_workspace(ctx._h, None, 0) == kv.KV_OK
+        y = to_dev(S.perturbation(n, 5))
+        ctx.set_preconditioner(True, 1.0)
+        assert ctx._lib.kv_apply_preconditioner(ctx._h, ctypes.c_void_p(y.data_ptr()),
+                                                ctypes.c_void_p(F.data_ptr())) == kv.KV_EINVAL
+    finally:
+        ctx.close()
+    # the mixed projection needs the even/odd split: an 8 x 6 x 4 clustered grid
+    fx = [faces("clustered", n) for n in (8, 6, 4)]
+    g = O.Grid(*fx, Gr=1e4, Pr=0.71)
+    ctx = context(fx, 1e4, 0.71, O.project(g, S.base_flow(*fx, K=2, amp=0.05, seed=31)))
+    try:
+        y0 = S.perturbation(g.size, 5)
+        y = to_dev(y0)
+        assert ctx._lib.kv_project(ctx._h, ctypes.c_void_p(y.data_ptr()), kv.KV_PROJECT | kv.KV_MIXED,
+                                   None, None) == kv.KV_EINVAL
+        assert np.array_equal(to_host(y), y0)
+        ctx.project(y, mixed=True)                      # the binding sets a torch workspace
+        assert O.div_measure(g, to_host(y)) <= 1e-10
     finally:
         ctx.close()

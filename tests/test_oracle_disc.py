@@ -428,3 +428,71 @@ def test_workload_grids():
     assert S.packed_size(256, 256, 256) == 66_912_256
     assert S.packed_size(32, 32, 32) == 128_000
     assert S.packed_size(100, 100, 100) == 3_970_000
+
+
+def _div_measure_brute(xf, yf, zf, y, shapes):
+    """max |net flux| / max |face flux| by explicit loops over the cells of
+    a small grid: each interior face carries (normal velocity) x (its area,
+    the product of the two cell widths across it, taken from the face
+    coordinates); a cell's net flux is the sum of its six face fluxes with
+    outward signs, wall faces carrying none (no penetration)."""
+    nx, ny, nz = len(xf) - 1, len(yf) - 1, len(zf) - 1
+    sizes = [int(np.prod(s)) for s in shapes]
+    u = y[:sizes[0]].reshape(shapes[0])
+    v = y[sizes[0]:sizes[0] + sizes[1]].reshape(shapes[1])
+    w = y[sizes[0] + sizes[1]:sizes[0] + sizes[1] + sizes[2]].reshape(shapes[2])
+
+    def fx(i, j, k):    # flux through x-face i (0..nx) of cell row (j, k)
+        return 0.0 if i in (0, nx) else u[k, j, i - 1] * (yf[j + 1] - yf[j]) * (zf[k + 1] - zf[k])
+
+    def fy(i, j, k):
+        return 0.0 if j in (0, ny) else v[k, j - 1, i] * (xf[i + 1] - xf[i]) * (zf[k + 1] - zf[k])
+
+    def fz(i, j, k):
+        return 0.0 if k in (0, nz) else w[k - 1, j, i] * (xf[i + 1] - xf[i]) * (yf[j + 1] - yf[j])
+
+    net, face = 0.0, 0.0
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                b = fx(i + 1, j, k) - fx(i, j, k) + fy(i, j + 1, k) - fy(i, j, k) + fz(i, j, k + 1) - fz(i, j, k)
+                net = max(net, abs(b))
+                face = max(face, abs(fx(i, j, k)), abs(fy(i, j, k)), abs(fz(i, j, k)))
+    return net / face
+
+
+def test_div_measure_against_brute_force_face_loops():
+    """The normalized divergence (the mixed form's stopping quantity, Sec. 3:
+    divergence-free Krylov vectors) equals an explicit loop over cells and
+    faces on a 6 x 5 x 4 wall-clustered grid, for a field that is not
+    divergence free and for a projected one; a copy of the oracle's formula
+    with one axis's face area taken across the wrong axis is caught."""
+    xf, yf, zf = S.faces_clustered(6), S.faces_clustered(5), S.faces_clustered(4)
+    g = O.Grid(xf, yf, zf, Gr=1e5, Pr=0.71)
+    for seed in (41, 42):
+        y = S.perturbation(g.size, seed)
+        ref = _div_measure_brute(xf, yf, zf, y, g.shapes)
+        assert abs(O.div_measure(g, y) - ref) <= 1e-13 * ref
+        yp = O.project(g, y)
+        refp = _div_measure_brute(xf, yf, zf, yp, g.shapes)
+        # at round-off level the two summation orders differ; both are ~eps
+        assert refp < 1e-13 and O.div_measure(g, yp) < 1e-13
+
+    def planted(g, y, wrong):
+        b = O.divergence(g, y) * g.cell_volume()
+        vel = g.unpack(y)[:3]
+        fl = 0.0
+        for a in range(3):
+            areas = [g.along(g.h[c], c) for c in range(3)]
+            areas[a] = 1.0
+            if a == wrong:      # the z-width of an x-face read along y
+                areas[2] = g.along(g.h[1], 1)
+            fl = max(fl, float(np.max(np.abs(vel[a] * areas[0] * areas[1] * areas[2]))))
+        return float(np.max(np.abs(b))) / fl
+
+    # an x-velocity field alone, so the largest face flux is an x-face's
+    y = np.zeros(g.size)
+    y[:g.shapes[0][0] * g.shapes[0][1] * g.shapes[0][2]] = S.perturbation(g.size, 43)[:np.prod(g.shapes[0])]
+    ref = _div_measure_brute(xf, yf, zf, y, g.shapes)
+    assert abs(O.div_measure(g, y) - ref) <= 1e-13 * ref
+    assert abs(planted(g, y, 0) - ref) > 1e-2 * ref

@@ -169,20 +169,32 @@ def test_newton_quadratic_convergence_and_symmetry():
     assert O.div_measure(g, X) < 1e-11
 
 
-def test_breakdown_falls_back_to_gmres():
-    """A shadow vector orthogonal to the residual stops BiCGstab(2) at once;
-    the combined solver then finishes with GMRES (the paper combines them)."""
-    f = [S.faces_uniform(6), S.faces_uniform(5), S.faces_uniform(4)]
+@pytest.mark.parametrize("with_delta0", [False, True])
+def test_forced_gmres_handover_matches_dense_saddle_solve(with_delta0):
+    """A stagnation limit of 0 cycles hands the Newton correction to GMRES
+    before the first BiCGstab(2) cycle (Sec. 1: BiCGstab(2) combined with
+    GMRES).  The continuation must still reach the unique correction of the
+    dense saddle system J delta - G q = -N, D delta = 0 (no projection and no
+    fast diagonalization involved), also from a nonzero initial iterate."""
+    f = [S.faces_clustered(6), S.faces_clustered(5), S.faces_clustered(4)]
     g = O.Grid(*f, Gr=1e4, Pr=0.71)
-    X0 = O.project(g, S.base_flow(*f, K=2, amp=0.1, seed=25))
+    X0 = O.project(g, S.base_flow(*f, K=2, amp=0.1, seed=25) + 0.01 * S.perturbation(g.size, 26))
+    J, D, G = saddle(g, X0)
+    n, C = g.size, g.ncell
+    M = np.block([[J, -G], [D, np.zeros((C, C))]])
+    rhs = np.concatenate([-O.nonlinear(g, X0), np.zeros(C)])
+    delta_ref = np.linalg.lstsq(M, rhs, rcond=None)[0][:n]
     A = SV.Operator(g, X0)
-    F = O.residual(g, X0)
-    d, info = SV.newton_correction(A, F, tol=1e-10, max_matvec=3000)
+    d0 = O.project(g, S.perturbation(g.size, 27)) * 1e-3 if with_delta0 else None
+    d, info = SV.newton_correction(A, O.residual(g, X0), tol=1e-11, max_matvec=4000, delta0=d0,
+                                   stall_cycles=0, gmres_m=100)
+    assert info["used_gmres"] == 1 and info["cycles"] >= 1
     assert info["status"] == "converged"
-    # forced: zero budget for BiCGstab stagnation -> GMRES used
-    b = -SV.A_project(A, F)
-    x, binfo = SV.bicgstab2(A, b, tol=1e-10, max_matvec=3000, stall_cycles=0)
-    assert binfo["status"] in ("stagnation", "converged")
+    assert np.linalg.norm(d - delta_ref) <= 1e-8 * np.linalg.norm(delta_ref)
+    # the default limit keeps BiCGstab(2) on this easy system
+    d2, info2 = SV.newton_correction(A, O.residual(g, X0), tol=1e-11, max_matvec=4000, delta0=d0)
+    assert info2["used_gmres"] == 0 and info2["status"] == "converged"
+    assert np.linalg.norm(d2 - delta_ref) <= 1e-8 * np.linalg.norm(delta_ref)
 
 
 def test_chebyshev_growth_rate_and_restart_weights():
