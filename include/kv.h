@@ -124,7 +124,8 @@ enum kv_workspace_op {
   KV_WS_PROJECT_MIXED = 1,
   KV_WS_APPLY_PRECONDITIONER = 2,
   KV_WS_NEWTON = 3,
-  KV_WS_ARNOLDI = 4
+  KV_WS_ARNOLDI = 4,
+  KV_WS_TIME_STEPS = 5        /* kv_time_steps: 4 vectors */
 };
 int kv_workspace_size(const kv_ctx* ctx, int op, int krylov_dim, int n_eigs, size_t* bytes);
 int kv_set_workspace(kv_ctx* ctx, void* dev_ptr, size_t bytes);
@@ -213,6 +214,26 @@ int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matve
                          unsigned flags, const double* delta0, double* delta,
                          kv_solve_info* info);
 
+/* Time integration of Eqs. 1-6 (Sec. 4.2 follows the oscillatory states that
+ * the primary instability leads to by fully nonlinear computations; the
+ * paper gives no scheme).  Semi-implicit steps: diffusion implicit, through
+ * the Helmholtz solves of the Stokes/heat preconditioner (kv_set_
+ * preconditioner's operators at shift s), advection and buoyancy explicit,
+ * and every step projected by P, with F = P N(X) the steady residual:
+ *   order 1:  X(t+dt) = X + M_{1/dt}^-1 F(X)
+ *   order 2 (SBDF2, s = 3/(2 dt)):
+ *     X(t+dt) = 2X - Xprev + M_s^-1 [ (2s/3)(Xprev - X) + 2F(X) - F(Xprev) ]
+ * The steady states are exactly its fixed points.  X: device, packed, the
+ * state at t (in) and at t + nsteps dt (out); Xprev: device, n values, the
+ * state at t - dt (in, when start == 0) and at t + (nsteps - 1) dt (out).
+ * start = 1 takes the first step at order 1 (Xprev is only written), then
+ * order 2.  dt > 0 (host), nsteps >= 0.  The KV_WS_TIME_STEPS workspace
+ * is used; the first call builds the preconditioner's bases if
+ * kv_set_preconditioner has not; the preconditioner setting is kept.
+ * KV_ENONFINITE if the state blows up (explicit advection: dt must respect
+ * the convective CFL limit of the grid).  Needs no base flow. */
+int kv_time_steps(kv_ctx* ctx, double dt, int nsteps, int start, double* X, double* Xprev);
+
 /* Restart length m of the GMRES(m) that continues a stalled BiCGstab(2) in
  * kv_newton_correction (Sec. 1: BiCGstab(2) combined with GMRES); 10 <= m <=
  * 400, default 40.  A longer restart keeps the few eigenvalues of P J near
@@ -260,6 +281,15 @@ typedef struct {
                            to that symmetry class (v0, every P J x and every
                            restart vector projected onto it); meaningful at
                            a base flow with all three symmetries */
+  int keep;             /* 0: restart from one Chebyshev-filtered vector
+                           (below).  n_eigs < keep <= krylov_dim - 2: restart
+                           thick instead -- the real and imaginary parts of
+                           the keep leading Ritz vectors (a pair whole, at
+                           most 63 vectors), orthonormalized, start the next
+                           cycle with the last Arnoldi vector after them, so
+                           the cluster of weakly damped modes near the
+                           imaginary axis stays in the Krylov space across
+                           restarts (no filter, no locking) */
 } kv_arnoldi_params;
 
 typedef struct {

@@ -251,10 +251,13 @@ constexpr double kMixedDivTol = 1e-10;
 
 int ws_bind(kv_ctx* c, int op, int m, int neig);
 
-int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
+}  // namespace
+
+// The mixed projection with its scratch vector ymix (n doubles of device
+// memory the caller provides).
+int kv::project_mixed_with(kv_ctx* c, double* y, double* div_out, int* sweeps_out, double* ymix) {
   const int64_t C = c->ncell;
-  int rc = ws_bind(c, KV_WS_PROJECT_MIXED, 0, 0);
-  if (rc) return rc;
+  int rc;
   // FP32 fields inside the two FP64 cell buffers
   float* F0 = reinterpret_cast<float*>(c->cellA);
   float* F1 = F0 + C;
@@ -267,8 +270,8 @@ int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
   while (sweeps < 8) {
     // even sweeps read y and write the scratch vector, odd ones the reverse
     const bool from_y = sweeps % 2 == 0;
-    const double* src = from_y ? y : c->ymix;
-    double* dst = from_y ? c->ymix : y;
+    const double* src = from_y ? y : ymix;
+    double* dst = from_y ? ymix : y;
     float* b = from_y ? F0 : F1;
     float* bn = from_y ? F1 : F0;
     {
@@ -289,7 +292,7 @@ int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
   if (sweeps % 2 == 1) {
     // the result is in the scratch vector: its velocity back into y (T of y is final)
     PhaseMark pm(c, 3);
-    HIPCHK(c, hipMemcpyAsync(y, c->ymix, c->g.oT * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(y, ymix, c->g.oT * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   }
   if (div_out) *div_out = div;
   if (sweeps_out) *sweeps_out = sweeps;
@@ -297,7 +300,19 @@ int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
   return KV_OK;
 }
 
-bool mixed_ok(const kv_ctx* c) { return c->split[0] && c->split[1] && c->split[2]; }
+bool kv::mixed_grid(const kv_ctx* c) { return c->split[0] && c->split[1] && c->split[2]; }
+
+size_t kv::mixed_scratch_bytes(const kv_ctx* c) { return (size_t)c->g.n * sizeof(double); }
+
+namespace {
+
+int project_mixed(kv_ctx* c, double* y, double* div_out, int* sweeps_out) {
+  int rc = ws_bind(c, KV_WS_PROJECT_MIXED, 0, 0);
+  if (rc) return rc;
+  return project_mixed_with(c, y, div_out, sweeps_out, c->ymix);
+}
+
+bool mixed_ok(const kv_ctx* c) { return mixed_grid(c); }
 
 int apply_operator(kv_ctx* c, const double* x, double* y) {
   PhaseMark pm(c, 0);
@@ -425,13 +440,18 @@ size_t ws_vectors(const kv_ctx* c, int op, int m, int neig) {
     case KV_WS_APPLY_PRECONDITIONER: return 1;
     case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0);
     case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1);
+    case KV_WS_TIME_STEPS: return 4;
     default: return 0;
   }
 }
 
+// Ritz vectors the Hessenberg area holds: the wanted set (n_eigs + 1 with a
+// pair kept whole), or a thick restart's kept set (at most 64)
+int ritz_slots(int m, int neig) { return std::max(neig + 1, std::min(m, 64)); }
+
 size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
   size_t bytes = ws_vectors(c, op, m, neig) * (size_t)c->g.n * sizeof(double);
-  if (op == KV_WS_ARNOLDI) bytes += hess_area(m, neig + 1) * sizeof(double);
+  if (op == KV_WS_ARNOLDI) bytes += hess_area(m, ritz_slots(m, neig)) * sizeof(double);
   return bytes;
 }
 
@@ -442,6 +462,7 @@ size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
 //   APPLY_PRECONDITIONER   pc_scr
 //   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr
 //   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) | Hessenberg area
+//   TIME_STEPS             F | F of the previous step | right-hand side | pc_scr
 int ws_bind(kv_ctx* c, int op, int m, int neig) {
   const size_t need = ws_need(c, op, m, neig);
   if (!c->ws || c->ws_bytes < need) {
@@ -463,6 +484,7 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
       }
       break;
     case KV_WS_ARNOLDI: c->hess = c->ws + (int64_t)(m + 4 + 2 * (neig + 1)) * n; break;
+    case KV_WS_TIME_STEPS: c->pc_scr = c->ws + 3 * n; break;
     default: return fail(c, KV_EINVAL, "unknown workspace operation");
   }
   return KV_OK;
@@ -472,11 +494,11 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
 // V holds up to m+1 vectors (stride n).  On entry V[0] is W-normalized.  Fills
 // H ((m+1) x m, column-major by j: H[i + j*(m+1)]) and returns the number of
 // completed steps k (k < m on a lucky breakdown).
-int arnoldi(kv_ctx* c, double* V, int m, std::vector<double>& H, int* kout, int* matvecs) {
+int arnoldi(kv_ctx* c, double* V, int m, std::vector<double>& H, int* kout, int* matvecs, int j0 = 0) {
   const int64_t n = c->g.n;
-  H.assign((size_t)(m + 1) * m, 0.0);
+  if (j0 == 0) H.assign((size_t)(m + 1) * m, 0.0);  // else columns < j0 (and row j0) are kept
   int rc;
-  for (int j = 0; j < m; ++j) {
+  for (int j = j0; j < m; ++j) {
     double* w = V + (int64_t)(j + 1) * n;
     if ((rc = op_apply(c, V + (int64_t)j * n, w))) return rc;
     ++*matvecs;
@@ -1369,6 +1391,67 @@ static int build_preconditioner(kv_ctx* c) {
   return KV_OK;
 }
 
+// ---- time integration ------------------------------------------------------------------------
+// Semi-implicit steps of Eqs. 1-6 with the library's operators: diffusion
+// implicit through the Helmholtz solves of the Stokes/heat preconditioner,
+// advection and buoyancy explicit, every step projected.  With F = P N(X)
+// (diffusion included) and M_s^-1 = the preconditioner at shift s:
+//   order 1:  X+ = X + M_{1/dt}^-1 F(X)
+//   order 2 (SBDF2), s = 3/(2 dt):
+//     X+ = 2X - X- + M_s^-1 [ (2s/3)(X- - X) + 2F(X) - F(X-) ]
+// which is (3X+ - 4X + X-)/(2 dt) = 2E(X) - E(X-) + L X+ rewritten with
+// E = N - L (L the homogeneous diffusion inside M; the inhomogeneous wall
+// terms cancel).  Fixed points are exactly the steady states (M_s^-1 is
+// W-positive definite on range(P)).
+int kv_time_steps(kv_ctx* c, double dt, int nsteps, int start, double* X, double* Xprev) {
+  if (!c) return KV_EINVAL;
+  if (!X || !Xprev || X == Xprev) return fail(c, KV_EINVAL, "X and Xprev must be distinct device vectors");
+  if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0 || (start != 0 && start != 1))
+    return fail(c, KV_EINVAL, "bad time-step arguments");
+  int rc;
+  if ((rc = ws_bind(c, KV_WS_TIME_STEPS, 0, 0))) return rc;
+  if ((rc = build_preconditioner(c))) return rc;
+  const int64_t n = c->g.n;
+  double* F = c->ws;
+  double* Fp = c->ws + n;
+  double* R = c->ws + 2 * n;
+  const int kind0 = c->pc_kind;
+  const double sig0 = c->pc_sigma;
+  c->pc_kind = KV_PC_STOKES;
+  auto restore = [&](int code) {
+    c->pc_kind = kind0;
+    c->pc_sigma = sig0;
+    return code;
+  };
+  auto residual_into = [&](const double* Xs, double* out) -> int {
+    HIPCHK(c, launch_operator(c, Xs, Xs, out, 1));
+    return project_inplace(c, out);
+  };
+  if (nsteps > 0 && !start)
+    if ((rc = residual_into(Xprev, Fp))) return restore(rc);
+  for (int s = 0; s < nsteps; ++s) {
+    if ((rc = residual_into(X, F))) return restore(rc);
+    if (s == 0 && start) {
+      c->pc_sigma = 1.0 / dt;
+      if ((rc = precond_apply(c, F, R))) return restore(rc);
+      HIPCHK(c, hipMemcpyAsync(Xprev, X, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      if ((rc = lincomb(c, 2, {1.0, 1.0}, {X, R}, X))) return restore(rc);
+    } else {
+      const double sg = 1.5 / dt;
+      c->pc_sigma = sg;
+      const double a = 2.0 * sg / 3.0;
+      if ((rc = lincomb(c, 4, {a, -a, 2.0, -1.0}, {Xprev, X, F, Fp}, R))) return restore(rc);
+      if ((rc = precond_apply(c, R, R))) return restore(rc);
+      if ((rc = lincomb(c, 3, {2.0, -1.0, 1.0}, {X, Xprev, R}, R))) return restore(rc);
+      HIPCHK(c, hipMemcpyAsync(Xprev, X, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(X, R, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
+    std::swap(F, Fp);  // F(X) of this step is F(X-) of the next
+  }
+  if (nsteps > 0 && (rc = check_finite(c, X, n, "time step"))) return restore(rc);
+  return restore(KV_OK);
+}
+
 int kv_set_gmres_restart(kv_ctx* c, int m) {
   if (!c) return KV_EINVAL;
   if (m < 10 || m > 400) return fail(c, KV_EINVAL, "GMRES restart length must be in 10..400");
@@ -1378,7 +1461,7 @@ int kv_set_gmres_restart(kv_ctx* c, int m) {
 
 int kv_workspace_size(const kv_ctx* c, int op, int krylov_dim, int n_eigs, size_t* bytes) {
   if (!c || !bytes) return KV_EINVAL;
-  if (op < KV_WS_PROJECT_MIXED || op > KV_WS_ARNOLDI) return KV_EINVAL;
+  if (op < KV_WS_PROJECT_MIXED || op > KV_WS_TIME_STEPS) return KV_EINVAL;
   if (op == KV_WS_ARNOLDI && (krylov_dim < 2 || krylov_dim > 400 || n_eigs < 1 || n_eigs >= krylov_dim))
     return KV_EINVAL;
   *bytes = ws_need(c, op, krylov_dim, n_eigs);
@@ -1522,6 +1605,250 @@ int kv_state_add_cell_increment(kv_ctx* c, const float* cells, const float* cell
   return state_from_cells(c, cells, cells_ref, rx, ry, rz, xc, yc, zc, zero, scale, X);
 }
 
+// ---- thick-restarted Arnoldi -----------------------------------------------------------------
+// Upper Hessenberg form Z^T A Z of a dense m x m matrix (row-major, in
+// place) with Z e_m = e_m: rows are reduced from the bottom up, row i by a
+// Householder reflector on coordinates 0..i-1 that maps A[i, 0..i-1] to a
+// multiple of e_{i-1}, so the last coordinate is never touched and the
+// Arnoldi residual of a Ritz vector Z s keeps the form |h_{m+1,m}| |s_m|.
+static void hessenberg_keep_last(std::vector<double>& A, int m, std::vector<double>& Z) {
+  Z.assign((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
+  std::vector<double> v(m);
+  for (int i = m - 1; i >= 2; --i) {
+    const int L = i;  // coordinates 0..L-1
+    double nrm = 0.0;
+    for (int j = 0; j < L; ++j) nrm += A[(size_t)i * m + j] * A[(size_t)i * m + j];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double xl = A[(size_t)i * m + L - 1];
+    const double alpha = xl > 0 ? -nrm : nrm;
+    for (int j = 0; j < L; ++j) v[j] = A[(size_t)i * m + j];
+    v[L - 1] -= alpha;
+    double vv = 0.0;
+    for (int j = 0; j < L; ++j) vv += v[j] * v[j];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // A <- A H (columns 0..L-1 of every row), Z <- Z H
+    for (std::vector<double>* M : {&A, &Z})
+      for (int r = 0; r < m; ++r) {
+        double* row = M->data() + (size_t)r * m;
+        double t = 0.0;
+        for (int j = 0; j < L; ++j) t += row[j] * v[j];
+        t *= beta;
+        for (int j = 0; j < L; ++j) row[j] -= t * v[j];
+      }
+    // A <- H A (rows 0..L-1)
+    for (int cc = 0; cc < m; ++cc) {
+      double t = 0.0;
+      for (int j = 0; j < L; ++j) t += v[j] * A[(size_t)j * m + cc];
+      t *= beta;
+      for (int j = 0; j < L; ++j) A[(size_t)j * m + cc] -= t * v[j];
+    }
+    for (int j = 0; j < L - 1; ++j) A[(size_t)i * m + j] = 0.0;
+  }
+}
+
+// Leading eigenvalues by Arnoldi restarted thick (Morgan's restart with
+// Ritz vectors, the same space as Krylov-Schur with exact shifts): after m
+// steps the real and imaginary parts of the `keep` leading Ritz vectors
+// (pairs whole), orthonormalized, become the first basis vectors, the last
+// Arnoldi vector follows them, and the projected matrix restarts as their
+// k x k block plus the residual row.  No filter and no locking: converged
+// vectors stay in the kept set.  Workspace layout as the Chebyshev driver.
+static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int sym_rot, double* lam_re,
+                         double* lam_im, double* resid, double* evecs, kv_eig_info* info) {
+  const int64_t n = c->g.n;
+  const int m = p->krylov_dim;
+  int rc;
+  double* V = c->ws;
+  double* zp = V + (int64_t)(m + 1) * n;
+  double* zc = zp + n;
+  double* tmp = zc + n;
+  double* L = tmp + n;
+  double* Ys = L + (int64_t)(p->n_eigs + 1) * n;
+  EigScope scope(c, sym_ref, sym_rot, L);
+  c->relaxed_qr = 0;
+  HIPCHK(c, hipMemcpyAsync(V, p->v0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = project_inplace(c, V))) return rc;
+  if (sym_ref || sym_rot) HIPCHK(c, launch_symmetry_class(c, V, V, sym_ref, sym_rot));
+  double vn = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
+  if (rc) return rc;
+  if (!(vn > 0) || !std::isfinite(vn)) return fail(c, KV_ENONFINITE, "zero or non-finite start vector");
+  if ((rc = lincomb(c, 1, {1.0 / vn}, {V}, V))) return rc;
+  const char* ev = getenv("KV_ARNOLDI_TRACE");
+  const bool trace = ev && atoi(ev) != 0;
+  std::vector<double> H, A((size_t)m * m), Z, Hh;
+  int matvecs = 0, restarts = 0, k0 = 0;
+  bool conv = false;
+  Ritz rz;
+  std::vector<int> wsel;  // indices (into rz.sel order) of the wanted values
+  for (;;) {
+    int k = 0;
+    if ((rc = arnoldi(c, V, m, H, &k, &matvecs, k0))) {
+      if (info) *info = kv_eig_info{0, matvecs, restarts, 0, c->relaxed_qr};
+      return rc;
+    }
+    // Hessenberg form of the projected k x k matrix, last coordinate fixed
+    const int ld = m + 1;
+    A.assign((size_t)k * k, 0.0);
+    for (int r = 0; r < k; ++r)
+      for (int cc = 0; cc < k; ++cc) A[(size_t)r * k + cc] = H[r + (size_t)cc * ld];
+    hessenberg_keep_last(A, k, Z);
+    Hh.assign((size_t)ld * m, 0.0);
+    for (int r = 0; r < k; ++r)
+      for (int cc = std::max(0, r - 1); cc < k; ++cc) Hh[r + (size_t)cc * ld] = A[(size_t)r * k + cc];
+    if (k < m || k == m) Hh[k + (size_t)(k - 1) * ld] = (k < m) ? 0.0 : H[m + (size_t)(m - 1) * ld];
+    const int nkeep = std::min({p->keep, k - 2, 63});
+    if ((rc = ritz(c, Hh, m, k, std::max(nkeep, p->n_eigs), rz))) {
+      if (info) *info = kv_eig_info{0, matvecs, restarts, 0, c->relaxed_qr};
+      return rc;
+    }
+    // the wanted set (first n_eigs in leading order, a pair whole) inside rz.sel
+    const std::vector<int> want = wanted_set(rz.vals, p->n_eigs);
+    double scale = 0.0;
+    for (int i : want) scale = std::max(scale, std::abs(rz.vals[i]));
+    wsel.clear();
+    bool all = true;
+    for (int i : want) {
+      const int q = (int)(std::find(rz.sel.begin(), rz.sel.end(), i) - rz.sel.begin());
+      wsel.push_back(q);
+      if (!(rz.res[q] <= p->tol * scale)) all = false;
+    }
+    conv = all || k < m;
+    if (trace) {
+      double rmx = 0.0;
+      for (int q : wsel) rmx = std::max(rmx, rz.res[q]);
+      fprintf(stderr, "[arnoldi-thick] restart %d matvecs %d res/scale %.3e", restarts, matvecs, rmx / scale);
+      for (size_t q = 0; q < wsel.size() && q < 4; ++q)
+        fprintf(stderr, "  (%.6g, %.6g)", rz.vals[rz.sel[wsel[q]]].real(), rz.vals[rz.sel[wsel[q]]].imag());
+      fprintf(stderr, "\n");
+    }
+    if (conv || matvecs + (m - nkeep) > p->max_matvec || (p->max_restarts > 0 && restarts >= p->max_restarts) ||
+        p->max_restarts == 0)
+      break;
+    // kept set: the leading nkeep Ritz values of rz.sel (a pair whole), as
+    // real coefficient vectors in the V basis (Z s), orthonormalized
+    int kq = 0;
+    std::vector<std::vector<double>> Wc;
+    for (int q = 0; q < (int)rz.sel.size() && kq < nkeep; ++q) {
+      const auto th = rz.vals[rz.sel[q]];
+      if (th.imag() < 0) continue;  // its +Im partner carries the pair
+      const int parts = th.imag() > 0 ? 2 : 1;
+      if (kq + parts > 63) break;
+      for (int part = 0; part < parts; ++part) {
+        std::vector<double> w(k, 0.0);
+        for (int r = 0; r < k; ++r) {
+          double acc = 0.0;
+          for (int t = 0; t < k; ++t)
+            acc += Z[(size_t)r * k + t] * (part == 0 ? rz.vecs[q][t].real() : rz.vecs[q][t].imag());
+          w[r] = acc;
+        }
+        // twice modified Gram-Schmidt against the kept ones
+        for (int pass = 0; pass < 2; ++pass)
+          for (const auto& u : Wc) {
+            double d = 0.0;
+            for (int r = 0; r < k; ++r) d += u[r] * w[r];
+            for (int r = 0; r < k; ++r) w[r] -= d * u[r];
+          }
+        double nw = 0.0;
+        for (double x : w) nw += x * x;
+        nw = std::sqrt(nw);
+        if (!(nw > 1e-12)) continue;  // dependent: drop
+        for (double& x : w) x /= nw;
+        Wc.push_back(w);
+        ++kq;
+      }
+    }
+    if (kq < 1) return fail(c, KV_ENOCONV, "thick restart: no Ritz vector kept");
+    // T = W^T G W and the residual row h_{m+1,m} W[m-1, :]
+    std::vector<double> GW((size_t)k * kq, 0.0);
+    for (int cc = 0; cc < kq; ++cc)
+      for (int r = 0; r < k; ++r) {
+        double acc = 0.0;
+        for (int t = 0; t < k; ++t) acc += H[r + (size_t)t * ld] * Wc[cc][t];
+        GW[(size_t)r * kq + cc] = acc;
+      }
+    const double hlast = H[m + (size_t)(m - 1) * ld];
+    std::vector<double> Hn((size_t)ld * m, 0.0);
+    for (int r = 0; r < kq; ++r)
+      for (int cc = 0; cc < kq; ++cc) {
+        double acc = 0.0;
+        for (int t = 0; t < k; ++t) acc += Wc[r][t] * GW[(size_t)t * kq + cc];
+        Hn[r + (size_t)cc * ld] = acc;
+      }
+    for (int cc = 0; cc < kq; ++cc) Hn[kq + (size_t)cc * ld] = hlast * Wc[cc][k - 1];
+    H.swap(Hn);
+    // V[0..kq) = V W in place, then the last Arnoldi vector becomes V[kq]
+    std::vector<double> Wrow((size_t)k * kq);
+    for (int r = 0; r < k; ++r)
+      for (int cc = 0; cc < kq; ++cc) Wrow[(size_t)r * kq + cc] = Wc[cc][r];
+    double* dW = c->hess;  // the Hessenberg area is free between cycles
+    if ((rc = upload(c, dW, Wrow.data(), Wrow.size() * sizeof(double)))) return rc;
+    HIPCHK(c, launch_combine(c, V, n, k, dW, kq, V, n));
+    HIPCHK(c, hipMemcpyAsync(V + (int64_t)kq * n, V + (int64_t)m * n, n * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    // back into range(P) (and the class): A = P J has the eigenvalue 0 on
+    // gradient fields, right of every wanted value of a stable state, and
+    // the restarts amplify the round-off the basis carries there until a
+    // spurious Ritz value 0 converges (seen on the Gr = 0 conduction state)
+    for (int q = 0; q <= kq; ++q) {
+      double* vq = V + (int64_t)q * n;
+      if ((rc = project_inplace(c, vq))) return rc;
+      if (sym_ref || sym_rot) HIPCHK(c, launch_symmetry_class(c, vq, vq, sym_ref, sym_rot));
+    }
+    k0 = kq;
+    ++restarts;
+  }
+  // outputs: the wanted values in leading order
+  const int nout = (int)wsel.size();
+  for (int q = 0; q < nout; ++q) {
+    lam_re[q] = rz.vals[rz.sel[wsel[q]]].real();
+    lam_im[q] = rz.vals[rz.sel[wsel[q]]].imag();
+    if (resid) resid[q] = rz.res[wsel[q]];
+  }
+  if (evecs) {
+    // Ritz vectors V Z s of the wanted values (real and imaginary parts) into
+    // the Ritz slots, then normalized and turned like the Chebyshev driver's
+    const int k = (int)rz.vecs.empty() ? 0 : (int)rz.vecs[0].size();
+    std::vector<const double*> src_re(nout, nullptr), src_im(nout, nullptr);
+    std::vector<int> nl(nout, 0), outidx(nout);
+    std::vector<std::complex<double>> vals(nout);
+    int slot = 0;
+    for (int q = 0; q < nout; ++q) {
+      const auto th = rz.vals[rz.sel[wsel[q]]];
+      vals[q] = th;
+      outidx[q] = q;
+      if (th.imag() < 0) {
+        src_re[q] = src_re[q - 1];
+        src_im[q] = src_im[q - 1];
+        continue;
+      }
+      const int parts = th.imag() > 0 ? 2 : 1;
+      std::vector<double> Wrow((size_t)k * parts);
+      for (int r = 0; r < k; ++r)
+        for (int part = 0; part < parts; ++part) {
+          double acc = 0.0;
+          for (int t = 0; t < k; ++t)
+            acc += Z[(size_t)r * k + t] *
+                   (part == 0 ? rz.vecs[wsel[q]][t].real() : rz.vecs[wsel[q]][t].imag());
+          Wrow[(size_t)r * parts + part] = acc;
+        }
+      if (slot + parts > p->n_eigs + 1) return fail(c, KV_EINVAL, "eigenvector workspace exhausted");
+      if ((rc = upload(c, c->hess, Wrow.data(), Wrow.size() * sizeof(double)))) return rc;
+      HIPCHK(c, launch_combine(c, V, n, k, c->hess, parts, Ys + (int64_t)slot * n, n));
+      src_re[q] = Ys + (int64_t)slot * n;
+      src_im[q] = parts == 2 ? src_re[q] + n : nullptr;
+      slot += parts;
+    }
+    c->nlock = 0;
+    if ((rc = write_eigenvectors(c, L, outidx, vals, src_re, src_im, nl, evecs, zp, zc, tmp, &matvecs))) return rc;
+  }
+  if (info) *info = kv_eig_info{nout, matvecs, restarts, conv ? 1 : 0, c->relaxed_qr};
+  if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");
+  return KV_OK;
+}
+
 // ---- Chebyshev-preconditioned Arnoldi -------------------------------------------------------
 int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_re, double* lam_im,
                             double* resid, double* evecs, kv_eig_info* info) {
@@ -1539,6 +1866,10 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   // vectors (+ as many lock-time Ritz vectors when eigenvectors are asked for)
   const int nslot = p->n_eigs + 1;
   if ((rc = ws_bind(c, KV_WS_ARNOLDI, m, p->n_eigs))) return rc;
+  if (p->keep > 0) {
+    if (p->keep <= p->n_eigs || p->keep > m - 2) return fail(c, KV_EINVAL, "keep must be in n_eigs+1..krylov_dim-2");
+    return arnoldi_thick(c, p, sym_ref, sym_rot, lam_re, lam_im, resid, evecs, info);
+  }
   double* V = c->ws;
   double* zp = c->ws + (int64_t)(m + 1) * n;
   double* zc = zp + n;

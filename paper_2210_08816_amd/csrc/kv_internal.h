@@ -136,6 +136,10 @@ hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const doub
 hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w);
 // w -= sum_i h[i] V_i, h on the device (nvec values)
 hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w);
+// out_q = sum_{j<m} W[j kq + q] V_j (V row stride ldv, out row stride ldo,
+// W on the device, kq <= 64); out may be V itself with ldo == ldv
+hipError_t launch_combine(const kv_ctx* c, const double* V, int64_t ldv, int m, const double* W, int kq,
+                          double* out, int64_t ldo);
 // out = sum_k coef[k] * in[k], k < nterm <= 4 (out may alias in[k])
 hipError_t launch_lincomb(const kv_ctx* c, int64_t n, int nterm, const double* coef,
                           const double* const* in, double* out);
@@ -149,6 +153,13 @@ hipError_t launch_div_measure(kv_ctx* c, const double* y);
 hipError_t launch_symmetry(kv_ctx* c, const double* X);
 // y = projection of x onto a symmetry class; e_ref, e_rot in {-1, 0, +1}; y may equal x
 hipError_t launch_symmetry_class(kv_ctx* c, const double* x, double* y, int e_ref, int e_rot);
+
+// The mixed-form projection of y (kv_project with KV_MIXED) with its
+// scratch vector ymix (n doubles) supplied by the caller.
+int project_mixed_with(kv_ctx* c, double* y, double* div_out, int* sweeps_out, double* ymix);
+bool mixed_grid(const kv_ctx* c);
+// Bytes of device scratch the mixed projection needs on c's grid.
+size_t mixed_scratch_bytes(const kv_ctx* c);
 
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
 // KV_FD_TILE=64 or 32: the tile shape every FD and Helmholtz GEMM pass must

@@ -146,6 +146,33 @@ __global__ void __launch_bounds__(256) mupdate_kernel(int64_t n, const double* _
   }
 }
 
+// out_q = sum_j W[j kq + q] V_j for q < kq <= KQ (a tall-skinny product V W
+// of m vectors by an m x kq matrix).  Each thread owns one element index e:
+// it reads V_j[e] for every j before writing out_q[e], so out may be V
+// itself (ldo == ldv): the restart of a thick-restarted Arnoldi overwrites
+// the first kq basis vectors in place.  W is read through scalar loads (its
+// indices are uniform across the wave).
+template <int KQ>
+__global__ void __launch_bounds__(256) combine_kernel(int64_t n, const double* V, int64_t ldv, int m,
+                                                      const double* __restrict__ W, int kq, double* out,
+                                                      int64_t ldo) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double acc[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) acc[q] = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double v = V[j * ldv + e];
+      const double* wj = W + (int64_t)j * kq;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q)
+        if (q < kq) acc[q] += wj[q] * v;
+    }
+#pragma unroll
+    for (int q = 0; q < KQ; ++q)
+      if (q < kq) out[q * ldo + e] = acc[q];
+  }
+}
+
 struct Coef4 {
   double c[4];
 };
@@ -235,6 +262,18 @@ hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const 
 hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
   mupdate_kernel<<<flat_blocks(c->g.n), 256, 0, c->stream>>>(c->g.n, V, ldv, nvec, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const kv_ctx* c, const double* V, int64_t ldv, int m, const double* W, int kq,
+                          double* out, int64_t ldo) {
+  if (m < 1 || kq < 1 || kq > 64) return hipErrorInvalidValue;
+  const int64_t n = c->g.n;
+  const int nb = flat_blocks(n);
+  if (kq <= 8) combine_kernel<8><<<nb, 256, 0, c->stream>>>(n, V, ldv, m, W, kq, out, ldo);
+  else if (kq <= 16) combine_kernel<16><<<nb, 256, 0, c->stream>>>(n, V, ldv, m, W, kq, out, ldo);
+  else if (kq <= 32) combine_kernel<32><<<nb, 256, 0, c->stream>>>(n, V, ldv, m, W, kq, out, ldo);
+  else combine_kernel<64><<<nb, 256, 0, c->stream>>>(n, V, ldv, m, W, kq, out, ldo);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libkv_hip.so")
 KV_OK, KV_EINVAL, KV_ENOMEM, KV_EDEVICE, KV_ENOCONV, KV_ENONFINITE, KV_ESTATE = range(7)
 KV_PROJECT, KV_MIXED = 1, 2
 KV_PC_NONE, KV_PC_STOKES = 0, 1
-KV_WS_PROJECT_MIXED, KV_WS_APPLY_PRECONDITIONER, KV_WS_NEWTON, KV_WS_ARNOLDI = 1, 2, 3, 4
+KV_WS_PROJECT_MIXED, KV_WS_APPLY_PRECONDITIONER, KV_WS_NEWTON, KV_WS_ARNOLDI, KV_WS_TIME_STEPS = 1, 2, 3, 4, 5
 KV_SYM_REF_EVEN, KV_SYM_REF_ODD, KV_SYM_ROT_EVEN, KV_SYM_ROT_ODD = 1 << 4, 1 << 5, 1 << 6, 1 << 7
 
 
@@ -40,7 +40,7 @@ ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_
                "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
-               "kv_arnoldi_leading_eigs", "kv_cells_from_state",
+               "kv_arnoldi_leading_eigs", "kv_time_steps", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
 
 
@@ -64,7 +64,8 @@ class _SolveInfo(ctypes.Structure):
 class _ArnoldiParams(ctypes.Structure):
     _fields_ = [("krylov_dim", ctypes.c_int), ("n_eigs", ctypes.c_int), ("max_matvec", ctypes.c_int),
                 ("max_restarts", ctypes.c_int), ("cheb_degree_max", ctypes.c_int),
-                ("tol", ctypes.c_double), ("v0", ctypes.c_void_p), ("flags", ctypes.c_uint)]
+                ("tol", ctypes.c_double), ("v0", ctypes.c_void_p), ("flags", ctypes.c_uint),
+                ("keep", ctypes.c_int)]
 
 
 class _EigInfo(ctypes.Structure):
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH):
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD, P,
                                             ctypes.POINTER(_EigInfo)]
+    lib.kv_time_steps.argtypes = [P, D, ctypes.c_int, ctypes.c_int, P, P]
     lib.kv_cells_from_state.argtypes = [P, P, ctypes.c_int, PD, PD, P]
     lib.kv_state_from_cells.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, PD, PD, PD, PD, PD, P]
     lib.kv_state_add_cell_increment.argtypes = [P, P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, PD, PD, PD,
@@ -321,6 +323,13 @@ class Context:
         self._ensure_workspace(KV_WS_APPLY_PRECONDITIONER)
         self._check(self._lib.kv_apply_preconditioner(self._h, _dptr(x, self.n), _dptr(y, self.n)))
 
+    def time_steps(self, X, Xprev, dt, nsteps, start=True):
+        """nsteps semi-implicit time steps of Eqs. 1-6 (SBDF2; the first at
+        order 1 when start), X and Xprev updated in place (kv_time_steps)."""
+        self._ensure_workspace(KV_WS_TIME_STEPS)
+        self._check(self._lib.kv_time_steps(self._h, float(dt), int(nsteps), 1 if start else 0,
+                                            _dptr(X, self.n), _dptr(Xprev, self.n)))
+
     def cells_from_state(self, X, factor, shift, scale, out):
         """Normalized cell-centred (u, v, w, theta) of X on the grid coarsened
         by factor, into out (float32 CUDA, 4 * ncells)."""
@@ -355,14 +364,15 @@ class Context:
                                                           rz, *pc, psc, _dptr(X, self.n)))
 
     def arnoldi_leading_eigs(self, v0, krylov_dim, n_eigs, tol=1e-8, max_matvec=100000,
-                             max_restarts=1000, cheb_degree_max=200, sym=None, evecs=None, check=True):
+                             max_restarts=1000, cheb_degree_max=200, sym=None, evecs=None, check=True, keep=0):
         """sym: a symmetry class (e_ref, e_rot) to restrict the Krylov space
         to (see sym_flags), or None.  evecs: None, or a float64 CUDA tensor of
         (n_eigs + 1) * n values that receives the eigenvectors, one per row
         (a conjugate pair as the real and imaginary part of the +Im member's)."""
         self._ensure_workspace(KV_WS_ARNOLDI, krylov_dim, n_eigs)
         p = _ArnoldiParams(int(krylov_dim), int(n_eigs), int(max_matvec), int(max_restarts),
-                           int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, sym_flags(sym))
+                           int(cheb_degree_max), float(tol), _dptr(v0, self.n).value, sym_flags(sym),
+                           int(keep))
         re = (ctypes.c_double * (n_eigs + 1))()
         im = (ctypes.c_double * (n_eigs + 1))()
         res = (ctypes.c_double * (n_eigs + 1))()

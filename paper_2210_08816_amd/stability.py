@@ -22,7 +22,8 @@ from .continuation import sweep
 
 
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
-        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, log=print):
+        cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, keep=0,
+        log=print):
     """state: a converged packed state at Gr (host array) to start from
     instead of continuation; save_state: file to store the converged state;
     sym: None (one unrestricted Arnoldi run) or a list of symmetry classes
@@ -69,10 +70,12 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
-                                                       cheb_degree_max=cheb_degree_max, sym=cls, check=False)
+                                                       cheb_degree_max=cheb_degree_max, sym=cls, check=False,
+                                                       keep=keep)
             torch.cuda.synchronize()
             t_eig = time.perf_counter() - t1
             runs.append({"symmetry_class": list(cls) if cls else None, "krylov_dim": krylov, "n_eigs": n_eigs,
+                         "restart": f"thick, keep {keep}" if keep else "Chebyshev filter",
                          "tol": tol, "seconds": round(t_eig, 3), "matvecs": info["matvecs"],
                          "restarts": info["restarts"], "converged": info["converged"], "status": info["status"],
                          "eigenvalues": [[float(v.real), float(v.imag)] for v in vals],
@@ -127,11 +130,13 @@ def main(argv=None):
     ap.add_argument("--sym", default=None,
                     help="symmetry classes for restricted Arnoldi runs: 'all', or a comma list of sign pairs "
                          "(reflection, 2-D rotation), p = kept and m = broken, such as --sym pm,mm")
+    ap.add_argument("--keep", type=int, default=0,
+                    help="thick restart keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
               max_matvec=a.max_matvec, precond_sigma=None if a.sigma < 0 else a.sigma, state=state,
-              save_state=a.save_state, sym=parse_sym(a.sym), log=lambda m: print(m, flush=True))
+              save_state=a.save_state, sym=parse_sym(a.sym), keep=a.keep, log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
         with open(a.json, "w") as fh:

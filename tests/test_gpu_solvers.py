@@ -440,9 +440,10 @@ def test_workspace_is_caller_owned():
         ctx.set_preconditioner(False)
         m, k = 20, 4
         kk = m * m
-        hess = 4 * kk + 4 * m + 2 + 2 * (k + 1) * (kk + m)
+        slots = max(k + 1, min(m, 64))     # Ritz vectors: the wanted set, or a thick restart's kept set
+        hess = 4 * kk + 4 * m + 2 + 2 * slots * (kk + m)
         assert ctx.workspace_size(kv.KV_WS_ARNOLDI, m, k) == (m + 4 + 2 * (k + 1)) * vec + 8 * hess
-        for bad in ((0, 0, 0), (5, 0, 0), (kv.KV_WS_ARNOLDI, 20, 20), (kv.KV_WS_ARNOLDI, 1, 1)):
+        for bad in ((0, 0, 0), (6, 0, 0), (kv.KV_WS_ARNOLDI, 20, 20), (kv.KV_WS_ARNOLDI, 1, 1)):
             b = ctypes.c_size_t()
             assert ctx._lib.kv_workspace_size(ctx._h, *bad, ctypes.byref(b)) == kv.KV_EINVAL
         F = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -492,3 +493,59 @@ def test_workspace_is_caller_owned():
         assert O.div_measure(g, to_host(y)) <= 1e-10
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered"])
+def test_thick_restart_leading_eigenvalues(kind):
+    """The thick-restarted Arnoldi (keep > 0) reaches the same leading
+    eigenvalues as the dense generalized saddle problem, and its eigenvectors
+    are certified by the oracle's own operator A = P J."""
+    print(f"case thick restart {kind}", flush=True)
+    fx = [faces(kind, n) for n in (6, 5, 4)]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    X0 = S.base_flow(*fx, K=2, amp=0.3, seed=21)
+    ctx = context(fx, 2e4, 0.71, X0)
+    ev = torch.zeros(5 * g.size, dtype=torch.float64, device="cuda")
+    vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=24, n_eigs=4,
+                                               tol=1e-11, max_matvec=20000, keep=10, evecs=ev)
+    assert info["converged"] and info["restarts"] >= 1, info
+    lam = dense_saddle_eigs(g, X0)
+    scale = np.max(np.abs(lam[:4]))
+    assert closest(vals, lam[:6]) <= 1e-8 * scale, (vals, lam[:6])
+    assert closest(lam[:4], vals) <= 1e-8 * scale
+    A = SV.Operator(g, X0)
+    E = to_host(ev).reshape(5, g.size)
+    q = 0
+    while q < len(vals):
+        lam_q = vals[q]
+        if lam_q.imag > 0:
+            x = E[q] + 1j * E[q + 1]
+            r = (A(x.real) + 1j * A(x.imag)) - lam_q * x
+            nx = np.sqrt(A.norm(x.real) ** 2 + A.norm(x.imag) ** 2)
+            assert np.sqrt(A.norm(r.real) ** 2 + A.norm(r.imag) ** 2) <= 1e-8 * scale * nx
+            q += 2
+        else:
+            assert abs(lam_q.imag) == 0.0
+            assert A.norm(A(E[q]) - lam_q.real * E[q]) <= 1e-8 * scale * A.norm(E[q])
+            q += 1
+
+
+def test_thick_restart_gr0_closed_form_and_bad_keep():
+    from paper_2210_08816_amd import kv
+    nx, ny, nz = 7, 6, 5
+    fx = [S.faces_uniform(k) for k in (nx, ny, nz)]
+    g = O.Grid(*fx, Gr=0.0, Pr=10.0)
+    ctx = context(fx, 0.0, 10.0, S.conduction_state(*fx))
+    v0 = to_dev(S.perturbation(g.size, 77))
+    vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov_dim=24, n_eigs=4, tol=1e-10, max_matvec=20000, keep=12)
+    assert info["converged"], info
+    lx = -(4.0 * nx * nx) * np.sin(np.arange(1, nx + 1) * np.pi / (2 * nx)) ** 2
+    ly = -(4.0 * ny * ny) * np.sin(np.arange(ny) * np.pi / (2 * ny)) ** 2
+    lz = -(4.0 * nz * nz) * np.sin(np.arange(nz) * np.pi / (2 * nz)) ** 2
+    closed = np.sort((lx[:, None, None] + ly[None, :, None] + lz[None, None, :]).ravel() * g.kappa)[::-1]
+    assert np.max(np.abs(vals.imag)) < 1e-8
+    assert np.allclose(np.sort(vals.real)[::-1][:4], closed[:4], rtol=1e-8)
+    for keep in (4, 23):            # keep must exceed n_eigs and leave room to extend
+        with pytest.raises(kv.KVError) as e:
+            ctx.arnoldi_leading_eigs(v0, krylov_dim=24, n_eigs=4, keep=keep)
+        assert e.value.code == kv.KV_EINVAL
