@@ -152,6 +152,21 @@ int kv_apply_jacobian(kv_ctx* ctx, const double* x, double* y, unsigned flags);
  * the FP64 projection, the refinement sweeps with KV_MIXED). */
 int kv_project(kv_ctx* ctx, double* y, unsigned flags, double* div_max, int* sweeps);
 
+/* kv_project with KV_MIXED for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same mixed projection of y in place, its scratch vector
+ * in the library's static device array instead of a caller workspace.  The
+ * array (64 MiB per GPU, held until the process ends) serves grids with
+ * n <= 8,388,608 packed unknowns (128^3 and below); larger ones give
+ * KV_EINVAL without touching y, as does a grid without the even/odd split
+ * (it would take the FP64 projection, which needs no scratch: use
+ * kv_project).  No allocation of any kind and no phase timing; div_max and
+ * sweeps (host, may be NULL) as in kv_project.  All calls on one GPU share
+ * the array, so calls that overlap on one GPU (other contexts, other
+ * threads, other streams) race; each call writes every scratch entry it
+ * reads. */
+int kv_project_mixed_static(kv_ctx* ctx, double* y, double* div_max, int* sweeps);
+
 /* <a, b>_W on the device, result to host *out. */
 int kv_dot(kv_ctx* ctx, const double* a, const double* b, double* out);
 

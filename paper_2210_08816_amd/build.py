@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkv_hip.so")
 
 SOURCES = ["kv_capi.cpp", "kv_eig1d.cpp", "kv_stencil.hip", "kv_fd.hip", "kv_fd_split.hip", "kv_vec.hip",
-           "kv_hess.hip", "kv_transfer.hip", "kvnn.hip"]
+           "kv_hess.hip", "kv_transfer.hip", "kvnn.hip", "kv_static.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",

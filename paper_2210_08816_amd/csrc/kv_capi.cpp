@@ -253,8 +253,9 @@ int ws_bind(kv_ctx* c, int op, int m, int neig);
 
 }  // namespace
 
-// The mixed projection with its scratch vector ymix (n doubles of device
-// memory the caller provides).
+// The mixed projection with its scratch vector ymix (n doubles, any device
+// memory the caller provides: the workspace, or the library's static scratch
+// for kv_project_mixed_static).
 int kv::project_mixed_with(kv_ctx* c, double* y, double* div_out, int* sweeps_out, double* ymix) {
   const int64_t C = c->ncell;
   int rc;
@@ -903,6 +904,7 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   }
   if (hipHostMalloc(&c->hres, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return cleanup(KV_ENOMEM, "hres");
+  if (static_scratch_init(c->device) != 0) return cleanup(KV_EDEVICE, "static scratch");
   // kv_hessenberg_eigenvalues (m <= 400) and the interpolation tables of
   // kv_state_from_cells: small, fixed by the limits and the grid
   if (hipMalloc(&c->hess_small, (400 * 400 + 2 * 400 + 2) * sizeof(double)) != hipSuccess)

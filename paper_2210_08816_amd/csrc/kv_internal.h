@@ -160,6 +160,9 @@ int project_mixed_with(kv_ctx* c, double* y, double* div_out, int* sweeps_out, d
 bool mixed_grid(const kv_ctx* c);
 // Bytes of device scratch the mixed projection needs on c's grid.
 size_t mixed_scratch_bytes(const kv_ctx* c);
+// Set-up of the library's static device scratch on the current device
+// (kv_static.hip); called by kv_create.
+int static_scratch_init(int device);
 
 // FD GEMM self-test entry (C = A B, row-major), used by the unit test only.
 // KV_FD_TILE=64 or 32: the tile shape every FD and Helmholtz GEMM pass must

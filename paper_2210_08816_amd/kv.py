@@ -37,7 +37,7 @@ STATUS_NAMES = {0: "KV_OK", 1: "KV_EINVAL", 2: "KV_ENOMEM", 3: "KV_EDEVICE", 4: 
 # every extern "C" symbol declared in include/kv.h
 ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_set_workspace",
                "kv_set_base_flow", "kv_residual",
-               "kv_apply_jacobian", "kv_project", "kv_dot", "kv_axpby", "kv_symmetry_measures",
+               "kv_apply_jacobian", "kv_project", "kv_project_mixed_static", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_time_steps", "kv_cells_from_state",
@@ -96,6 +96,7 @@ def load(path: str = LIB_PATH):
     lib.kv_residual.argtypes = [P, P, PD]
     lib.kv_apply_jacobian.argtypes = [P, P, P, ctypes.c_uint]
     lib.kv_project.argtypes = [P, P, ctypes.c_uint, PD, ctypes.POINTER(ctypes.c_int)]
+    lib.kv_project_mixed_static.argtypes = [P, P, PD, ctypes.POINTER(ctypes.c_int)]
     lib.kv_dot.argtypes = [P, P, P, PD]
     lib.kv_axpby.argtypes = [P, D, P, D, P]
     lib.kv_symmetry_measures.argtypes = [P, P, PD]
