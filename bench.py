@@ -67,25 +67,45 @@ def profiled_traffic(kernel, source):
     return int(t.group(1))
 
 
-def cpu_baseline(g_args, X0, x0, y_gpu):
-    """Time the oracle on the host for one projected Krylov vector and report
-    the GPU output's error against it."""
-    from oracle import disc as O
+def host_cpu():
+    """nproc and the CPU model name of the host."""
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def field_errors(g, got, ref):
+    """Per field u, v, w, T: relative 2-norm and largest element error over
+    the field's largest magnitude."""
+    l2, mx = [], []
+    for a, b in zip(g.unpack(got), g.unpack(ref)):
+        l2.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        mx.append(float(np.max(np.abs(a - b)) / np.max(np.abs(b))))
+    return {"l2": l2, "max": mx}
+
+
+def cpu_baseline(g_args, X0, x0, y_gpu):
+    """Time the oracle on one host core (BLAS limited to one thread) for one
+    projected Krylov vector and report the GPU outputs' errors against it."""
+    from oracle import disc as O
+    from threadpoolctl import threadpool_limits
     g = O.Grid(*g_args["faces"], Gr=g_args["Gr"], Pr=g_args["Pr"])
-    t0 = time.perf_counter()
-    fd = O.FastDiag(g)
-    ref = O.apply_jacobian(g, X0, x0, projected=True, fd=fd)
-    dt = time.perf_counter() - t0
-    errs = {}
-    for form, y in y_gpu.items():
-        errs[form] = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(g.unpack(y), g.unpack(ref))]
-    return {"value": 1.0 / dt, "unit": "Krylov vectors/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one P J x application (x seed 1000) on the full grid, {dt:.1f} s wall"}, errs
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fd = O.FastDiag(g)
+        ref = O.apply_jacobian(g, X0, x0, projected=True, fd=fd)
+        dt = time.perf_counter() - t0
+    errs = {form: field_errors(g, y, ref) for form, y in y_gpu.items()}
+    cpu = host_cpu()
+    return {"value": 1.0 / dt, "unit": "Krylov vectors/s", "cores": 1, "kind": "oracle",
+            "sample": f"one P J x application (x seed 1000) on the full grid, serial (one thread), "
+                      f"{dt:.1f} s wall; host {cpu['nproc']} CPUs, {cpu['model']}"}, errs
 
 
 # (ci, co, kernel size, resolution divisor) of the U-Net's 11 convolutions
@@ -104,14 +124,15 @@ def unet_flops(r, batch):
 
 def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
     """One restart-free Arnoldi cycle of Krylov dimension m (m projected
-    Jacobians and classical Gram-Schmidt twice) on the bench context.  The
-    Gram-Schmidt time is the cycle's wall time less m projected Jacobians at
-    the measured per-vector time, so it also carries the cycle's host
-    synchronizations and the Hessenberg eigensolve.  Its algorithmic bytes
-    follow the kernels: at step j (nv = j + 1 basis vectors) each of the two
-    passes reads the nv vectors and w once per group of 16 (multi-dot), reads
-    the nv vectors and w and writes w (update); the norm and the scaling of w
-    add three vector volumes."""
+    Jacobians and classical Gram-Schmidt twice, its second pass delayed by one
+    step) on the bench context.  The Gram-Schmidt time is the cycle's wall
+    time less m projected Jacobians at the measured per-vector time, so it
+    also carries the cycle's host synchronizations and the Hessenberg
+    eigensolve.  Its algorithmic bytes follow the kernels: at step j the
+    two-vector multi-dot reads the j + 1 basis vectors once and v_j and w once
+    per group of 16, and the fused update reads the j finished vectors, v_j
+    and w and writes v_j and w; the last vector's second pass reads the m + 1
+    vectors (and itself once per group of 16), then updates and scales it."""
     best = None
     for r in range(reps + 1):
         torch.cuda.synchronize()
@@ -121,7 +142,8 @@ def arnoldi_leg(torch, ctx, v0, n, matvec_ms, m=20, reps=3):
         dt = time.perf_counter() - t0
         if r > 0:  # the first call allocates the basis
             best = dt if best is None else min(best, dt)
-    vols = sum(2 * (2 * (j + 1) + (j + 1 + 15) // 16 + 2) + 3 for j in range(m))
+    vols = sum((j + 1) + 2 * ((j + 1 + 15) // 16) + j + 4 for j in range(m))
+    vols += (m + 1) + (m + 1 + 15) // 16 + (m + 2) + 2
     cgs_bytes = vols * 8.0 * n
     cgs_s = max(best - m * matvec_ms * 1e-3, 1e-9)
     ach = cgs_bytes / cgs_s / 1e9
@@ -215,6 +237,81 @@ def learned_leg(torch, steps=10):
             "predict_tflops": round(fwd_flops / t_pred / 1e12, 3)}
 
 
+def thousand_leg(torch, ctx, X0, faces, spec, count, oracle_r=(0, 499, 999), threads=16):
+    """The 256^3 workload's protocol: count projected Jacobians on x_r ~
+    N(0,1) seeded 1000 + r (r = 0 .. count-1), FP64 and mixed.  Every mixed
+    output is compared on the GPU with the FP64 output of the same x_r (per
+    field, relative 2-norm and largest element error over the field's
+    largest magnitude); the outputs for r in oracle_r are compared with the
+    oracle on the host.  Inputs are drawn on the host by a thread pool
+    (numpy releases the GIL) while the GPU works; only the GPU calls are
+    timed (events around each, median / p10 / p90)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import disc as O
+    from synth import inputs as S
+    n = ctx.n
+    offs = ctx.offsets
+    x = torch.empty(n, dtype=torch.float64, device="cuda")
+    y64 = torch.empty_like(x)
+    ymx = torch.empty_like(x)
+    pinned = [torch.empty(n, dtype=torch.float64, pin_memory=True) for _ in range(2)]
+    t64, tmx, worst_l2, worst_max, l2s = [], [], [0.0] * 4, [0.0] * 4, []
+    keep = {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_start = time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        futs = {r: pool.submit(S.perturbation, n, 1000 + r) for r in range(min(count, 2 * threads))}
+        nxt = len(futs)
+        for r in range(count):
+            xh = futs.pop(r).result()
+            if nxt < count:
+                futs[nxt] = pool.submit(S.perturbation, n, 1000 + nxt)
+                nxt += 1
+            buf = pinned[r % 2]
+            buf.numpy()[:] = xh
+            x.copy_(buf, non_blocking=True)
+            ev[0].record()
+            ctx.apply_jacobian(x, y64, project=True, mixed=False)
+            ev[1].record()
+            ctx.apply_jacobian(x, ymx, project=True, mixed=True)
+            ev[2].record()
+            d = ymx - y64
+            l2, mx = [], []
+            for f in range(4):
+                a, b = d[offs[f]:offs[f + 1]], y64[offs[f]:offs[f + 1]]
+                l2.append(torch.linalg.vector_norm(a) / torch.linalg.vector_norm(b))
+                mx.append(a.abs().max() / b.abs().max())
+            vals = torch.stack(l2 + mx).cpu().numpy()          # synchronizes
+            t64.append(ev[0].elapsed_time(ev[1]))
+            tmx.append(ev[1].elapsed_time(ev[2]))
+            for f in range(4):
+                worst_l2[f] = max(worst_l2[f], float(vals[f]))
+                worst_max[f] = max(worst_max[f], float(vals[4 + f]))
+            l2s.append(float(vals[:4].max()))
+            if r in oracle_r:
+                keep[r] = (xh, y64.cpu().numpy(), ymx.cpu().numpy())
+            if r % 100 == 0:
+                log(f"[bench] 256^3 protocol: {r + 1}/{count} vectors")
+    t_all = time.perf_counter() - t_start
+    g = O.Grid(*faces, Gr=spec["Gr"], Pr=spec["Pr"])
+    fd = O.FastDiag(g)
+    per_out = {}
+    for r, (xh, a64, amx) in sorted(keep.items()):
+        log(f"[bench] oracle for r = {r}")
+        ref = O.apply_jacobian(g, X0, xh, projected=True, fd=fd)
+        per_out[str(r)] = {"fp64": field_errors(g, a64, ref), "mixed": field_errors(g, amx, ref)}
+
+    def stats(v):
+        v = np.asarray(v)
+        return {"median": round(float(np.median(v)), 5), "p10": round(float(np.percentile(v, 10)), 5),
+                "p90": round(float(np.percentile(v, 90)), 5)}
+    return {"count": count, "seeds": f"1000 + r, r = 0..{count - 1}", "wall_s": round(t_all, 1),
+            "ms_per_vector": {"fp64": stats(t64), "mixed": stats(tmx)},
+            "mixed_vs_fp64_gpu": {"worst_l2_per_field": worst_l2, "worst_max_per_field": worst_max,
+                                  "median_of_worst_field_l2": float(np.median(l2s))},
+            "vs_oracle": per_out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +326,11 @@ def main():
     ap.add_argument("--no-arnoldi", action="store_true", help="skip the Arnoldi-cycle timing leg")
     ap.add_argument("--learned-only", action="store_true",
                     help="run only the network timing leg and print its JSON (for profiling)")
+    ap.add_argument("--thousand", type=int, default=0,
+                    help="run the 256^3 protocol on this many perturbations (1000: the full one) and print "
+                         "its JSON instead of the bench line")
+    ap.add_argument("--oracle-only", action="store_true",
+                    help="time only the serial oracle's P J x on the workload (host only, no GPU) and print it")
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="also run this many plain device copies of one vector (a known-size "
                          "reference for hardware byte counters)")
@@ -237,6 +339,26 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(one solve per GPU is the sharding plan); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_only:
+        from synth import inputs as S
+        from oracle import disc as O
+        from threadpoolctl import threadpool_limits
+        spec = S.WORKLOADS[args.workload]
+        fx = S.workload_grid(spec)
+        X0 = S.base_flow(*fx, K=spec["K"], amp=spec["amp"], seed=spec["base_seed"])
+        g = O.Grid(*fx, Gr=spec["Gr"], Pr=spec["Pr"])
+        x = S.perturbation(g.size, 1000)
+        with threadpool_limits(limits=1):
+            fd = O.FastDiag(g)
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                O.apply_jacobian(g, X0, x, projected=True, fd=fd)
+                ts.append(time.perf_counter() - t0)
+        print(json.dumps({"workload": args.workload, "oracle_PJx_ms_serial": round(1e3 * float(np.median(ts)), 1),
+                          "repeats": 3, "host": host_cpu()}), flush=True)
+        return
 
     import torch
     from synth import inputs as S
@@ -262,6 +384,10 @@ def main():
     ys = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(B)]
     torch.cuda.synchronize()
     log(f"[bench] inputs resident: n = {n}, batch {B}")
+    if args.thousand > 0:
+        res = thousand_leg(torch, ctx, X0, (xf, yf, zf), spec, args.thousand)
+        print(json.dumps({"workload": args.workload, "protocol": res, "host": host_cpu()}), flush=True)
+        return
 
     def run_form(mixed):
         """Time args.steps projected Jacobians, then the per-phase device time
@@ -274,6 +400,18 @@ def main():
             ctx.apply_jacobian(xs[i % B], ys[i % B], project=True, mixed=mixed)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # per-vector device times (events on the library's stream, the torch
+        # stream current at context creation) over a further pass
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evs[0].record()
+        for i in range(args.steps):
+            ctx.apply_jacobian(xs[i % B], ys[i % B], project=True, mixed=mixed)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+        dist = {"median": round(float(np.median(per)), 5), "p10": round(float(np.percentile(per, 10)), 5),
+                "p90": round(float(np.percentile(per, 90)), 5), "mean": round(float(per.mean()), 5),
+                "n": int(per.size)}
         log(f"[bench] {'mixed' if mixed else 'fp64'}: {args.steps} steps in {dt:.3f} s: "
             f"{args.steps / dt:.1f} vectors/s")
         ctx.timing(True)
@@ -322,7 +460,8 @@ def main():
             t_dense = dense_transform_model_s(n_cells, spec["n"])
             extra = {"dense_transform_model_ms": round(1e3 * t_dense, 4),
                      "dense_transform_model_frac": round(t_dense / t_meas, 4)}
-        return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "roofline": roofline,
+        return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "ms_per_vector_events": dist,
+                "roofline": roofline,
                 "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / t_meas, 4), **extra,
                 "sweeps_per_vector": round(sweeps, 3),
                 "phases_ms_per_vector": {"stencil": round(per_vec[0], 5), "divergence": round(per_vec[1], 5),
@@ -350,6 +489,7 @@ def main():
         "config": {"workload": args.workload, "grid": f"{spec['n']}^3 {spec['grid']}", "Gr": spec["Gr"],
                    "Pr": spec["Pr"], "form": head_name, "resident_batch": B,
                    "unknowns": n},
+        "ms_per_vector": head["ms_per_vector_events"],
         "roofline": head["roofline"],
         "roofline_secondary": head["roofline_secondary"],
         "step_roofline_frac": head["step_roofline_frac"],
@@ -377,7 +517,7 @@ def main():
         base, errs = cpu_baseline({"faces": (xf, yf, zf), "Gr": spec["Gr"], "Pr": spec["Pr"]}, X0, xs_host0,
                                   outs)
         result["cpu_baseline"] = base
-        result["parity_vs_oracle"] = {"x_seed": 1000, "field_rel_err_l2": errs}
+        result["parity_vs_oracle"] = {"x_seed": 1000, "field_errors": errs}
     print(json.dumps(result), flush=True)
 
 

@@ -75,10 +75,11 @@ enum kv_status {
 
 /* Per-call flags.  KV_PROJECT: follow J by the projection P.  KV_MIXED
  * (kv_apply_jacobian, kv_project): the mixed-precision projection -- the
- * fast-diagonalization solve in FP32 storage on the FP32 matrix cores,
- * refined on the FP64 residual (in pairs of sweeps) until the normalized
- * divergence max|net flux| / max|face flux| is <= 1e-10 (KV_ENOCONV after 8
- * sweeps).  It needs every axis mirror-symmetric with an even cell count; on
+ * fast-diagonalization solve in FP32 storage on the FP32 matrix cores
+ * (KV_MIXED_FD=bf16x3 in the environment: bf16x3 split products on the bf16
+ * matrix cores), refined on the FP64 residual, the normalized divergence
+ * max|net flux| / max|face flux| checked after every sweep from the second
+ * until it is <= 1e-10 (KV_ENOCONV after 8 sweeps).  It needs every axis mirror-symmetric with an even cell count; on
  * other grids the FP64 projection is used.  The solvers reject KV_MIXED. */
 enum kv_flags { KV_PROJECT = 1u, KV_MIXED = 2u };
 

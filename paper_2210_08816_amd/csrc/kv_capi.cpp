@@ -249,6 +249,16 @@ int project_inplace(kv_ctx* c, double* y) {
 // most 8 sweeps).
 constexpr double kMixedDivTol = 1e-10;
 
+// Transforms of the mixed sweeps: FP32 products on the FP32 matrix cores
+// (default), or KV_MIXED_FD=bf16x3 for bf16x3 split products on the bf16
+// matrix cores (read at every call, for tests and measurements).  The bf16x3
+// passes are more accurate per sweep but, with their operands split and
+// transposed in LDS, slower than the FP32 ones on this hardware.
+bool mixed_fd_bf16x3() {
+  const char* e = getenv("KV_MIXED_FD");
+  return e && std::strcmp(e, "bf16x3") == 0;
+}
+
 int ws_bind(kv_ctx* c, int op, int m, int neig);
 
 }  // namespace
@@ -277,7 +287,8 @@ int kv::project_mixed_with(kv_ctx* c, double* y, double* div_out, int* sweeps_ou
     float* bn = from_y ? F1 : F0;
     {
       PhaseMark pm(c, 2);
-      HIPCHK(c, launch_fd_solve_f32(c, b, b));
+      if (mixed_fd_bf16x3()) HIPCHK(c, launch_fd_solve_bf3(c, b, b));
+      else HIPCHK(c, launch_fd_solve_f32(c, b, b));
     }
     {
       PhaseMark pm(c, 3);
@@ -491,37 +502,120 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
   return KV_OK;
 }
 
-// ---- Arnoldi with classical Gram-Schmidt twice -----------------------------------------
-// V holds up to m+1 vectors (stride n).  On entry V[0] is W-normalized.  Fills
-// H ((m+1) x m, column-major by j: H[i + j*(m+1)]) and returns the number of
-// completed steps k (k < m on a lucky breakdown).
+// ---- Arnoldi with delayed classical Gram-Schmidt twice ---------------------------------------
+// V holds up to m+1 vectors (stride n).  On entry V[j0] is the next vector
+// (W-normalized for j0 = 0) and, for j0 > 0, V[0..j0) and the columns < j0 of H
+// (with row j0) come from a thick restart.  Fills H ((m+1) x m, column-major
+// by j: H[i + j*(m+1)]) and returns the number of completed steps k (k < m on
+// a lucky breakdown); V[0..k] is W-orthonormal on return.
+//
+// Classical Gram-Schmidt twice with the second pass delayed by one step
+// (low-synchronization CGS2): step j applies A to v_j as orthogonalized once,
+// then ONE two-vector multi-dot over V[0..j] gives the coefficients that
+// finish v_j (s = V^T W v_j, its norm from <v_j, v_j> - |s|^2) and those of
+// w = A v_j; the coefficients of A v_j(final) follow on the host from the
+// Arnoldi relation already built (A V s = V H s), and ONE fused update pass
+// finishes v_j and orthogonalizes w once against V[0..j].  Against plain
+// CGS2 this reads the basis twice per step instead of four times and
+// synchronizes once.  The last vector gets its second pass at the end.
 int arnoldi(kv_ctx* c, double* V, int m, std::vector<double>& H, int* kout, int* matvecs, int j0 = 0) {
   const int64_t n = c->g.n;
-  if (j0 == 0) H.assign((size_t)(m + 1) * m, 0.0);  // else columns < j0 (and row j0) are kept
+  const int ld = m + 1;
+  if (j0 == 0) H.assign((size_t)ld * m, 0.0);  // else columns < j0 (and row j0) are kept
   int rc;
-  for (int j = j0; j < m; ++j) {
-    double* w = V + (int64_t)(j + 1) * n;
-    if ((rc = op_apply(c, V + (int64_t)j * n, w))) return rc;
-    ++*matvecs;
-    for (int pass = 0; pass < 2; ++pass) {
-      HIPCHK(c, launch_mdot(c, V, n, j + 1, w));
-      HIPCHK(c, launch_mupdate(c, V, n, j + 1, c->dres, w));
-      if ((rc = read_results(c, j + 1))) return rc;
-      for (int i = 0; i <= j; ++i) H[i + (size_t)j * (m + 1)] += c->hres[i];
+  std::vector<double> sv, g, h;
+  // finishes v_j (provisional, orthogonalized once) given s = V[0..j)^T W v_j
+  // and a = <v_j, v_j>_W: rho and the corrected columns of H; false if v_j
+  // vanishes (lucky breakdown)
+  auto finish_coeffs = [&](int jj, const double* sj, double a, double* rho_out) -> bool {
+    double ss = 0.0;
+    for (int i = 0; i < jj; ++i) ss += sj[i] * sj[i];
+    const double r2 = a - ss;
+    if (!(r2 > 1e-26 * a) || !std::isfinite(r2)) return false;
+    const double rho = std::sqrt(r2);
+    for (int cc = 0; cc < jj; ++cc) {
+      const double hj = H[jj + (size_t)cc * ld];
+      if (hj == 0.0) continue;
+      for (int i = 0; i < jj; ++i) H[i + (size_t)cc * ld] += hj * sj[i];
+      H[jj + (size_t)cc * ld] = hj * rho;
     }
-    const double hn = std::sqrt(std::max(0.0, dot1(c, w, w, &rc)));
-    if (rc) return rc;
-    if (!std::isfinite(hn)) return fail(c, KV_ENONFINITE, "non-finite Arnoldi vector");
-    double col = hn * hn;
-    for (int i = 0; i <= j; ++i) col += H[i + (size_t)j * (m + 1)] * H[i + (size_t)j * (m + 1)];
-    H[j + 1 + (size_t)j * (m + 1)] = hn;
-    if (hn <= 1e-14 * std::sqrt(col)) {
-      *kout = j + 1;
+    *rho_out = rho;
+    return true;
+  };
+  for (int j = j0; j < m; ++j) {
+    double* vj = V + (int64_t)j * n;
+    double* w = V + (int64_t)(j + 1) * n;
+    if ((rc = op_apply(c, vj, w))) return rc;
+    ++*matvecs;
+    HIPCHK(c, launch_mdot2(c, V, n, j + 1, vj, w, c->dres, c->dres + 512));
+    if ((rc = read_results(c, 1024))) return rc;
+    const double* a = c->hres;        // <V_i, v_j>, i <= j
+    const double* b = c->hres + 512;  // <V_i, w>, i <= j
+    if (!std::isfinite(a[j]) || !std::isfinite(b[j])) return fail(c, KV_ENONFINITE, "non-finite Arnoldi vector");
+    // scale of A v_{j-1} for the breakdown test of v_j
+    double col = a[j];
+    if (j > 0)
+      for (int i = 0; i < j; ++i) col += H[i + (size_t)(j - 1) * ld] * H[i + (size_t)(j - 1) * ld];
+    double rho = 0.0;
+    sv.assign(a, a + j);
+    const bool ok = finish_coeffs(j, sv.data(), a[j], &rho);
+    if (!ok || (j > j0 && rho <= 1e-14 * std::sqrt(col))) {
+      if (ok) {
+        // v_j is tiny: the space is invariant; H[j][j-1] keeps the tiny value
+      } else {
+        for (int cc = 0; cc < j; ++cc) H[j + (size_t)cc * ld] = 0.0;
+      }
+      *kout = j;
+      if (j == 0) return fail(c, KV_ENONFINITE, "zero Arnoldi start vector");
       return KV_OK;
     }
-    if ((rc = lincomb(c, 1, {1.0 / hn}, {w}, w))) return rc;
+    // A V s = V H s over the columns < j (H corrected above)
+    g.assign(j + 1, 0.0);
+    for (int cc = 0; cc < j; ++cc) {
+      const double scc = sv[cc];
+      if (scc == 0.0) continue;
+      for (int i = 0; i <= j; ++i) g[i] += H[i + (size_t)cc * ld] * scc;
+    }
+    double vw = b[j];
+    for (int i = 0; i < j; ++i) vw -= sv[i] * b[i];
+    vw /= rho;                                        // <v_j(final), w>
+    h.assign(j + 1, 0.0);
+    for (int i = 0; i < j; ++i) h[i] = (b[i] - g[i]) / rho;
+    h[j] = (vw - g[j]) / rho;
+    const double cvj = (g[j] / rho + h[j]) / rho;
+    // coefficients of the fused update: w <- w/rho - cvj v_j - V d,
+    // v_j <- (v_j - V s)/rho
+    double* hc = c->hcoef;
+    for (int i = 0; i < j; ++i) {
+      hc[i] = g[i] / rho + h[i] - cvj * sv[i];
+      hc[512 + i] = sv[i];
+    }
+    if (j > 0)
+      HIPCHK(c, hipMemcpyAsync(c->dcoef, hc, 1024 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_mupdate2(c, V, n, j, c->dcoef, c->dcoef + 512, 1.0 / rho, cvj, 1.0 / rho, w, vj));
+    for (int i = 0; i <= j; ++i) H[i + (size_t)j * ld] = h[i];
+    H[j + 1 + (size_t)j * ld] = 1.0;  // w holds v_{j+1} unnormalized (finished at the next step)
   }
+  // second pass of the last vector: v_m <- (v_m - V s)/rho
+  double* vm = V + (int64_t)m * n;
+  HIPCHK(c, launch_mdot(c, V, n, m + 1, vm, c->dres));
+  if ((rc = read_results(c, m + 1))) return rc;
+  sv.assign(c->hres, c->hres + m);
+  double col = c->hres[m];
+  for (int i = 0; i < m; ++i) col += H[i + (size_t)(m - 1) * ld] * H[i + (size_t)(m - 1) * ld];
+  double rho = 0.0;
+  if (!finish_coeffs(m, sv.data(), c->hres[m], &rho)) {
+    for (int cc = 0; cc < m; ++cc) H[m + (size_t)cc * ld] = 0.0;
+    *kout = m;
+    return KV_OK;
+  }
+  double* hc = c->hcoef;
+  for (int i = 0; i < m; ++i) hc[i] = sv[i];
+  HIPCHK(c, hipMemcpyAsync(c->dcoef, hc, m * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_mupdate(c, V, n, m, c->dcoef, vm));
+  if ((rc = lincomb(c, 1, {1.0 / rho}, {vm}, vm))) return rc;
   *kout = m;
+  (void)col;
   return KV_OK;
 }
 
@@ -892,9 +986,12 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   if (hipMalloc(&c->X0, g.n * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "X0");
   if (hipMalloc(&c->cellA, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellA");
   if (hipMalloc(&c->cellB, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellB");
-  if (hipMalloc(&c->part, (size_t)512 * c->npart_blocks * sizeof(double)) != hipSuccess)
+  if (hipMalloc(&c->part, (size_t)1024 * c->npart_blocks * sizeof(double)) != hipSuccess)
     return cleanup(KV_ENOMEM, "part");
   if (hipMalloc(&c->dres, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dres");
+  if (hipMalloc(&c->dcoef, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dcoef");
+  if (hipHostMalloc(&c->hcoef, 1024 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return cleanup(KV_ENOMEM, "hcoef");
   {
     // one pair of maxima per 64 x 4 block of the cell grid
     const int64_t cb = ((nx + 63) / 64) * ((ny + 3) / 4) * nz;
@@ -935,7 +1032,9 @@ int kv_destroy(kv_ctx* c) {
   hipFree(c->cellB);
   hipFree(c->part);
   hipFree(c->dres);
+  hipFree(c->dcoef);
   if (c->hres) hipHostFree(c->hres);
+  if (c->hcoef) hipHostFree(c->hcoef);
   for (auto& m : c->ev_marks) {
     hipEventDestroy(m.second.first);
     hipEventDestroy(m.second.second);

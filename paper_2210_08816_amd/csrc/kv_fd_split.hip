@@ -451,6 +451,316 @@ fd_split_kernel(SplitArgs<T> a, SplitEpi ep) {
     }
 }
 
+// ---- bf16x3 split products (mixed form) --------------------------------------------------
+// The same passes in FP32 storage, each operand split as x = hi + lo with hi
+// = bf16(x) and lo = bf16(x - hi) (round to nearest even; hi + lo holds x to
+// about 2^-17 relative), the product formed as hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the dropped lo*lo and
+// the split leave about 2^-16 relative per product).  Operands are split
+// when they are stashed into LDS, where each tile is held k-contiguous
+// (rows of BK bf16 plus a pad of 8), so that a lane's eight consecutive k
+// values of one row or column are one 16-byte read: MFMA lane l takes
+// A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i < 8, and
+// holds D[4 (l / 16) + q][l % 16].  64 x 64 output tiles, four waves in a
+// 2 x 2 layout, a 32-wide k chunk per LDS stage.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KIND, int EPI>
+__global__ void __launch_bounds__(256) fd_split_bf3_kernel(SplitArgs<float> a, SplitEpi ep) {
+  typedef v4f acc_t;
+  constexpr int BM = 64, BN = 64, BK = 32, KP = BK + 8;
+  constexpr bool INV = (KIND == RIGHT_INV || KIND == LEFT_INV);
+  constexpr bool RIGHT = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  constexpr int NS = INV ? 2 : 1;
+  constexpr int RM = BM / 32, RN = BN / 32;
+  constexpr int AE = BM * BK / 256, BE = BK * BN / 256;
+  constexpr int NB = INV ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) __bf16 As[NB][NS][2][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[NB][NS][2][BN][KP];
+
+  const int pars = INV ? 1 : 2;
+  const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * pars;
+  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (w >= total) return;
+  int mt, nt, par;
+  int64_t b;
+  {
+    int64_t t = w;
+    par = (int)(t % pars);
+    t /= pars;
+    if (RIGHT) {
+      nt = (int)(t % a.ntiles);
+      t /= a.ntiles;
+      mt = (int)(t % a.mtiles);
+      t /= a.mtiles;
+    } else {
+      mt = (int)(t % a.mtiles);
+      t /= a.mtiles;
+      nt = (int)(t % a.ntiles);
+      t /= a.ntiles;
+    }
+    b = t;
+  }
+  if (INV) par = 0;
+  const int N = a.N, H = a.H;
+  const float sgn = par ? -1.0f : 1.0f;
+  float* out = a.out + (RIGHT ? 0 : b * a.bstride);
+  const int M = RIGHT ? (int)a.R : H;
+  const int64_t NN = RIGHT ? H : a.P;
+  const int K = H;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = mt * BM;
+  const int64_t n0 = (int64_t)nt * BN;
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  constexpr int AKT = BK / AE;                      // threads per A row (4), AE = 8 consecutive k each
+  const int ar = tid / AKT, ak = (tid % AKT) * AE;
+  constexpr int BNT = BN / BE;                      // threads per B row (8), BE = 8 consecutive n each
+  const int bk = tid / BNT, bn = (tid % BNT) * BE;
+  constexpr bool AFLY = (KIND == RIGHT_FWD), BFLY = (KIND == LEFT_FWD);
+  const int64_t in_elems = RIGHT ? a.R * (int64_t)N : (int64_t)a.batch * a.bstride + (a.batch == 1 ? (int64_t)N * a.P : 0);
+  const __amdgpu_buffer_rsrc_t rin = make_rsrc(a.in, in_elems);
+  const __amdgpu_buffer_rsrc_t rq = make_rsrc(a.Qs, 2 * (int64_t)H * H);
+  const __amdgpu_buffer_rsrc_t rqt = make_rsrc(a.QsT, 2 * (int64_t)H * H);
+  const int64_t boff = RIGHT ? 0 : b * a.bstride;
+  float ra[NS][AE], rb[NS][BE];
+  float rah[AFLY ? NS : 1][AFLY ? AE : 1], rbh[BFLY ? NS : 1][BFLY ? BE : 1];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int ps = INV ? s : par;
+#pragma unroll
+      for (int q = 0; q < AE; ++q) {
+        const int gm = m0 + ar, gk = k0 + ak + q;
+        const bool ok = gm < M && gk < K;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD) {
+          o = ok ? (gm * N + gk) * 4 : OOB;
+          oh = ok ? (gm * N + N - 1 - gk) * 4 : OOB;
+        } else if (KIND == RIGHT_INV) {
+          o = ok ? (gm * N + ps * H + gk) * 4 : OOB;
+        } else {
+          o = ok ? ((ps * H + gm) * H + gk) * 4 : OOB;
+        }
+        if (KIND == RIGHT_FWD || KIND == RIGHT_INV) ra[s][q] = bload<float>(rin, o);
+        else if (KIND == LEFT_FWD) ra[s][q] = bload<float>(rqt, o);
+        else ra[s][q] = bload<float>(rq, o);
+        if (AFLY) rah[AFLY ? s : 0][AFLY ? q : 0] = bload<float>(rin, oh);
+      }
+#pragma unroll
+      for (int q = 0; q < BE; ++q) {
+        const int gk = k0 + bk;
+        const int64_t gn = n0 + bn + q;
+        const bool ok = gk < K && gn < NN;
+        int o = OOB, oh = OOB;
+        if (KIND == RIGHT_FWD || KIND == RIGHT_INV) {
+          o = ok ? ((ps * H + gk) * H + (int)gn) * 4 : OOB;
+          rb[s][q] = bload<float>(KIND == RIGHT_FWD ? rq : rqt, o);
+        } else if (KIND == LEFT_FWD) {
+          o = ok ? (int)((boff + (int64_t)gk * a.P + gn) * 4) : OOB;
+          oh = ok ? (int)((boff + (int64_t)(N - 1 - gk) * a.P + gn) * 4) : OOB;
+          rb[s][q] = bload<float>(rin, o);
+          rbh[BFLY ? s : 0][BFLY ? q : 0] = bload<float>(rin, oh);
+        } else {
+          o = ok ? (int)((boff + (int64_t)(ps * H + gk) * a.P + gn) * 4) : OOB;
+          rb[s][q] = bload<float>(rin, o);
+        }
+      }
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+#pragma unroll
+      for (int q = 0; q < AE; ++q) {
+        const float v = AFLY ? ra[s][q] + sgn * rah[AFLY ? s : 0][AFLY ? q : 0] : ra[s][q];
+        const __bf16 hi = (__bf16)v;
+        As[buf][s][0][ar][ak + q] = hi;
+        As[buf][s][1][ar][ak + q] = (__bf16)(v - (float)hi);
+      }
+#pragma unroll
+      for (int q = 0; q < BE; ++q) {
+        const float v = BFLY ? rb[s][q] + sgn * rbh[BFLY ? s : 0][BFLY ? q : 0] : rb[s][q];
+        const __bf16 hi = (__bf16)v;
+        Bs[buf][s][0][bn + q][bk] = hi;
+        Bs[buf][s][1][bn + q][bk] = (__bf16)(v - (float)hi);
+      }
+    }
+  };
+
+  acc_t acc[NS][RM][RN];
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+      for (int c = 0; c < RN; ++c) acc[s][r][c] = acc_t{0, 0, 0, 0};
+
+  constexpr bool HASEPI = EPI != EPI_NONE;
+  __shared__ double Erow[HASEPI ? BM : 1], Ecol[HASEPI ? 2 : 1][HASEPI ? BN : 1];
+  if constexpr (HASEPI) {
+    if (tid < BM) {
+      const int gm = m0 + tid;
+      double v = 0.0;
+      if (gm < M) v = (EPI == EPI_DIVIDE) ? ep.lz[par * H + gm] : ep.isy[gm % ep.ny] * ep.isz[gm / ep.ny];
+      Erow[tid] = v;
+    }
+    if (tid < BN) {
+      const int64_t gn = n0 + tid;
+      double v0 = 0.0, v1 = 0.0;
+      if (gn < NN) {
+        if (EPI == EPI_DIVIDE) {
+          const int g32 = (int)gn;
+          const int bb = g32 / ep.nx, aa = g32 - bb * ep.nx;
+          v0 = ep.ly[bb] + ep.lx[aa];
+        } else {
+          v0 = ep.isx[gn];
+          v1 = ep.isx[N - 1 - gn];
+        }
+      }
+      Ecol[0][tid] = v0;
+      Ecol[HASEPI ? 1 : 0][tid] = v1;
+    }
+  }
+
+  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) fetch(k0 + BK);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      bf16x8 ah[RM], al[RM], bh[RN], bl[RN];
+#pragma unroll
+      for (int r = 0; r < RM; ++r) {
+        ah[r] = *reinterpret_cast<const bf16x8*>(&As[buf][s][0][wm + 16 * r + lr][lk]);
+        al[r] = *reinterpret_cast<const bf16x8*>(&As[buf][s][1][wm + 16 * r + lr][lk]);
+      }
+#pragma unroll
+      for (int c = 0; c < RN; ++c) {
+        bh[c] = *reinterpret_cast<const bf16x8*>(&Bs[buf][s][0][wn + 16 * c + lr][lk]);
+        bl[c] = *reinterpret_cast<const bf16x8*>(&Bs[buf][s][1][wn + 16 * c + lr][lk]);
+      }
+#pragma unroll
+      for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int c = 0; c < RN; ++c) {
+          acc[s][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh[c], acc[s][r][c], 0, 0, 0);
+          acc[s][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl[c], acc[s][r][c], 0, 0, 0);
+          acc[s][r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh[c], acc[s][r][c], 0, 0, 0);
+        }
+    }
+    if (NB == 2) {
+      if (more) stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();
+      if (more) {
+        stash(0);
+        __syncthreads();
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < RM; ++r)
+#pragma unroll
+    for (int c = 0; c < RN; ++c) {
+      const int64_t gn = n0 + wn + c * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int lrow = wm + r * 16 + 4 * (lane >> 4) + q;
+        const int gm = m0 + lrow;
+        if (gm >= M || gn >= NN) continue;
+        if (!INV) {
+          double v = acc[0][r][c][q];
+          if (RIGHT) {
+            out[(int64_t)gm * N + par * H + gn] = (float)v;
+          } else {
+            const int mode = par * H + gm;
+            if (EPI == EPI_DIVIDE) {
+              const int64_t flat = (int64_t)mode * ((int64_t)ep.nx * ep.ny) + gn;
+              v = (flat == ep.null3) ? 0.0 : v / (Erow[lrow] + Ecol[0][wn + c * 16 + (lane & 15)]);
+            }
+            out[(int64_t)mode * a.P + gn] = (float)v;
+          }
+        } else {
+          const double t = acc[0][r][c][q], u = acc[1][r][c][q];
+          double lo = t + u, hi = t - u;
+          if (RIGHT) {
+            const int i = (int)gn;
+            if (EPI == EPI_ISQ) {
+              const double syz = Erow[lrow];
+              lo *= Ecol[0][wn + c * 16 + (lane & 15)] * syz;
+              hi *= Ecol[HASEPI ? 1 : 0][wn + c * 16 + (lane & 15)] * syz;
+            }
+            out[(int64_t)gm * N + i] = (float)lo;
+            out[(int64_t)gm * N + (N - 1 - i)] = (float)hi;
+          } else {
+            const int i = gm;
+            out[(int64_t)i * a.P + gn] = (float)lo;
+            out[(int64_t)(N - 1 - i) * a.P + gn] = (float)hi;
+          }
+        }
+      }
+    }
+}
+
+template <int KIND, int EPI>
+hipError_t launch_bf3(const SplitArgs<float>& a0, const SplitEpi& ep, hipStream_t s) {
+  SplitArgs<float> a = a0;
+  const bool inv = (KIND == RIGHT_INV || KIND == LEFT_INV);
+  const bool right = (KIND == RIGHT_FWD || KIND == RIGHT_INV);
+  const int64_t M = right ? a.R : a.H;
+  const int64_t NN = right ? a.H : a.P;
+  a.mtiles = (int)((M + 63) / 64);
+  a.ntiles = (int)((NN + 63) / 64);
+  const int64_t total = (int64_t)a.mtiles * a.ntiles * a.batch * (inv ? 1 : 2);
+  const int64_t blocks = ((total + 7) / 8) * 8;
+  fd_split_bf3_kernel<KIND, EPI><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(a, ep);
+  return hipGetLastError();
+}
+
+hipError_t split_pass_bf3(const kv_ctx* c, int axis, bool inverse, int epi, const float* in, float* out) {
+  const Grid& g = c->g;
+  SplitArgs<float> a{};
+  a.in = in;
+  a.out = out;
+  a.Qs = c->Qf32[axis];
+  a.QsT = c->Qt32[axis];
+  a.N = g.ax[axis].n;
+  a.H = a.N / 2;
+  a.batch = 1;
+  const int64_t nx = g.nx, ny = g.ny, nz = g.nz;
+  if (axis == 0) {
+    a.R = ny * nz;
+  } else if (axis == 1) {
+    a.P = nx;
+    a.bstride = nx * ny;
+    a.batch = (int)nz;
+  } else {
+    a.P = nx * ny;
+  }
+  SplitEpi ep{g.ax[0].lam, g.ax[1].lam, g.ax[2].lam, g.ax[0].isq, g.ax[1].isq, g.ax[2].isq,
+              g.nx, g.ny, g.null3};
+  hipStream_t s = c->stream;
+  if (axis == 0) {
+    if (!inverse) return launch_bf3<RIGHT_FWD, EPI_NONE>(a, ep, s);
+    if (epi == 2) return launch_bf3<RIGHT_INV, EPI_ISQ>(a, ep, s);
+    return launch_bf3<RIGHT_INV, EPI_NONE>(a, ep, s);
+  }
+  if (!inverse) {
+    if (epi == 1) return launch_bf3<LEFT_FWD, EPI_DIVIDE>(a, ep, s);
+    return launch_bf3<LEFT_FWD, EPI_NONE>(a, ep, s);
+  }
+  return launch_bf3<LEFT_INV, EPI_NONE>(a, ep, s);
+}
+
 // Pair loads on by default; KV_FD_PAIRS=0 selects one element per load
 // (read at every launch, so tests can cover both paths in one process).
 bool pair_loads() {
@@ -561,6 +871,20 @@ hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi
 // The same in FP32 storage on the FP32 matrix cores (mixed form).
 hipError_t launch_fd_split_pass_f32(const kv_ctx* c, int axis, bool inverse, int epi, const float* in, float* out) {
   return split_pass<float>(c, axis, inverse, epi, in, out, c->Qf32[axis], c->Qt32[axis]);
+}
+
+// The six passes with bf16x3 split products (FP32 storage): in (scaled
+// divergence) -> out (pressure); every axis must be split.  in is overwritten.
+hipError_t launch_fd_solve_bf3(const kv_ctx* c, float* in, float* out) {
+  float* A = in;
+  float* Bf = reinterpret_cast<float*>(c->cellB);
+  hipError_t e;
+  if ((e = split_pass_bf3(c, 0, false, 0, A, Bf))) return e;
+  if ((e = split_pass_bf3(c, 1, false, 0, Bf, A))) return e;
+  if ((e = split_pass_bf3(c, 2, false, 1, A, Bf))) return e;
+  if ((e = split_pass_bf3(c, 2, true, 0, Bf, A))) return e;
+  if ((e = split_pass_bf3(c, 1, true, 0, A, Bf))) return e;
+  return split_pass_bf3(c, 0, true, 2, Bf, out);
 }
 
 // Poisson solve in FP32 storage: in (scaled divergence) -> out (pressure);

@@ -72,6 +72,8 @@ struct kv_ctx {
   double* part = nullptr;     // reduction partials
   double* dres = nullptr;     // reduction results on the device (64 doubles)
   double* hres = nullptr;     // pinned host mirror of dres
+  double* dcoef = nullptr;    // device coefficients of the Gram-Schmidt updates (1024 doubles)
+  double* hcoef = nullptr;    // pinned host staging of dcoef
   int npart_blocks = 0;
   // caller-owned workspace (kv_set_workspace): solver vectors, Krylov
   // bases, the mixed-form scratch vector and the Ritz-vector work area are
@@ -120,6 +122,8 @@ hipError_t launch_fd_split_pass(const kv_ctx* c, int axis, bool inverse, int epi
 hipError_t launch_fd_split_pass_f32(const kv_ctx* c, int axis, bool inverse, int epi, const float* in, float* out);
 // FP32-storage Poisson solve (all axes split): in = scaled divergence, out = p
 hipError_t launch_fd_solve_f32(const kv_ctx* c, float* in, float* out);
+// The same with bf16x3 split products on the bf16 matrix cores
+hipError_t launch_fd_solve_bf3(const kv_ctx* c, float* in, float* out);
 // mixed form: FP32 b = V^1/2 D y from FP64 y
 hipError_t launch_scaled_divergence_f32(const kv_ctx* c, const double* y, float* out);
 // mixed form: yout = yin - G p (FP32 p), and from the corrected field the
@@ -131,9 +135,19 @@ hipError_t launch_gradient_correction(const kv_ctx* c, const double* p, double* 
 
 // Weighted dot products over the packed layout.  npair <= 4 pairs (a_i, b_i);
 // results land in c->dres[0..npair).
-hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b);
-// res[i] = <V_i, w>_W for i < nvec (V row stride ldv), results in c->dres (nvec <= 1024)
-hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w);
+hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b,
+                        double* out = nullptr);
+// res[i] = <V_i, w>_W for i < nvec (V row stride ldv), results in out (device,
+// default c->dres; nvec <= 512)
+hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w, double* out = nullptr);
+// out1[i] = <V_i, x1>_W, out2[i] = <V_i, x2>_W for i < nvec <= 512, one pass
+// over V (device outputs)
+hipError_t launch_mdot2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* x1, const double* x2,
+                       double* out1, double* out2);
+// w <- cw w - cv v - sum_i d[i] V_i and v <- cn (v - sum_i sv[i] V_i), one
+// pass over V (d, sv on the device, nvec <= 512 values, nvec may be 0)
+hipError_t launch_mupdate2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* d, const double* sv,
+                           double cw, double cv, double cn, double* w, double* v);
 // w -= sum_i h[i] V_i, h on the device (nvec values)
 hipError_t launch_mupdate(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* h, double* w);
 // out_q = sum_{j<m} W[j kq + q] V_j (V row stride ldv, out row stride ldo,

@@ -121,6 +121,69 @@ __global__ void __launch_bounds__(256) mdot_kernel(Grid g, const double* __restr
   }
 }
 
+// Two-vector block multi-dot of the delayed Gram-Schmidt: part[q] and
+// part[MD + q] for q < nv <= MD: <V_q, x1>_W and <V_q, x2>_W, each element
+// of V read once for both.
+__global__ void __launch_bounds__(256) mdot2_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
+                                                    const double* __restrict__ x1, const double* __restrict__ x2,
+                                                    double* __restrict__ part, int qbase, int ldp) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double a1[MD], a2[MD];
+#pragma unroll
+  for (int q = 0; q < MD; ++q) a1[q] = a2[q] = 0.0;
+  const int64_t nrows = total_rows(g);
+  for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
+    const RowInfo ri = row_info(g, r);
+    for (int e = lane; e < ri.len; e += 64) {
+      const int64_t idx = ri.off + e;
+      const double wt = ri.wx[e] * ri.wyz;
+      const double w1 = wt * x1[idx], w2 = wt * x2[idx];
+#pragma unroll
+      for (int q = 0; q < MD; ++q)
+        if (q < nv) {
+          const double v = V[q * ldv + idx];
+          a1[q] += w1 * v;
+          a2[q] += w2 * v;
+        }
+    }
+  }
+  for (int q = 0; q < nv; ++q) {
+    const double s1 = block_sum(a1[q], sh);
+    if (threadIdx.x == 0) part[(int64_t)(qbase + q) * gridDim.x + blockIdx.x] = s1;
+    const double s2 = block_sum(a2[q], sh);
+    if (threadIdx.x == 0) part[(int64_t)(ldp + qbase + q) * gridDim.x + blockIdx.x] = s2;
+  }
+}
+
+// The fused update of the delayed Gram-Schmidt, one pass over V_0..V_{nv-1}:
+//   w  <- cw w - cv v - sum_q d[q] V_q
+//   v  <- cn (v - sum_q s[q] V_q)
+// (d, s on the device, nv values each; nv may be 0).
+__global__ void __launch_bounds__(256) mupdate2_kernel(int64_t n, const double* __restrict__ V, int64_t ldv, int nv,
+                                                       const double* __restrict__ d, const double* __restrict__ sv,
+                                                       double cw, double cv, double cn, double* __restrict__ w,
+                                                       double* __restrict__ v) {
+  __shared__ double ds[512], ss[512];
+  for (int q = threadIdx.x; q < nv; q += 256) {
+    ds[q] = d[q];
+    ss[q] = sv[q];
+  }
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double au = 0.0, av = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < nv; ++q) {
+      const double x = V[q * ldv + e];
+      au += ds[q] * x;
+      av += ss[q] * x;
+    }
+    const double ve = v[e];
+    w[e] = cw * w[e] - cv * ve - au;
+    v[e] = cn * (ve - av);
+  }
+}
+
 __global__ void sum_finish_kernel(const double* __restrict__ part, int nblk, int nq, double* __restrict__ out) {
   __shared__ double sh[4];
   for (int q = 0; q < nq; ++q) {
@@ -230,7 +293,7 @@ inline int flat_blocks(int64_t n) {
 
 }  // namespace
 
-hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b) {
+hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const double* const* b, double* out) {
   Ptr4 pa{}, pb{};
   for (int q = 0; q < npair; ++q) {
     pa.p[q] = a[q];
@@ -244,18 +307,39 @@ hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const doub
     case 4: wdots_kernel<4><<<nblk, 256, 0, c->stream>>>(c->g, pa, pb, c->part); break;
     default: return hipErrorInvalidValue;
   }
-  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, npair, c->dres);
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, npair, out ? out : c->dres);
   return hipGetLastError();
 }
 
-hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w) {
+hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w, double* out) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
   const int nblk = c->npart_blocks;
   for (int q0 = 0; q0 < nvec; q0 += MD) {
     const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
     mdot_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
   }
-  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, c->dres);
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, out ? out : c->dres);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdot2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* x1, const double* x2,
+                       double* out1, double* out2) {
+  if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
+  const int nblk = c->npart_blocks;
+  // partials: [q][blk] for x1 at rows q < nvec, for x2 at rows 512 + q
+  for (int q0 = 0; q0 < nvec; q0 += MD) {
+    const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
+    mdot2_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, x1, x2, c->part, q0, 512);
+  }
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, out1);
+  sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part + (int64_t)512 * nblk, nblk, nvec, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_mupdate2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* d, const double* sv,
+                           double cw, double cv, double cn, double* w, double* v) {
+  if (nvec < 0 || nvec > 512) return hipErrorInvalidValue;
+  mupdate2_kernel<<<flat_blocks(c->g.n), 256, 0, c->stream>>>(c->g.n, V, ldv, nvec, d, sv, cw, cv, cn, w, v);
   return hipGetLastError();
 }
 
