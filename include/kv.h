@@ -258,6 +258,15 @@ int kv_time_steps(kv_ctx* ctx, double dt, int nsteps, int start, double* X, doub
  * to m + 9 vectors.  Kept until changed. */
 int kv_set_gmres_restart(kv_ctx* ctx, int m);
 
+/* Deflated restarting of the GMRES(m) continuation (Morgan's GMRES-DR): k
+ * harmonic Ritz vectors of the values of smallest modulus are kept from one
+ * cycle to the next, with the residual, so that the few eigenvalues of the
+ * (preconditioned) operator near zero -- which a steady branch near a Hopf
+ * point has -- are not rebuilt every cycle.  0 <= k <= 62 (and at most m - 2),
+ * default 0 (plain restarts).  The KV_WS_NEWTON workspace grows by one
+ * vector and a Hessenberg area when k > 0.  Kept until changed. */
+int kv_set_gmres_deflation(kv_ctx* ctx, int k);
+
 /* Stagnation limit of the BiCGstab(2) part of kv_newton_correction (Sec. 1:
  * BiCGstab(2) combined with GMRES): after this many cycles without a 10%
  * drop of the residual norm below its best value the solve continues as

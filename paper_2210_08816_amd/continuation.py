@@ -18,7 +18,8 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
     """Newton iteration on a context (its Gr fixed).  X: torch float64 CUDA
     tensor, updated in place (left at the last iterate on failure).  Stops
     when ||F|| <= max(tol_abs, tol_rel * ||F(X_start)||).  The inner solve
-    tolerance is max(1e-10, min(1e-2, ||F||)).  delta0_fn(X) gives the first
+    tolerance is max(1e-10, min(1e-2, ||F||)), loosened to a tenth of the
+    target over ||F|| near the end.  delta0_fn(X) gives the first
     BiCGstab(2) iterate of the first Newton step (None: zero).  Returns a dict
     with the residual history, matvecs, wall time and whether it converged."""
     import torch
@@ -41,10 +42,18 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
             break
         if it == max_iter:
             break
-        eta = max(1e-10, min(1e-2, fn))
+        # inner tolerance: min(1e-2, ||F||) (quadratic convergence), floored at
+        # 1e-10, but never tighter than what brings ||F|| to a tenth of the
+        # target (solving the last correction to 1e-10 relative is wasted
+        # work once a 1e-3 reduction reaches the target)
+        target = max(tol_abs, tol_rel * hist[0])
+        eta = max(1e-10, min(1e-2, fn), min(0.5, 0.1 * target / fn))
         d0 = delta0_fn(X) if delta0_fn is not None and it == 0 else None
         info = ctx.newton_correction(F, d, tol=eta, max_matvec=max_matvec, delta0=d0, check=False)
         mv += info["matvecs"]
+        if log:
+            log(f"  correction: tol {eta:.2e} matvecs {info['matvecs']} relres {info['relres']:.2e} "
+                f"gmres {info['used_gmres']} status {info['status']}")
         if info["status"] != 0:
             break
         ctx.axpby(1.0, d, 1.0, X)  # X <- X + delta on the device
@@ -53,14 +62,15 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
 
 
 def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12,
-          precond_sigma=None, gmres_restart=None, gr0=None, **kw):
+          precond_sigma=None, gmres_restart=None, gr0=None, gmres_deflation=0, **kw):
     """Continuation over increasing Gr values, from X0 (default: the
     conduction state) converged at Gr = gr0 (None: X0 is not a converged
     state).  A failed step is retried from the last converged state at the
     geometric midpoint in Gr, at most max_halvings times per requested value
     (a first step from an X0 without gr0 is not retried).  precond_sigma: None, or the shift of the Stokes/heat
     preconditioner of the Newton corrections; gmres_restart: None (the
-    library's default) or the restart length of their GMRES continuation.
+    library's default) or the restart length of their GMRES continuation;
+    gmres_deflation: harmonic Ritz vectors kept across its restarts (0: none).
     Returns (states, infos) for
     the requested Gr values reached; a value that cannot be reached ends the
     sweep."""
@@ -82,8 +92,10 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
                     ctx.set_preconditioner(True, precond_sigma)
                 if gmres_restart is not None:
                     ctx.set_gmres_restart(gmres_restart)
+                if gmres_deflation:
+                    ctx.set_gmres_deflation(gmres_deflation)
                 ctx.project(Xtry)
-                info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, **kw)
+                info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, log=log, **kw)
             finally:
                 ctx.close()
             info["Gr"] = target

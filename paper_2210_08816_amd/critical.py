@@ -138,12 +138,15 @@ def same_mode_by_frequency(info_a, info_b, rel=0.25, abs_tol=0.02):
 
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
         tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
-        newton_max_matvec=20000, gmres_restart=None, log=print):
+        newton_max_matvec=20000, gmres_restart=None, keep=0, state=None, log=print):
     """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
     the Arnoldi tolerance (relative to the largest wanted modulus): the sign
     of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
     newton_max_matvec: budget of each Newton correction; gmres_restart: the
-    restart length of its GMRES continuation (None: the library default)."""
+    restart length of its GMRES continuation (None: the library default);
+    keep: thick restart keeping that many Ritz vectors (0: the Chebyshev-
+    filtered restart); state: a converged state at gr_lo (host array) in place
+    of the continuation from rest."""
     import numpy as np
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
@@ -159,10 +162,13 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         g *= 1.6
     grs.append(gr_lo)
     t0 = time.perf_counter()
-    states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
-                          gmres_restart=gmres_restart, log=lambda m: None)
-    if len(states) < len(grs):
-        raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
+    if state is not None:
+        states = [torch.as_tensor(np.asarray(state, dtype=np.float64)).cuda()]
+    else:
+        states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20,
+                              precond_sigma=precond_sigma, gmres_restart=gmres_restart, log=lambda m: None)
+        if len(states) < len(grs):
+            raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
     known = [(gr_lo, states[-1])]   # converged states, nearest one starts each new Newton solve
     v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(states[-1].numel())).cuda()
     counts = {"newton_matvecs": 0, "arnoldi_matvecs": 0}
@@ -182,12 +188,16 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         try:
             ctx.set_base_flow(X)
             vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
-                                                       cheb_degree_max=cheb_degree_max, sym=sym, check=False)
+                                                       cheb_degree_max=cheb_degree_max, sym=sym, check=False,
+                                                       keep=keep)
         finally:
             ctx.close()
         counts["arnoldi_matvecs"] += info["matvecs"]
         lead = [[float(v.real), float(v.imag)] for v in vals[:2]]
         resid = [float(r) for r in res[:2]]
+        log(f"[critical] Gr={gr:.6e} leading {lead} residuals {resid} converged {info['converged']} "
+            f"arnoldi matvecs {info['matvecs']} newton matvecs so far {counts['newton_matvecs']} "
+            f"{time.perf_counter() - t0:.0f}s")
         if not info["converged"] or len(vals) == 0:
             return None, {"arnoldi": "not converged", "values": lead, "residuals": resid}
         return float(vals[0].real), {"values": lead, "residuals": resid, "matvecs": info["matvecs"]}
@@ -216,6 +226,9 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-5, help="Arnoldi tolerance")
     ap.add_argument("--newton-max-matvec", type=int, default=20000, help="budget of each Newton correction")
     ap.add_argument("--gmres-restart", type=int, default=None, help="GMRES restart length of the Newton corrections")
+    ap.add_argument("--keep", type=int, default=0,
+                    help="thick-restart Arnoldi keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
+    ap.add_argument("--load-state", default=None, help="a converged state at --gr-lo (.npy) instead of continuation")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     cls = parse_sym(a.sym)
@@ -223,7 +236,8 @@ def main(argv=None):
         raise SystemExit("--sym takes one class")
     res = run(n=a.n, grid=a.grid, gr_lo=a.gr_lo, gr_hi=a.gr_hi, ratio=a.ratio, sym=cls[0] if cls else None,
               krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
-              gmres_restart=a.gmres_restart,
+              gmres_restart=a.gmres_restart, keep=a.keep,
+              state=__import__("numpy").load(a.load_state) if a.load_state else None,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:

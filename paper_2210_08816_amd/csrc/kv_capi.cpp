@@ -450,7 +450,7 @@ size_t ws_vectors(const kv_ctx* c, int op, int m, int neig) {
   switch (op) {
     case KV_WS_PROJECT_MIXED: return 1;
     case KV_WS_APPLY_PRECONDITIONER: return 1;
-    case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0);
+    case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0) + (c->gmres_defl ? 1 : 0);
     case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1);
     case KV_WS_TIME_STEPS: return 4;
     default: return 0;
@@ -464,6 +464,7 @@ int ritz_slots(int m, int neig) { return std::max(neig + 1, std::min(m, 64)); }
 size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
   size_t bytes = ws_vectors(c, op, m, neig) * (size_t)c->g.n * sizeof(double);
   if (op == KV_WS_ARNOLDI) bytes += hess_area(m, ritz_slots(m, neig)) * sizeof(double);
+  if (op == KV_WS_NEWTON && c->gmres_defl) bytes += hess_area(c->gmres_m, c->gmres_defl + 1) * sizeof(double);
   return bytes;
 }
 
@@ -472,7 +473,8 @@ size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
 // vectors of n doubles:
 //   PROJECT_MIXED          ymix
 //   APPLY_PRECONDITIONER   pc_scr
-//   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr
+//   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr |
+//                          (deflated GMRES) a spare vector, the Hessenberg area
 //   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) | Hessenberg area
 //   TIME_STEPS             F | F of the previous step | right-hand side | pc_scr
 int ws_bind(kv_ctx* c, int op, int m, int neig) {
@@ -487,14 +489,17 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
   switch (op) {
     case KV_WS_PROJECT_MIXED: c->ymix = c->ws; break;
     case KV_WS_APPLY_PRECONDITIONER: c->pc_scr = c->ws; break;
-    case KV_WS_NEWTON:
+    case KV_WS_NEWTON: {
+      double* p = c->ws + (int64_t)(8 + c->gmres_m + 1) * n;
       if (c->pc_kind != KV_PC_NONE) {
-        double* p = c->ws + (int64_t)(8 + c->gmres_m + 1) * n;
         c->pc_tmp = p;
         c->pc_d0 = p + n;
         c->pc_scr = p + 2 * n;
+        p += 3 * n;
       }
+      if (c->gmres_defl) c->hess = p + n;  // after one spare vector
       break;
+    }
     case KV_WS_ARNOLDI: c->hess = c->ws + (int64_t)(m + 4 + 2 * (neig + 1)) * n; break;
     case KV_WS_TIME_STEPS: c->pc_scr = c->ws + 3 * n; break;
     default: return fail(c, KV_EINVAL, "unknown workspace operation");
@@ -649,7 +654,33 @@ std::vector<int> wanted_set(const std::vector<std::complex<double>>& v, int k) {
 }
 
 // Eigen-decomposition of H_k on the device; Ritz residuals h_{k+1,k} |e_k^T s|.
-int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out) {
+// The k values of smallest modulus, extended by one when that would split a
+// conjugate pair.
+std::vector<int> smallest_set(const std::vector<std::complex<double>>& v, int k) {
+  std::vector<int> idx(v.size());
+  for (size_t i = 0; i < v.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    if (std::abs(v[a]) != std::abs(v[b])) return std::abs(v[a]) < std::abs(v[b]);
+    return v[a].imag() > v[b].imag();
+  });
+  std::vector<int> sel(idx.begin(), idx.begin() + std::min<size_t>(k, idx.size()));
+  if (!sel.empty() && (size_t)k < idx.size()) {
+    const auto last = v[sel.back()];
+    if (last.imag() != 0.0) {
+      bool partner = false;
+      for (int i : sel) partner = partner || (i != sel.back() && std::abs(v[i] - std::conj(last)) <= 1e-12 * std::max(1.0, std::abs(last)));
+      if (!partner)
+        for (size_t q = k; q < idx.size(); ++q)
+          if (std::abs(v[idx[q]] - std::conj(last)) <= 1e-12 * std::max(1.0, std::abs(last))) {
+            sel.push_back(idx[q]);
+            break;
+          }
+    }
+  }
+  return sel;
+}
+
+int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out, bool smallest = false) {
   // device layout: Hk (k*k) | Hcopy (k*k) | wr k | wi k | lr, li (k each) | vr, vi (k*k) | info | cwork
   const size_t kk = (size_t)k * k;
   int rc;
@@ -674,7 +705,7 @@ int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz
   if (info & 2) ++c->relaxed_qr;  // a nearly defective cluster deflated at sqrt(eps)
   out.vals.resize(k);
   for (int i = 0; i < k; ++i) out.vals[i] = {wr[i], wi[i]};
-  out.sel = wanted_set(out.vals, n_eigs);
+  out.sel = smallest ? smallest_set(out.vals, n_eigs) : wanted_set(out.vals, n_eigs);
   const int ns = (int)out.sel.size();
   std::vector<double> lr(ns), li(ns);
   for (int q = 0; q < ns; ++q) {
@@ -983,10 +1014,13 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   }
   const int64_t rows = 2 * nz * ny + nz * (ny - 1) + (nz - 1) * ny;
   c->npart_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 3) / 4));
+  // the Gram-Schmidt multi-dots carry 16-32 accumulators per thread and run
+  // few waves per SIMD: they take up to four times as many blocks
+  c->nmd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (rows + 3) / 4));
   if (hipMalloc(&c->X0, g.n * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "X0");
   if (hipMalloc(&c->cellA, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellA");
   if (hipMalloc(&c->cellB, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellB");
-  if (hipMalloc(&c->part, (size_t)1024 * c->npart_blocks * sizeof(double)) != hipSuccess)
+  if (hipMalloc(&c->part, (size_t)1024 * std::max(c->npart_blocks, c->nmd_blocks) * sizeof(double)) != hipSuccess)
     return cleanup(KV_ENOMEM, "part");
   if (hipMalloc(&c->dres, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dres");
   if (hipMalloc(&c->dcoef, 1024 * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "dcoef");
@@ -1150,59 +1184,221 @@ int kv_symmetry_measures(kv_ctx* c, const double* X, double out[3]) {
 }
 
 // ---- Newton correction: BiCGstab(2), continued by GMRES(m) -------------------------------
+static void hessenberg_keep_last(std::vector<double>& A, int m, std::vector<double>& Z);
+
+// min || cv - Hb y || over y for a (k+1) x k matrix Hb (column-major, leading
+// dimension ld) by Householder QR on the host; res = cv - Hb y.
+static void lsq_solve(const std::vector<double>& Hb, int ld, int k, const std::vector<double>& cv,
+                      std::vector<double>& y, std::vector<double>& res) {
+  const int rows = k + 1;
+  std::vector<double> R((size_t)rows * k), q(cv.begin(), cv.begin() + rows), v(rows);
+  for (int cc = 0; cc < k; ++cc)
+    for (int r = 0; r < rows; ++r) R[(size_t)r * k + cc] = Hb[r + (size_t)cc * ld];
+  for (int cc = 0; cc < k; ++cc) {
+    double nrm = 0.0;
+    for (int r = cc; r < rows; ++r) nrm += R[(size_t)r * k + cc] * R[(size_t)r * k + cc];
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const double x0 = R[(size_t)cc * k + cc];
+    const double alpha = x0 > 0 ? -nrm : nrm;
+    double vv = 0.0;
+    for (int r = cc; r < rows; ++r) {
+      v[r] = R[(size_t)r * k + cc] - (r == cc ? alpha : 0.0);
+      vv += v[r] * v[r];
+    }
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    for (int c2 = cc; c2 < k; ++c2) {
+      double t = 0.0;
+      for (int r = cc; r < rows; ++r) t += v[r] * R[(size_t)r * k + c2];
+      t *= beta;
+      for (int r = cc; r < rows; ++r) R[(size_t)r * k + c2] -= t * v[r];
+    }
+    double t = 0.0;
+    for (int r = cc; r < rows; ++r) t += v[r] * q[r];
+    t *= beta;
+    for (int r = cc; r < rows; ++r) q[r] -= t * v[r];
+  }
+  y.assign(k, 0.0);
+  for (int r = k - 1; r >= 0; --r) {
+    double acc = q[r];
+    for (int c2 = r + 1; c2 < k; ++c2) acc -= R[(size_t)r * k + c2] * y[c2];
+    const double d = R[(size_t)r * k + r];
+    y[r] = d != 0.0 ? acc / d : 0.0;
+  }
+  res.assign(rows, 0.0);
+  for (int r = 0; r < rows; ++r) {
+    double acc = cv[r];
+    for (int cc = 0; cc < k; ++cc) acc -= Hb[r + (size_t)cc * ld] * y[cc];
+    res[r] = acc;
+  }
+}
+
+// Solves M^T f = e (M k x k column-major ld, e = last unit vector) by
+// Gaussian elimination with partial pivoting; false if singular.
+static bool solve_transposed_last(const std::vector<double>& Hb, int ld, int k, std::vector<double>& f) {
+  std::vector<double> A((size_t)k * k);
+  for (int r = 0; r < k; ++r)
+    for (int cc = 0; cc < k; ++cc) A[(size_t)r * k + cc] = Hb[cc + (size_t)r * ld];  // A = M^T
+  f.assign(k, 0.0);
+  f[k - 1] = 1.0;
+  for (int col = 0; col < k; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < k; ++r)
+      if (std::fabs(A[(size_t)r * k + col]) > std::fabs(A[(size_t)piv * k + col])) piv = r;
+    if (!(std::fabs(A[(size_t)piv * k + col]) > 0)) return false;
+    if (piv != col) {
+      for (int cc = 0; cc < k; ++cc) std::swap(A[(size_t)piv * k + cc], A[(size_t)col * k + cc]);
+      std::swap(f[piv], f[col]);
+    }
+    for (int r = col + 1; r < k; ++r) {
+      const double t = A[(size_t)r * k + col] / A[(size_t)col * k + col];
+      if (t == 0.0) continue;
+      for (int cc = col; cc < k; ++cc) A[(size_t)r * k + cc] -= t * A[(size_t)col * k + cc];
+      f[r] -= t * f[col];
+    }
+  }
+  for (int r = k - 1; r >= 0; --r) {
+    for (int cc = r + 1; cc < k; ++cc) f[r] -= A[(size_t)r * k + cc] * f[cc];
+    f[r] /= A[(size_t)r * k + r];
+  }
+  return true;
+}
+
+// Restarted GMRES(m) on A x = b from the current x (A = op_apply), with
+// deflated restarting when c->gmres_defl > 0 (Morgan's GMRES-DR): after a
+// full cycle the harmonic Ritz vectors of the gmres_defl values of smallest
+// modulus (eigenvalues of H_m + h^2 H_m^-T e_m e_m^T) and the residual
+// vector start the next cycle, so the few eigenvalues of the operator near
+// zero -- the weakly damped modes of a steady branch near a Hopf point --
+// stay in the space instead of being rebuilt every cycle.  The recursive
+// residual estimate ends a cycle; the true residual b - A x confirms it.
 static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, double tol, int m, int budget,
                        int* used, int* cycles, double* relres) {
   const int64_t n = c->g.n;
   int rc;
   double* V = c->ws + 8 * n;  // after the 8 BiCGstab(2) vectors (ws_bind, KV_WS_NEWTON)
-  std::vector<double> H;
+  std::vector<double> H, cv, y, res;
+  const int kd = std::min(c->gmres_defl, std::min(m - 2, 62));
+  bool fresh = true;
+  int j0 = 0;
   for (;;) {
-    // r = b - A x into V[0]
-    if ((rc = op_apply(c, x, V))) return rc;
-    ++*used;
-    if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
-    double beta = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
-    if (rc) return rc;
-    *relres = bnorm > 0 ? beta / bnorm : 0.0;
-    if (!std::isfinite(beta)) return fail(c, KV_ENONFINITE, "non-finite GMRES residual");
-    if (beta <= tol * bnorm) return KV_OK;
-    if (*used + 2 > budget) return KV_ENOCONV;
-    if ((rc = lincomb(c, 1, {1.0 / beta}, {V}, V))) return rc;
-    const int mm = std::max(1, std::min(m, budget - *used - 1));
+    if (fresh) {
+      // r = b - A x into V[0]
+      if ((rc = op_apply(c, x, V))) return rc;
+      ++*used;
+      if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
+      double beta = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
+      if (rc) return rc;
+      *relres = bnorm > 0 ? beta / bnorm : 0.0;
+      if (!std::isfinite(beta)) return fail(c, KV_ENONFINITE, "non-finite GMRES residual");
+      if (beta <= tol * bnorm) return KV_OK;
+      if (*used + 2 > budget) return KV_ENOCONV;
+      if ((rc = lincomb(c, 1, {1.0 / beta}, {V}, V))) return rc;
+      cv.assign(1, beta);
+      j0 = 0;
+    }
+    const int mm = std::max(j0 + 1, std::min(m, budget - *used - 1));
     int k = 0, mv = 0;
-    if ((rc = arnoldi(c, V, mm, H, &k, &mv))) return rc;
+    if ((rc = arnoldi(c, V, mm, H, &k, &mv, j0))) return rc;
     *used += mv;
-    // least squares min || beta e1 - H y || by Givens rotations on the host
     const int ld = mm + 1;
-    std::vector<double> R(H), g(k + 1, 0.0), cs(k), sn(k);
-    g[0] = beta;
-    for (int j = 0; j < k; ++j) {
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * R[i + j * ld] + sn[i] * R[i + 1 + j * ld];
-        R[i + 1 + j * ld] = -sn[i] * R[i + j * ld] + cs[i] * R[i + 1 + j * ld];
-        R[i + j * ld] = t;
-      }
-      const double a = R[j + j * ld], bb = R[j + 1 + j * ld];
-      const double r = std::hypot(a, bb);
-      cs[j] = r > 0 ? a / r : 1.0;
-      sn[j] = r > 0 ? bb / r : 0.0;
-      R[j + j * ld] = r;
-      R[j + 1 + j * ld] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-    }
-    std::vector<double> y(k, 0.0);
-    for (int i = k - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int q = i + 1; q < k; ++q) s -= R[i + q * ld] * y[q];
-      y[i] = (R[i + i * ld] != 0.0) ? s / R[i + i * ld] : 0.0;
-    }
+    cv.resize(k + 1, 0.0);
+    lsq_solve(H, ld, k, cv, y, res);
     // x += V y  (mupdate subtracts, so pass -y)
     std::vector<double> ny(k);
     for (int i = 0; i < k; ++i) ny[i] = -y[i];
     if ((rc = upload(c, c->dres, ny.data(), k * sizeof(double)))) return rc;
     HIPCHK(c, launch_mupdate(c, V, n, k, c->dres, x));
     ++*cycles;
+    double rn = 0.0;
+    for (double t : res) rn += t * t;
+    rn = std::sqrt(rn);
+    *relres = bnorm > 0 ? rn / bnorm : 0.0;
+    if (rn <= tol * bnorm || kd == 0 || k < mm || mm < kd + 2 || *used + 2 > budget) {
+      fresh = true;  // plain restart (or the final check) from the true residual
+      continue;
+    }
+    // deflated restart: harmonic Ritz vectors of the kd values nearest zero
+    std::vector<double> f;
+    const double hl = H[k + (size_t)(k - 1) * ld];
+    if (!solve_transposed_last(H, ld, k, f)) {
+      fresh = true;
+      continue;
+    }
+    std::vector<double> Mr((size_t)k * k), Z;
+    for (int r = 0; r < k; ++r)
+      for (int cc = 0; cc < k; ++cc) Mr[(size_t)r * k + cc] = H[r + (size_t)cc * ld];
+    for (int r = 0; r < k; ++r) Mr[(size_t)r * k + (k - 1)] += hl * hl * f[r];
+    hessenberg_keep_last(Mr, k, Z);
+    std::vector<double> Hh((size_t)ld * mm, 0.0);
+    for (int r = 0; r < k; ++r)
+      for (int cc = std::max(0, r - 1); cc < k; ++cc) Hh[r + (size_t)cc * ld] = Mr[(size_t)r * k + cc];
+    Ritz hz;
+    if ((rc = ritz(c, Hh, mm, k, kd, hz, true))) return rc;
+    std::vector<std::vector<double>> Q;  // columns of length k + 1
+    auto push = [&](std::vector<double> u) {
+      for (int pass = 0; pass < 2; ++pass)
+        for (const auto& qv : Q) {
+          double d = 0.0;
+          for (int r = 0; r <= k; ++r) d += qv[r] * u[r];
+          for (int r = 0; r <= k; ++r) u[r] -= d * qv[r];
+        }
+      double nu = 0.0;
+      for (double t : u) nu += t * t;
+      nu = std::sqrt(nu);
+      if (!(nu > 1e-12)) return false;
+      for (double& t : u) t /= nu;
+      Q.push_back(u);
+      return true;
+    };
+    for (size_t q = 0; q < hz.sel.size() && (int)Q.size() < kd; ++q) {
+      const auto th = hz.vals[hz.sel[q]];
+      if (th.imag() < 0) continue;
+      for (int part = 0; part < (th.imag() > 0 ? 2 : 1); ++part) {
+        std::vector<double> u(k + 1, 0.0);
+        for (int r = 0; r < k; ++r) {
+          double acc = 0.0;
+          for (int t = 0; t < k; ++t) acc += Z[(size_t)r * k + t] * (part == 0 ? hz.vecs[q][t].real() : hz.vecs[q][t].imag());
+          u[r] = acc;
+        }
+        push(u);
+      }
+    }
+    const int kq = (int)Q.size();
+    if (kq < 1 || !push(res)) {  // the residual direction comes last
+      fresh = true;
+      continue;
+    }
+    // H_new = Q^T Hbar Q[0..k), cv_new = Q^T res, V <- V Q
+    std::vector<double> HQ((size_t)(k + 1) * kq, 0.0);
+    for (int cc = 0; cc < kq; ++cc)
+      for (int r = 0; r <= k; ++r) {
+        double acc = 0.0;
+        for (int t = 0; t < k; ++t) acc += H[r + (size_t)t * ld] * Q[cc][t];
+        HQ[(size_t)r * kq + cc] = acc;
+      }
+    std::vector<double> Hn((size_t)ld * mm, 0.0);
+    for (int r = 0; r <= kq; ++r)
+      for (int cc = 0; cc < kq; ++cc) {
+        double acc = 0.0;
+        for (int t = 0; t <= k; ++t) acc += Q[r][t] * HQ[(size_t)t * kq + cc];
+        Hn[r + (size_t)cc * ld] = acc;
+      }
+    cv.assign(kq + 1, 0.0);
+    for (int r = 0; r <= kq; ++r) {
+      double acc = 0.0;
+      for (int t = 0; t <= k; ++t) acc += Q[r][t] * res[t];
+      cv[r] = acc;
+    }
+    std::vector<double> Wrow((size_t)(k + 1) * (kq + 1));
+    for (int t = 0; t <= k; ++t)
+      for (int cc = 0; cc <= kq; ++cc) Wrow[(size_t)t * (kq + 1) + cc] = Q[cc][t];
+    if ((rc = upload(c, c->hess, Wrow.data(), Wrow.size() * sizeof(double)))) return rc;
+    HIPCHK(c, launch_combine(c, V, n, k + 1, c->hess, kq + 1, V, n));
+    H.swap(Hn);
+    j0 = kq;
+    fresh = false;
   }
 }
 
@@ -1576,6 +1772,13 @@ int kv_set_workspace(kv_ctx* c, void* dev_ptr, size_t bytes) {
   c->ws = static_cast<double*>(dev_ptr);
   c->ws_bytes = bytes;
   c->ymix = c->pc_tmp = c->pc_d0 = c->pc_scr = c->hess = nullptr;
+  return KV_OK;
+}
+
+int kv_set_gmres_deflation(kv_ctx* c, int k) {
+  if (!c) return KV_EINVAL;
+  if (k < 0 || k > 62) return fail(c, KV_EINVAL, "GMRES deflation must be in 0..62");
+  c->gmres_defl = k;
   return KV_OK;
 }
 

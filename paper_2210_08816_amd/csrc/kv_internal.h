@@ -75,6 +75,7 @@ struct kv_ctx {
   double* dcoef = nullptr;    // device coefficients of the Gram-Schmidt updates (1024 doubles)
   double* hcoef = nullptr;    // pinned host staging of dcoef
   int npart_blocks = 0;
+  int nmd_blocks = 0;         // blocks of the multi-dot kernels (their partials also in part)
   // caller-owned workspace (kv_set_workspace): solver vectors, Krylov
   // bases, the mixed-form scratch vector and the Ritz-vector work area are
   // carved from it per call; the library never allocates them
@@ -96,6 +97,7 @@ struct kv_ctx {
   bool pc_active = false;     // set while a preconditioned solve runs
   int gmres_m = 40;           // restart length of the GMRES continuation of the Newton correction
   int stall_cycles = 50;      // BiCGstab(2) cycles without a 10% residual drop before GMRES takes over
+  int gmres_defl = 0;         // harmonic Ritz vectors kept across GMRES restarts (0: plain restarts)
   int sym_ref = 0, sym_rot = 0;  // symmetry class kept by matvec while a restricted Arnoldi runs
   const double* lockQ = nullptr;  // locked W-orthonormal vectors matvec deflates while Arnoldi runs
   int nlock = 0;

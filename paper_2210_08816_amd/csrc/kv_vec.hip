@@ -135,16 +135,22 @@ __global__ void __launch_bounds__(256) mdot2_kernel(Grid g, const double* __rest
   const int64_t nrows = total_rows(g);
   for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
     const RowInfo ri = row_info(g, r);
-    for (int e = lane; e < ri.len; e += 64) {
-      const int64_t idx = ri.off + e;
-      const double wt = ri.wx[e] * ri.wyz;
-      const double w1 = wt * x1[idx], w2 = wt * x2[idx];
+    // two elements per lane per iteration: the loads of both are in flight
+    // before the products (a lane past the row end reads element 0 with
+    // weight 0)
+    for (int e = lane; e < ri.len; e += 128) {
+      const int e1 = e + 64;
+      const bool in1 = e1 < ri.len;
+      const int64_t i0 = ri.off + e, i1 = ri.off + (in1 ? e1 : e);
+      const double wt0 = ri.wx[e] * ri.wyz, wt1 = in1 ? ri.wx[e1] * ri.wyz : 0.0;
+      const double u0 = wt0 * x1[i0], z0 = wt0 * x2[i0];
+      const double u1 = wt1 * x1[i1], z1 = wt1 * x2[i1];
 #pragma unroll
       for (int q = 0; q < MD; ++q)
         if (q < nv) {
-          const double v = V[q * ldv + idx];
-          a1[q] += w1 * v;
-          a2[q] += w2 * v;
+          const double v0 = V[q * ldv + i0], v1 = V[q * ldv + i1];
+          a1[q] += u0 * v0 + u1 * v1;
+          a2[q] += z0 * v0 + z1 * v1;
         }
     }
   }
@@ -313,7 +319,7 @@ hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const doub
 
 hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w, double* out) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
-  const int nblk = c->npart_blocks;
+  const int nblk = c->nmd_blocks;
   for (int q0 = 0; q0 < nvec; q0 += MD) {
     const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
     mdot_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
@@ -325,7 +331,7 @@ hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const 
 hipError_t launch_mdot2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* x1, const double* x2,
                        double* out1, double* out2) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
-  const int nblk = c->npart_blocks;
+  const int nblk = c->nmd_blocks;
   // partials: [q][blk] for x1 at rows q < nvec, for x2 at rows 512 + q
   for (int q0 = 0; q0 < nvec; q0 += MD) {
     const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;

@@ -39,6 +39,7 @@ ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_
                "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_project_mixed_static", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
+               "kv_set_gmres_deflation",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_time_steps", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
     lib.kv_set_preconditioner.argtypes = [P, ctypes.c_int, D]
     lib.kv_set_gmres_restart.argtypes = [P, ctypes.c_int]
     lib.kv_set_bicgstab_stall.argtypes = [P, ctypes.c_int]
+    lib.kv_set_gmres_deflation.argtypes = [P, ctypes.c_int]
     lib.kv_apply_preconditioner.argtypes = [P, P, P]
     lib.kv_arnoldi_leading_eigs.argtypes = [P, ctypes.POINTER(_ArnoldiParams), PD, PD, PD, P,
                                             ctypes.POINTER(_EigInfo)]
@@ -314,6 +316,10 @@ class Context:
     def set_gmres_restart(self, m):
         """Restart length of the GMRES continuation of newton_correction."""
         self._check(self._lib.kv_set_gmres_restart(self._h, int(m)))
+
+    def set_gmres_deflation(self, k):
+        """Harmonic Ritz vectors kept across GMRES restarts (GMRES-DR; 0: plain)."""
+        self._check(self._lib.kv_set_gmres_deflation(self._h, int(k)))
 
     def set_bicgstab_stall(self, cycles):
         """Cycles without a 10% residual drop after which the BiCGstab(2) part

@@ -23,7 +23,8 @@ from .continuation import sweep
 
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
         cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, keep=0,
-        log=print):
+        from_state=None, from_gr=None, gmres_restart=None, gmres_deflation=0, newton_max_matvec=20000,
+        max_restarts=100000, log=print):
     """state: a converged packed state at Gr (host array) to start from
     instead of continuation; save_state: file to store the converged state;
     sym: None (one unrestricted Arnoldi run) or a list of symmetry classes
@@ -35,15 +36,16 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
     cont = None
     if state is None:
         grs = []
-        g = 1e4
+        g = 1e4 if from_state is None else from_gr * ratio
         while g < Gr:
             grs.append(g)
             g *= ratio
         grs.append(Gr)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        states, infos = sweep(faces, grs, Pr=Pr, max_matvec=20000, max_iter=20, precond_sigma=precond_sigma,
-                              log=log)
+        states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20,
+                              precond_sigma=precond_sigma, gmres_restart=gmres_restart,
+                              gmres_deflation=gmres_deflation, X0=from_state, gr0=from_gr, log=log)
         torch.cuda.synchronize()
         t_cont = time.perf_counter() - t0
         if len(states) < len(grs):
@@ -71,7 +73,7 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
             t1 = time.perf_counter()
             vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
                                                        cheb_degree_max=cheb_degree_max, sym=cls, check=False,
-                                                       keep=keep)
+                                                       keep=keep, max_restarts=max_restarts)
             torch.cuda.synchronize()
             t_eig = time.perf_counter() - t1
             runs.append({"symmetry_class": list(cls) if cls else None, "krylov_dim": krylov, "n_eigs": n_eigs,
@@ -132,11 +134,21 @@ def main(argv=None):
                          "(reflection, 2-D rotation), p = kept and m = broken, such as --sym pm,mm")
     ap.add_argument("--keep", type=int, default=0,
                     help="thick restart keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
+    ap.add_argument("--from-state", default=None,
+                    help="continue from a stored converged state (.npy) at --from-gr instead of from rest")
+    ap.add_argument("--from-gr", type=float, default=None)
+    ap.add_argument("--ratio", type=float, default=1.6, help="continuation step ratio in Gr")
+    ap.add_argument("--gmres-restart", type=int, default=None)
+    ap.add_argument("--gmres-deflation", type=int, default=0)
+    ap.add_argument("--newton-max-matvec", type=int, default=20000)
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
               max_matvec=a.max_matvec, precond_sigma=None if a.sigma < 0 else a.sigma, state=state,
-              save_state=a.save_state, sym=parse_sym(a.sym), keep=a.keep, log=lambda m: print(m, flush=True))
+              save_state=a.save_state, sym=parse_sym(a.sym), keep=a.keep, ratio=a.ratio,
+              from_state=np.load(a.from_state) if a.from_state else None, from_gr=a.from_gr,
+              gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
+              newton_max_matvec=a.newton_max_matvec, log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
         with open(a.json, "w") as fh:

@@ -549,3 +549,45 @@ def test_thick_restart_gr0_closed_form_and_bad_keep():
         with pytest.raises(kv.KVError) as e:
             ctx.arnoldi_leading_eigs(v0, krylov_dim=24, n_eigs=4, keep=keep)
         assert e.value.code == kv.KV_EINVAL
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_deflated_gmres_converges_where_plain_restarts_stall(precond):
+    """GMRES(40) continuation with deflated restarting (20 harmonic Ritz
+    vectors kept, GMRES-DR) on the forced hand-over system where plain
+    GMRES(40) stagnates: it reaches the tolerance, and the correction is the
+    unique one (oracle residual certificate and the oracle's own solve)."""
+    print(f"case gmres-dr precond={precond}", flush=True)
+    from paper_2210_08816_amd import kv
+    shape = (7, 6, 5)
+    fx = [faces("clustered", n) for n in shape]
+    g = O.Grid(*fx, Gr=1e4, Pr=0.71)
+    X0 = O.project(g, S.base_flow(*fx, K=3, amp=0.05, seed=31) + 0.01 * S.perturbation(g.size, 32))
+    ctx = context(fx, 1e4, 0.71, X0)
+    try:
+        for bad in (-1, 63):
+            assert ctx._lib.kv_set_gmres_deflation(ctx._h, bad) == kv.KV_EINVAL
+        ctx.set_bicgstab_stall(0)
+        if precond:
+            ctx.set_preconditioner(True, 0.0)
+        F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        tol = 1e-10
+        plain = ctx.newton_correction(F, torch.empty_like(F), tol=tol, max_matvec=3000)
+        ctx.set_gmres_deflation(20)
+        delta = torch.empty_like(F)
+        info = ctx.newton_correction(F, delta, tol=tol, max_matvec=3000)
+        print("plain", plain, "deflated", info, flush=True)
+        assert info["status"] == 0 and info["used_gmres"] == 1, info
+        if not precond:
+            assert plain["status"] == kv.KV_ENOCONV      # plain GMRES(40) stalls within the budget
+        assert info["matvecs"] < 3000
+        A = SV.Operator(g, X0)
+        Fo = SV.A_project(A, O.residual(g, X0))
+        d = to_host(delta)
+        assert A.norm(A(d) + Fo) / A.norm(Fo) <= 10 * tol
+        d_ref, _ = SV.newton_correction(A, O.residual(g, X0), tol=1e-12, max_matvec=4000, stall_cycles=0,
+                                        gmres_m=100)
+        assert A.norm(d - d_ref) <= 1e-7 * A.norm(d_ref)
+    finally:
+        ctx.close()
