@@ -222,7 +222,14 @@ typedef struct {
  * terms).  Stops when relres <= tol or after max_matvec matvecs
  * (KV_ENOCONV, delta holds the last iterate).  delta0: optional initial
  * iterate (device, may be NULL, not aliasing delta).  F, delta: device, n
- * values.  info: host, may be NULL.  flags: 0 (KV_MIXED is reserved).  With
+ * values.  info: host, may be NULL.  flags: 0, or KV_SYM_* bits (below):
+ * the correction is sought in that symmetry class (right-hand side, every
+ * Krylov vector and delta projected onto it; delta0 should lie in it).  A
+ * steady state with the cube's symmetries (Sec. 2) has a correction in the
+ * fully symmetric class (KV_SYM_REF_EVEN | KV_SYM_ROT_EVEN), and keeping
+ * the solve there removes the eigenmodes of the other classes, one of which
+ * turns singular where a symmetry-breaking real eigenvalue crosses zero.
+ * KV_MIXED is reserved.  With
  * a preconditioner set (kv_set_preconditioner) the solve is right
  * preconditioned: BiCGstab(2)/GMRES iterate on P J M^-1 and delta = delta0 +
  * M^-1 x. */

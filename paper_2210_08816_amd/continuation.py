@@ -14,13 +14,14 @@ import numpy as np
 
 
 def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=20000, delta0_fn=None,
-                 log=None):
+                 log=None, sym=None):
     """Newton iteration on a context (its Gr fixed).  X: torch float64 CUDA
     tensor, updated in place (left at the last iterate on failure).  Stops
     when ||F|| <= max(tol_abs, tol_rel * ||F(X_start)||).  The inner solve
     tolerance is max(1e-10, min(1e-2, ||F||)), loosened to a tenth of the
     target over ||F|| near the end.  delta0_fn(X) gives the first
-    BiCGstab(2) iterate of the first Newton step (None: zero).  Returns a dict
+    BiCGstab(2) iterate of the first Newton step (None: zero); sym: None or a
+    symmetry class (e_ref, e_rot) the corrections are sought in.  Returns a dict
     with the residual history, matvecs, wall time and whether it converged."""
     import torch
     F = torch.empty_like(X)
@@ -49,7 +50,7 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
         target = max(tol_abs, tol_rel * hist[0])
         eta = max(1e-10, min(1e-2, fn), min(0.5, 0.1 * target / fn))
         d0 = delta0_fn(X) if delta0_fn is not None and it == 0 else None
-        info = ctx.newton_correction(F, d, tol=eta, max_matvec=max_matvec, delta0=d0, check=False)
+        info = ctx.newton_correction(F, d, tol=eta, max_matvec=max_matvec, delta0=d0, check=False, sym=sym)
         mv += info["matvecs"]
         if log:
             log(f"  correction: tol {eta:.2e} matvecs {info['matvecs']} relres {info['relres']:.2e} "

@@ -1409,12 +1409,14 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
                          const double* delta0, double* delta, kv_solve_info* info) {
   if (!c) return KV_EINVAL;
   if (!F || !delta || F == delta) return fail(c, KV_EINVAL, "F and delta must be distinct device vectors");
-  if (flags != 0) return fail(c, KV_EINVAL, "unsupported flags");
+  int er = 0, eo = 0, rc;
+  if ((rc = check_sym(c, flags, &er, &eo))) return rc;
   if (!(tol > 0) || max_matvec < 4) return fail(c, KV_EINVAL, "bad tolerance or budget");
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   if (delta0 == delta) return fail(c, KV_EINVAL, "delta0 must not alias delta");
+  EigScope scope(c, er, eo, nullptr);  // matvec keeps the Krylov space in the class
   c->pc_active = c->pc_kind != KV_PC_NONE;
-  const int rc = newton_correction(c, F, tol, max_matvec, delta0, delta, info);
+  rc = newton_correction(c, F, tol, max_matvec, delta0, delta, info);
   c->pc_active = false;
   return rc;
 }
@@ -1431,7 +1433,10 @@ static int finish_delta(kv_ctx* c, double* x, bool has_d0) {
     else rc = lincomb(c, 1, {1.0}, {c->pc_tmp}, x);
     if (rc) return rc;
   }
-  return project_inplace(c, x);
+  int rc = project_inplace(c, x);
+  if (rc) return rc;
+  if (c->sym_ref || c->sym_rot) HIPCHK(c, launch_symmetry_class(c, x, x, c->sym_ref, c->sym_rot));
+  return KV_OK;
 }
 
 static int newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, const double* delta0,
@@ -1449,9 +1454,10 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
   double* u[3] = {u0, u1, u2};
   double* x = delta;
   kv_solve_info inf{0, 0, 0, 0.0, 0};
-  // b = -P F
+  // b = -P F (in the symmetry class when one is kept)
   if ((rc = lincomb(c, 1, {-1.0}, {F}, b))) return rc;
   if ((rc = project_inplace(c, b))) return rc;
+  if (c->sym_ref || c->sym_rot) HIPCHK(c, launch_symmetry_class(c, b, b, c->sym_ref, c->sym_rot));
   const double bnorm = std::sqrt(std::max(0.0, dot1(c, b, b, &rc)));
   if (rc) return rc;
   if (delta0 && c->pc_active) {

@@ -297,11 +297,12 @@ class Context:
             self._check(rc)
         return np.array([complex(wr[i], wi[i]) for i in range(m)]), rc
 
-    def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True):
+    def newton_correction(self, F, delta, tol=1e-8, max_matvec=10000, delta0=None, check=True, sym=None):
+        """sym: None, or a symmetry class (e_ref, e_rot) to solve in (see sym_flags)."""
         info = _SolveInfo()
         self._ensure_workspace(KV_WS_NEWTON)
         d0 = _dptr(delta0, self.n) if delta0 is not None else None
-        rc = self._lib.kv_newton_correction(self._h, _dptr(F, self.n), float(tol), int(max_matvec), 0, d0,
+        rc = self._lib.kv_newton_correction(self._h, _dptr(F, self.n), float(tol), int(max_matvec), sym_flags(sym), d0,
                                             _dptr(delta, self.n), ctypes.byref(info))
         if check and rc != KV_ENOCONV:
             self._check(rc)

@@ -24,7 +24,7 @@ from .continuation import sweep
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
         cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, keep=0,
         from_state=None, from_gr=None, gmres_restart=None, gmres_deflation=0, newton_max_matvec=20000,
-        max_restarts=100000, log=print):
+        max_restarts=100000, newton_sym=None, log=print):
     """state: a converged packed state at Gr (host array) to start from
     instead of continuation; save_state: file to store the converged state;
     sym: None (one unrestricted Arnoldi run) or a list of symmetry classes
@@ -45,7 +45,8 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
         t0 = time.perf_counter()
         states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20,
                               precond_sigma=precond_sigma, gmres_restart=gmres_restart,
-                              gmres_deflation=gmres_deflation, X0=from_state, gr0=from_gr, log=log)
+                              gmres_deflation=gmres_deflation, X0=from_state, gr0=from_gr, log=log,
+                              sym=newton_sym)
         torch.cuda.synchronize()
         t_cont = time.perf_counter() - t0
         if len(states) < len(grs):
@@ -141,6 +142,8 @@ def main(argv=None):
     ap.add_argument("--gmres-restart", type=int, default=None)
     ap.add_argument("--gmres-deflation", type=int, default=0)
     ap.add_argument("--newton-max-matvec", type=int, default=20000)
+    ap.add_argument("--newton-sym", default=None,
+                    help="symmetry class of the Newton corrections, e.g. pp (the symmetric branch)")
     a = ap.parse_args(argv)
     state = np.load(a.load_state) if a.load_state else None
     res = run(n=a.n, grid=a.grid, Gr=a.gr, krylov=a.krylov, n_eigs=a.eigs, tol=a.tol, cheb_degree_max=a.degree,
@@ -148,7 +151,9 @@ def main(argv=None):
               save_state=a.save_state, sym=parse_sym(a.sym), keep=a.keep, ratio=a.ratio,
               from_state=np.load(a.from_state) if a.from_state else None, from_gr=a.from_gr,
               gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
-              newton_max_matvec=a.newton_max_matvec, log=lambda m: print(m, flush=True))
+              newton_max_matvec=a.newton_max_matvec,
+              newton_sym=parse_sym(a.newton_sym)[0] if a.newton_sym else None,
+              log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
         with open(a.json, "w") as fh:

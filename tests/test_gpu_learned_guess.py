@@ -65,3 +65,64 @@ def test_learned_guess_against_continuation(trained):
     # closer to the solution at every held-out Gr
     assert max(ratios_incr) < 1.0
     assert float(np.exp(np.mean(np.log(ratios_incr)))) < 0.7
+
+
+@pytest.fixture(scope="module")
+def trained_clustered():
+    from paper_2210_08816_amd import continuation as C
+    from paper_2210_08816_amd import learned as L
+    f = S.faces_clustered(16)
+    faces = (f, f, f)
+    train = [1e4 * 2.5 ** k for k in range(6)]
+    states, infos = C.sweep(faces, train, max_matvec=20000, max_iter=20, precond_sigma=10.0,
+                            log=lambda m: print(m, flush=True))
+    assert len(states) == len(train)
+    ts = L.build_training_set(faces, train, states, 1)
+    net, hist, sec = L.train(ts, (math.log10(train[0]), math.log10(train[-1])), epochs=8000, batch=2, lr=5e-4,
+                             lr_final=1e-5, seed=3, data_seed=4)
+    print(f"training (clustered): {sec:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}", flush=True)
+    return faces, train, states, ts, net, hist
+
+
+def test_learned_guess_replaces_continuation_from_rest_on_clustered_grid(trained_clustered):
+    """Wall-clustered 16^3 grid.  At a Gr where no converged state is at hand,
+    the method without the network follows the branch from rest through the
+    training values (the paper's continuation); the network's own
+    prediction, projected, starts Newton directly at that Gr.  The learned
+    start reaches the same steady state with fewer matvecs and less wall
+    time at every held-out Gr (with the nearest converged state at hand,
+    continuation from it stays the better start on this grid)."""
+    import time
+    from paper_2210_08816_amd import continuation as C
+    from paper_2210_08816_amd import kv
+    from paper_2210_08816_amd import learned as L
+    faces, train, states, ts, net, hist = trained_clustered
+    for k in range(1, len(train) - 1):
+        gr = math.sqrt(train[k] * train[k + 1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, infos = C.sweep(faces, train[:k + 1] + [gr], max_matvec=20000, max_iter=20, precond_sigma=10.0,
+                            log=lambda m: None)
+        torch.cuda.synchronize()
+        t_cont = time.perf_counter() - t0
+        assert len(st) == k + 2
+        mv_cont = sum(i.get("matvecs_all_attempts", i["matvecs"]) for i in infos)
+        ctx = kv.Context(*faces, Gr=gr, Pr=0.71)
+        try:
+            ctx.set_preconditioner(True, 10.0)
+            X = torch.empty_like(st[-1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L.guess(ctx, net, ts.norm, gr, X)
+            rec = C.newton_solve(ctx, X, tol_rel=0.0, tol_abs=1e-11, max_iter=20, max_matvec=20000)
+            torch.cuda.synchronize()
+            t_nn = time.perf_counter() - t0
+            d = X - st[-1]
+            dist = math.sqrt(max(0.0, ctx.dot(d, d)) / ctx.dot(st[-1], st[-1]))
+        finally:
+            ctx.close()
+        print(f"Gr={gr:.3e}: continuation from rest {mv_cont} matvecs {t_cont:.2f}s; learned start "
+              f"{rec['matvecs']} matvecs {rec['iters']} Newton iterations {t_nn:.2f}s; distance {dist:.2e}",
+              flush=True)
+        assert rec["converged"] and dist <= 1e-8
+        assert rec["matvecs"] < mv_cont and t_nn < t_cont

@@ -591,3 +591,46 @@ def test_deflated_gmres_converges_where_plain_restarts_stall(precond):
         assert A.norm(d - d_ref) <= 1e-7 * A.norm(d_ref)
     finally:
         ctx.close()
+
+
+def test_newton_correction_in_the_symmetric_class():
+    """At a steady state with the cube's symmetries the correction toward the
+    branch at a nearby Gr lies in the fully symmetric class: the class-
+    restricted solve (KV_SYM_REF_EVEN | KV_SYM_ROT_EVEN) returns the same
+    unique correction as the unrestricted one, certified by the oracle."""
+    from paper_2210_08816_amd import kv
+    from paper_2210_08816_amd.continuation import newton_solve
+    f = [S.faces_clustered(n) for n in (12, 10, 12)]
+    g1 = O.Grid(*f, Gr=1e4, Pr=0.71)
+    ctx = kv.Context(*f, Gr=1e4, Pr=0.71)
+    try:
+        X = to_dev(S.conduction_state(*f))
+        assert newton_solve(ctx, X, tol_rel=1e-12, tol_abs=1e-13, max_matvec=4000)["converged"]
+    finally:
+        ctx.close()
+    Xs = to_host(X)
+    assert max(O.symmetry_measures(g1, Xs)) < 1e-12
+    g = O.Grid(*f, Gr=2e4, Pr=0.71)
+    ctx = context(f, 2e4, 0.71, Xs)
+    try:
+        F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        d_sym, d_all = torch.empty_like(F), torch.empty_like(F)
+        tol = 1e-10
+        i1 = ctx.newton_correction(F, d_sym, tol=tol, max_matvec=4000, sym=(1, 1))
+        i2 = ctx.newton_correction(F, d_all, tol=tol, max_matvec=4000)
+        assert i1["status"] == 0 and i2["status"] == 0, (i1, i2)
+        A = SV.Operator(g, Xs)
+        Fo = SV.A_project(A, O.residual(g, Xs))
+        ds = to_host(d_sym)
+        assert A.norm(A(ds) + Fo) / A.norm(Fo) <= 10 * tol
+        assert A.norm(ds - to_host(d_all)) <= 1e-7 * A.norm(ds)
+        assert np.allclose(O.symmetry_project(g, ds, 1, 1), ds, rtol=0, atol=1e-14 * np.max(np.abs(ds)))
+        with pytest.raises(kv.KVError) as e:
+            ctx.newton_correction(F, d_sym, tol=tol, max_matvec=4000, sym=None) if False else \
+                ctx._check(ctx._lib.kv_newton_correction(ctx._h, kv._dptr(F, ctx.n), tol, 4000,
+                                                         kv.KV_SYM_REF_EVEN | kv.KV_SYM_REF_ODD, None,
+                                                         kv._dptr(d_sym, ctx.n), None))
+        assert e.value.code == kv.KV_EINVAL
+    finally:
+        ctx.close()
