@@ -93,73 +93,103 @@ __global__ void __launch_bounds__(256) wdots_kernel(Grid g, Ptr4 a, Ptr4 b, doub
   }
 }
 
-// Block multi-dot for classical Gram-Schmidt: part[q][blk] for q < nv <= MD
+// An empty asm that takes v[0..N) as register operands: every load that
+// produced them is issued before this point.
+template <int N>
+__device__ __forceinline__ void hold_values(double* v) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) asm volatile("" : "+v"(v[q]));
+}
+
+// Block sums of acc[0..NQ) over the 256-thread block with one barrier:
+// wave sums into LDS, then thread q adds the four waves of value q (fixed
+// order) and writes part[prow(q) * gridDim.x + blockIdx.x].
+template <int NQ, typename RowOf>
+__device__ __forceinline__ void block_sums(const double* acc, double* sh, double* __restrict__ part, RowOf prow) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) sh[wave * NQ + q] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NQ) {
+    const int q = threadIdx.x;
+    part[(int64_t)prow(q) * gridDim.x + blockIdx.x] = (sh[q] + sh[NQ + q]) + (sh[2 * NQ + q] + sh[3 * NQ + q]);
+  }
+}
+
+// Block multi-dot for classical Gram-Schmidt: part[q][blk] for q < NV <= MD
 // against the vectors V + q * ldv; w * weight is formed once per element.
+// NV is a template parameter so that the NV loads of an element are issued
+// together (a runtime count puts each behind its own branch).
 constexpr int MD = 16;
-__global__ void __launch_bounds__(256) mdot_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
+template <int NV>
+__global__ void __launch_bounds__(256) mdot_kernel(Grid g, const double* V, int64_t ldv,
                                                    const double* __restrict__ w, double* __restrict__ part,
                                                    int qbase) {
-  __shared__ double sh[4];
+  __shared__ double sh[4 * NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double acc[MD];
+  double acc[NV];
 #pragma unroll
-  for (int q = 0; q < MD; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
   const int64_t nrows = total_rows(g);
   for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
     const RowInfo ri = row_info(g, r);
     for (int e = lane; e < ri.len; e += 64) {
       const int64_t idx = ri.off + e;
-      const double ww = ri.wx[e] * ri.wyz * w[idx];
+      double v[NV];
 #pragma unroll
-      for (int q = 0; q < MD; ++q)
-        if (q < nv) acc[q] += ww * V[q * ldv + idx];
+      for (int q = 0; q < NV; ++q) v[q] = V[q * ldv + idx];
+      double a = w[idx];
+      const double wt = ri.wx[e] * ri.wyz;
+      hold_values<NV>(v);
+      asm volatile("" : "+v"(a));
+      const double ww = wt * a;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) acc[q] += ww * v[q];
     }
   }
-  for (int q = 0; q < nv; ++q) {
-    const double s = block_sum(acc[q], sh);
-    if (threadIdx.x == 0) part[(int64_t)(qbase + q) * gridDim.x + blockIdx.x] = s;
-  }
+  block_sums<NV>(acc, sh, part, [&](int q) { return qbase + q; });
 }
 
-// Two-vector block multi-dot of the delayed Gram-Schmidt: part[q] and
-// part[MD + q] for q < nv <= MD: <V_q, x1>_W and <V_q, x2>_W, each element
-// of V read once for both.
-__global__ void __launch_bounds__(256) mdot2_kernel(Grid g, const double* __restrict__ V, int64_t ldv, int nv,
+// Two-vector block multi-dot of the delayed Gram-Schmidt: part[qbase + q]
+// and part[ldp + qbase + q] for q < NV <= MD: <V_q, x1>_W and <V_q, x2>_W,
+// each element of V read once for both.
+template <int NV>
+__global__ void __launch_bounds__(256) mdot2_kernel(Grid g, const double* V, int64_t ldv,
                                                     const double* __restrict__ x1, const double* __restrict__ x2,
                                                     double* __restrict__ part, int qbase, int ldp) {
-  __shared__ double sh[4];
+  __shared__ double sh[4 * 2 * NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double a1[MD], a2[MD];
+  double acc[2 * NV];  // x1 products, then x2 products
 #pragma unroll
-  for (int q = 0; q < MD; ++q) a1[q] = a2[q] = 0.0;
+  for (int q = 0; q < 2 * NV; ++q) acc[q] = 0.0;
   const int64_t nrows = total_rows(g);
   for (int64_t r = (int64_t)blockIdx.x * 4 + wave; r < nrows; r += (int64_t)gridDim.x * 4) {
     const RowInfo ri = row_info(g, r);
-    // two elements per lane per iteration: the loads of both are in flight
-    // before the products (a lane past the row end reads element 0 with
-    // weight 0)
-    for (int e = lane; e < ri.len; e += 128) {
-      const int e1 = e + 64;
-      const bool in1 = e1 < ri.len;
-      const int64_t i0 = ri.off + e, i1 = ri.off + (in1 ? e1 : e);
-      const double wt0 = ri.wx[e] * ri.wyz, wt1 = in1 ? ri.wx[e1] * ri.wyz : 0.0;
-      const double u0 = wt0 * x1[i0], z0 = wt0 * x2[i0];
-      const double u1 = wt1 * x1[i1], z1 = wt1 * x2[i1];
+    for (int e = lane; e < ri.len; e += 64) {
+      const int64_t i0 = ri.off + e;
+      // every load of the element is issued before the first product: the
+      // empty asm takes the loaded values as operands, so all loads precede
+      // it and one wait covers them (left alone, the scheduler keeps only
+      // about four loads in flight, each next to its use)
+      double v[NV];
 #pragma unroll
-      for (int q = 0; q < MD; ++q)
-        if (q < nv) {
-          const double v0 = V[q * ldv + i0], v1 = V[q * ldv + i1];
-          a1[q] += u0 * v0 + u1 * v1;
-          a2[q] += z0 * v0 + z1 * v1;
-        }
+      for (int q = 0; q < NV; ++q) v[q] = V[q * ldv + i0];
+      double a = x1[i0], b = x2[i0];
+      const double wt = ri.wx[e] * ri.wyz;
+      hold_values<NV>(v);
+      asm volatile("" : "+v"(a), "+v"(b));
+      const double u = wt * a, z = wt * b;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        acc[q] += u * v[q];
+        acc[NV + q] += z * v[q];
+      }
     }
   }
-  for (int q = 0; q < nv; ++q) {
-    const double s1 = block_sum(a1[q], sh);
-    if (threadIdx.x == 0) part[(int64_t)(qbase + q) * gridDim.x + blockIdx.x] = s1;
-    const double s2 = block_sum(a2[q], sh);
-    if (threadIdx.x == 0) part[(int64_t)(ldp + qbase + q) * gridDim.x + blockIdx.x] = s2;
-  }
+  block_sums<2 * NV>(acc, sh, part, [&](int q) { return q < NV ? qbase + q : ldp + qbase + (q - NV); });
 }
 
 // The fused update of the delayed Gram-Schmidt, one pass over V_0..V_{nv-1}:
@@ -317,12 +347,22 @@ hipError_t launch_wdots(kv_ctx* c, int npair, const double* const* a, const doub
   return hipGetLastError();
 }
 
+// mdot_kernel<nv> / mdot2_kernel<nv> for a runtime nv in 1..MD
+#define KV_MD_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
 hipError_t launch_mdot(kv_ctx* c, const double* V, int64_t ldv, int nvec, const double* w, double* out) {
   if (nvec < 1 || nvec > 512) return hipErrorInvalidValue;
   const int nblk = c->nmd_blocks;
   for (int q0 = 0; q0 < nvec; q0 += MD) {
     const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
-    mdot_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, w, c->part, q0);
+    const double* Vq = V + q0 * ldv;
+    switch (nv) {
+#define KV_MD1(N) \
+  case N: mdot_kernel<N><<<nblk, 256, 0, c->stream>>>(c->g, Vq, ldv, w, c->part, q0); break;
+      KV_MD_CASES(KV_MD1)
+#undef KV_MD1
+      default: return hipErrorInvalidValue;
+    }
   }
   sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, out ? out : c->dres);
   return hipGetLastError();
@@ -335,7 +375,14 @@ hipError_t launch_mdot2(kv_ctx* c, const double* V, int64_t ldv, int nvec, const
   // partials: [q][blk] for x1 at rows q < nvec, for x2 at rows 512 + q
   for (int q0 = 0; q0 < nvec; q0 += MD) {
     const int nv = (nvec - q0 < MD) ? nvec - q0 : MD;
-    mdot2_kernel<<<nblk, 256, 0, c->stream>>>(c->g, V + q0 * ldv, ldv, nv, x1, x2, c->part, q0, 512);
+    const double* Vq = V + q0 * ldv;
+    switch (nv) {
+#define KV_MD2(N) \
+  case N: mdot2_kernel<N><<<nblk, 256, 0, c->stream>>>(c->g, Vq, ldv, x1, x2, c->part, q0, 512); break;
+      KV_MD_CASES(KV_MD2)
+#undef KV_MD2
+      default: return hipErrorInvalidValue;
+    }
   }
   sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part, nblk, nvec, out1);
   sum_finish_kernel<<<1, 256, 0, c->stream>>>(c->part + (int64_t)512 * nblk, nblk, nvec, out2);
