@@ -111,8 +111,9 @@ int kv_layout(const kv_ctx* ctx, int64_t* n, int64_t off[5]);
  *                               preconditioner set, 3 more vectors
  *   KV_WS_ARNOLDI               kv_arnoldi_leading_eigs: the Krylov basis
  *                               (krylov_dim + 1), 3 filter vectors, 2 (n_eigs
- *                               + 1) locked and Ritz vectors, and the
- *                               Hessenberg / Ritz-vector area
+ *                               + 1) locked and Ritz vectors, the inner-solve
+ *                               vectors of a spectral transform (below) and
+ *                               the Hessenberg / Ritz-vector area
  * kv_workspace_size writes the bytes op needs (host out; krylov_dim and
  * n_eigs are read for KV_WS_ARNOLDI only; the Newton size depends on the
  * current GMRES restart and preconditioner, so query after setting them).
@@ -335,6 +336,9 @@ typedef struct {
                      relaxes to sqrt(eps): a nearly defective Ritz cluster,
                      whose values are then fixed only to about sqrt(eps)
                      relative); 0 when every deflation met eps */
+  int inner_matvecs; /* with a spectral transform: applications of P J by
+                        its inner solves (matvecs then counts applications
+                        of the transformed operator); 0 otherwise */
 } kv_eig_info;
 
 /* Leading eigenvalues (largest real part first, +Im before -Im within a
@@ -364,6 +368,34 @@ typedef struct {
  * matvecs and restarts count the work done). */
 int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam_re,
                             double* lam_im, double* resid, double* evecs, kv_eig_info* info);
+
+/* Spectral transform of the thick-restarted Arnoldi (keep > 0) above, with
+ * the Stokes/heat preconditioner of kv_set_preconditioner (an addition: the
+ * paper runs Arnoldi on A itself, Sec. 3).  KV_ST_CAYLEY: Arnoldi runs on
+ *   C = (A - pole)^-1 (A - zero),
+ * which has the eigenvectors of A and maps an eigenvalue lambda to
+ * theta = (lambda - zero) / (lambda - pole): values near the pole become
+ * dominant and the stiff diffusive part of the spectrum (|lambda| >> |pole -
+ * zero|) gathers near theta = 1.  Each application solves (A - pole) z = x by
+ * restarted GMRES (the length of kv_set_gmres_restart, no deflated restarts),
+ * right-preconditioned by M^-1 when a preconditioner is set, from z = 0 to
+ * inner_tol relative residual within inner_max_matvec applications of P J
+ * (else the Arnoldi call fails with KV_ENOCONV).  The wanted set is the
+ * n_eigs values of largest |theta|; the convergence test applies tol to the
+ * Ritz residuals of C relative to the largest wanted |theta|, and resid
+ * reports those residuals.  Outputs are mapped back,
+ * lambda = (pole theta - zero) / (theta - 1), and ordered as above (largest
+ * real part first), with their eigenvectors.  pole: a real shift just right
+ * of the wanted eigenvalues; zero: left of them, |pole - zero| about the
+ * spread of the wanted part of the spectrum.  Kept until changed; KV_ST_NONE
+ * switches it off.  The KV_WS_ARNOLDI workspace grows by gmres_m + 2 vectors
+ * (+ 2 with a preconditioner): query kv_workspace_size after setting both.
+ * Errors: KV_EINVAL (unknown kind, pole == zero, non-finite values,
+ * inner_tol outside (0, 1), inner_max_matvec < 4); kv_arnoldi_leading_eigs
+ * returns KV_EINVAL with a transform set and keep == 0. */
+enum kv_spectral_transform { KV_ST_NONE = 0, KV_ST_CAYLEY = 1 };
+int kv_set_spectral_transform(kv_ctx* ctx, int kind, double pole, double zero, double inner_tol,
+                              int inner_max_matvec);
 
 /* Eigenvalues of a small upper Hessenberg matrix on the GPU: the Ritz
  * values of an Arnoldi cycle (Sec. 1) come from this Francis double-shift QR

@@ -419,13 +419,23 @@ int precond_apply(kv_ctx* c, const double* x, double* y) {
   return project_inplace(c, y);
 }
 
+int cayley_apply(kv_ctx* c, const double* x, double* y);
+
 // The operator of the Krylov solvers: P J, or P J M^-1 while a
-// preconditioned Newton correction runs.
+// preconditioned Newton correction runs.  While a transformed Arnoldi runs
+// it is the Cayley operator (cayley_apply), and inside that operator's
+// inner solve (P J - pole) M^-1.
 int op_apply(kv_ctx* c, const double* x, double* y) {
-  if (!c->pc_active) return matvec(c, x, y);
-  int rc = precond_apply(c, x, c->pc_tmp);
-  if (rc) return rc;
-  return matvec(c, c->pc_tmp, y);
+  if (c->st_on && !c->st_inner) return cayley_apply(c, x, y);
+  const double* u = x;
+  int rc;
+  if (c->pc_active) {
+    if ((rc = precond_apply(c, x, c->pc_tmp))) return rc;
+    u = c->pc_tmp;
+  }
+  if ((rc = matvec(c, u, y))) return rc;
+  if (c->st_inner) return lincomb(c, 2, {1.0, -c->st_pole}, {y, u}, y);
+  return KV_OK;
 }
 
 int check_finite(kv_ctx* c, const double* a, int64_t n, const char* what) {
@@ -445,13 +455,20 @@ size_t hess_area(int k, int nsel) {
   return 4 * kk + 4 * (size_t)k + 2 + 2 * (size_t)nsel * (kk + (size_t)k);
 }
 
+// Vectors of a spectral transform's inner solve: its iterate, the GMRES
+// basis and, with a preconditioner, M^-1 x and the Helmholtz scratch.
+size_t st_vectors(const kv_ctx* c) {
+  if (c->st_kind == KV_ST_NONE) return 0;
+  return 1 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 2 : 0);
+}
+
 // Packed vectors an operation carves from the workspace (see ws_bind).
 size_t ws_vectors(const kv_ctx* c, int op, int m, int neig) {
   switch (op) {
     case KV_WS_PROJECT_MIXED: return 1;
     case KV_WS_APPLY_PRECONDITIONER: return 1;
     case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0) + (c->gmres_defl ? 1 : 0);
-    case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1);
+    case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1) + st_vectors(c);
     case KV_WS_TIME_STEPS: return 4;
     default: return 0;
   }
@@ -475,7 +492,9 @@ size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
 //   APPLY_PRECONDITIONER   pc_scr
 //   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr |
 //                          (deflated GMRES) a spare vector, the Hessenberg area
-//   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) | Hessenberg area
+//   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) |
+//                          (spectral transform) inner iterate, GMRES basis (gmres_m+1),
+//                          (with a preconditioner) pc_tmp pc_scr | Hessenberg area
 //   TIME_STEPS             F | F of the previous step | right-hand side | pc_scr
 int ws_bind(kv_ctx* c, int op, int m, int neig) {
   const size_t need = ws_need(c, op, m, neig);
@@ -500,7 +519,21 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
       if (c->gmres_defl) c->hess = p + n;  // after one spare vector
       break;
     }
-    case KV_WS_ARNOLDI: c->hess = c->ws + (int64_t)(m + 4 + 2 * (neig + 1)) * n; break;
+    case KV_WS_ARNOLDI: {
+      double* p = c->ws + (int64_t)(m + 4 + 2 * (neig + 1)) * n;
+      if (c->st_kind != KV_ST_NONE) {
+        c->st_t = p;
+        c->st_V = p + n;
+        p += (int64_t)(c->gmres_m + 2) * n;
+        if (c->pc_kind != KV_PC_NONE) {
+          c->pc_tmp = p;
+          c->pc_scr = p + n;
+          p += 2 * n;
+        }
+      }
+      c->hess = p;
+      break;
+    }
     case KV_WS_TIME_STEPS: c->pc_scr = c->ws + 3 * n; break;
     default: return fail(c, KV_EINVAL, "unknown workspace operation");
   }
@@ -654,13 +687,13 @@ std::vector<int> wanted_set(const std::vector<std::complex<double>>& v, int k) {
 }
 
 // Eigen-decomposition of H_k on the device; Ritz residuals h_{k+1,k} |e_k^T s|.
-// The k values of smallest modulus, extended by one when that would split a
-// conjugate pair.
-std::vector<int> smallest_set(const std::vector<std::complex<double>>& v, int k) {
+// The k values of smallest (or largest) modulus, extended by one when that
+// would split a conjugate pair.
+std::vector<int> modulus_set(const std::vector<std::complex<double>>& v, int k, bool largest) {
   std::vector<int> idx(v.size());
   for (size_t i = 0; i < v.size(); ++i) idx[i] = (int)i;
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-    if (std::abs(v[a]) != std::abs(v[b])) return std::abs(v[a]) < std::abs(v[b]);
+    if (std::abs(v[a]) != std::abs(v[b])) return largest ? std::abs(v[a]) > std::abs(v[b]) : std::abs(v[a]) < std::abs(v[b]);
     return v[a].imag() > v[b].imag();
   });
   std::vector<int> sel(idx.begin(), idx.begin() + std::min<size_t>(k, idx.size()));
@@ -680,7 +713,12 @@ std::vector<int> smallest_set(const std::vector<std::complex<double>>& v, int k)
   return sel;
 }
 
-int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out, bool smallest = false) {
+// Which Ritz values ritz() selects: largest real part first (the leading
+// eigenvalues), smallest modulus (harmonic values of deflated GMRES) or
+// largest modulus (the dominant values of a transformed operator).
+enum { SEL_LEADING = 0, SEL_SMALLEST = 1, SEL_LARGEST = 2 };
+
+int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz& out, int order = SEL_LEADING) {
   // device layout: Hk (k*k) | Hcopy (k*k) | wr k | wi k | lr, li (k each) | vr, vi (k*k) | info | cwork
   const size_t kk = (size_t)k * k;
   int rc;
@@ -705,7 +743,7 @@ int ritz(kv_ctx* c, const std::vector<double>& H, int m, int k, int n_eigs, Ritz
   if (info & 2) ++c->relaxed_qr;  // a nearly defective cluster deflated at sqrt(eps)
   out.vals.resize(k);
   for (int i = 0; i < k; ++i) out.vals[i] = {wr[i], wi[i]};
-  out.sel = smallest ? smallest_set(out.vals, n_eigs) : wanted_set(out.vals, n_eigs);
+  out.sel = order == SEL_LEADING ? wanted_set(out.vals, n_eigs) : modulus_set(out.vals, n_eigs, order == SEL_LARGEST);
   const int ns = (int)out.sel.size();
   std::vector<double> lr(ns), li(ns);
   for (int q = 0; q < ns; ++q) {
@@ -1273,21 +1311,29 @@ static bool solve_transposed_last(const std::vector<double>& Hb, int ld, int k, 
 // zero -- the weakly damped modes of a steady branch near a Hopf point --
 // stay in the space instead of being rebuilt every cycle.  The recursive
 // residual estimate ends a cycle; the true residual b - A x confirms it.
-static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, double tol, int m, int budget,
-                       int* used, int* cycles, double* relres) {
+// V: the basis (m + 1 vectors).  x_zero: x is 0 on entry, so the first
+// residual is b itself (no operator application).
+static int gmres_solve(kv_ctx* c, double* V, const double* b, double bnorm, double* x, double tol, int m, int budget,
+                       int* used, int* cycles, double* relres, bool x_zero = false) {
   const int64_t n = c->g.n;
   int rc;
-  double* V = c->ws + 8 * n;  // after the 8 BiCGstab(2) vectors (ws_bind, KV_WS_NEWTON)
   std::vector<double> H, cv, y, res;
-  const int kd = std::min(c->gmres_defl, std::min(m - 2, 62));
+  // deflated restarts use the Hessenberg area, which a transformed Arnoldi
+  // around an inner solve holds
+  const int kd = c->st_inner ? 0 : std::min(c->gmres_defl, std::min(m - 2, 62));
   bool fresh = true;
   int j0 = 0;
   for (;;) {
     if (fresh) {
       // r = b - A x into V[0]
-      if ((rc = op_apply(c, x, V))) return rc;
-      ++*used;
-      if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
+      if (x_zero) {
+        HIPCHK(c, hipMemcpyAsync(V, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        x_zero = false;
+      } else {
+        if ((rc = op_apply(c, x, V))) return rc;
+        ++*used;
+        if ((rc = lincomb(c, 2, {1.0, -1.0}, {b, V}, V))) return rc;
+      }
       double beta = std::sqrt(std::max(0.0, dot1(c, V, V, &rc)));
       if (rc) return rc;
       *relres = bnorm > 0 ? beta / bnorm : 0.0;
@@ -1335,7 +1381,7 @@ static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, doub
     for (int r = 0; r < k; ++r)
       for (int cc = std::max(0, r - 1); cc < k; ++cc) Hh[r + (size_t)cc * ld] = Mr[(size_t)r * k + cc];
     Ritz hz;
-    if ((rc = ritz(c, Hh, mm, k, kd, hz, true))) return rc;
+    if ((rc = ritz(c, Hh, mm, k, kd, hz, SEL_SMALLEST))) return rc;
     std::vector<std::vector<double>> Q;  // columns of length k + 1
     auto push = [&](std::vector<double> u) {
       for (int pass = 0; pass < 2; ++pass)
@@ -1401,6 +1447,43 @@ static int gmres_solve(kv_ctx* c, const double* b, double bnorm, double* x, doub
     fresh = false;
   }
 }
+
+namespace {
+// Cayley transform C = (A - pole)^-1 (A - zero) of A = P J:
+//   y = C x = x + (pole - zero) z,  (A - pole) z = x,
+// z = M^-1 t from right-preconditioned restarted GMRES on (A - pole) M^-1 t
+// = x from t = 0 (without a preconditioner z = t), to st_tol relative.  x
+// and z stay in range(P) and in the symmetry class kept.
+int cayley_apply(kv_ctx* c, const double* x, double* y) {
+  const int64_t n = c->g.n;
+  int rc = KV_OK;
+  const double bn = std::sqrt(std::max(0.0, dot1(c, x, x, &rc)));
+  if (rc) return rc;
+  HIPCHK(c, launch_fill(c, n, 0.0, c->st_t));
+  c->st_inner = true;
+  c->pc_active = c->pc_kind != KV_PC_NONE;
+  int used = 0, cyc = 0;
+  double rr = 0.0;
+  rc = gmres_solve(c, c->st_V, x, bn, c->st_t, c->st_tol, c->gmres_m, c->st_max_matvec, &used, &cyc, &rr, true);
+  c->st_matvecs += used;
+  ++c->st_solves;
+  double* z = c->st_t;
+  if (rc == KV_OK && c->pc_active) {
+    rc = precond_apply(c, c->st_t, c->pc_tmp);
+    z = c->pc_tmp;
+  }
+  c->st_inner = false;
+  c->pc_active = false;
+  if (rc == KV_ENOCONV) {
+    char msg[160];
+    snprintf(msg, sizeof msg, "spectral transform: inner solve at relative residual %.3e after %d matvecs", rr, used);
+    return fail(c, KV_ENOCONV, msg);
+  }
+  if (rc) return rc;
+  if (c->sym_ref || c->sym_rot) HIPCHK(c, launch_symmetry_class(c, z, z, c->sym_ref, c->sym_rot));
+  return lincomb(c, 2, {1.0, c->st_pole - c->st_zero}, {x, z}, y);
+}
+}  // namespace
 
 static int newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec, const double* delta0,
                              double* delta, kv_solve_info* info);
@@ -1576,7 +1659,8 @@ static int newton_correction(kv_ctx* c, const double* F, double tol, int max_mat
     // solves P J M^-1 x = b - P J delta0, whose right-hand side is the
     // initial residual: the shadow vector rt still holds it.
     const double* rhs = (c->pc_active && delta0) ? rt : b;
-    rc = gmres_solve(c, rhs, bnorm, x, tol, c->gmres_m, max_matvec, &used, &cyc, &rr);
+    // the basis follows the 8 BiCGstab(2) vectors (ws_bind, KV_WS_NEWTON)
+    rc = gmres_solve(c, c->ws + 8 * n, rhs, bnorm, x, tol, c->gmres_m, max_matvec, &used, &cyc, &rr);
     inf.matvecs = used;
     inf.cycles = cyc;
     inf.relres = rr;
@@ -1788,6 +1872,25 @@ int kv_set_gmres_deflation(kv_ctx* c, int k) {
   return KV_OK;
 }
 
+int kv_set_spectral_transform(kv_ctx* c, int kind, double pole, double zero, double inner_tol, int inner_max_matvec) {
+  if (!c) return KV_EINVAL;
+  if (kind == KV_ST_NONE) {
+    c->st_kind = KV_ST_NONE;
+    return KV_OK;
+  }
+  if (kind != KV_ST_CAYLEY) return fail(c, KV_EINVAL, "unknown spectral transform");
+  if (!std::isfinite(pole) || !std::isfinite(zero) || pole == zero)
+    return fail(c, KV_EINVAL, "the pole and zero of the Cayley transform must be finite and distinct");
+  if (!(inner_tol > 0.0 && inner_tol < 1.0) || inner_max_matvec < 4)
+    return fail(c, KV_EINVAL, "bad inner tolerance or budget");
+  c->st_kind = kind;
+  c->st_pole = pole;
+  c->st_zero = zero;
+  c->st_tol = inner_tol;
+  c->st_max_matvec = inner_max_matvec;
+  return KV_OK;
+}
+
 int kv_set_bicgstab_stall(kv_ctx* c, int cycles) {
   if (!c) return KV_EINVAL;
   if (cycles < 0 || cycles > 100000) return fail(c, KV_EINVAL, "stall cycles must be in 0..100000");
@@ -1978,6 +2081,31 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
   double* L = tmp + n;
   double* Ys = L + (int64_t)(p->n_eigs + 1) * n;
   EigScope scope(c, sym_ref, sym_rot, L);
+  // with a spectral transform the Krylov operator is C = (A - pole)^-1 (A - zero)
+  // and the wanted values are its dominant ones
+  struct StScope {
+    kv_ctx* c;
+    explicit StScope(kv_ctx* cc) : c(cc) {
+      c->st_on = c->st_kind != KV_ST_NONE;
+      c->st_inner = false;
+      c->st_matvecs = 0;
+      c->st_solves = 0;
+    }
+    ~StScope() {
+      c->st_on = c->st_inner = false;
+      c->pc_active = false;
+    }
+  } st_scope(c);
+  const bool st = c->st_on;
+  const int sel_order = st ? SEL_LARGEST : SEL_LEADING;
+  auto eig_of = [&](std::complex<double> th) {
+    return st ? (c->st_pole * th - c->st_zero) / (th - 1.0) : th;
+  };
+  auto eig_info = [&](int nout, int mv, int rs, int cv) {
+    kv_eig_info e{nout, mv, rs, cv, c->relaxed_qr, 0};
+    e.inner_matvecs = (int)std::min<long long>(c->st_matvecs, 2147483647LL);
+    return e;
+  };
   c->relaxed_qr = 0;
   HIPCHK(c, hipMemcpyAsync(V, p->v0, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if ((rc = project_inplace(c, V))) return rc;
@@ -1996,7 +2124,7 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
   for (;;) {
     int k = 0;
     if ((rc = arnoldi(c, V, m, H, &k, &matvecs, k0))) {
-      if (info) *info = kv_eig_info{0, matvecs, restarts, 0, c->relaxed_qr};
+      if (info) *info = eig_info(0, matvecs, restarts, 0);
       return rc;
     }
     // Hessenberg form of the projected k x k matrix, last coordinate fixed
@@ -2010,12 +2138,13 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
       for (int cc = std::max(0, r - 1); cc < k; ++cc) Hh[r + (size_t)cc * ld] = A[(size_t)r * k + cc];
     if (k < m || k == m) Hh[k + (size_t)(k - 1) * ld] = (k < m) ? 0.0 : H[m + (size_t)(m - 1) * ld];
     const int nkeep = std::min({p->keep, k - 2, 63});
-    if ((rc = ritz(c, Hh, m, k, std::max(nkeep, p->n_eigs), rz))) {
-      if (info) *info = kv_eig_info{0, matvecs, restarts, 0, c->relaxed_qr};
+    if ((rc = ritz(c, Hh, m, k, std::max(nkeep, p->n_eigs), rz, sel_order))) {
+      if (info) *info = eig_info(0, matvecs, restarts, 0);
       return rc;
     }
-    // the wanted set (first n_eigs in leading order, a pair whole) inside rz.sel
-    const std::vector<int> want = wanted_set(rz.vals, p->n_eigs);
+    // the wanted set (first n_eigs in leading order, or of largest modulus
+    // under a transform; a pair whole) inside rz.sel
+    const std::vector<int> want = st ? modulus_set(rz.vals, p->n_eigs, true) : wanted_set(rz.vals, p->n_eigs);
     double scale = 0.0;
     for (int i : want) scale = std::max(scale, std::abs(rz.vals[i]));
     wsel.clear();
@@ -2030,8 +2159,11 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
       double rmx = 0.0;
       for (int q : wsel) rmx = std::max(rmx, rz.res[q]);
       fprintf(stderr, "[arnoldi-thick] restart %d matvecs %d res/scale %.3e", restarts, matvecs, rmx / scale);
-      for (size_t q = 0; q < wsel.size() && q < 4; ++q)
-        fprintf(stderr, "  (%.6g, %.6g)", rz.vals[rz.sel[wsel[q]]].real(), rz.vals[rz.sel[wsel[q]]].imag());
+      if (st) fprintf(stderr, " inner matvecs %lld", c->st_matvecs);
+      for (size_t q = 0; q < wsel.size() && q < 4; ++q) {
+        const auto lam = eig_of(rz.vals[rz.sel[wsel[q]]]);
+        fprintf(stderr, "  (%.6g, %.6g)", lam.real(), lam.imag());
+      }
       fprintf(stderr, "\n");
     }
     if (conv || matvecs + (m - nkeep) > p->max_matvec || (p->max_restarts > 0 && restarts >= p->max_restarts) ||
@@ -2110,12 +2242,25 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
     k0 = kq;
     ++restarts;
   }
-  // outputs: the wanted values in leading order
+  // outputs: the wanted values of A in leading order.  Under the transform
+  // lambda = (pole theta - zero) / (theta - 1) and Im theta = (zero - pole)
+  // Im lambda / |lambda - pole|^2, so the +Im member of a pair of A is the
+  // -Im member of C; its Ritz vector is the eigenvector of both
   const int nout = (int)wsel.size();
+  std::vector<std::complex<double>> lam(nout);
+  std::vector<int> ord(nout);
   for (int q = 0; q < nout; ++q) {
-    lam_re[q] = rz.vals[rz.sel[wsel[q]]].real();
-    lam_im[q] = rz.vals[rz.sel[wsel[q]]].imag();
-    if (resid) resid[q] = rz.res[wsel[q]];
+    lam[q] = eig_of(rz.vals[rz.sel[wsel[q]]]);
+    ord[q] = q;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (lam[a].real() != lam[b].real()) return lam[a].real() > lam[b].real();
+    return lam[a].imag() > lam[b].imag();
+  });
+  for (int r = 0; r < nout; ++r) {
+    lam_re[r] = lam[ord[r]].real();
+    lam_im[r] = lam[ord[r]].imag();
+    if (resid) resid[r] = rz.res[wsel[ord[r]]];
   }
   if (evecs) {
     // Ritz vectors V Z s of the wanted values (real and imaginary parts) into
@@ -2125,36 +2270,36 @@ static int arnoldi_thick(kv_ctx* c, const kv_arnoldi_params* p, int sym_ref, int
     std::vector<int> nl(nout, 0), outidx(nout);
     std::vector<std::complex<double>> vals(nout);
     int slot = 0;
-    for (int q = 0; q < nout; ++q) {
-      const auto th = rz.vals[rz.sel[wsel[q]]];
-      vals[q] = th;
-      outidx[q] = q;
-      if (th.imag() < 0) {
-        src_re[q] = src_re[q - 1];
-        src_im[q] = src_im[q - 1];
+    for (int r = 0; r < nout; ++r) {
+      const int q = ord[r];
+      vals[r] = lam[q];
+      outidx[r] = r;
+      if (lam[q].imag() < 0) {
+        src_re[r] = src_re[r - 1];
+        src_im[r] = src_im[r - 1];
         continue;
       }
-      const int parts = th.imag() > 0 ? 2 : 1;
+      const int parts = lam[q].imag() > 0 ? 2 : 1;
       std::vector<double> Wrow((size_t)k * parts);
-      for (int r = 0; r < k; ++r)
+      for (int rr = 0; rr < k; ++rr)
         for (int part = 0; part < parts; ++part) {
           double acc = 0.0;
           for (int t = 0; t < k; ++t)
-            acc += Z[(size_t)r * k + t] *
+            acc += Z[(size_t)rr * k + t] *
                    (part == 0 ? rz.vecs[wsel[q]][t].real() : rz.vecs[wsel[q]][t].imag());
-          Wrow[(size_t)r * parts + part] = acc;
+          Wrow[(size_t)rr * parts + part] = acc;
         }
       if (slot + parts > p->n_eigs + 1) return fail(c, KV_EINVAL, "eigenvector workspace exhausted");
       if ((rc = upload(c, c->hess, Wrow.data(), Wrow.size() * sizeof(double)))) return rc;
       HIPCHK(c, launch_combine(c, V, n, k, c->hess, parts, Ys + (int64_t)slot * n, n));
-      src_re[q] = Ys + (int64_t)slot * n;
-      src_im[q] = parts == 2 ? src_re[q] + n : nullptr;
+      src_re[r] = Ys + (int64_t)slot * n;
+      src_im[r] = parts == 2 ? src_re[r] + n : nullptr;
       slot += parts;
     }
     c->nlock = 0;
     if ((rc = write_eigenvectors(c, L, outidx, vals, src_re, src_im, nl, evecs, zp, zc, tmp, &matvecs))) return rc;
   }
-  if (info) *info = kv_eig_info{nout, matvecs, restarts, conv ? 1 : 0, c->relaxed_qr};
+  if (info) *info = eig_info(nout, matvecs, restarts, conv ? 1 : 0);
   if (!conv && p->max_restarts > 0) return fail(c, KV_ENOCONV, "Arnoldi: not converged within the budget");
   return KV_OK;
 }
@@ -2180,6 +2325,7 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
     if (p->keep <= p->n_eigs || p->keep > m - 2) return fail(c, KV_EINVAL, "keep must be in n_eigs+1..krylov_dim-2");
     return arnoldi_thick(c, p, sym_ref, sym_rot, lam_re, lam_im, resid, evecs, info);
   }
+  if (c->st_kind != KV_ST_NONE) return fail(c, KV_EINVAL, "a spectral transform needs the thick restart (keep > 0)");
   double* V = c->ws;
   double* zp = c->ws + (int64_t)(m + 1) * n;
   double* zc = zp + n;

@@ -102,6 +102,17 @@ struct kv_ctx {
   const double* lockQ = nullptr;  // locked W-orthonormal vectors matvec deflates while Arnoldi runs
   int nlock = 0;
   int relaxed_qr = 0;         // Arnoldi cycles whose Hessenberg QR deflated by the relaxed test
+  // spectral transform of Arnoldi (kv_set_spectral_transform): Cayley
+  // C = (A - pole)^-1 (A - zero), the inverse by preconditioned GMRES
+  int st_kind = 0;            // KV_ST_NONE or KV_ST_CAYLEY
+  double st_pole = 0.0, st_zero = 0.0, st_tol = 1e-10;
+  int st_max_matvec = 20000;  // budget of one inner solve
+  bool st_on = false;         // set while a transformed Arnoldi runs
+  bool st_inner = false;      // set while its inner solve runs: the operator is (A - pole) M^-1
+  double* st_t = nullptr;     // workspace: the inner iterate
+  double* st_V = nullptr;     // workspace: the inner GMRES basis (gmres_m + 1 vectors)
+  long long st_matvecs = 0;   // applications of P J by the inner solves of one Arnoldi call
+  int st_solves = 0;
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events

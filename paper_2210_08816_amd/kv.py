@@ -21,6 +21,7 @@ KV_PROJECT, KV_MIXED = 1, 2
 KV_PC_NONE, KV_PC_STOKES = 0, 1
 KV_WS_PROJECT_MIXED, KV_WS_APPLY_PRECONDITIONER, KV_WS_NEWTON, KV_WS_ARNOLDI, KV_WS_TIME_STEPS = 1, 2, 3, 4, 5
 KV_SYM_REF_EVEN, KV_SYM_REF_ODD, KV_SYM_ROT_EVEN, KV_SYM_ROT_ODD = 1 << 4, 1 << 5, 1 << 6, 1 << 7
+KV_ST_NONE, KV_ST_CAYLEY = 0, 1
 
 
 def sym_flags(cls):
@@ -39,7 +40,7 @@ ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_
                "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_project_mixed_static", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
-               "kv_set_gmres_deflation",
+               "kv_set_gmres_deflation", "kv_set_spectral_transform",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_time_steps", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -71,7 +72,7 @@ class _ArnoldiParams(ctypes.Structure):
 
 class _EigInfo(ctypes.Structure):
     _fields_ = [("n_out", ctypes.c_int), ("matvecs", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("converged", ctypes.c_int), ("relaxed_qr", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("relaxed_qr", ctypes.c_int), ("inner_matvecs", ctypes.c_int)]
 
 
 _lib = None
@@ -322,6 +323,15 @@ class Context:
         """Harmonic Ritz vectors kept across GMRES restarts (GMRES-DR; 0: plain)."""
         self._check(self._lib.kv_set_gmres_deflation(self._h, int(k)))
 
+    def set_spectral_transform(self, kind, pole=0.0, zero=-1.0, inner_tol=1e-10, inner_max_matvec=20000):
+        """Cayley transform (A - pole)^-1 (A - zero) for the thick-restarted
+        Arnoldi (kind KV_ST_CAYLEY; KV_ST_NONE switches it off).  The inner
+        solves are preconditioned GMRES with the context's restart length and
+        preconditioner."""
+        self._check(self._lib.kv_set_spectral_transform(self._h, int(kind), ctypes.c_double(pole),
+                                                        ctypes.c_double(zero), ctypes.c_double(inner_tol),
+                                                        int(inner_max_matvec)))
+
     def set_bicgstab_stall(self, cycles):
         """Cycles without a 10% residual drop after which the BiCGstab(2) part
         of newton_correction hands over to GMRES (0: GMRES from the start)."""
@@ -393,4 +403,4 @@ class Context:
         vals = np.array([complex(re[i], im[i]) for i in range(k)])
         return vals, np.array(res[:k]), dict(status=rc, n_out=k, matvecs=info.matvecs,
                                               restarts=info.restarts, converged=bool(info.converged),
-                                              relaxed_qr=info.relaxed_qr)
+                                              relaxed_qr=info.relaxed_qr, inner_matvecs=info.inner_matvecs)

@@ -634,3 +634,66 @@ def test_newton_correction_in_the_symmetric_class():
         assert e.value.code == kv.KV_EINVAL
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("precond", [False, True])
+def test_cayley_transform_arnoldi(precond):
+    """Thick-restarted Arnoldi on the Cayley transform (A - pole)^-1 (A - zero),
+    the inverse by (preconditioned) GMRES: the values it returns are the
+    eigenvalues of the dense generalized saddle problem whose images
+    (lambda - zero)/(lambda - pole) have the largest modulus, mapped back, and
+    its eigenvectors are certified by the oracle's own operator A = P J."""
+    from paper_2210_08816_amd import kv
+    print(f"case cayley precond={precond}", flush=True)
+    fx = [faces("clustered", n) for n in (6, 5, 4)]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    X0 = S.base_flow(*fx, K=2, amp=0.3, seed=21)
+    lam = dense_saddle_eigs(g, X0)
+    pole, zero = float(lam[0].real) + 2.0, float(lam[0].real) - 60.0
+    theta = (lam - zero) / (lam - pole)
+    order = np.argsort(-np.abs(theta), kind="stable")
+    mods = np.abs(theta[order])
+    n_want = 4 if abs(mods[3] - mods[4]) > 1e-9 * mods[3] else 5   # a pair kept whole
+    assert mods[n_want - 1] > 1.05 * mods[n_want], mods[:8]         # a well-separated wanted set
+    want = lam[order[:n_want]]
+    ctx = context(fx, 2e4, 0.71, X0)
+    try:
+        if precond:
+            ctx.set_preconditioner(True, 10.0)
+        ctx.set_spectral_transform(kv.KV_ST_CAYLEY, pole=pole, zero=zero, inner_tol=1e-12, inner_max_matvec=4000)
+        ev = torch.zeros((n_want + 1) * g.size, dtype=torch.float64, device="cuda")
+        vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=24,
+                                                   n_eigs=n_want, tol=1e-11, max_matvec=2000, keep=10, evecs=ev)
+        assert info["converged"] and info["inner_matvecs"] > info["matvecs"], info
+        scale = np.max(np.abs(want))
+        assert len(vals) == n_want
+        assert closest(vals, want) <= 1e-8 * scale, (vals, want)
+        assert closest(want, vals) <= 1e-8 * scale
+        assert np.all(np.diff(vals.real) <= 1e-12 * scale)              # leading order
+        A = SV.Operator(g, X0)
+        E = to_host(ev).reshape(n_want + 1, g.size)
+        q = 0
+        while q < len(vals):
+            lam_q = vals[q]
+            if lam_q.imag > 0:
+                x = E[q] + 1j * E[q + 1]
+                r = (A(x.real) + 1j * A(x.imag)) - lam_q * x
+                nx = np.sqrt(A.norm(x.real) ** 2 + A.norm(x.imag) ** 2)
+                assert np.sqrt(A.norm(r.real) ** 2 + A.norm(r.imag) ** 2) <= 1e-7 * scale * nx
+                q += 2
+            else:
+                assert A.norm(A(E[q]) - lam_q.real * E[q]) <= 1e-7 * scale * A.norm(E[q])
+                q += 1
+        # a transform needs the thick restart; pole == zero is refused
+        with pytest.raises(kv.KVError) as e:
+            ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=24, n_eigs=4, keep=0)
+        assert e.value.code == kv.KV_EINVAL
+        with pytest.raises(kv.KVError) as e:
+            ctx.set_spectral_transform(kv.KV_ST_CAYLEY, pole=1.0, zero=1.0)
+        assert e.value.code == kv.KV_EINVAL
+        ctx.set_spectral_transform(kv.KV_ST_NONE)
+        v2, _, i2 = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=24, n_eigs=4,
+                                             tol=1e-11, max_matvec=20000, keep=10)
+        assert i2["inner_matvecs"] == 0 and closest(v2, lam[:6]) <= 1e-8 * np.max(np.abs(lam[:4]))
+    finally:
+        ctx.close()
