@@ -138,15 +138,21 @@ def same_mode_by_frequency(info_a, info_b, rel=0.25, abs_tol=0.02):
 
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
         tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
-        newton_max_matvec=20000, gmres_restart=None, keep=0, state=None, log=print):
+        newton_max_matvec=20000, gmres_restart=None, gmres_deflation=0, newton_sym=None, keep=0, state=None,
+        warm_start=True, log=print):
     """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
     the Arnoldi tolerance (relative to the largest wanted modulus): the sign
     of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
     newton_max_matvec: budget of each Newton correction; gmres_restart: the
     restart length of its GMRES continuation (None: the library default);
-    keep: thick restart keeping that many Ritz vectors (0: the Chebyshev-
-    filtered restart); state: a converged state at gr_lo (host array) in place
-    of the continuation from rest."""
+    gmres_deflation: harmonic Ritz vectors kept across its restarts;
+    newton_sym: None, or a symmetry class the corrections are restricted to
+    (the steady branch's own, (1, 1)); keep: thick restart keeping that many
+    Ritz vectors (0: the Chebyshev-filtered restart); state: a converged state
+    at gr_lo (host array) in place of the continuation from rest; warm_start:
+    start each Arnoldi run from the leading eigenvector found at the previous
+    Gr (plus a tenth of the seeded random start), not from the random start
+    alone."""
     import numpy as np
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
@@ -161,37 +167,48 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         grs.append(g)
         g *= 1.6
     grs.append(gr_lo)
+    nkw = dict(Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
+               gmres_restart=gmres_restart, gmres_deflation=gmres_deflation, log=lambda m: None)
+    if newton_sym is not None:
+        nkw["sym"] = newton_sym
     t0 = time.perf_counter()
     if state is not None:
         states = [torch.as_tensor(np.asarray(state, dtype=np.float64)).cuda()]
     else:
-        states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20,
-                              precond_sigma=precond_sigma, gmres_restart=gmres_restart, log=lambda m: None)
+        states, infos = sweep(faces, grs, **nkw)
         if len(states) < len(grs):
             raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
     known = [(gr_lo, states[-1])]   # converged states, nearest one starts each new Newton solve
     v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(states[-1].numel())).cuda()
+    v0 /= v0.norm()
     counts = {"newton_matvecs": 0, "arnoldi_matvecs": 0}
+    lead_vec = []   # leading eigenvector of the last converged Arnoldi run
 
     def sigma(gr):
         near = min(known, key=lambda t: abs(math.log(t[0] / gr)))
         X = near[1]
         if near[0] != gr:
-            st, inf = sweep(faces, [gr], Pr=Pr, X0=near[1], gr0=near[0], max_matvec=newton_max_matvec, max_iter=20,
-                            precond_sigma=precond_sigma, gmres_restart=gmres_restart, log=lambda m: None)
+            st, inf = sweep(faces, [gr], X0=near[1], gr0=near[0], **nkw)
             counts["newton_matvecs"] += sum(i.get("matvecs_all_attempts", i["matvecs"]) for i in inf)
             if not st:
                 return None, {"newton": "not converged", "stop": True}
             X = st[-1]
             known.append((gr, X))
         ctx = kv.Context(*faces, Gr=gr, Pr=Pr)
+        start = v0
+        if warm_start and lead_vec:
+            start = lead_vec[0] + 0.1 * v0
+        ev = torch.empty((n_eigs + 1) * X.numel(), dtype=torch.float64, device=X.device)
         try:
             ctx.set_base_flow(X)
-            vals, res, info = ctx.arnoldi_leading_eigs(v0, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
+            vals, res, info = ctx.arnoldi_leading_eigs(start, krylov, n_eigs, tol=tol, max_matvec=max_matvec,
                                                        cheb_degree_max=cheb_degree_max, sym=sym, check=False,
-                                                       keep=keep)
+                                                       keep=keep, evecs=ev)
         finally:
             ctx.close()
+        if info["converged"] and len(vals):
+            e = ev[:X.numel()].clone()
+            lead_vec[:] = [e / e.norm()]
         counts["arnoldi_matvecs"] += info["matvecs"]
         lead = [[float(v.real), float(v.imag)] for v in vals[:2]]
         resid = [float(r) for r in res[:2]]
@@ -226,6 +243,11 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-5, help="Arnoldi tolerance")
     ap.add_argument("--newton-max-matvec", type=int, default=20000, help="budget of each Newton correction")
     ap.add_argument("--gmres-restart", type=int, default=None, help="GMRES restart length of the Newton corrections")
+    ap.add_argument("--gmres-deflation", type=int, default=0,
+                    help="harmonic Ritz vectors kept across GMRES restarts in the Newton corrections")
+    ap.add_argument("--newton-sym", default=None, help="restrict the Newton corrections to one class, e.g. pp")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="start every Arnoldi run from the seeded random vector")
     ap.add_argument("--keep", type=int, default=0,
                     help="thick-restart Arnoldi keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
     ap.add_argument("--load-state", default=None, help="a converged state at --gr-lo (.npy) instead of continuation")
@@ -236,7 +258,9 @@ def main(argv=None):
         raise SystemExit("--sym takes one class")
     res = run(n=a.n, grid=a.grid, gr_lo=a.gr_lo, gr_hi=a.gr_hi, ratio=a.ratio, sym=cls[0] if cls else None,
               krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
-              gmres_restart=a.gmres_restart, keep=a.keep,
+              gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
+              newton_sym=parse_sym(a.newton_sym)[0] if a.newton_sym else None,
+              warm_start=not a.no_warm_start, keep=a.keep,
               state=__import__("numpy").load(a.load_state) if a.load_state else None,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
