@@ -15,6 +15,7 @@ Every step runs in the library's kernels; this module sequences the calls.
 from __future__ import annotations
 
 import json
+import os
 import math
 import time
 
@@ -139,7 +140,7 @@ def same_mode_by_frequency(info_a, info_b, rel=0.25, abs_tol=0.02):
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
         tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
         newton_max_matvec=20000, gmres_restart=None, gmres_deflation=0, newton_sym=None, keep=0, state=None,
-        warm_start=True, log=print):
+        warm_start=True, save_states=None, log=print):
     """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
     the Arnoldi tolerance (relative to the largest wanted modulus): the sign
     of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
@@ -152,7 +153,9 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
     at gr_lo (host array) in place of the continuation from rest; warm_start:
     start each Arnoldi run from the leading eigenvector found at the previous
     Gr (plus a tenth of the seeded random start), not from the random start
-    alone."""
+    alone; save_states: None, or a directory that receives every converged
+    steady state of the search as state_<n>_<Gr>.npy (a later search can
+    start from one with state=)."""
     import numpy as np
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
@@ -194,6 +197,9 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
                 return None, {"newton": "not converged", "stop": True}
             X = st[-1]
             known.append((gr, X))
+            if save_states:
+                os.makedirs(save_states, exist_ok=True)
+                np.save(os.path.join(save_states, f"state_{n}_{gr:.6e}.npy"), X.cpu().numpy())
         ctx = kv.Context(*faces, Gr=gr, Pr=Pr)
         start = v0
         if warm_start and lead_vec:
@@ -251,6 +257,7 @@ def main(argv=None):
     ap.add_argument("--keep", type=int, default=0,
                     help="thick-restart Arnoldi keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
     ap.add_argument("--load-state", default=None, help="a converged state at --gr-lo (.npy) instead of continuation")
+    ap.add_argument("--save-states", default=None, help="directory for every converged steady state (.npy)")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     cls = parse_sym(a.sym)
@@ -260,7 +267,7 @@ def main(argv=None):
               krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
               gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
               newton_sym=parse_sym(a.newton_sym)[0] if a.newton_sym else None,
-              warm_start=not a.no_warm_start, keep=a.keep,
+              warm_start=not a.no_warm_start, save_states=a.save_states, keep=a.keep,
               state=__import__("numpy").load(a.load_state) if a.load_state else None,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
