@@ -1053,8 +1053,15 @@ int kv_create(const kv_params* p, void* hip_stream, kv_ctx** out) {
   const int64_t rows = 2 * nz * ny + nz * (ny - 1) + (nz - 1) * ny;
   c->npart_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (rows + 3) / 4));
   // the Gram-Schmidt multi-dots carry 16-32 accumulators per thread and run
-  // few waves per SIMD: they take up to four times as many blocks
-  c->nmd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (rows + 3) / 4));
+  // few waves per SIMD: up to four times as many blocks, but at least 8 rows
+  // per wave, so that the per-block reduction of those accumulators stays
+  // small beside the streaming on small grids (KV_MD_BLOCKS overrides, for
+  // measurements)
+  c->nmd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (rows + 31) / 32));
+  if (const char* mb = getenv("KV_MD_BLOCKS")) {
+    const int v = atoi(mb);
+    if (v >= 1 && v <= 8192) c->nmd_blocks = v;
+  }
   if (hipMalloc(&c->X0, g.n * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "X0");
   if (hipMalloc(&c->cellA, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellA");
   if (hipMalloc(&c->cellB, c->ncell * sizeof(double)) != hipSuccess) return cleanup(KV_ENOMEM, "cellB");
@@ -1467,6 +1474,11 @@ int cayley_apply(kv_ctx* c, const double* x, double* y) {
   rc = gmres_solve(c, c->st_V, x, bn, c->st_t, c->st_tol, c->gmres_m, c->st_max_matvec, &used, &cyc, &rr, true);
   c->st_matvecs += used;
   ++c->st_solves;
+  static const bool trace = [] {
+    const char* ev = getenv("KV_ARNOLDI_TRACE");
+    return ev && atoi(ev) != 0;
+  }();
+  if (trace) fprintf(stderr, "[cayley] inner solve %d: %d matvecs, relative residual %.3e\n", c->st_solves, used, rr);
   double* z = c->st_t;
   if (rc == KV_OK && c->pc_active) {
     rc = precond_apply(c, c->st_t, c->pc_tmp);
