@@ -140,7 +140,7 @@ def same_mode_by_frequency(info_a, info_b, rel=0.25, abs_tol=0.02):
 def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=None, krylov=60, n_eigs=2,
         tol=1e-5, max_matvec=60000, cheb_degree_max=400, precond_sigma=10.0, rtol=1e-3, v0_seed=77,
         newton_max_matvec=20000, gmres_restart=None, gmres_deflation=0, newton_sym=None, keep=0, state=None,
-        warm_start=True, save_states=None, log=print):
+        warm_start=True, save_states=None, state_gr=None, log=print):
     """Critical Gr on an n^3 grid for one symmetry class (or none).  tol is
     the Arnoldi tolerance (relative to the largest wanted modulus): the sign
     of Re lambda_1 needs far less than the 1e-8 of an eigenvalue table.
@@ -150,12 +150,16 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
     newton_sym: None, or a symmetry class the corrections are restricted to
     (the steady branch's own, (1, 1)); keep: thick restart keeping that many
     Ritz vectors (0: the Chebyshev-filtered restart); state: a converged state
-    at gr_lo (host array) in place of the continuation from rest; warm_start:
+    at gr_lo (host array) in place of the continuation from rest, or at
+    state_gr < gr_lo when that is given (Newton then starts the search from
+    it); warm_start:
     start each Arnoldi run from the leading eigenvector found at the previous
     Gr (plus a tenth of the seeded random start), not from the random start
     alone; save_states: None, or a directory that receives every converged
     steady state of the search as state_<n>_<Gr>.npy (a later search can
     start from one with state=)."""
+    if state_gr is not None and (state is None or not state_gr < gr_lo):
+        raise ValueError("state_gr needs a state and must lie below gr_lo")
     import numpy as np
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
@@ -171,7 +175,7 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         g *= 1.6
     grs.append(gr_lo)
     nkw = dict(Pr=Pr, max_matvec=newton_max_matvec, max_iter=20, precond_sigma=precond_sigma,
-               gmres_restart=gmres_restart, gmres_deflation=gmres_deflation, log=lambda m: None)
+               gmres_restart=gmres_restart, gmres_deflation=gmres_deflation, log=log)
     if newton_sym is not None:
         nkw["sym"] = newton_sym
     t0 = time.perf_counter()
@@ -181,7 +185,8 @@ def run(n=24, grid="clustered", gr_lo=1e7, gr_hi=2e8, Pr=0.71, ratio=1.6, sym=No
         states, infos = sweep(faces, grs, **nkw)
         if len(states) < len(grs):
             raise RuntimeError(f"continuation stopped at Gr = {infos[-1]['Gr']:.4e}")
-    known = [(gr_lo, states[-1])]   # converged states, nearest one starts each new Newton solve
+    # converged states; the nearest one starts each new Newton solve
+    known = [(state_gr if state_gr is not None else gr_lo, states[-1])]
     v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(states[-1].numel())).cuda()
     v0 /= v0.norm()
     counts = {"newton_matvecs": 0, "arnoldi_matvecs": 0}
@@ -258,6 +263,9 @@ def main(argv=None):
                     help="thick-restart Arnoldi keeping this many Ritz vectors (0: Chebyshev-filtered restart)")
     ap.add_argument("--load-state", default=None, help="a converged state at --gr-lo (.npy) instead of continuation")
     ap.add_argument("--save-states", default=None, help="directory for every converged steady state (.npy)")
+    ap.add_argument("--rtol", type=float, default=1e-3, help="relative width at which the bracket is accepted")
+    ap.add_argument("--state-gr", type=float, default=None,
+                    help="Gr of the --load-state state when it lies below --gr-lo")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     cls = parse_sym(a.sym)
@@ -267,7 +275,8 @@ def main(argv=None):
               krylov=a.krylov, max_matvec=a.max_matvec, tol=a.tol, newton_max_matvec=a.newton_max_matvec,
               gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
               newton_sym=parse_sym(a.newton_sym)[0] if a.newton_sym else None,
-              warm_start=not a.no_warm_start, save_states=a.save_states, keep=a.keep,
+              warm_start=not a.no_warm_start, save_states=a.save_states, state_gr=a.state_gr, keep=a.keep,
+              rtol=a.rtol,
               state=__import__("numpy").load(a.load_state) if a.load_state else None,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)

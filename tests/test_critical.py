@@ -3,6 +3,8 @@ regula falsi in log Gr, pinned on closed-form sigma(Gr) curves (the GPU
 side, continuation and Arnoldi, is covered by the solver tests)."""
 import math
 
+import pytest
+
 from paper_2210_08816_amd.critical import find_crossing, same_mode_by_frequency
 
 
@@ -131,3 +133,11 @@ def test_mode_switch_is_not_a_crossing():
     assert same_mode_by_frequency({"values": [[0, 0.05]]}, {"values": [[0, 0.055]]})
     assert not same_mode_by_frequency({"values": [[0, 0.043]]}, {"values": [[0, 0.67]]})
     assert not same_mode_by_frequency({"values": []}, {"values": [[0, 0.1]]})
+
+
+def test_run_rejects_state_gr_without_state_or_above_gr_lo():
+    from paper_2210_08816_amd.critical import run
+    with pytest.raises(ValueError):
+        run(n=8, gr_lo=2e7, gr_hi=3e7, state=None, state_gr=1e7)
+    with pytest.raises(ValueError):
+        run(n=8, gr_lo=2e7, gr_hi=3e7, state=[0.0], state_gr=2e7)
