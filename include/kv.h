@@ -80,7 +80,8 @@ enum kv_status {
  * matrix cores), refined on the FP64 residual, the normalized divergence
  * max|net flux| / max|face flux| checked after every sweep from the second
  * until it is <= 1e-10 (KV_ENOCONV after 8 sweeps).  It needs every axis mirror-symmetric with an even cell count; on
- * other grids the FP64 projection is used.  The solvers reject KV_MIXED. */
+ * other grids the FP64 projection is used.  The solvers take it through
+ * kv_set_solver_projection. */
 enum kv_flags { KV_PROJECT = 1u, KV_MIXED = 2u };
 
 typedef struct {
@@ -230,8 +231,8 @@ typedef struct {
  * fully symmetric class (KV_SYM_REF_EVEN | KV_SYM_ROT_EVEN), and keeping
  * the solve there removes the eigenmodes of the other classes, one of which
  * turns singular where a symmetry-breaking real eigenvalue crosses zero.
- * KV_MIXED is reserved.  With
- * a preconditioner set (kv_set_preconditioner) the solve is right
+ * (The mixed projection is chosen per context: kv_set_solver_projection.)
+ * With a preconditioner set (kv_set_preconditioner) the solve is right
  * preconditioned: BiCGstab(2)/GMRES iterate on P J M^-1 and delta = delta0 +
  * M^-1 x. */
 int kv_newton_correction(kv_ctx* ctx, const double* F, double tol, int max_matvec,
@@ -394,6 +395,18 @@ int kv_arnoldi_leading_eigs(kv_ctx* ctx, const kv_arnoldi_params* p, double* lam
  * inner_tol outside (0, 1), inner_max_matvec < 4); kv_arnoldi_leading_eigs
  * returns KV_EINVAL with a transform set and keep == 0. */
 enum kv_spectral_transform { KV_ST_NONE = 0, KV_ST_CAYLEY = 1 };
+
+/* Projection inside the solvers (kv_newton_correction, including its
+ * preconditioner and final projection, and kv_arnoldi_leading_eigs,
+ * including a spectral transform's inner solves): flags 0 for the FP64
+ * projection (default) or KV_MIXED for the mixed form of kv_project
+ * (normalized divergence <= 1e-10 after each projection).  The mixed form
+ * is what the paper's mixed-precision configuration asks of the solvers;
+ * it is an addition (the paper computes in FP64).  Kept until changed; the
+ * KV_WS_NEWTON and KV_WS_ARNOLDI workspaces grow by one vector while
+ * KV_MIXED is set.  KV_EINVAL for other flags, or KV_MIXED on a grid whose
+ * axes are not mirror-symmetric of even size. */
+int kv_set_solver_projection(kv_ctx* ctx, unsigned flags);
 int kv_set_spectral_transform(kv_ctx* ctx, int kind, double pole, double zero, double inner_tol,
                               int inner_max_matvec);
 

@@ -63,7 +63,7 @@ def newton_solve(ctx, X, tol_rel=1e-10, tol_abs=1e-12, max_iter=30, max_matvec=2
 
 
 def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10, tol_abs=1e-12,
-          precond_sigma=None, gmres_restart=None, gr0=None, gmres_deflation=0, **kw):
+          precond_sigma=None, gmres_restart=None, gr0=None, gmres_deflation=0, mixed=False, **kw):
     """Continuation over increasing Gr values, from X0 (default: the
     conduction state) converged at Gr = gr0 (None: X0 is not a converged
     state).  A failed step is retried from the last converged state at the
@@ -71,7 +71,8 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
     (a first step from an X0 without gr0 is not retried).  precond_sigma: None, or the shift of the Stokes/heat
     preconditioner of the Newton corrections; gmres_restart: None (the
     library's default) or the restart length of their GMRES continuation;
-    gmres_deflation: harmonic Ritz vectors kept across its restarts (0: none).
+    gmres_deflation: harmonic Ritz vectors kept across its restarts (0: none);
+    mixed: the corrections' projections in the mixed form.
     Returns (states, infos) for
     the requested Gr values reached; a value that cannot be reached ends the
     sweep."""
@@ -95,6 +96,8 @@ def sweep(faces, grs, Pr=0.71, X0=None, log=print, max_halvings=3, tol_rel=1e-10
                     ctx.set_gmres_restart(gmres_restart)
                 if gmres_deflation:
                     ctx.set_gmres_deflation(gmres_deflation)
+                if mixed:
+                    ctx.set_solver_projection(True)
                 ctx.project(Xtry)
                 info = newton_solve(ctx, Xtry, tol_rel=tol_rel, tol_abs=tol_abs, log=log, **kw)
             finally:

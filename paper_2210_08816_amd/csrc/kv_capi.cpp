@@ -224,6 +224,7 @@ struct PhaseMark {
 };
 
 int project_inplace(kv_ctx* c, double* y) {
+  if (c->solve_mixed) return kv::project_mixed_with(c, y, nullptr, nullptr, c->ymix_solve);
   {
     PhaseMark pm(c, 1);
     HIPCHK(c, launch_scaled_divergence(c, y, c->cellA));
@@ -397,6 +398,14 @@ struct EigScope {
   }
 };
 
+// Makes every projection of one solver call the mixed form when the
+// context asks for it (kv_set_solver_projection); cleared on every exit.
+struct MixedScope {
+  kv_ctx* c;
+  explicit MixedScope(kv_ctx* cc) : c(cc) { c->solve_mixed = c->solve_mixed_set; }
+  ~MixedScope() { c->solve_mixed = false; }
+};
+
 // y = M^-1 x of the Stokes/heat preconditioner: per block the Helmholtz
 // solve (sigma - nu Lap_v) or (sigma - kappa Lap_T), then P on the velocity.
 int precond_apply(kv_ctx* c, const double* x, double* y) {
@@ -467,8 +476,10 @@ size_t ws_vectors(const kv_ctx* c, int op, int m, int neig) {
   switch (op) {
     case KV_WS_PROJECT_MIXED: return 1;
     case KV_WS_APPLY_PRECONDITIONER: return 1;
-    case KV_WS_NEWTON: return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0) + (c->gmres_defl ? 1 : 0);
-    case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1) + st_vectors(c);
+    case KV_WS_NEWTON:
+      return 8 + (size_t)c->gmres_m + 1 + (c->pc_kind != KV_PC_NONE ? 3 : 0) + (c->gmres_defl ? 1 : 0) +
+             (c->solve_mixed_set ? 1 : 0);
+    case KV_WS_ARNOLDI: return (size_t)m + 4 + 2 * (size_t)(neig + 1) + st_vectors(c) + (c->solve_mixed_set ? 1 : 0);
     case KV_WS_TIME_STEPS: return 4;
     default: return 0;
   }
@@ -491,10 +502,12 @@ size_t ws_need(const kv_ctx* c, int op, int m, int neig) {
 //   PROJECT_MIXED          ymix
 //   APPLY_PRECONDITIONER   pc_scr
 //   NEWTON                 8 BiCGstab(2) vectors | GMRES basis (m+1) | pc_tmp pc_d0 pc_scr |
+//                          (mixed solver projection) ymix_solve |
 //                          (deflated GMRES) a spare vector, the Hessenberg area
 //   ARNOLDI                V (m+1) | zp zc tmp | locked (neig+1) | Ritz (neig+1) |
 //                          (spectral transform) inner iterate, GMRES basis (gmres_m+1),
-//                          (with a preconditioner) pc_tmp pc_scr | Hessenberg area
+//                          (with a preconditioner) pc_tmp pc_scr | (mixed solver
+//                          projection) ymix_solve | Hessenberg area
 //   TIME_STEPS             F | F of the previous step | right-hand side | pc_scr
 int ws_bind(kv_ctx* c, int op, int m, int neig) {
   const size_t need = ws_need(c, op, m, neig);
@@ -516,6 +529,10 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
         c->pc_scr = p + 2 * n;
         p += 3 * n;
       }
+      if (c->solve_mixed_set) {
+        c->ymix_solve = p;
+        p += n;
+      }
       if (c->gmres_defl) c->hess = p + n;  // after one spare vector
       break;
     }
@@ -530,6 +547,10 @@ int ws_bind(kv_ctx* c, int op, int m, int neig) {
           c->pc_scr = p + n;
           p += 2 * n;
         }
+      }
+      if (c->solve_mixed_set) {
+        c->ymix_solve = p;
+        p += n;
       }
       c->hess = p;
       break;
@@ -1510,6 +1531,7 @@ int kv_newton_correction(kv_ctx* c, const double* F, double tol, int max_matvec,
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   if (delta0 == delta) return fail(c, KV_EINVAL, "delta0 must not alias delta");
   EigScope scope(c, er, eo, nullptr);  // matvec keeps the Krylov space in the class
+  MixedScope mixed(c);
   c->pc_active = c->pc_kind != KV_PC_NONE;
   rc = newton_correction(c, F, tol, max_matvec, delta0, delta, info);
   c->pc_active = false;
@@ -1881,6 +1903,15 @@ int kv_set_gmres_deflation(kv_ctx* c, int k) {
   if (!c) return KV_EINVAL;
   if (k < 0 || k > 62) return fail(c, KV_EINVAL, "GMRES deflation must be in 0..62");
   c->gmres_defl = k;
+  return KV_OK;
+}
+
+int kv_set_solver_projection(kv_ctx* c, unsigned flags) {
+  if (!c) return KV_EINVAL;
+  if (flags & ~(unsigned)KV_MIXED) return fail(c, KV_EINVAL, "unsupported flags");
+  if ((flags & KV_MIXED) && !mixed_grid(c))
+    return fail(c, KV_EINVAL, "the mixed projection needs mirror-symmetric axes of even size");
+  c->solve_mixed_set = (flags & KV_MIXED) != 0;
   return KV_OK;
 }
 
@@ -2329,6 +2360,7 @@ int kv_arnoldi_leading_eigs(kv_ctx* c, const kv_arnoldi_params* p, double* lam_r
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
   const int64_t n = c->g.n;
   if ((rc = check_finite(c, p->v0, n, "v0"))) return rc;
+  MixedScope mixed(c);
   // workspace: V (m+1 vectors) + z_prev, z, tmp + up to n_eigs+1 locked
   // vectors (+ as many lock-time Ritz vectors when eigenvectors are asked for)
   const int nslot = p->n_eigs + 1;

@@ -113,6 +113,11 @@ struct kv_ctx {
   double* st_V = nullptr;     // workspace: the inner GMRES basis (gmres_m + 1 vectors)
   long long st_matvecs = 0;   // applications of P J by the inner solves of one Arnoldi call
   int st_solves = 0;
+  // projection of the solvers' operators (kv_set_solver_projection): the
+  // mixed form while a Newton correction or an Arnoldi call runs
+  bool solve_mixed_set = false;
+  bool solve_mixed = false;
+  double* ymix_solve = nullptr;  // workspace: the mixed sweeps' scratch vector
   // phase timing (kv_timing): events recorded around each phase while enabled
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;       // reusable events

@@ -40,7 +40,7 @@ ABI_SYMBOLS = ("kv_create", "kv_destroy", "kv_layout", "kv_workspace_size", "kv_
                "kv_set_base_flow", "kv_residual",
                "kv_apply_jacobian", "kv_project", "kv_project_mixed_static", "kv_dot", "kv_axpby", "kv_symmetry_measures",
                "kv_symmetry_project", "kv_hessenberg_eigenvalues", "kv_set_gmres_restart", "kv_set_bicgstab_stall",
-               "kv_set_gmres_deflation", "kv_set_spectral_transform",
+               "kv_set_gmres_deflation", "kv_set_spectral_transform", "kv_set_solver_projection",
                "kv_newton_correction", "kv_set_preconditioner", "kv_apply_preconditioner",
                "kv_arnoldi_leading_eigs", "kv_time_steps", "kv_cells_from_state",
                "kv_state_from_cells", "kv_state_add_cell_increment", "kv_timing", "kv_last_error")
@@ -331,6 +331,11 @@ class Context:
         self._check(self._lib.kv_set_spectral_transform(self._h, int(kind), ctypes.c_double(pole),
                                                         ctypes.c_double(zero), ctypes.c_double(inner_tol),
                                                         int(inner_max_matvec)))
+
+    def set_solver_projection(self, mixed):
+        """The projection inside newton_correction and arnoldi_leading_eigs:
+        the mixed form (True) or FP64 (False, the default)."""
+        self._check(self._lib.kv_set_solver_projection(self._h, KV_MIXED if mixed else 0))
 
     def set_bicgstab_stall(self, cycles):
         """Cycles without a 10% residual drop after which the BiCGstab(2) part

@@ -24,14 +24,16 @@ from .continuation import sweep
 def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10, tol=1e-8, max_matvec=200000,
         cheb_degree_max=200, precond_sigma=10.0, v0_seed=77, state=None, save_state=None, sym=None, keep=0,
         from_state=None, from_gr=None, gmres_restart=None, gmres_deflation=0, newton_max_matvec=20000,
-        max_restarts=100000, newton_sym=None, cayley=None, inner_tol=1e-10, inner_max_matvec=20000, log=print):
+        max_restarts=100000, newton_sym=None, cayley=None, inner_tol=1e-10, inner_max_matvec=20000, mixed=False,
+        log=print):
     """state: a converged packed state at Gr (host array) to start from
     instead of continuation; save_state: file to store the converged state;
     sym: None (one unrestricted Arnoldi run) or a list of symmetry classes
     (e_ref, e_rot), one restricted run each; cayley: None, or (pole, zero) of
     a Cayley transform for the (thick-restarted) Arnoldi runs, whose inner
     solves take the Stokes/heat preconditioner of precond_sigma, the GMRES
-    restart gmres_restart, inner_tol and inner_max_matvec."""
+    restart gmres_restart, inner_tol and inner_max_matvec; mixed: the
+    projections inside Newton and Arnoldi in the mixed form."""
     import torch
     from synth import inputs as S  # seeded grid faces (input construction only)
     f = S.faces_uniform(n) if grid == "uniform" else S.faces_clustered(n)
@@ -49,7 +51,7 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
         states, infos = sweep(faces, grs, Pr=Pr, max_matvec=newton_max_matvec, max_iter=20,
                               precond_sigma=precond_sigma, gmres_restart=gmres_restart,
                               gmres_deflation=gmres_deflation, X0=from_state, gr0=from_gr, log=log,
-                              sym=newton_sym)
+                              sym=newton_sym, mixed=mixed)
         torch.cuda.synchronize()
         t_cont = time.perf_counter() - t0
         if len(states) < len(grs):
@@ -71,6 +73,8 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
         fn = ctx.residual(F)
         meas = ctx.symmetry_measures(X)
         v0 = torch.from_numpy(np.random.default_rng(v0_seed).standard_normal(ctx.n)).cuda()
+        if mixed:
+            ctx.set_solver_projection(True)
         if cayley is not None:
             if precond_sigma is not None:
                 ctx.set_preconditioner(True, precond_sigma)
@@ -89,7 +93,7 @@ def run(n=64, grid="clustered", Gr=4e7, Pr=0.71, ratio=1.6, krylov=60, n_eigs=10
             t_eig = time.perf_counter() - t1
             runs.append({"symmetry_class": list(cls) if cls else None, "krylov_dim": krylov, "n_eigs": n_eigs,
                          "restart": f"thick, keep {keep}" if keep else "Chebyshev filter",
-                         "cayley": list(cayley) if cayley is not None else None,
+                         "cayley": list(cayley) if cayley is not None else None, "mixed": bool(mixed),
                          "inner_matvecs": info["inner_matvecs"],
                          "tol": tol, "seconds": round(t_eig, 3), "matvecs": info["matvecs"],
                          "restarts": info["restarts"], "converged": info["converged"], "status": info["status"],
@@ -156,6 +160,7 @@ def main(argv=None):
     ap.add_argument("--newton-max-matvec", type=int, default=20000)
     ap.add_argument("--newton-sym", default=None,
                     help="symmetry class of the Newton corrections, e.g. pp (the symmetric branch)")
+    ap.add_argument("--mixed", action="store_true", help="mixed-form projections inside Newton and Arnoldi")
     ap.add_argument("--cayley", default=None,
                     help="POLE,ZERO: thick-restarted Arnoldi on (A - pole)^-1 (A - zero) (needs --keep)")
     ap.add_argument("--inner-tol", type=float, default=1e-10, help="relative tolerance of the Cayley inner solves")
@@ -172,7 +177,7 @@ def main(argv=None):
               gmres_restart=a.gmres_restart, gmres_deflation=a.gmres_deflation,
               newton_max_matvec=a.newton_max_matvec,
               newton_sym=parse_sym(a.newton_sym)[0] if a.newton_sym else None,
-              cayley=cayley, inner_tol=a.inner_tol, inner_max_matvec=a.inner_max_matvec,
+              cayley=cayley, inner_tol=a.inner_tol, inner_max_matvec=a.inner_max_matvec, mixed=a.mixed,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:

@@ -697,3 +697,54 @@ def test_cayley_transform_arnoldi(precond):
         assert i2["inner_matvecs"] == 0 and closest(v2, lam[:6]) <= 1e-8 * np.max(np.abs(lam[:4]))
     finally:
         ctx.close()
+
+
+def test_solver_projection_mixed():
+    """The solvers with the mixed projection (kv_set_solver_projection):
+    the Newton correction meets the oracle's residual certificate and equals
+    the FP64 solve's to the solve tolerance, thick-restarted Arnoldi reaches
+    the dense leading eigenvalues, and the workspaces grow by one vector."""
+    from paper_2210_08816_amd import kv
+    print("case mixed solver projection", flush=True)
+    shape = (12, 10, 8)
+    fx = [faces("clustered", n) for n in shape]
+    Gr = 1e4
+    g = O.Grid(*fx, Gr=Gr, Pr=0.71)
+    X0 = O.project(g, S.base_flow(*fx, K=3, amp=0.05, seed=31) + 0.01 * S.perturbation(g.size, 32))
+    ctx = context(fx, Gr, 0.71, X0)
+    try:
+        F = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.residual(F)
+        d64 = torch.empty_like(F)
+        dmx = torch.empty_like(F)
+        ctx.newton_correction(F, d64, tol=1e-10, max_matvec=4000)
+        n64 = ctx.workspace_size(kv.KV_WS_NEWTON)
+        ctx.set_solver_projection(True)
+        assert ctx.workspace_size(kv.KV_WS_NEWTON) - n64 == 8 * g.size
+        info = ctx.newton_correction(F, dmx, tol=1e-10, max_matvec=4000)
+        assert info["status"] == 0 and info["relres"] <= 1e-10, info
+        A = SV.Operator(g, X0)
+        Fo = SV.A_project(A, O.residual(g, X0))
+        d = to_host(dmx)
+        assert A.norm(A(d) + Fo) / A.norm(Fo) <= 1e-9
+        assert O.div_measure(g, d) <= 1e-10
+        assert A.norm(d - to_host(d64)) <= 1e-8 * A.norm(to_host(d64))
+        # Arnoldi with the mixed projection, on a recipe flow small enough for
+        # the dense generalized eigenproblem (even, mirror-symmetric axes)
+        f1 = [faces("clustered", n) for n in (6, 6, 4)]
+        X1 = S.base_flow(*f1, K=2, amp=0.3, seed=21)
+        g1 = O.Grid(*f1, Gr=2e4, Pr=0.71)
+        c1 = context(f1, 2e4, 0.71, X1)
+        try:
+            c1.set_solver_projection(True)
+            vals, res, info = c1.arnoldi_leading_eigs(to_dev(S.perturbation(g1.size, 77)), krylov_dim=40, n_eigs=4,
+                                                      tol=1e-10, max_matvec=40000, keep=16)
+            assert info["converged"], info
+            lam = dense_saddle_eigs(g1, X1)
+            scale = np.max(np.abs(lam[:4]))
+            assert closest(vals, lam[:6]) <= 1e-8 * scale, (vals, lam[:6])
+            assert closest(lam[:4], vals) <= 1e-8 * scale
+        finally:
+            c1.close()
+    finally:
+        ctx.close()
