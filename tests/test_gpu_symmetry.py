@@ -324,3 +324,35 @@ def test_ritz_vectors_at_256():
             q += step
     finally:
         ctx.close()
+
+
+def test_cayley_arnoldi_in_each_class():
+    """The Cayley-transformed thick-restarted Arnoldi restricted to a class
+    (6x6x4 clustered, fully symmetric recipe flow): its values are the dense
+    class-filtered eigenvalues of largest |(lambda - zero)/(lambda - pole)|."""
+    from paper_2210_08816_amd import kv
+    fx = [faces("clustered", n) for n in (6, 6, 4)]
+    g = O.Grid(*fx, Gr=2e4, Pr=0.71)
+    X0 = O.symmetry_project(g, S.base_flow(*fx, K=2, amp=0.3, seed=21), 1, 1)
+    lam, cls = saddle_eigs_by_class(g, X0)
+    ctx = make_ctx(fx)
+    try:
+        ctx.set_base_flow(to_dev(X0))
+        ctx.set_preconditioner(True, 10.0)
+        for c in [(1, 1), (-1, 1), (-1, -1)]:
+            print(f"cayley arnoldi, class {c}", flush=True)
+            ref = np.array([lam[q] for q in range(len(lam)) if cls[q] == c])
+            pole, zero = float(np.max(ref.real)) + 2.0, float(np.max(ref.real)) - 60.0
+            th = (ref - zero) / (ref - pole)
+            mods = np.sort(np.abs(th))[::-1]
+            n_want = 2 if abs(mods[1] - mods[2]) > 1e-9 * mods[1] else 3
+            assert mods[n_want - 1] > 1.02 * mods[n_want], (c, mods[:6])
+            want = ref[np.argsort(-np.abs(th), kind="stable")[:n_want]]
+            ctx.set_spectral_transform(kv.KV_ST_CAYLEY, pole=pole, zero=zero, inner_tol=1e-12, inner_max_matvec=4000)
+            vals, res, info = ctx.arnoldi_leading_eigs(to_dev(S.perturbation(g.size, 77)), krylov_dim=20,
+                                                       n_eigs=n_want, tol=1e-11, max_matvec=2000, keep=8, sym=c)
+            assert info["converged"], (c, info)
+            scale = np.max(np.abs(want))
+            assert closest(vals, want) <= 1e-8 * scale and closest(want, vals) <= 1e-8 * scale, (c, vals, want)
+    finally:
+        ctx.close()
