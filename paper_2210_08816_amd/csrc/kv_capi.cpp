@@ -2070,7 +2070,7 @@ int kv_state_add_cell_increment(kv_ctx* c, const float* cells, const float* cell
 static void hessenberg_keep_last(std::vector<double>& A, int m, std::vector<double>& Z) {
   Z.assign((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) Z[(size_t)i * m + i] = 1.0;
-  std::vector<double> v(m);
+  std::vector<double> v(m), tv;
   for (int i = m - 1; i >= 2; --i) {
     const int L = i;  // coordinates 0..L-1
     double nrm = 0.0;
@@ -2094,12 +2094,18 @@ static void hessenberg_keep_last(std::vector<double>& A, int m, std::vector<doub
         t *= beta;
         for (int j = 0; j < L; ++j) row[j] -= t * v[j];
       }
-    // A <- H A (rows 0..L-1)
-    for (int cc = 0; cc < m; ++cc) {
-      double t = 0.0;
-      for (int j = 0; j < L; ++j) t += v[j] * A[(size_t)j * m + cc];
-      t *= beta;
-      for (int j = 0; j < L; ++j) A[(size_t)j * m + cc] -= t * v[j];
+    // A <- H A (rows 0..L-1): t = v^T A accumulated row by row (contiguous),
+    // then the rank-one update
+    tv.assign(m, 0.0);
+    for (int j = 0; j < L; ++j) {
+      const double* row = A.data() + (size_t)j * m;
+      const double vj = v[j];
+      for (int cc = 0; cc < m; ++cc) tv[cc] += vj * row[cc];
+    }
+    for (int j = 0; j < L; ++j) {
+      double* row = A.data() + (size_t)j * m;
+      const double bv = beta * v[j];
+      for (int cc = 0; cc < m; ++cc) row[cc] -= bv * tv[cc];
     }
     for (int j = 0; j < L - 1; ++j) A[(size_t)i * m + j] = 0.0;
   }

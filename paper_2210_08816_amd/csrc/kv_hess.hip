@@ -51,15 +51,27 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
     // linearly, is taken as converged; its values carry the cluster's own
     // ill-conditioning, eps^(1/p) for p coalescing values)
     const double tol = its < 100 ? eps : 1.4901161193847656e-08;
-    int l = hi;
-    while (l > 0) {
-      double sc = fabs(h(l - 1, l - 1)) + fabs(h(l, l));
-      if (sc == 0.0) sc = anorm;
-      if (fabs(h(l, l - 1)) <= tol * sc) {
-        if (fabs(h(l, l - 1)) > eps * sc) status |= 2;  // deflated by the relaxed test only
+    // the largest l <= hi with a negligible h(l, l-1) (0 if none), 64
+    // candidates per round, one per lane (lane 0 the highest): the reads of a
+    // round are independent instead of one dependent read per candidate
+    int l = 0;
+    for (int top = hi; top > 0; top -= 64) {
+      const int cand = top - lane;
+      bool neg = false, strict = false;
+      if (cand > 0) {
+        double sc = fabs(h(cand - 1, cand - 1)) + fabs(h(cand, cand));
+        if (sc == 0.0) sc = anorm;
+        const double sub = fabs(h(cand, cand - 1));
+        neg = sub <= tol * sc;
+        strict = sub <= eps * sc;
+      }
+      const unsigned long long hit = __ballot(neg);
+      if (hit) {
+        const int first = __ffsll((long long)hit) - 1;
+        l = top - first;
+        if (!((__ballot(strict) >> first) & 1ull)) status |= 2;  // deflated by the relaxed test only
         break;
       }
-      --l;
     }
     if (l == hi) {
       if (lane == 0) {
@@ -211,8 +223,12 @@ __global__ void __launch_bounds__(64) inviter_kernel(const double* __restrict__ 
   cplx* b = ball + (int64_t)q * m;
   __shared__ int piv[512];
   const cplx lam = {lr[q], li[q]};
+  // max |H| over the matrix: a strided maximum per lane, then across the
+  // wave (a maximum is exact in any order)
   double hn = 0.0;
-  for (int e = 0; e < m * m; ++e) hn = fmax(hn, fabs(H[e]));
+  for (int e = lane; e < m * m; e += 64) hn = fmax(hn, fabs(H[e]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) hn = fmax(hn, __shfl_xor(hn, o, 64));
   const double tiny = 1e-15 * (hn > 0.0 ? hn : 1.0);
   // W = H - lambda I
   for (int e = lane; e < m * m; e += 64) {
