@@ -64,3 +64,37 @@ def test_time_steps_keep_a_steady_state():
         assert O.wnorm(w, to_host(X) - Xs) <= 1e-10 * O.wnorm(w, Xs)
     finally:
         ctx.close()
+
+
+def test_time_stepper_reproduces_the_leading_eigenvalue():
+    """16^3 clustered steady state at Gr = 2e7 (continuation from rest):
+    perturbed along the real part of the leading class-(-,+) eigenvector, the
+    time stepper multiplies the perturbation by exp(Re lambda T) over T (one
+    period 2 pi / Im lambda for a complex pair, with the sign flip after half
+    a period; 1 / |lambda| for a real value), as the Arnoldi eigenvalue of the
+    same grid predicts."""
+    from paper_2210_08816_amd import continuation as C
+    from paper_2210_08816_amd import growth
+    from paper_2210_08816_amd import kv
+    print("case growth 16^3", flush=True)
+    f = S.faces_clustered(16)
+    grs = [1e4 * 1.6 ** k for k in range(21) if 1e4 * 1.6 ** k < 2e7] + [2e7]
+    states, infos = C.sweep((f, f, f), grs, max_matvec=20000, max_iter=20, precond_sigma=10.0, log=lambda m: None)
+    assert len(states) == len(grs)
+    X = states[-1]
+    ctx = kv.Context(f, f, f, Gr=2e7, Pr=0.71)
+    try:
+        ctx.set_base_flow(X)
+        v0 = to_dev(S.perturbation(ctx.n, 77))
+        ev = torch.empty(3 * ctx.n, dtype=torch.float64, device="cuda")
+        vals, res, info = ctx.arnoldi_leading_eigs(v0, 60, 2, tol=1e-10, max_matvec=100000, sym=(-1, 1), keep=20,
+                                                   evecs=ev)
+        assert info["converged"], info
+        lam = complex(vals[0])
+        T = 2 * np.pi / lam.imag if lam.imag > 0 else 1.0 / abs(lam.real)
+        steps = int(min(60000, max(2000, np.ceil(T / 0.004))))   # dt <= 0.004 (the explicit advection's limit)
+        out = growth.measure(ctx, X, ev[:ctx.n].clone(), lam, steps, eps=1e-7, log=lambda m: print(m, flush=True))
+        assert abs(out["rate_measured"] - lam.real) <= 2e-3 * abs(lam), out
+        assert abs(out["projection_half_period"] - out["predicted_half_period"]) <= 1e-2 * abs(out["predicted_half_period"]), out
+    finally:
+        ctx.close()
