@@ -17,7 +17,7 @@ import math
 import time
 
 
-def measure(ctx, X, v, lam, steps_per_period, eps=1e-6, log=print):
+def measure(ctx, X, v, lam, steps_per_period, eps=1e-6, log=print, chunk=10000):
     """X: converged steady state (device); v: unit real vector, the real part
     of the eigenvector of lam (device); lam: the eigenvalue (Im >= 0).
     Integrates X + eps v over one period T = 2 pi / Im lam (for a real lam,
@@ -43,9 +43,22 @@ def measure(ctx, X, v, lam, steps_per_period, eps=1e-6, log=print):
     n0 = ctx.dot(d0, d0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.time_steps(Y, Yp, dt, half, start=True)
+    done = [0]
+
+    def advance(k):
+        # in chunks (the same SBDF2 sequence: a call continues from (Y, Yp)),
+        # one progress line per chunk
+        while k > 0:
+            c = min(k, chunk)
+            ctx.time_steps(Y, Yp, dt, c, start=done[0] == 0)
+            done[0] += c
+            k -= c
+            log(f"[growth] {done[0]}/{steps_per_period} steps, |d|/|d0| = "
+                f"{math.sqrt(ctx.dot(pert(), pert()) / n0):.6f}")
+
+    advance(half)
     c_half = ctx.dot(pert(), d0) / n0
-    ctx.time_steps(Y, Yp, dt, steps_per_period - half, start=False)
+    advance(steps_per_period - half)
     dT = pert()
     ratio = math.sqrt(ctx.dot(dT, dT) / n0)
     c_full = ctx.dot(dT, d0) / n0
@@ -113,10 +126,13 @@ def main(argv=None):
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--krylov", type=int, default=200)
     ap.add_argument("--keep", type=int, default=63)
+    ap.add_argument("--tol", type=float, default=1e-8, help="Arnoldi tolerance")
+    ap.add_argument("--max-matvec", type=int, default=200000, help="Arnoldi budget")
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     res = run(n=a.n, grid=a.grid, Gr=a.gr, state=np.load(a.load_state), sym=parse_sym(a.sym)[0],
-              steps_per_period=a.steps_per_period, eps=a.eps, krylov=a.krylov, keep=a.keep,
+              steps_per_period=a.steps_per_period, eps=a.eps, krylov=a.krylov, keep=a.keep, tol=a.tol,
+              max_matvec=a.max_matvec,
               log=lambda m: print(m, flush=True))
     text = json.dumps(res)
     if a.json:
