@@ -163,12 +163,15 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
     for (int k = l - 1; k <= hi - 2; ++k) {
       const int nr = (k < hi - 2) ? 3 : 2;  // reflector size
       // Householder v with (I - tau v v^T)(x,y,z)^T = (beta,0,0)^T, v0 = 1
+      // (no barrier here: x, y, z are in registers before any store below
+      // can be issued, and the entries the row update reads were ordered by
+      // the previous step's second barrier)
       const double nrm = sqrt(x * x + y * y + (nr == 3 ? z * z : 0.0));
-      __syncthreads();
       if (nrm != 0.0) {
         const double beta = (x >= 0.0) ? -nrm : nrm;
         const double v0 = x - beta;
-        const double v1 = y / v0, v2 = (nr == 3) ? z / v0 : 0.0;
+        const double iv0 = 1.0 / v0;
+        const double v1 = y * iv0, v2 = (nr == 3) ? z * iv0 : 0.0;
         const double tau = (beta - x) / beta;
         const int r0 = k + 1;
         // rows r0..r0+nr-1, columns max(k, l)..hi
@@ -192,13 +195,13 @@ __global__ void __launch_bounds__(64) hqr_kernel(double* __restrict__ H, int m, 
         }
         __syncthreads();
         if (k >= l) {
-          // the bulge column below the subdiagonal is now zero
+          // the bulge column below the subdiagonal is now zero (column k is
+          // not read again in this sweep: no barrier)
           if (lane == 0) {
             h(k + 2, k) = 0.0;
             if (nr == 3) h(k + 3, k) = 0.0;
           }
         }
-        __syncthreads();
       }
       if (k + 1 <= hi - 2) {
         x = h(k + 2, k + 1);
