@@ -34,8 +34,16 @@ def log(*a):
 
 def algorithmic_bytes_per_cell_fp64():
     """HBM bytes per cell of one projected Krylov vector if every phase makes
-    one pass: stencil 104, 6 transform passes 96, correction 56."""
+    one pass: the stencil with the divergence fused 104 (read x and X0, write
+    y and the divergence; 96 without the divergence), 6 transform passes 96,
+    correction 56; a separate divergence pass would move 32."""
     return {"stencil": 104.0, "stencil_io": 96.0, "fd": 96.0, "correction": 56.0, "divergence": 32.0}
+
+
+def divergence_fused():
+    """The library's stencil writes the divergence itself unless KV_FUSED_DIV=0
+    (on every grid whose vector fits 32-bit byte offsets, 256^3 included)."""
+    return os.environ.get("KV_FUSED_DIV", "1") != "0"
 
 
 def dense_transform_model_s(n_cells, n_axis):
@@ -443,13 +451,16 @@ def main():
                              % ("float" if mixed else "double"),
                    "launch_ms": round(fd_launch_ms, 5), "launches_per_step": round(6 * sweeps, 2)}
         bpc = algorithmic_bytes_per_cell_fp64()
-        st_bytes = bpc["stencil_io"] * n_cells
+        fused = divergence_fused() and not mixed
+        st_bytes = (bpc["stencil"] if fused else bpc["stencil_io"]) * n_cells
         st_ach = st_bytes / (per_vec[0] * 1e-3) / 1e9 if per_vec[0] else 0.0
+        st_kernel = "operator_divergence_kernel" if fused else "operator_tiled_kernel"
         roof_st = {"bound": "hbm", "achieved": round(st_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                    "frac": round(st_ach / HBM_PEAK_GBS, 4),
-                   "traffic": profiled_traffic("operator_tiled_kernel", "kv_stencil.hip"),
-                   "kernel": "operator_tiled_kernel (J x stencil)", "launch_ms": round(per_vec[0], 5),
-                   "launches_per_step": 1}
+                   "traffic": profiled_traffic(st_kernel, "kv_stencil.hip"),
+                   "kernel": st_kernel + (" (J x stencil with the net-flux divergence fused)" if fused
+                                          else " (J x stencil)"),
+                   "launch_ms": round(per_vec[0], 5), "launches_per_step": 1}
         if per_vec[2] >= per_vec[0]:
             roofline, secondary = roof_fd, roof_st
         else:
@@ -462,7 +473,10 @@ def main():
             # fused correction + divergence (read y 24, p 4; write y 24, b 4)
             t_roof = (96.0 + 28.0 + sweeps * (48.0 + 56.0)) * n_cells / (HBM_PEAK_GBS * 1e9)
         else:
-            t_roof = ((bpc["stencil"] + bpc["divergence"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
+            # the method's minimum: the fused stencil (104 B per cell) and the
+            # correction (56 B) at the HBM peak, six transform passes at the
+            # FP64 matrix-core peak (with or without the fusion enabled)
+            t_roof = ((bpc["stencil"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
                       + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
             # the same step priced as the method without the even/odd split
             t_dense = dense_transform_model_s(n_cells, spec["n"])
@@ -472,6 +486,9 @@ def main():
                 "roofline": roofline,
                 "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / t_meas, 4), **extra,
                 "sweeps_per_vector": round(sweeps, 3),
+                "divergence_fused": fused,
+                # with the fusion, "stencil" includes the divergence and
+                # "divergence" is the pass that completes the tiles' edge cells
                 "phases_ms_per_vector": {"stencil": round(per_vec[0], 5), "divergence": round(per_vec[1], 5),
                                          "fd_transforms": round(per_vec[2], 5),
                                          "correction": round(per_vec[3], 5)}}

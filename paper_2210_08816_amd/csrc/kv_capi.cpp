@@ -223,12 +223,8 @@ struct PhaseMark {
   }
 };
 
-int project_inplace(kv_ctx* c, double* y) {
-  if (c->solve_mixed) return kv::project_mixed_with(c, y, nullptr, nullptr, c->ymix_solve);
-  {
-    PhaseMark pm(c, 1);
-    HIPCHK(c, launch_scaled_divergence(c, y, c->cellA));
-  }
+// The FP64 projection from the scaled divergence of y already in cellA.
+int project_from_divergence(kv_ctx* c, double* y) {
   {
     PhaseMark pm(c, 2);
     HIPCHK(c, launch_fd_solve(c, c->cellA, c->cellA));
@@ -238,6 +234,15 @@ int project_inplace(kv_ctx* c, double* y) {
     HIPCHK(c, launch_gradient_correction(c, c->cellA, y));
   }
   return KV_OK;
+}
+
+int project_inplace(kv_ctx* c, double* y) {
+  if (c->solve_mixed) return kv::project_mixed_with(c, y, nullptr, nullptr, c->ymix_solve);
+  {
+    PhaseMark pm(c, 1);
+    HIPCHK(c, launch_scaled_divergence(c, y, c->cellA));
+  }
+  return project_from_divergence(c, y);
 }
 
 // Mixed form of the projection: FP32-storage fast diagonalization on the
@@ -333,6 +338,32 @@ int apply_operator(kv_ctx* c, const double* x, double* y) {
   return KV_OK;
 }
 
+// The stencil writes the scaled divergence of its output itself unless
+// KV_FUSED_DIV=0 (read at every call, for tests and measurements), where
+// the separate divergence pass runs.
+bool fused_divergence_on(const kv_ctx* c) {
+  const char* e = getenv("KV_FUSED_DIV");
+  return !(e && std::strcmp(e, "0") == 0) && operator_fuses_divergence(c);
+}
+
+// y = P J(X0) x in FP64 (the mixed projection when the solvers use it)
+int apply_projected(kv_ctx* c, const double* x, double* y) {
+  if (c->solve_mixed || !fused_divergence_on(c)) {
+    int rc = apply_operator(c, x, y);
+    if (rc) return rc;
+    return project_inplace(c, y);
+  }
+  {
+    PhaseMark pm(c, 0);
+    HIPCHK(c, launch_operator_divergence(c, c->X0, x, y, c->cellA));
+  }
+  {
+    PhaseMark pm(c, 1);
+    HIPCHK(c, launch_divergence_edges(c, y, c->cellA));
+  }
+  return project_from_divergence(c, y);
+}
+
 // y <- (I - Q Q^T W) y over the locked vectors Q (classical Gram-Schmidt
 // twice, no host synchronization); nothing while none are locked.
 int deflate(kv_ctx* c, double* y) {
@@ -344,9 +375,8 @@ int deflate(kv_ctx* c, double* y) {
 }
 
 int matvec(kv_ctx* c, const double* x, double* y) {
-  int rc = apply_operator(c, x, y);
+  int rc = apply_projected(c, x, y);
   if (rc) return rc;
-  if ((rc = project_inplace(c, y))) return rc;
   if (c->sym_ref || c->sym_rot) HIPCHK(c, launch_symmetry_class(c, y, y, c->sym_ref, c->sym_rot));
   return deflate(c, y);
 }
@@ -1175,12 +1205,10 @@ int kv_apply_jacobian(kv_ctx* c, const double* x, double* y, unsigned flags) {
   if (!x || !y || x == y) return fail(c, KV_EINVAL, "x and y must be distinct device vectors");
   if (flags & ~(unsigned)(KV_PROJECT | KV_MIXED)) return fail(c, KV_EINVAL, "unsupported flags");
   if (!c->has_base) return fail(c, KV_ESTATE, "no base flow");
+  if ((flags & KV_PROJECT) && !((flags & KV_MIXED) && mixed_ok(c))) return apply_projected(c, x, y);
   int rc = apply_operator(c, x, y);
   if (rc) return rc;
-  if (flags & KV_PROJECT) {
-    if ((flags & KV_MIXED) && mixed_ok(c)) return project_mixed(c, y, nullptr, nullptr);
-    return project_inplace(c, y);
-  }
+  if (flags & KV_PROJECT) return project_mixed(c, y, nullptr, nullptr);
   return KV_OK;
 }
 

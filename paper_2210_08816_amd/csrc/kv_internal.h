@@ -132,6 +132,14 @@ namespace kv {
 hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode);
 // cellA = V^1/2 D y  (net face flux over sqrt of the cell volume)
 hipError_t launch_scaled_divergence(const kv_ctx* c, const double* y, double* out);
+// Whether the tiled stencil can write the scaled divergence of its output
+// (the grid fits its 32-bit offsets and its LDS request is granted).
+bool operator_fuses_divergence(const kv_ctx* c);
+// y = J(X0) x, and div = V^1/2 D y except on the tiles' edge cells, which
+// hold the partial unscaled net flux until launch_divergence_edges completes
+// them (hipErrorNotSupported where the stencil cannot fuse).
+hipError_t launch_operator_divergence(const kv_ctx* c, const double* X0, const double* x, double* y, double* div);
+hipError_t launch_divergence_edges(const kv_ctx* c, const double* y, double* div);
 // p = L^+ (V^-1/2 in) by fast diagonalization; in and out are cell fields.
 // in is overwritten (used as scratch); result in out.
 hipError_t launch_fd_solve(const kv_ctx* c, double* in, double* out);

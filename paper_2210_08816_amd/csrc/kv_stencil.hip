@@ -14,6 +14,8 @@
 // Wall values: no-slip (velocities 0) at half-cell distance, T = +-1/2 on
 // the x-walls for N (Eq. 4 in the centred variable), 0 for J, and no flux
 // through the y- and z-walls (Eqs. 5-6).
+#include <type_traits>
+
 #include "kv_internal.h"
 
 namespace kv {
@@ -49,9 +51,12 @@ struct GlobalAcc {
 // s = 0 for the base flow and 1 for the perturbation, zero on walls.
 // Outputs: plain stores (one-cell kernel) or raw buffer stores with 32-bit
 // offsets (tiled kernel).
+// face(c, v) hands the value of the cell's own face of component c (u, v,
+// w) to an output that also forms the cell's net flux; a no-op otherwise.
 struct PtrOut {
   double* y;
   __device__ __forceinline__ void put(int64_t idx, double v) const { y[idx] = v; }
+  __device__ __forceinline__ void face(int, double) const {}
 };
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 struct BufOut {
@@ -60,6 +65,15 @@ struct BufOut {
   __device__ __forceinline__ void put(int64_t idx, double v) const {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)idx * 8, 0, 0);
   }
+  __device__ __forceinline__ void face(int, double) const {}
+};
+// Buffer stores that also put the cell's low-face velocities into LDS
+// (fl: u, v, w of the block's 256 cells; cleared beforehand, so a face the
+// cell does not own, on a wall or outside the domain, reads as zero).  In
+// LDS they occupy no registers while the rest of the point is computed.
+struct FaceOut : BufOut {
+  double* fl;
+  __device__ __forceinline__ void face(int c, double v) const { fl[c * 256 + threadIdx.x] = v; }
 };
 
 // The metrics one cell needs along one axis, held in registers: at the
@@ -159,7 +173,9 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     double lap = ((up - uc) * MX.ih0 - (uc - um) * MX.ihm) * MX.id0;
     lap += ((uN - uc) * MY.id1 - (uc - uS) * MY.id0) * MY.ih0;
     lap += (gT - gB) * MZ.ih0;
-    y.put(g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1), -s * adv + g.nu * lap);
+    const double r = -s * adv + g.nu * lap;
+    y.put(g.ou + ((int64_t)k * ny + j) * (nx - 1) + (i - 1), r);
+    y.face(0, r);
   }
 
   // ---------------- v on y-face j ----------------
@@ -218,7 +234,9 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     double lap = ((vp - vc) * MY.ih0 - (vc - vm) * MY.ihm) * MY.id0;
     lap += ((vE - vc) * MX.id1 - (vc - vW) * MX.id0) * MX.ih0;
     lap += (gT - gB) * MZ.ih0;
-    y.put(g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i, -s * adv + g.nu * lap);
+    const double r = -s * adv + g.nu * lap;
+    y.put(g.ov + ((int64_t)k * (ny - 1) + (j - 1)) * nx + i, r);
+    y.face(1, r);
   }
 
   // ---------------- w on z-face k ----------------
@@ -282,7 +300,9 @@ __device__ __forceinline__ void point(const Grid& g, const Acc& A, int i, int j,
     lap += ((wE - wc) * MX.id1 - (wc - wW) * MX.id0) * MX.ih0;
     lap += ((wN - wc) * MY.id1 - (wc - wS) * MY.id0) * MY.ih0;
     const double buoy = zl * A.T(1, i, j, k - 1) + zh * A.T(1, i, j, k);
-    y.put(g.ow + ((int64_t)(k - 1) * ny + j) * nx + i, -s * adv + g.nu * lap + g.beta * buoy);
+    const double r = -s * adv + g.nu * lap + g.beta * buoy;
+    y.put(g.ow + ((int64_t)(k - 1) * ny + j) * nx + i, r);
+    y.face(2, r);
   }
 
   // ---------------- T at the cell centre ----------------
@@ -530,10 +550,20 @@ __device__ __forceinline__ void store_plane(double* lds, const FetchMap& m, int 
   }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const double* __restrict__ B,
-                                                             const double* __restrict__ x, double* __restrict__ y,
-                                                             int tiles_x, int tiles_y, int chunks, int kc) {
+// DIV: the kernel also writes the net face flux of y over each cell into dv
+// (the divergence that the projection starts from, Eq. 2 integrated over
+// the cell), scaled by V^-1/2 like scaled_divergence_kernel.  A cell's own
+// faces are the low ones it computes; its high faces come from the next
+// lane (u), from the next wave through LDS (v) and from the next plane of
+// the march (w).  Where that neighbour lies in another block (the last
+// column of a tile, its last row, the last plane of a z-chunk) the cell
+// gets the unscaled partial flux instead, completed by
+// divergence_edges_kernel.
+template <int MODE, bool DIV>
+__device__ __forceinline__ void operator_tiled_body(const Grid& g, const double* __restrict__ B,
+                                                    const double* __restrict__ x, double* __restrict__ y,
+                                                    int tiles_x, int tiles_y, int chunks, int kc,
+                                                    double* __restrict__ dv) {
   constexpr int NF = MODE ? 4 : 8;
   constexpr int NSF = NF / 4;
   extern __shared__ double lds[];
@@ -555,7 +585,27 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
   ZCarry zc;
   const FetchMap fm = fetch_map(g, i0, j0);
   const __amdgpu_buffer_rsrc_t rB = vec_rsrc(B, g.n), rx = vec_rsrc(x, g.n);
-  BufOut out{vec_rsrc(y, g.n), &g};
+  // DIV: the faces of the block's cells in LDS, and there too the net flux
+  // over the volume of each thread's cell below, less its top face's term
+  double* fl = lds + (MODE ? 7 : 14) * PLANE;
+  typename std::conditional<DIV, FaceOut, BufOut>::type out;
+  out.r = vec_rsrc(y, g.n);
+  out.g = &g;
+  if constexpr (DIV) out.fl = fl;
+  const int lane = threadIdx.x % TX, row = threadIdx.x / TX;
+  const bool ex = lane == TX - 1 && i + 1 < g.nx, ey = row == TY - 1 && j + 1 < g.ny;
+  const __amdgpu_buffer_rsrc_t rd = vec_rsrc(dv, (int64_t)g.nx * g.ny * g.nz);
+  // the column's sqrt(h_x), read back from LDS (fl[1024 + lane]) where it is
+  // used rather than held in registers
+  if (DIV && row == 0) fl[1024 + lane] = g.ax[0].sq[min(i, g.nx - 1)];
+  // cell (i, j, kk) of dv: V^-1/2 (net flux) = sqrt(V) (net flux / V), or the
+  // partial net flux / V on tile edges
+  auto emit = [&](int kk, double net) {
+    if (i >= g.nx || j >= g.ny) return;
+    const bool edge = ex || ey || (kk == k1 - 1 && k1 < g.nz);
+    const double v = edge ? net : net * (fl[1024 + lane] * g.ax[1].sq[j] * g.ax[2].sq[kk]);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rd, ((kk * g.ny + j) * g.nx + i) * 8, 0, 0);
+  };
   TileAcc<NF> A;
   A.lds = lds;
   A.ic = i;
@@ -593,6 +643,7 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
       wk[s] = A.ld(2, s, k, i, j);
       tk[s] = A.ld(3, s, k, i, j);
     }
+    if constexpr (DIV) fl[threadIdx.x] = fl[256 + threadIdx.x] = fl[512 + threadIdx.x] = 0.0;
     if (i < g.nx && j < g.ny) point<MODE>(g, A, i, j, k, MX, MY, load_met(g.ax[2], k), out, zc, k == k0);
     __syncthreads();
     if (more) {
@@ -611,8 +662,40 @@ __global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const doubl
         A.tp[s] = tk[s];
       }
     }
+    if constexpr (DIV) {
+      // (after the plane shift, where the fewest registers are live) u on
+      // the east face is the next lane's own (zero past the domain or on
+      // the tile's last column), v on the north face the next row's
+      const int t = threadIdx.x;
+      const double uo = fl[t], uh = lane < TX - 1 ? fl[t + 1] : 0.0;
+      const double vo = fl[256 + t], vh = row < TY - 1 ? fl[256 + t + TX] : 0.0;
+      const double wo = fl[512 + t];
+      // the carry lives in LDS between iterations (fl[768 + t], own slot)
+      if (k > k0) emit(k - 1, fl[768 + t] + wo * g.ax[2].ih[k - 1]);
+      fl[768 + t] = (uh - uo) * MX.ih0 + (vh - vo) * MY.ih0 - wo * g.ax[2].ih[k];
+    }
     __syncthreads();
   }
+  // the chunk's last cell: its top face is the wall (w = 0) or the next
+  // chunk's first plane
+  if constexpr (DIV) emit(k1 - 1, fl[768 + threadIdx.x]);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) operator_tiled_kernel(Grid g, const double* __restrict__ B,
+                                                             const double* __restrict__ x, double* __restrict__ y,
+                                                             int tiles_x, int tiles_y, int chunks, int kc) {
+  operator_tiled_body<MODE, false>(g, B, x, y, tiles_x, tiles_y, chunks, kc, nullptr);
+}
+
+// y = J(X0) x with the scaled divergence of y in dv.  Three waves per SIMD
+// (at most 168 VGPRs) are asked for explicitly: left alone, the compiler
+// gives the fused kernel 174 and the CU only two blocks.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+operator_divergence_kernel(Grid g, const double* __restrict__ B, const double* __restrict__ x,
+                           double* __restrict__ y, int tiles_x, int tiles_y, int chunks, int kc,
+                           double* __restrict__ dv) {
+  operator_tiled_body<0, true>(g, B, x, y, tiles_x, tiles_y, chunks, kc, dv);
 }
 
 // Column-marching kernels: a (64, 4) block owns a tile of (x, y) columns
@@ -648,6 +731,55 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
     out[((int64_t)k * g.ny + j) * g.nx + i] = (OutT)(net * (sxy * AZ.isq[k]));
     wlo = whi;
   }
+}
+
+// Index q of the values in [0, n) that are not of the form p m + p - 1,
+// m < c (those are the first c such values).
+__device__ __forceinline__ int skip_edges(int q, int c, int p) {
+  return q < (p - 1) * c ? (q / (p - 1)) * p + q % (p - 1) : p * c + (q - (p - 1) * c);
+}
+
+// Completes the cells the fused stencil left with a partial net flux: adds
+// u on the east face of a tile's last column (i = 64 m + 63), v on the north
+// face of its last row (j = 4 m + 3), w on the top face of a z-chunk's last
+// plane (k = kc m + kc - 1), each where that face is inside the domain, then
+// scales by V^-1/2.  The threads cover three disjoint sets: every cell of the
+// edge rows (n1), the edge columns' cells in the other rows (n2), and the
+// chunk-end planes' cells in neither (n3); cx, cy, cz count the edge columns,
+// rows and planes.
+__global__ void __launch_bounds__(256) divergence_edges_kernel(Grid g, const double* __restrict__ y,
+                                                               double* __restrict__ dv, int kc, int cx, int cy,
+                                                               int64_t n1, int64_t n2, int64_t n3) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < n1) {
+    i = (int)(t % nx);
+    const int64_t r = t / nx;
+    j = 4 * (int)(r % cy) + 3;
+    k = (int)(r / cy);
+  } else if ((t -= n1) < n2) {
+    i = 64 * (int)(t % cx) + 63;
+    const int64_t r = t / cx;
+    j = skip_edges((int)(r % (ny - cy)), cy, 4);
+    k = (int)(r / (ny - cy));
+  } else if ((t -= n2) < n3) {
+    i = skip_edges((int)(t % (nx - cx)), cx, 64);
+    const int64_t r = t / (nx - cx);
+    j = skip_edges((int)(r % (ny - cy)), cy, 4);
+    k = kc * (int)(r / (ny - cy)) + kc - 1;
+  } else {
+    return;
+  }
+  const Axis& AX = g.ax[0];
+  const Axis& AY = g.ax[1];
+  const Axis& AZ = g.ax[2];
+  const int64_t cell = ((int64_t)k * ny + j) * nx + i;
+  double net = dv[cell];  // net flux / V, less the missing faces' terms
+  if (i % 64 == 63 && i + 1 < nx) net += Uat(y, g, i + 1, j, k) * AX.ih[i];
+  if (j % 4 == 3 && j + 1 < ny) net += Vat(y, g, i, j + 1, k) * AY.ih[j];
+  if (k % kc == kc - 1 && k + 1 < nz) net += Wat(y, g, i, j, k + 1) * AZ.ih[k];
+  dv[cell] = net * (AX.sq[i] * AY.sq[j] * AZ.sq[k]);
 }
 
 __device__ __forceinline__ double fin_abs(double v);
@@ -929,38 +1061,92 @@ inline dim3 march_grid(const Grid& g) {
 
 }  // namespace
 
+namespace {
+
+// Launch shape of the tiled stencil: tiles, z-chunk and (padded) block count.
+struct TiledShape {
+  int tx, ty, kc, ch;
+  unsigned blocks;
+};
+
+TiledShape tiled_shape(const Grid& g) {
+  TiledShape t;
+  // z-chunk: 32 planes, shortened on small grids until about 1024 blocks
+  // exist (four per CU; one block is 4 waves), but not below 4 planes, since
+  // every chunk also loads the plane below and the two above it
+  t.tx = (g.nx + TX - 1) / TX;
+  t.ty = (g.ny + TY - 1) / TY;
+  t.kc = 32;
+  while (t.kc > 4 && (int64_t)t.tx * t.ty * ((g.nz + t.kc - 1) / t.kc) < 1024) t.kc /= 2;
+  t.ch = (g.nz + t.kc - 1) / t.kc;
+  const int64_t total = (int64_t)t.tx * t.ty * t.ch;
+  t.blocks = (unsigned)(((total + 7) / 8) * 8);
+  return t;
+}
+
+// LDS per block: 14 planes for J, 7 for N, plus for the fused divergence
+// the u, v, w faces of the tile, each thread's carried flux and the
+// columns' sqrt(h_x) (51.8 KB: three blocks still share a CU's 160 KB)
+constexpr size_t kLdsJ = 14 * PLANE * sizeof(double), kLdsN = 7 * PLANE * sizeof(double);
+constexpr size_t kLdsJDiv = kLdsJ + (4 * TX * TY + TX) * sizeof(double);
+
+// raise the dynamic-LDS limit of a kernel explicitly, whatever its default
+// (once per kernel)
+template <const void* (*K)()>
+bool tiled_lds_ok(size_t bytes) {
+  static int ok = -1;
+  if (ok < 0) ok = hipFuncSetAttribute(K(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+  return ok == 1;
+}
+const void* kernel_j() { return reinterpret_cast<const void*>(&operator_tiled_kernel<0>); }
+const void* kernel_jdiv() { return reinterpret_cast<const void*>(&operator_divergence_kernel); }
+
+// the tiled kernels address a vector with 32-bit byte offsets
+bool tiled_fits(const Grid& g) { return g.n * 8 < ((int64_t)1 << 31); }
+
+}  // namespace
+
 hipError_t launch_operator(const kv_ctx* c, const double* X0, const double* x, double* y, int mode) {
   const Grid& g = c->g;
-  if (g.n * 8 >= ((int64_t)1 << 31)) {  // 32-bit byte offsets: fall back to the one-cell-per-thread kernel
+  if (!tiled_fits(g) || (mode == 0 && !tiled_lds_ok<kernel_j>(kLdsJ))) {
+    // the one-cell-per-thread kernel
     if (mode == 0)
       operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
     else
       operator_kernel<1><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, x, x, y);
     return hipGetLastError();
   }
-  // z-chunk: 32 planes, shortened on small grids until about 1024 blocks
-  // exist (four per CU; one block is 4 waves), but not below 4 planes, since
-  // every chunk also loads the plane below and the two above it
-  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
-  int kc = 32;
-  while (kc > 4 && (int64_t)tx * ty * ((g.nz + kc - 1) / kc) < 1024) kc /= 2;
-  const int ch = (g.nz + kc - 1) / kc;
-  const int64_t total = (int64_t)tx * ty * ch;
-  const unsigned blocks = (unsigned)(((total + 7) / 8) * 8);
-  const size_t lds0 = 14 * PLANE * sizeof(double), lds1 = 7 * PLANE * sizeof(double);
-  // raise the dynamic-LDS limit explicitly, whatever its default
-  static int lds_ok = -1;
-  if (lds_ok < 0)
-    lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&operator_tiled_kernel<0>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds0) == hipSuccess;
-  if (mode == 0) {
-    if (lds_ok)
-      operator_tiled_kernel<0><<<blocks, 256, lds0, c->stream>>>(g, X0, x, y, tx, ty, ch, kc);
-    else
-      operator_kernel<0><<<cell_grid(g), cell_block(g), 0, c->stream>>>(g, X0, x, y);
-  } else {
-    operator_tiled_kernel<1><<<blocks, 256, lds1, c->stream>>>(g, x, x, y, tx, ty, ch, kc);
-  }
+  const TiledShape t = tiled_shape(g);
+  if (mode == 0)
+    operator_tiled_kernel<0><<<t.blocks, 256, kLdsJ, c->stream>>>(g, X0, x, y, t.tx, t.ty, t.ch, t.kc);
+  else
+    operator_tiled_kernel<1><<<t.blocks, 256, kLdsN, c->stream>>>(g, x, x, y, t.tx, t.ty, t.ch, t.kc);
+  return hipGetLastError();
+}
+
+bool operator_fuses_divergence(const kv_ctx* c) {
+  return tiled_fits(c->g) && tiled_lds_ok<kernel_jdiv>(kLdsJDiv);
+}
+
+hipError_t launch_operator_divergence(const kv_ctx* c, const double* X0, const double* x, double* y,
+                                      double* div) {
+  const Grid& g = c->g;
+  if (!operator_fuses_divergence(c)) return hipErrorNotSupported;
+  const TiledShape t = tiled_shape(g);
+  operator_divergence_kernel<<<t.blocks, 256, kLdsJDiv, c->stream>>>(g, X0, x, y, t.tx, t.ty, t.ch, t.kc, div);
+  return hipGetLastError();
+}
+
+hipError_t launch_divergence_edges(const kv_ctx* c, const double* y, double* div) {
+  const Grid& g = c->g;
+  const int kc = tiled_shape(g).kc;
+  const int cx = (g.nx - 1) / TX, cy = (g.ny - 1) / TY, cz = (g.nz - 1) / kc;
+  const int64_t n1 = (int64_t)g.nx * cy * g.nz, n2 = (int64_t)cx * (g.ny - cy) * g.nz,
+                n3 = (int64_t)(g.nx - cx) * (g.ny - cy) * cz;
+  const int64_t total = n1 + n2 + n3;
+  if (total == 0) return hipSuccess;
+  divergence_edges_kernel<<<(unsigned)((total + 255) / 256), 256, 0, c->stream>>>(g, y, div, kc, cx, cy, n1, n2,
+                                                                                  n3);
   return hipGetLastError();
 }
 

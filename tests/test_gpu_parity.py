@@ -62,6 +62,34 @@ def test_projected_jacobian(kind, shape, Gr, K, amp):
         assert O.div_measure(g, got) < 1e-11
 
 
+# The stencil writes the divergence that the projection starts from, partial
+# on the cells whose high faces another block computes (a tile's last
+# column and row, a z-chunk's last plane), which a second pass completes;
+# KV_FUSED_DIV=0 selects the separate divergence pass instead.  Both against
+# the oracle, and against each other element by element, on grids with x-tile
+# edges (nx > 64), y-tile edges, z-chunk ends (4-plane chunks on grids this
+# small) and ragged tails.
+FUSED_GRIDS = [GRIDS[2], ("clustered", (130, 21, 37), 4e7, 3, 0.1), ("uniform", (65, 5, 9), 1e5, 2, 0.1)]
+
+
+@pytest.mark.parametrize("kind,shape,Gr,K,amp", FUSED_GRIDS)
+def test_fused_divergence_matches_separate_pass(monkeypatch, kind, shape, Gr, K, amp):
+    print(f"case fused divergence {kind} {shape}", flush=True)
+    g, X0, ctx = make(kind, shape, Gr, K, amp)
+    x = S.perturbation(g.size, 1234)
+    ref = O.apply_jacobian(g, X0, x)
+    got = {}
+    for flag in ("1", "0"):
+        monkeypatch.setenv("KV_FUSED_DIV", flag)
+        y = torch.empty(g.size, dtype=torch.float64, device="cuda")
+        ctx.apply_jacobian(to_dev(x), y, project=True)
+        got[flag] = to_host(y)
+        assert_parity(g, got[flag], ref, TOL64, label=f"PJ KV_FUSED_DIV={flag}")
+        assert O.div_measure(g, got[flag]) < 1e-11
+    for a, b in zip(g.unpack(got["1"]), g.unpack(got["0"])):
+        assert np.max(np.abs(a - b)) <= 1e-13 * max(np.max(np.abs(b)), 1e-300)
+
+
 @pytest.mark.parametrize("kind,shape,Gr,K,amp", GRIDS[:3])
 def test_project_and_divergence(kind, shape, Gr, K, amp):
     g, X0, ctx = make(kind, shape, Gr, K, amp)
