@@ -733,43 +733,42 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
   }
 }
 
-// Index q of the values in [0, n) that are not of the form p m + p - 1,
-// m < c (those are the first c such values).
-__device__ __forceinline__ int skip_edges(int q, int c, int p) {
-  return q < (p - 1) * c ? (q / (p - 1)) * p + q % (p - 1) : p * c + (q - (p - 1) * c);
-}
-
 // Completes the cells the fused stencil left with a partial net flux: adds
 // u on the east face of a tile's last column (i = 64 m + 63), v on the north
 // face of its last row (j = 4 m + 3), w on the top face of a z-chunk's last
 // plane (k = kc m + kc - 1), each where that face is inside the domain, then
-// scales by V^-1/2.  The threads cover three disjoint sets: every cell of the
-// edge rows (n1), the edge columns' cells in the other rows (n2), and the
-// chunk-end planes' cells in neither (n3); cx, cy, cz count the edge columns,
-// rows and planes.
+// scales by sqrt(V).  Three disjoint sets of blocks: every cell of the edge
+// rows (b1 blocks: 256 cells of a row each), the edge columns' cells in the
+// other rows (b2: 256 rows of a column), and the chunk-end planes' cells in
+// neither (the rest: 256 cells of a row).  Block indices are split with
+// wave-uniform arithmetic; cx, cy, cz count the edge columns, rows and planes.
 __global__ void __launch_bounds__(256) divergence_edges_kernel(Grid g, const double* __restrict__ y,
                                                                double* __restrict__ dv, int kc, int cx, int cy,
-                                                               int64_t n1, int64_t n2, int64_t n3) {
+                                                               unsigned b1, unsigned b2) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned nbx = (unsigned)(nx + 255) / 256, nby = (unsigned)(ny + 255) / 256;
+  unsigned b = blockIdx.x;
+  const int t = threadIdx.x;
   int i, j, k;
-  if (t < n1) {
-    i = (int)(t % nx);
-    const int64_t r = t / nx;
-    j = 4 * (int)(r % cy) + 3;
-    k = (int)(r / cy);
-  } else if ((t -= n1) < n2) {
-    i = 64 * (int)(t % cx) + 63;
-    const int64_t r = t / cx;
-    j = skip_edges((int)(r % (ny - cy)), cy, 4);
-    k = (int)(r / (ny - cy));
-  } else if ((t -= n2) < n3) {
-    i = skip_edges((int)(t % (nx - cx)), cx, 64);
-    const int64_t r = t / (nx - cx);
-    j = skip_edges((int)(r % (ny - cy)), cy, 4);
-    k = kc * (int)(r / (ny - cy)) + kc - 1;
+  if (b < b1) {
+    i = (int)(b % nbx) * 256 + t;
+    b /= nbx;
+    j = 4 * (int)(b % (unsigned)cy) + 3;
+    k = (int)(b / (unsigned)cy);
+    if (i >= nx) return;
+  } else if ((b -= b1) < b2) {
+    i = 64 * (int)(b % (unsigned)cx) + 63;
+    b /= (unsigned)cx;
+    j = (int)(b % nby) * 256 + t;
+    k = (int)(b / nby);
+    if (j >= ny || (j % 4 == 3 && j + 1 < ny)) return;
   } else {
-    return;
+    b -= b2;
+    i = (int)(b % nbx) * 256 + t;
+    b /= nbx;
+    j = (int)(b % (unsigned)ny);
+    k = kc * (int)(b / (unsigned)ny) + kc - 1;
+    if (i >= nx || (j % 4 == 3 && j + 1 < ny) || (i % 64 == 63 && i + 1 < nx)) return;
   }
   const Axis& AX = g.ax[0];
   const Axis& AY = g.ax[1];
@@ -1141,12 +1140,13 @@ hipError_t launch_divergence_edges(const kv_ctx* c, const double* y, double* div
   const Grid& g = c->g;
   const int kc = tiled_shape(g).kc;
   const int cx = (g.nx - 1) / TX, cy = (g.ny - 1) / TY, cz = (g.nz - 1) / kc;
-  const int64_t n1 = (int64_t)g.nx * cy * g.nz, n2 = (int64_t)cx * (g.ny - cy) * g.nz,
-                n3 = (int64_t)(g.nx - cx) * (g.ny - cy) * cz;
-  const int64_t total = n1 + n2 + n3;
-  if (total == 0) return hipSuccess;
-  divergence_edges_kernel<<<(unsigned)((total + 255) / 256), 256, 0, c->stream>>>(g, y, div, kc, cx, cy, n1, n2,
-                                                                                  n3);
+  const int64_t nbx = (g.nx + 255) / 256, nby = (g.ny + 255) / 256;
+  const int64_t b1 = nbx * cy * g.nz, b2 = (int64_t)cx * nby * g.nz, b3 = nbx * g.ny * cz;
+  const int64_t blocks = b1 + b2 + b3;
+  if (blocks == 0) return hipSuccess;
+  if (blocks >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  divergence_edges_kernel<<<(unsigned)blocks, 256, 0, c->stream>>>(g, y, div, kc, cx, cy, (unsigned)b1,
+                                                                   (unsigned)b2);
   return hipGetLastError();
 }
 
