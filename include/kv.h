@@ -146,7 +146,9 @@ int kv_residual(kv_ctx* ctx, double* F, double* norm);
 /* y = J(X0) x, or y = P J(X0) x when flags has KV_PROJECT: one Krylov vector
  * of the paper's Newton and Arnoldi iterations (Sec. 3: divergence free and
  * satisfying all boundary conditions).  x, y: device, n values, must not
- * overlap. */
+ * overlap.  With KV_PROJECT (FP64 form) the stencil also writes the scaled
+ * net-flux divergence V^1/2 D y the projection starts from (Eq. 2 over each
+ * cell). */
 int kv_apply_jacobian(kv_ctx* ctx, const double* x, double* y, unsigned flags);
 
 /* In place y <- P y (velocity block; T unchanged).  div_max (host, may be
@@ -471,7 +473,10 @@ int kv_state_add_cell_increment(kv_ctx* ctx, const float* cells, const float* ce
  * returned (after synchronizing the stream) in ms[0..4) (host, may be NULL):
  * stencil, divergence, fast-diagonalization transforms (6 GEMM passes per
  * projection), gradient correction; calls[0..2) (host, may be NULL): number of
- * stencil applications and of projections measured. */
+ * stencil applications and of projections measured.  For P J x the stencil
+ * writes the divergence of its output itself (unless the environment sets
+ * KV_FUSED_DIV=0), so "stencil" includes it and "divergence" is the pass
+ * that completes the cells on the stencil's tile edges. */
 int kv_timing(kv_ctx* ctx, int enable, double ms[4], int calls[2]);
 
 /* Message of the last failed call on ctx (static text if ctx is NULL). */
