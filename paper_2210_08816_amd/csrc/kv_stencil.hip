@@ -397,6 +397,7 @@ __global__ void __launch_bounds__(256) operator_kernel(Grid g, const double* __r
 // one-cell halo in x and y, in LDS and registers; each plane is loaded once,
 // as coalesced x-rows, and every output row is written once.
 constexpr int TX = 64, TY = 4;
+static_assert(TX * TY == 256, "one tile cell per thread of a 256-thread block (FaceOut's LDS slots)");
 constexpr int PX = TX + 2, PY = TY + 2, PLANE = PX * PY;
 
 // LDS holds only what other columns read: every field on plane k; u and v
@@ -557,8 +558,8 @@ __device__ __forceinline__ void store_plane(double* lds, const FetchMap& m, int 
 // lane (u), from the next wave through LDS (v) and from the next plane of
 // the march (w).  Where that neighbour lies in another block (the last
 // column of a tile, its last row, the last plane of a z-chunk) the cell
-// gets the unscaled partial flux instead, completed by
-// divergence_edges_kernel.
+// gets its partial net flux over its volume, unscaled, which
+// divergence_edges_kernel completes.
 template <int MODE, bool DIV>
 __device__ __forceinline__ void operator_tiled_body(const Grid& g, const double* __restrict__ B,
                                                     const double* __restrict__ x, double* __restrict__ y,
@@ -741,7 +742,7 @@ __global__ void __launch_bounds__(256) scaled_divergence_kernel(Grid g, const do
 // rows (b1 blocks: 256 cells of a row each), the edge columns' cells in the
 // other rows (b2: 256 rows of a column), and the chunk-end planes' cells in
 // neither (the rest: 256 cells of a row).  Block indices are split with
-// wave-uniform arithmetic; cx, cy, cz count the edge columns, rows and planes.
+// wave-uniform arithmetic; cx and cy count the edge columns and rows.
 __global__ void __launch_bounds__(256) divergence_edges_kernel(Grid g, const double* __restrict__ y,
                                                                double* __restrict__ dv, int kc, int cx, int cy,
                                                                unsigned b1, unsigned b2) {
