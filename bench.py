@@ -471,20 +471,28 @@ def main():
             # HBM bytes per cell: stencil 96, FP32 divergence 28 (read y 24,
             # write 4), per sweep six FP32 transform passes (8 B each) and the
             # fused correction + divergence (read y 24, p 4; write y 24, b 4)
-            t_roof = (96.0 + 28.0 + sweeps * (48.0 + 56.0)) * n_cells / (HBM_PEAK_GBS * 1e9)
+            b_cell = 96.0 + 28.0 + sweeps * (48.0 + 56.0)
+            t_roof = b_cell * n_cells / (HBM_PEAK_GBS * 1e9)
         else:
             # the method's minimum: the fused stencil (104 B per cell) and the
             # correction (56 B) at the HBM peak, six transform passes at the
             # FP64 matrix-core peak (with or without the fusion enabled)
             t_roof = ((bpc["stencil"] + bpc["correction"]) * n_cells / (HBM_PEAK_GBS * 1e9)
                       + 6 * fd_flops / (FP64_PEAK_TFLOPS * 1e12))
+            # every phase's compulsory HBM bytes: stencil 104, the six
+            # transform passes 96 (16 each), correction 56: 256 B per cell
+            b_cell = bpc["stencil"] + bpc["fd"] + bpc["correction"]
             # the same step priced as the method without the even/odd split
             t_dense = dense_transform_model_s(n_cells, spec["n"])
             extra = {"dense_transform_model_ms": round(1e3 * t_dense, 4),
                      "dense_transform_model_frac": round(t_dense / t_meas, 4)}
         return {"value": args.steps / dt, "ms_per_step": 1e3 * dt / args.steps, "ms_per_vector_events": dist,
                 "roofline": roofline,
-                "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / t_meas, 4), **extra,
+                "roofline_secondary": secondary, "step_roofline_frac": round(t_roof / t_meas, 4),
+                # the whole step's algorithmic bytes at the measured rate,
+                # against the HBM peak
+                "pure_hbm_frac": round(b_cell * n_cells / t_meas / (HBM_PEAK_GBS * 1e9), 4),
+                "algorithmic_bytes_per_cell": round(b_cell, 2), **extra,
                 "sweeps_per_vector": round(sweeps, 3),
                 "divergence_fused": fused,
                 # with the fusion, "stencil" includes the divergence and
@@ -518,6 +526,7 @@ def main():
         "roofline": head["roofline"],
         "roofline_secondary": head["roofline_secondary"],
         "step_roofline_frac": head["step_roofline_frac"],
+        "pure_hbm_frac": head["pure_hbm_frac"],
         **({"dense_transform_model_frac": head["dense_transform_model_frac"]}
            if "dense_transform_model_frac" in head else {}),
         "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in forms.items()},
