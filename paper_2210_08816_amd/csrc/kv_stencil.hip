@@ -1125,12 +1125,12 @@ constexpr size_t kLdsJ = 14 * PLANE * sizeof(double), kLdsN = 7 * PLANE * sizeof
 constexpr size_t kLdsJDiv = kLdsJ + (4 * TX * TY + TX) * sizeof(double);
 
 // raise the dynamic-LDS limit of a kernel explicitly, whatever its default
-// (once per kernel)
+// (once per kernel and process; the static's initialization is thread-safe)
 template <const void* (*K)()>
 bool tiled_lds_ok(size_t bytes) {
-  static int ok = -1;
-  if (ok < 0) ok = hipFuncSetAttribute(K(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
-  return ok == 1;
+  static const bool ok =
+      hipFuncSetAttribute(K(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+  return ok;
 }
 const void* kernel_j() { return reinterpret_cast<const void*>(&operator_tiled_kernel<0>); }
 const void* kernel_jdiv() { return reinterpret_cast<const void*>(&operator_divergence_kernel); }
